@@ -1,0 +1,113 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that at
+least one pin catches each of them."""
+import numpy as np
+import pytest
+
+import oracle.chi0_oracle as orc
+import pins
+
+
+def _weight_sign(delta, omega, wk):
+    d = np.asarray(delta, np.float64)
+    return 2.0 * wk * d / (d * d + omega * omega)
+
+
+def _weight_no_two(delta, omega, wk):
+    d = np.asarray(delta, np.float64)
+    return -wk * d / (d * d + omega * omega)
+
+
+def _weight_minus_omega2(delta, omega, wk):
+    d = np.asarray(delta, np.float64)
+    return -2.0 * wk * d / (d * d - omega * omega + 1e-300)
+
+
+def _weight_wk_twice(delta, omega, wk):
+    d = np.asarray(delta, np.float64)
+    return -2.0 * wk * wk * d / (d * d + omega * omega)
+
+
+def _delta_transposed(eps_occ, eps_unocc):
+    return np.asarray(eps_occ)[:, None] - np.asarray(eps_unocc)[None, :]
+
+
+def _included_strict(delta, delta_min):
+    return (delta > 0.0) & (delta > delta_min)
+
+
+def _block_conj_second(z, eps_occ, eps_unocc, wk, omega, delta_min):
+    z = np.asarray(z)
+    nocc, nunocc, npb = z.shape
+    a = z.reshape(nocc * nunocc, npb).astype(np.complex128)
+    delta = orc.pair_delta(eps_occ, eps_unocc).reshape(-1)
+    keep = orc.pair_included(delta, delta_min)
+    a, delta = a[keep], delta[keep]
+    out = np.empty((len(omega), npb, npb), np.complex128)
+    for iw, w in enumerate(omega):
+        c = orc.transition_weight(delta, float(w), wk)
+        out[iw] = a.T @ (c[:, None] * a.conj())
+    return out
+
+
+
+
+
+def _dielectric_plus(chi0, vsqrt):
+    s = np.asarray(vsqrt)
+    return np.eye(s.shape[0])[None] + s[None, :, None] * chi0 * s[None, None, :]
+
+
+def _dielectric_one_side(chi0, vsqrt):
+    s = np.asarray(vsqrt)
+    return np.eye(s.shape[0])[None] - (s * s)[None, :, None] * chi0
+
+
+def _gj_no_pivot(a):
+    a = np.array(a, dtype=np.complex128)
+    n = a.shape[0]
+    aug = np.concatenate([a, np.eye(n, dtype=np.complex128)], axis=1)
+    for k in range(n):
+        aug[k] = aug[k] / aug[k, k]
+        col = aug[:, k].copy()
+        col[k] = 0.0
+        aug -= col[:, None] * aug[k][None, :]
+    return aug[:, n:]
+
+
+def _wc_no_minus_one(eps_inv, vsqrt):
+    s = np.asarray(vsqrt)
+    d = np.asarray(eps_inv)
+    return s[..., :, None] * d * s[..., None, :]
+
+
+def _ref_drop_last_block(blocks, npb, omega, delta_min=0.0):
+    blocks = list(blocks)
+    acc = orc._CompensatedSum((len(omega), npb, npb))
+    for z, eo, eu, wk in blocks[:-1] if len(blocks) > 1 else blocks:
+        acc.add(orc.chi0_block(z, eo, eu, wk, omega, delta_min))
+    return acc.value()
+
+
+MUTATIONS = {
+    "weight_sign": ("transition_weight", _weight_sign),
+    "weight_no_two": ("transition_weight", _weight_no_two),
+    "weight_minus_omega2": ("transition_weight", _weight_minus_omega2),
+    "weight_wk_twice": ("transition_weight", _weight_wk_twice),
+    "delta_transposed": ("pair_delta", _delta_transposed),
+    "tie_excluded": ("pair_included", _included_strict),
+    "conj_second_index": ("chi0_block", _block_conj_second),
+    "dielectric_plus": ("dielectric", _dielectric_plus),
+    "dielectric_one_side": ("dielectric", _dielectric_one_side),
+    "gj_no_pivot": ("inverse_gauss_jordan", _gj_no_pivot),
+    "wc_no_minus_one": ("screened_wc", _wc_no_minus_one),
+    "drop_last_block": ("chi0_ref", _ref_drop_last_block),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name, monkeypatch):
+    attr, fn = MUTATIONS[name]
+    monkeypatch.setattr(orc, attr, fn)
+    res = pins.run_all(orc)
+    caught = [k for k, v in res.items() if v]
+    assert caught, f"mutation {name} not caught by any pin"
