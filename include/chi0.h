@@ -1,0 +1,201 @@
+/*
+ * chi0.h -- C ABI of libchi0: the imaginary-axis polarization chi0(q, i omega)
+ * of the quasiparticle self-consistent GW method and its dielectric step, on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Eq.(polfx) on the imaginary axis, Eq.(dielectricfunction),
+ * Eq.(wc) of the paper; Algorithm "hrcxq" accumulates Pi and then inverts eps):
+ *
+ *   chi0[w][I][J] = sum_blocks w_k sum_{n occ} sum_{n' unocc, included}
+ *                   f(D, omega_w) * conj(Z_{nn'}(I)) * Z_{nn'}(J)
+ *   f(D, omega)   = -2 D / (D^2 + omega^2),   D = eps_unocc[n'] - eps_occ[n]
+ *   a pair is included iff D > 0 and D >= delta_min
+ *   eps[w]        = 1 - diag(s) chi0[w] diag(s),   s = vsqrt (square roots of
+ *                   the Coulomb eigenvalues v_mu)
+ *   W^c[w]        = diag(s) (eps[w]^{-1} - 1) diag(s)
+ *
+ * chi0 is Hermitian and negative semidefinite; eps is Hermitian with every
+ * eigenvalue >= 1.
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved (re, im) pairs of float (complex64) or
+ *     double (complex128).  Matrices are row-major, [nomega][npb][npb].
+ *   - "DEVICE" pointers are device memory of the handle's GPU; "HOST"
+ *     pointers are ordinary host memory read during the call only.  The
+ *     library never frees, retains or writes caller memory other than the
+ *     documented outputs.
+ *   - Calls are asynchronous on the given HIP stream (hipStream_t passed as
+ *     void*; NULL is the default stream).  Argument errors are returned
+ *     synchronously and nothing is enqueued.  Device-side failures (launch
+ *     errors, a zero pivot during inversion) are reported by chi0_sync().
+ *   - A handle may be used from one host thread at a time.
+ *   - Return values are chi0_status codes; chi0_last_error() gives a message
+ *     for the calling thread's most recent failure.
+ */
+#ifndef CHI0_H
+#define CHI0_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CHI0_OK = 0,
+  CHI0_EINVAL = -1,        /* invalid argument                                */
+  CHI0_ENOMEM = -2,        /* device workspace allocation failed              */
+  CHI0_EDEVICE = -3,       /* HIP runtime / kernel launch failure             */
+  CHI0_ESINGULAR = -5,     /* exact zero pivot met while inverting eps        */
+  CHI0_EUNSUPPORTED = -6   /* valid but unsupported combination               */
+} chi0_status;
+
+/* Arithmetic of the rank-K contraction.  Cross-block accumulation of chi0 is
+ * FP64 on every path; the inversion of eps is always FP64. */
+typedef enum {
+  CHI0_PREC_FP64 = 0,      /* complex128 Z, FP64 matrix cores                 */
+  CHI0_PREC_FP32 = 1,      /* complex64 Z, FP32 matrix cores, FP32 runs of at
+                              most the flush length, then FP64 accumulation   */
+  CHI0_PREC_BF16X3 = 2     /* complex64 Z; each operand split into bf16
+                              hi + lo, products hi*hi + hi*lo + lo*hi on BF16
+                              matrix cores with FP32 accumulation, FP64 flush */
+} chi0_precision;
+
+typedef enum {
+  CHI0_Z_C128 = 0,         /* Z is complex128 (required by CHI0_PREC_FP64)    */
+  CHI0_Z_C64 = 1           /* Z is complex64 (required by FP32 and BF16X3)    */
+} chi0_ztype;
+
+/* chi0_accumulate flags (bitwise or) */
+enum {
+  CHI0_OVERWRITE = 0,      /* chi0 output is overwritten                      */
+  CHI0_ACCUMULATE = 1,     /* chi0 output += this call's sum (the lower
+                              triangle of the existing contents is taken as the
+                              Hermitian matrix to add to)                      */
+  CHI0_BF16_LOLO = 2,      /* BF16X3 path also adds the lo*lo product         */
+  CHI0_USE_GRAPH = 4       /* replay the call's kernels from a cached hipGraph
+                              keyed by the problem shapes                     */
+};
+
+/* dielectric_invert flags */
+enum {
+  CHI0_INV_GJ = 0,         /* blocked Gauss-Jordan with partial pivoting      */
+  CHI0_OUT_WC = 8          /* also write W^c                                  */
+};
+
+typedef struct chi0_ctx* chi0_handle;
+
+/* One k-point (x spin) block of one q-point: nocc x nunocc pairs. */
+typedef struct {
+  int32_t nocc;            /* >= 0                                            */
+  int32_t nunocc;          /* >= 0                                            */
+  const void* z;           /* DEVICE [nocc][nunocc][npb] complex, row-major
+                              (npb contiguous; the Fortran Z(npb, n', n) of
+                              Algorithm "hrcxq"), 16-byte aligned; may be
+                              NULL when nocc * nunocc == 0                    */
+  const double* eps_occ;   /* DEVICE [nocc]   eps_{k, n}                      */
+  const double* eps_unocc; /* DEVICE [nunocc] eps_{k+q, n'} (caller maps k+q) */
+  double wk;               /* k-point weight, finite, >= 0 (carries the
+                              Brillouin-zone and any spin normalisation)      */
+} chi0_block;
+
+/* One q-point. */
+typedef struct {
+  int32_t npb;             /* product-basis size, >= 1                        */
+  int32_t nblocks;         /* >= 0                                            */
+  const chi0_block* blocks;/* HOST [nblocks]                                  */
+  int32_t nomega;          /* >= 1                                            */
+  const double* omega;     /* DEVICE [nomega] imaginary frequencies (same
+                              energy unit as eps); only omega^2 enters        */
+  void* chi0;              /* DEVICE out [nomega][npb][npb] complex128,
+                              written as an exactly Hermitian matrix (imaginary
+                              part of the diagonal is 0), 16-byte aligned     */
+} chi0_problem;
+
+/* Create a handle on HIP device `device`.  The handle owns device workspace,
+ * cached plans and graphs, and the tile table.  Returns CHI0_EDEVICE when the
+ * device is absent or not gfx950. */
+int chi0_create(chi0_handle* h, int device);
+
+/* Destroy a handle (synchronises its device first).  NULL is accepted. */
+int chi0_destroy(chi0_handle h);
+
+/* chi0 for `nprob` q-points (Eq.(polfx) at i*omega; Algorithm "hrcxq",
+ * accumulation of Pi over k, pairs and frequencies), all in one persistent
+ * launch plus one reduction launch.  Each (frequency, lower-triangle tile) of
+ * each problem is a weighted Hermitian rank-K update; blocks with uneven
+ * nocc / nunocc are balanced across the GPU by the planner.
+ *
+ * zt must match prec (C128 for FP64, C64 otherwise), else CHI0_EUNSUPPORTED.
+ * delta_min >= 0 is the intraband cut; pairs with D < delta_min or D <= 0
+ * contribute nothing.  Problems may have different npb and nomega.  Output
+ * buffers of different problems must not overlap. */
+int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob,
+                    chi0_ztype zt, chi0_precision prec, double delta_min,
+                    uint32_t flags, void* hip_stream);
+
+/* Dielectric step for one q-point (Eq.(dielectricfunction), Eq.(wc);
+ * Algorithm "hrcxq" builds eps, inverts it, forms W^c):
+ *   eps[w] = 1 - diag(vsqrt) chi0[w] diag(vsqrt), eps_inv[w] = eps[w]^{-1}
+ * by blocked Gauss-Jordan elimination with partial pivoting in FP64, and
+ * W^c[w] = diag(vsqrt) (eps_inv[w] - 1) diag(vsqrt) when CHI0_OUT_WC is set.
+ *   vsqrt   DEVICE [npb] double, > 0
+ *   chi0    DEVICE [nomega][npb][npb] complex128 (input, not modified)
+ *   eps     DEVICE out, same shape, or NULL
+ *   eps_inv DEVICE out, same shape (must not alias chi0 or eps)
+ *   wc      DEVICE out, same shape, used iff CHI0_OUT_WC (else may be NULL)
+ * A zero pivot makes chi0_sync() return CHI0_ESINGULAR (eps_inv is then
+ * undefined for that frequency). */
+int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega,
+                      const double* vsqrt, const void* chi0, void* eps,
+                      void* eps_inv, void* wc, uint32_t flags,
+                      void* hip_stream);
+
+/* Wait for all work the handle enqueued, then report deferred failures:
+ * CHI0_EDEVICE for a runtime error, CHI0_ESINGULAR for a zero pivot since the
+ * previous chi0_sync(). */
+int chi0_sync(chi0_handle h);
+
+/* Static description of a status code. */
+const char* chi0_status_string(int status);
+
+/* Message describing the calling thread's most recent failing call. */
+const char* chi0_last_error(void);
+
+/* Tile configurations of the rank-K kernels.  chi0_tile_count() gives the
+ * number of configurations for a precision, chi0_tile_info() describes one
+ * (tile rows x tile cols in complex elements, pairs per LDS stage, FP32 run
+ * length before an FP64 flush; 0 for FP64).  chi0_set_tile() fixes the
+ * configuration used for a precision (-1 = the autotuned or built-in
+ * default). */
+int chi0_tile_count(chi0_precision prec);
+int chi0_tile_info(chi0_precision prec, int32_t tile, int32_t* tile_p,
+                   int32_t* tile_q, int32_t* kchunk, int32_t* flush_len);
+int chi0_set_tile(chi0_handle h, chi0_precision prec, int32_t tile);
+int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile);
+
+/* Autotuner: time every tile configuration of `prec` on the given problems
+ * (their chi0 outputs are overwritten), keep the fastest as the handle's
+ * default for `prec`, and return its index in *best (may be NULL).  Timings
+ * (milliseconds per configuration) are written to ms_out[0 .. count-1] when
+ * ms_out is not NULL. */
+int chi0_autotune(chi0_handle h, const chi0_problem* probs, int32_t nprob,
+                  chi0_ztype zt, chi0_precision prec, double delta_min,
+                  int32_t reps, int32_t* best, double* ms_out,
+                  void* hip_stream);
+
+/* Kernel timing.  When enabled, every launch of the rank-K kernel is
+ * bracketed by HIP events on the stream it runs on; chi0_profile_read()
+ * waits for them and returns the summed duration (ms) and the number of
+ * launches since the last read. */
+int chi0_profile_enable(chi0_handle h, int on);
+int chi0_profile_read(chi0_handle h, double* kernel_ms, int64_t* launches);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int chi0_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHI0_H */

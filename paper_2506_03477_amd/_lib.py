@@ -1,0 +1,268 @@
+"""ctypes binding of libchi0 (include/chi0.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libchi0.so.  Tensors are PyTorch device tensors; the binding passes
+their data pointers and the current HIP stream.  The library must have been
+built (``python -m paper_2506_03477_amd.build``); importing this module fails
+loudly otherwise, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_int32, c_int64, c_uint32, c_void_p
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchi0.so")
+
+CHI0_OK = 0
+CHI0_EINVAL = -1
+CHI0_ENOMEM = -2
+CHI0_EDEVICE = -3
+CHI0_ESINGULAR = -5
+CHI0_EUNSUPPORTED = -6
+
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+ZTYPE = {"c128": 0, "c64": 1}
+CHI0_ACCUMULATE = 1
+CHI0_BF16_LOLO = 2
+CHI0_USE_GRAPH = 4
+CHI0_INV_GJ = 0
+CHI0_OUT_WC = 8
+
+
+class chi0_block(ctypes.Structure):
+    _fields_ = [("nocc", c_int32), ("nunocc", c_int32), ("z", c_void_p),
+                ("eps_occ", c_void_p), ("eps_unocc", c_void_p), ("wk", c_double)]
+
+
+class chi0_problem(ctypes.Structure):
+    _fields_ = [("npb", c_int32), ("nblocks", c_int32), ("blocks", POINTER(chi0_block)),
+                ("nomega", c_int32), ("omega", c_void_p), ("chi0", c_void_p)]
+
+
+class Chi0Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libchi0 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libchi0.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built; run python -m paper_2506_03477_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = c_void_p
+    sig = {
+        "chi0_version": (c_int, []),
+        "chi0_status_string": (ctypes.c_char_p, [c_int]),
+        "chi0_last_error": (ctypes.c_char_p, []),
+        "chi0_create": (c_int, [POINTER(vp), c_int]),
+        "chi0_destroy": (c_int, [vp]),
+        "chi0_accumulate": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
+                                    c_uint32, vp]),
+        "dielectric_invert": (c_int, [vp, c_int32, c_int32, vp, vp, vp, vp, vp, c_uint32, vp]),
+        "chi0_sync": (c_int, [vp]),
+        "chi0_tile_count": (c_int, [c_int]),
+        "chi0_tile_info": (c_int, [c_int, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                   POINTER(c_int32), POINTER(c_int32)]),
+        "chi0_set_tile": (c_int, [vp, c_int, c_int32]),
+        "chi0_get_tile": (c_int, [vp, c_int, POINTER(c_int32)]),
+        "chi0_autotune": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
+                                  c_int32, POINTER(c_int32), POINTER(c_double), vp]),
+        "chi0_profile_enable": (c_int, [vp, c_int]),
+        "chi0_profile_read": (c_int, [vp, POINTER(c_double), POINTER(c_int64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        lib = load()
+        raise Chi0Error(rc, lib.chi0_last_error().decode() or lib.chi0_status_string(rc).decode())
+    return rc
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype=None, what="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    return c_void_p(t.data_ptr())
+
+
+@dataclass
+class Block:
+    """One k-point (x spin) block: z [nocc, nunocc, npb] complex device tensor,
+    eps_occ [nocc] / eps_unocc [nunocc] float64 device tensors, weight wk."""
+    z: object
+    eps_occ: object
+    eps_unocc: object
+    wk: float
+
+
+@dataclass
+class Problem:
+    """One q-point: blocks, omega [nomega] float64 device tensor, chi0 output
+    [nomega, npb, npb] complex128 device tensor."""
+    blocks: List[Block]
+    omega: object
+    chi0: object
+
+    @property
+    def npb(self) -> int:
+        return int(self.chi0.shape[-1])
+
+
+def _marshal(problems: Sequence[Problem]):
+    import torch
+    keep = []
+    arr = (chi0_problem * len(problems))()
+    for i, p in enumerate(problems):
+        nomega, npb, npb2 = p.chi0.shape
+        if npb != npb2 or p.omega.numel() != nomega:
+            raise ValueError("chi0 must be [nomega, npb, npb] with omega [nomega]")
+        barr = (chi0_block * max(1, len(p.blocks)))()
+        for j, b in enumerate(p.blocks):
+            nocc, nunocc = int(b.eps_occ.numel()), int(b.eps_unocc.numel())
+            if b.z is not None and b.z.numel():
+                if tuple(b.z.shape) != (nocc, nunocc, npb):
+                    raise ValueError(f"block {j}: z shape {tuple(b.z.shape)} != {(nocc, nunocc, npb)}")
+            barr[j].nocc = nocc
+            barr[j].nunocc = nunocc
+            barr[j].z = _dev_ptr(b.z, what="z") if b.z is not None and b.z.numel() else None
+            barr[j].eps_occ = _dev_ptr(b.eps_occ, torch.float64, "eps_occ") if nocc else None
+            barr[j].eps_unocc = _dev_ptr(b.eps_unocc, torch.float64, "eps_unocc") if nunocc else None
+            barr[j].wk = float(b.wk)
+        keep.append(barr)
+        arr[i].npb = npb
+        arr[i].nblocks = len(p.blocks)
+        arr[i].blocks = ctypes.cast(barr, POINTER(chi0_block))
+        arr[i].nomega = nomega
+        arr[i].omega = _dev_ptr(p.omega, torch.float64, "omega")
+        arr[i].chi0 = _dev_ptr(p.chi0, torch.complex128, "chi0")
+    return arr, keep
+
+
+def _ztype_of(problems: Sequence[Problem]) -> int:
+    import torch
+    for p in problems:
+        for b in p.blocks:
+            if b.z is not None and b.z.numel():
+                return ZTYPE["c128"] if b.z.dtype == torch.complex128 else ZTYPE["c64"]
+    return ZTYPE["c128"]
+
+
+class Context:
+    """A libchi0 handle on one GPU."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        self._h = c_void_p()
+        _check(self._lib.chi0_create(byref(self._h), int(device)))
+
+    def close(self):
+        if self._h:
+            self._lib.chi0_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- chi0 ---------------------------------------------------------------
+    def chi0_accumulate(self, problems: Sequence[Problem], precision: str = "fp64",
+                        delta_min: float = 0.0, accumulate: bool = False,
+                        lolo: bool = False, graph: bool = False, stream=None) -> None:
+        arr, keep = _marshal(problems)
+        flags = (CHI0_ACCUMULATE if accumulate else 0) | (CHI0_BF16_LOLO if lolo else 0) | \
+            (CHI0_USE_GRAPH if graph else 0)
+        _check(self._lib.chi0_accumulate(self._h, arr, len(problems), _ztype_of(problems),
+                                         PREC[precision], float(delta_min), flags,
+                                         _stream_ptr(stream)))
+
+    # -- dielectric ----------------------------------------------------------
+    def dielectric_invert(self, vsqrt, chi0, eps_inv, eps=None, wc=None, stream=None) -> None:
+        import torch
+        nomega, npb, _ = chi0.shape
+        flags = CHI0_OUT_WC if wc is not None else 0
+        _check(self._lib.dielectric_invert(
+            self._h, npb, nomega, _dev_ptr(vsqrt, torch.float64, "vsqrt"),
+            _dev_ptr(chi0, torch.complex128, "chi0"), _dev_ptr(eps, torch.complex128, "eps"),
+            _dev_ptr(eps_inv, torch.complex128, "eps_inv"), _dev_ptr(wc, torch.complex128, "wc"),
+            flags, _stream_ptr(stream)))
+
+    def sync(self) -> None:
+        _check(self._lib.chi0_sync(self._h))
+
+    # -- tiles / tuning / timing -----------------------------------------------
+    def tile_count(self, precision: str) -> int:
+        return _check(self._lib.chi0_tile_count(PREC[precision]))
+
+    def tile_info(self, precision: str, tile: int):
+        a, b, c, d = c_int32(), c_int32(), c_int32(), c_int32()
+        _check(self._lib.chi0_tile_info(PREC[precision], tile, byref(a), byref(b), byref(c), byref(d)))
+        return {"tile_p": a.value, "tile_q": b.value, "kchunk": c.value, "flush_len": d.value}
+
+    def set_tile(self, precision: str, tile: int) -> None:
+        _check(self._lib.chi0_set_tile(self._h, PREC[precision], tile))
+
+    def get_tile(self, precision: str) -> int:
+        t = c_int32()
+        _check(self._lib.chi0_get_tile(self._h, PREC[precision], byref(t)))
+        return t.value
+
+    def autotune(self, problems: Sequence[Problem], precision: str, delta_min: float = 0.0,
+                 reps: int = 2, stream=None):
+        arr, keep = _marshal(problems)
+        n = self.tile_count(precision)
+        ms = (c_double * max(1, n))()
+        best = c_int32()
+        _check(self._lib.chi0_autotune(self._h, arr, len(problems), _ztype_of(problems),
+                                       PREC[precision], float(delta_min), reps, byref(best), ms,
+                                       _stream_ptr(stream)))
+        return best.value, [ms[i] for i in range(n)]
+
+    def profile_enable(self, on: bool = True) -> None:
+        _check(self._lib.chi0_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        ms, n = c_double(), c_int64()
+        _check(self._lib.chi0_profile_read(self._h, byref(ms), byref(n)))
+        return ms.value, n.value
+
+
+def header_functions() -> List[str]:
+    """Names of the functions declared in include/chi0.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(_HERE), "include", "chi0.h")
+    with open(hdr) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(\w+)\s*\(", src, flags=re.M)))

@@ -1,0 +1,797 @@
+// libchi0 host library: C ABI, argument validation, work planning, workspace,
+// hipGraph cache, kernel timing and the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <queue>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/chi0.h"
+#include "common.h"
+
+using namespace chi0;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(CHI0_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+// Device buffer that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  int reserve(size_t bytes, uint64_t* gen) {
+    if (bytes <= n) return CHI0_OK;
+    if (p) {
+      hipDeviceSynchronize();
+      hipFree(p);
+      p = nullptr;
+      n = 0;
+    }
+    size_t want = std::max(bytes, static_cast<size_t>(256));
+    if (hipMalloc(&p, want) != hipSuccess) {
+      hipGetLastError();
+      p = nullptr;
+      return fail(CHI0_ENOMEM, "device allocation of %zu bytes failed", want);
+    }
+    n = want;
+    if (gen) ++*gen;
+    return CHI0_OK;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct Plan {
+  int kind = 0;
+  int tile_idx = 0;
+  TileConfig tc{};
+  int nwg = 0;
+  int nunits = 0;
+  int njobs = 0;
+  int nblocks_total = 0;
+  int nprob = 0;
+  DevBuf d_units, d_wg_off, d_wg_units, d_jobs, d_blocks, d_probs;
+  // graph per accumulate flag, valid for workspace generation graph_gen
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  uint64_t graph_gen[2] = {0, 0};
+  ~Plan() {
+    for (auto& g : graph)
+      if (g) hipGraphExecDestroy(g);
+    d_units.release();
+    d_wg_off.release();
+    d_wg_units.release();
+    d_jobs.release();
+    d_blocks.release();
+    d_probs.release();
+  }
+};
+
+}  // namespace
+
+struct chi0_ctx {
+  int device = 0;
+  int ncu = 0;
+  DevBuf partials;
+  DevBuf gj_work, gj_wrow, gj_piv, gj_perm;
+  uint64_t ws_gen = 1;
+  int32_t* d_status = nullptr;
+  void* staging = nullptr;  // pinned host staging for table uploads
+  size_t staging_n = 0;
+  hipEvent_t staging_done = nullptr;
+  bool staging_pending = false;
+  std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
+  int tile_sel[3] = {-1, -1, -1};
+  int tile_tuned[3] = {-1, -1, -1};
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
+  std::vector<hipEvent_t> event_pool;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+  bool sticky_error = false;
+};
+
+namespace {
+
+int kind_of(chi0_precision p) {
+  switch (p) {
+    case CHI0_PREC_FP64: return HERK_FP64;
+    case CHI0_PREC_FP32: return HERK_FP32;
+    case CHI0_PREC_BF16X3: return HERK_BF16X3;
+  }
+  return -1;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+hipEvent_t get_event(chi0_ctx* h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int validate_problems(const chi0_problem* probs, int32_t nprob, chi0_ztype zt,
+                      chi0_precision prec, double delta_min, uint32_t flags) {
+  if (nprob < 0) return fail(CHI0_EINVAL, "nprob = %d < 0", nprob);
+  if (nprob > 0 && !probs) return fail(CHI0_EINVAL, "probs is NULL");
+  if (prec != CHI0_PREC_FP64 && prec != CHI0_PREC_FP32 && prec != CHI0_PREC_BF16X3)
+    return fail(CHI0_EINVAL, "unknown precision %d", static_cast<int>(prec));
+  if (zt != CHI0_Z_C128 && zt != CHI0_Z_C64)
+    return fail(CHI0_EINVAL, "unknown Z type %d", static_cast<int>(zt));
+  if (!(delta_min >= 0.0) || !std::isfinite(delta_min))
+    return fail(CHI0_EINVAL, "delta_min must be finite and >= 0 (got %g)", delta_min);
+  if (flags & ~static_cast<uint32_t>(CHI0_ACCUMULATE | CHI0_BF16_LOLO | CHI0_USE_GRAPH))
+    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  for (int p = 0; p < nprob; ++p) {
+    const chi0_problem& pr = probs[p];
+    if (pr.npb < 1) return fail(CHI0_EINVAL, "problem %d: npb = %d < 1", p, pr.npb);
+    if (pr.nomega < 1) return fail(CHI0_EINVAL, "problem %d: nomega = %d < 1", p, pr.nomega);
+    if (pr.nblocks < 0) return fail(CHI0_EINVAL, "problem %d: nblocks = %d < 0", p, pr.nblocks);
+    if (pr.nblocks > 0 && !pr.blocks) return fail(CHI0_EINVAL, "problem %d: blocks is NULL", p);
+    if (!pr.omega) return fail(CHI0_EINVAL, "problem %d: omega is NULL", p);
+    if (!pr.chi0) return fail(CHI0_EINVAL, "problem %d: chi0 is NULL", p);
+    if (!aligned(pr.chi0, 16)) return fail(CHI0_EINVAL, "problem %d: chi0 not 16-byte aligned", p);
+    if (!aligned(pr.omega, 8)) return fail(CHI0_EINVAL, "problem %d: omega not 8-byte aligned", p);
+    for (int b = 0; b < pr.nblocks; ++b) {
+      const chi0_block& bl = pr.blocks[b];
+      if (bl.nocc < 0 || bl.nunocc < 0)
+        return fail(CHI0_EINVAL, "problem %d block %d: negative nocc/nunocc", p, b);
+      const int64_t K = static_cast<int64_t>(bl.nocc) * bl.nunocc;
+      if (K > 0x7fffffffLL)
+        return fail(CHI0_EINVAL, "problem %d block %d: more than 2^31-1 pairs", p, b);
+      if (!std::isfinite(bl.wk) || bl.wk < 0.0)
+        return fail(CHI0_EINVAL, "problem %d block %d: wk must be finite and >= 0", p, b);
+      if (K > 0) {
+        if (!bl.z) return fail(CHI0_EINVAL, "problem %d block %d: z is NULL", p, b);
+        if (!aligned(bl.z, 16))
+          return fail(CHI0_EINVAL, "problem %d block %d: z not 16-byte aligned", p, b);
+        if (!bl.eps_occ || !bl.eps_unocc)
+          return fail(CHI0_EINVAL, "problem %d block %d: energies are NULL", p, b);
+      }
+    }
+    // output buffers of different problems must not overlap
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(pr.chi0);
+    const uintptr_t a1 = a0 + static_cast<uintptr_t>(pr.nomega) * pr.npb * pr.npb * 16;
+    for (int q = 0; q < p; ++q) {
+      const uintptr_t b0 = reinterpret_cast<uintptr_t>(probs[q].chi0);
+      const uintptr_t b1 = b0 + static_cast<uintptr_t>(probs[q].nomega) * probs[q].npb * probs[q].npb * 16;
+      if (a0 < b1 && b0 < a1) return fail(CHI0_EINVAL, "problems %d and %d: chi0 outputs overlap", q, p);
+    }
+  }
+  const bool need128 = prec == CHI0_PREC_FP64;
+  if (need128 != (zt == CHI0_Z_C128))
+    return fail(CHI0_EUNSUPPORTED, "precision %d needs Z type %s", static_cast<int>(prec),
+                need128 ? "CHI0_Z_C128" : "CHI0_Z_C64");
+  return CHI0_OK;
+}
+
+std::string plan_key(int kind, int tile_idx, int nwg, const chi0_problem* probs, int nprob) {
+  std::string k;
+  k.reserve(64 + nprob * 16);
+  char buf[64];
+  snprintf(buf, sizeof(buf), "%d/%d/%d/%d|", kind, tile_idx, nwg, nprob);
+  k += buf;
+  for (int p = 0; p < nprob; ++p) {
+    snprintf(buf, sizeof(buf), "%d,%d,%d:", probs[p].npb, probs[p].nomega, probs[p].nblocks);
+    k += buf;
+    for (int b = 0; b < probs[p].nblocks; ++b) {
+      snprintf(buf, sizeof(buf), "%d.%d;", probs[p].blocks[b].nocc, probs[p].blocks[b].nunocc);
+      k += buf;
+    }
+  }
+  return k;
+}
+
+template <class T>
+int upload_sync(DevBuf& d, const std::vector<T>& v) {
+  const size_t bytes = std::max<size_t>(sizeof(T), v.size() * sizeof(T));
+  int rc = d.reserve(bytes, nullptr);
+  if (rc) return rc;
+  if (!v.empty()) HIP_TRY(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return CHI0_OK;
+}
+
+// Work decomposition.
+//  * Every (problem, frequency, lower tile) is split into s_p contiguous
+//    ranges of the problem's pairs (blocks concatenated); s_p is chosen so
+//    that there are several units per workgroup.
+//  * Units are ordered range-major (then tile, then frequency) so that the
+//    workgroups running at the same time stream the same rows of Z, and are
+//    dealt to workgroups by greedy list scheduling in that order (each unit
+//    goes to the workgroup that becomes free first, by the pair-count cost
+//    model).
+//  * Logical workgroups are placed XCD-major: consecutive logical
+//    workgroups share an XCD (workgroups are dispatched round-robin over the
+//    8 XCDs), so units that read the same Z columns share an L2.
+int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem* probs,
+               int nprob) {
+  const TileConfig tc = herk_tile_config(kind, tile_idx);
+  const int T = tc.tile;
+  const int wg_per_cu = std::max(1, herk_max_wg_per_cu(kind, tile_idx));
+  const int nwg = h->ncu * wg_per_cu;
+  pl.kind = kind;
+  pl.tile_idx = tile_idx;
+  pl.tc = tc;
+  pl.nwg = nwg;
+  pl.nprob = nprob;
+
+  struct P {
+    int npb, nomega, nt, ntl, b0, nb;
+    int64_t K;
+    std::vector<int64_t> cum;  // cumulative pairs at block starts
+  };
+  std::vector<P> ps(nprob);
+  int bflat = 0;
+  double work = 0.0;
+  for (int p = 0; p < nprob; ++p) {
+    P& q = ps[p];
+    q.npb = probs[p].npb;
+    q.nomega = probs[p].nomega;
+    q.nt = (q.npb + T - 1) / T;
+    q.ntl = q.nt * (q.nt + 1) / 2;
+    q.b0 = bflat;
+    q.nb = probs[p].nblocks;
+    q.cum.resize(q.nb + 1);
+    q.cum[0] = 0;
+    for (int b = 0; b < q.nb; ++b)
+      q.cum[b + 1] = q.cum[b] + static_cast<int64_t>(probs[p].blocks[b].nocc) * probs[p].blocks[b].nunocc;
+    q.K = q.cum[q.nb];
+    bflat += q.nb;
+    work += static_cast<double>(q.nomega) * q.ntl * static_cast<double>(q.K);
+  }
+  pl.nblocks_total = bflat;
+
+  // target pairs per unit: ~8 units per workgroup, at least 1024 pairs, and
+  // partial storage bounded
+  const double min_pairs = 1024.0;
+  double per_unit = std::max(min_pairs, work / (8.0 * nwg));
+  const double slot_bytes = static_cast<double>(T) * T * 16.0;
+  const double max_partial_bytes = 6.0e9;
+  auto count_units = [&](double pu) {
+    double n = 0;
+    for (auto& q : ps)
+      n += static_cast<double>(q.nomega) * q.ntl * std::max<int64_t>(1, std::llround(std::ceil(q.K / pu)));
+    return n;
+  };
+  while (count_units(per_unit) * slot_bytes > max_partial_bytes) per_unit *= 1.5;
+
+  std::vector<Unit> units;
+  std::vector<TileJob> jobs;
+  std::vector<double> cost;
+  // ranges per problem
+  struct Range { int b0, p0, b1, p1; int64_t n; };
+  std::vector<std::vector<Range>> ranges(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    P& q = ps[p];
+    int64_t s = std::max<int64_t>(1, std::llround(std::ceil(static_cast<double>(q.K) / per_unit)));
+    if (q.K == 0) s = 1;
+    for (int64_t r = 0; r < s; ++r) {
+      const int64_t g0 = q.K * r / s, g1 = q.K * (r + 1) / s;
+      Range rg{};
+      rg.n = g1 - g0;
+      if (q.nb == 0) {
+        rg.b0 = q.b0; rg.p0 = 0; rg.b1 = q.b0 - 1; rg.p1 = 0;  // empty: loop does nothing
+      } else {
+        int bb = static_cast<int>(std::upper_bound(q.cum.begin(), q.cum.end(), g0) - q.cum.begin()) - 1;
+        bb = std::min(bb, q.nb - 1);
+        rg.b0 = q.b0 + bb;
+        rg.p0 = static_cast<int>(g0 - q.cum[bb]);
+        int be = static_cast<int>(std::lower_bound(q.cum.begin(), q.cum.end(), g1) - q.cum.begin()) - 1;
+        be = std::max(be, 0);
+        be = std::min(be, q.nb - 1);
+        rg.b1 = q.b0 + be;
+        rg.p1 = static_cast<int>(g1 - q.cum[be]);
+        if (g1 == g0) { rg.b1 = rg.b0; rg.p1 = rg.p0; }
+      }
+      ranges[p].push_back(rg);
+    }
+  }
+  // units in tile-job order (slots of a job contiguous)
+  std::vector<int> unit_range_idx;
+  for (int p = 0; p < nprob; ++p) {
+    P& q = ps[p];
+    for (int iw = 0; iw < q.nomega; ++iw)
+      for (int tp = 0; tp < q.nt; ++tp)
+        for (int tq = 0; tq <= tp; ++tq) {
+          TileJob j{p, iw, tp, tq, static_cast<int32_t>(units.size()),
+                    static_cast<int32_t>(ranges[p].size())};
+          jobs.push_back(j);
+          for (size_t r = 0; r < ranges[p].size(); ++r) {
+            const Range& rg = ranges[p][r];
+            Unit u{};
+            u.prob = p; u.iw = iw; u.tp = tp; u.tq = tq;
+            u.b0 = rg.b0; u.p0 = rg.p0; u.b1 = rg.b1; u.p1 = rg.p1;
+            u.slot = static_cast<int32_t>(units.size());
+            units.push_back(u);
+            unit_range_idx.push_back(static_cast<int>(r));
+            // cost: pairs rounded up to staging chunks per block touched, plus a
+            // fixed per-unit cost (zeroing and writing the tile)
+            const double nblk = rg.b1 - rg.b0 + 1;
+            cost.push_back(static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0);
+          }
+        }
+  }
+  // locality order: (problem, range, tile, frequency)
+  std::vector<int> order(units.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const Unit& ua = units[a];
+    const Unit& ub = units[b];
+    if (ua.prob != ub.prob) return ua.prob < ub.prob;
+    if (unit_range_idx[a] != unit_range_idx[b]) return unit_range_idx[a] < unit_range_idx[b];
+    if (ua.tp != ub.tp) return ua.tp < ub.tp;
+    if (ua.tq != ub.tq) return ua.tq < ub.tq;
+    return ua.iw < ub.iw;
+  });
+  // greedy list scheduling over logical workgroups
+  std::vector<std::vector<int>> lists(nwg);
+  typedef std::pair<double, int> Slot;
+  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+  for (int w = 0; w < nwg; ++w) heap.push(Slot(0.0, w));
+  for (int id : order) {
+    Slot s = heap.top();
+    heap.pop();
+    lists[s.second].push_back(id);
+    s.first += cost[id];
+    heap.push(s);
+  }
+  // logical -> physical placement (XCD-major)
+  const int nxcd = 8;
+  std::vector<int> phys_of(nwg);
+  if (nwg % nxcd == 0) {
+    const int per = nwg / nxcd;
+    for (int L = 0; L < nwg; ++L) phys_of[L] = (L % per) * nxcd + L / per;
+  } else {
+    for (int L = 0; L < nwg; ++L) phys_of[L] = L;
+  }
+  std::vector<std::vector<int>> plists(nwg);
+  for (int L = 0; L < nwg; ++L) plists[phys_of[L]] = std::move(lists[L]);
+  std::vector<int32_t> off(nwg + 1, 0), flat;
+  flat.reserve(units.size());
+  for (int w = 0; w < nwg; ++w) {
+    off[w] = static_cast<int32_t>(flat.size());
+    for (int id : plists[w]) flat.push_back(id);
+  }
+  off[nwg] = static_cast<int32_t>(flat.size());
+
+  pl.nunits = static_cast<int>(units.size());
+  pl.njobs = static_cast<int>(jobs.size());
+  int rc;
+  if ((rc = upload_sync(pl.d_units, units))) return rc;
+  if ((rc = upload_sync(pl.d_wg_off, off))) return rc;
+  if ((rc = upload_sync(pl.d_wg_units, flat))) return rc;
+  if ((rc = upload_sync(pl.d_jobs, jobs))) return rc;
+  if ((rc = pl.d_blocks.reserve(std::max(1, bflat) * sizeof(BlockDesc), nullptr))) return rc;
+  if ((rc = pl.d_probs.reserve(std::max(1, nprob) * sizeof(ProbDesc), nullptr))) return rc;
+  return CHI0_OK;
+}
+
+int staging_reserve(chi0_ctx* h, size_t bytes) {
+  if (h->staging_pending) {
+    HIP_TRY(hipEventSynchronize(h->staging_done));
+    h->staging_pending = false;
+  }
+  if (bytes <= h->staging_n) return CHI0_OK;
+  if (h->staging) hipHostFree(h->staging);
+  h->staging = nullptr;
+  h->staging_n = 0;
+  HIP_TRY(hipHostMalloc(&h->staging, bytes, hipHostMallocDefault));
+  h->staging_n = bytes;
+  return CHI0_OK;
+}
+
+int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_precision prec,
+                   double delta_min, uint32_t flags, hipStream_t stream, int tile_override) {
+  const int kind = kind_of(prec);
+  const int ntile = herk_tile_count(kind);
+  if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this build", prec);
+  int tile_idx = tile_override >= 0 ? tile_override
+                 : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
+                 : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind] : 0;
+  if (tile_idx >= ntile) tile_idx = 0;
+  int wg_per_cu = std::max(1, herk_max_wg_per_cu(kind, tile_idx));
+  const int nwg = h->ncu * wg_per_cu;
+  const std::string key = plan_key(kind, tile_idx, nwg, probs, nprob);
+  auto it = h->plans.find(key);
+  Plan* pl;
+  if (it == h->plans.end()) {
+    std::unique_ptr<Plan> np(new Plan());
+    int rc = build_plan(h, *np, kind, tile_idx, probs, nprob);
+    if (rc) return rc;
+    pl = np.get();
+    h->plans.emplace(key, std::move(np));
+  } else {
+    pl = it->second.get();
+  }
+  if (pl->nunits == 0) return CHI0_OK;
+  const int T = pl->tc.tile;
+  int rc = h->partials.reserve(static_cast<size_t>(pl->nunits) * T * T * sizeof(double2), &h->ws_gen);
+  if (rc) return rc;
+
+  // per-call tables (pointers change between calls) via pinned staging
+  std::vector<BlockDesc> bt;
+  bt.reserve(pl->nblocks_total);
+  std::vector<ProbDesc> ptab(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    ptab[p].chi0 = static_cast<double2*>(probs[p].chi0);
+    ptab[p].omega = probs[p].omega;
+    ptab[p].npb = probs[p].npb;
+    ptab[p].nomega = probs[p].nomega;
+    for (int b = 0; b < probs[p].nblocks; ++b) {
+      const chi0_block& bl = probs[p].blocks[b];
+      BlockDesc d;
+      d.z = bl.z;
+      d.eps_occ = bl.eps_occ;
+      d.eps_unocc = bl.eps_unocc;
+      d.wk = bl.wk;
+      d.nocc = bl.nocc;
+      d.nunocc = bl.nunocc;
+      bt.push_back(d);
+    }
+  }
+  const size_t bt_bytes = bt.size() * sizeof(BlockDesc);
+  const size_t pt_bytes = ptab.size() * sizeof(ProbDesc);
+  if ((rc = staging_reserve(h, bt_bytes + pt_bytes + 64))) return rc;
+  char* st = static_cast<char*>(h->staging);
+  if (bt_bytes) memcpy(st, bt.data(), bt_bytes);
+  memcpy(st + bt_bytes, ptab.data(), pt_bytes);
+  if (bt_bytes) HIP_TRY(hipMemcpyAsync(pl->d_blocks.p, st, bt_bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(pl->d_probs.p, st + bt_bytes, pt_bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(h->staging_done, stream));
+  h->staging_pending = true;
+
+  HerkArgs ha;
+  ha.units = static_cast<const Unit*>(pl->d_units.p);
+  ha.wg_offsets = static_cast<const int32_t*>(pl->d_wg_off.p);
+  ha.wg_units = static_cast<const int32_t*>(pl->d_wg_units.p);
+  ha.blocks = static_cast<const BlockDesc*>(pl->d_blocks.p);
+  ha.probs = static_cast<const ProbDesc*>(pl->d_probs.p);
+  ha.partials = static_cast<double2*>(h->partials.p);
+  ha.delta_min = delta_min;
+  ha.flags = static_cast<int32_t>(flags);
+  ha.flush_len = pl->tc.flush;
+  ReduceArgs ra;
+  ra.jobs = static_cast<const TileJob*>(pl->d_jobs.p);
+  ra.probs = ha.probs;
+  ra.partials = ha.partials;
+  ra.tile = T;
+  ra.accumulate = (flags & CHI0_ACCUMULATE) ? 1 : 0;
+
+  const bool use_graph = (flags & CHI0_USE_GRAPH) && !h->profiling;
+  if (use_graph) {
+    // delta_min and the LO*LO flag are kernel arguments: the cached graph is
+    // only reused with the same values, so they join the key
+    const int gi = ra.accumulate;
+    char kb[96];
+    snprintf(kb, sizeof(kb), "#g%d/%a/%u", gi, delta_min, flags);
+    const std::string gkey = key + kb;
+    auto git = h->plans.find(gkey);
+    Plan* gp = nullptr;
+    if (git == h->plans.end()) {
+      std::unique_ptr<Plan> holder(new Plan());
+      gp = holder.get();
+      h->plans.emplace(gkey, std::move(holder));
+    } else {
+      gp = git->second.get();
+    }
+    if (!gp->graph[0] || gp->graph_gen[0] != h->ws_gen) {
+      if (gp->graph[0]) hipGraphExecDestroy(gp->graph[0]);
+      gp->graph[0] = nullptr;
+      hipStream_t cs;
+      HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) e = herk_launch(kind, pl->tile_idx, ha, pl->nwg, cs);
+      if (e == hipSuccess) e = reduce_launch(ra, pl->njobs, cs);
+      hipError_t e2 = hipStreamEndCapture(cs, &g);
+      hipStreamDestroy(cs);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return fail(CHI0_EDEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(CHI0_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+      gp->graph[0] = ex;
+      gp->graph_gen[0] = h->ws_gen;
+    }
+    HIP_TRY(hipGraphLaunch(gp->graph[0], stream));
+    return CHI0_OK;
+  }
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->profiling) {
+    e0 = get_event(h);
+    e1 = get_event(h);
+    if (e0) HIP_TRY(hipEventRecord(e0, stream));
+  }
+  hipError_t e = herk_launch(kind, pl->tile_idx, ha, pl->nwg, stream);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "rank-K kernel launch: %s", hipGetErrorString(e));
+  if (h->profiling && e0 && e1) {
+    HIP_TRY(hipEventRecord(e1, stream));
+    h->prof_pending.emplace_back(e0, e1);
+  }
+  e = reduce_launch(ra, pl->njobs, stream);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "reduction launch: %s", hipGetErrorString(e));
+  return CHI0_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chi0_version(void) { return 10000; }
+
+const char* chi0_status_string(int s) {
+  switch (s) {
+    case CHI0_OK: return "ok";
+    case CHI0_EINVAL: return "invalid argument";
+    case CHI0_ENOMEM: return "device allocation failed";
+    case CHI0_EDEVICE: return "HIP device or launch failure";
+    case CHI0_ESINGULAR: return "zero pivot while inverting eps";
+    case CHI0_EUNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+const char* chi0_last_error(void) { return g_err.c_str(); }
+
+int chi0_create(chi0_handle* out, int device) {
+  if (!out) return fail(CHI0_EINVAL, "handle pointer is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    hipGetLastError();
+    return fail(CHI0_EDEVICE, "no HIP device visible");
+  }
+  if (device < 0 || device >= ndev) return fail(CHI0_EINVAL, "device %d out of range [0, %d)", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(CHI0_EDEVICE, "device %d is %s; libchi0 is built for gfx950 only", device, prop.gcnArchName);
+  std::unique_ptr<chi0_ctx> h(new chi0_ctx());
+  h->device = device;
+  h->ncu = prop.multiProcessorCount;
+  HIP_TRY(hipMalloc(&h->d_status, 64));
+  HIP_TRY(hipMemset(h->d_status, 0, 64));
+  HIP_TRY(hipEventCreateWithFlags(&h->staging_done, hipEventDisableTiming));
+  *out = h.release();
+  return CHI0_OK;
+}
+
+int chi0_destroy(chi0_handle h) {
+  if (!h) return CHI0_OK;
+  hipSetDevice(h->device);
+  hipDeviceSynchronize();
+  h->plans.clear();
+  h->partials.release();
+  h->gj_work.release();
+  h->gj_wrow.release();
+  h->gj_piv.release();
+  h->gj_perm.release();
+  if (h->d_status) hipFree(h->d_status);
+  if (h->staging) hipHostFree(h->staging);
+  if (h->staging_done) hipEventDestroy(h->staging_done);
+  for (auto& pr : h->prof_pending) {
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  for (auto e : h->event_pool) hipEventDestroy(e);
+  delete h;
+  return CHI0_OK;
+}
+
+int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_ztype zt,
+                    chi0_precision prec, double delta_min, uint32_t flags, void* hip_stream) {
+  int rc = validate_problems(probs, nprob, zt, prec, delta_min, flags);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (nprob == 0) return CHI0_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  return run_accumulate(h, probs, nprob, prec, delta_min, flags,
+                        static_cast<hipStream_t>(hip_stream), -1);
+}
+
+int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* vsqrt,
+                      const void* chi0, void* eps, void* eps_inv, void* wc, uint32_t flags,
+                      void* hip_stream) {
+  if (npb < 1) return fail(CHI0_EINVAL, "npb = %d < 1", npb);
+  if (nomega < 1) return fail(CHI0_EINVAL, "nomega = %d < 1", nomega);
+  if (flags & ~static_cast<uint32_t>(CHI0_OUT_WC)) return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  if (!vsqrt || !chi0 || !eps_inv) return fail(CHI0_EINVAL, "vsqrt, chi0 and eps_inv must be non-NULL");
+  if ((flags & CHI0_OUT_WC) && !wc) return fail(CHI0_EINVAL, "CHI0_OUT_WC set but wc is NULL");
+  if (!aligned(chi0, 16) || !aligned(eps_inv, 16) || (eps && !aligned(eps, 16)) ||
+      ((flags & CHI0_OUT_WC) && !aligned(wc, 16)) || !aligned(vsqrt, 8))
+    return fail(CHI0_EINVAL, "buffers must be 16-byte aligned (vsqrt 8-byte)");
+  const size_t bytes = static_cast<size_t>(nomega) * npb * npb * 16;
+  auto overlap = [bytes](const void* a, const void* b) {
+    if (!a || !b) return false;
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+  };
+  if (overlap(eps_inv, chi0) || overlap(eps_inv, eps) || ((flags & CHI0_OUT_WC) && (overlap(wc, eps_inv) || overlap(wc, chi0))))
+    return fail(CHI0_EINVAL, "eps_inv / wc must not overlap chi0, eps or each other");
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int nb = gj_panel_width();
+  int rc;
+  if ((rc = h->gj_work.reserve(bytes, &h->ws_gen))) return rc;
+  if ((rc = h->gj_wrow.reserve(static_cast<size_t>(nomega) * nb * npb * 16, &h->ws_gen))) return rc;
+  if ((rc = h->gj_piv.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
+  if ((rc = h->gj_perm.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
+  double2* work = static_cast<double2*>(h->gj_work.p);
+  double2* wrow = static_cast<double2*>(h->gj_wrow.p);
+  int32_t* piv = static_cast<int32_t*>(h->gj_piv.p);
+  int32_t* perm = static_cast<int32_t*>(h->gj_perm.p);
+  hipError_t e = dielectric_build_launch(static_cast<const double2*>(chi0), vsqrt, work,
+                                         static_cast<double2*>(eps), npb, nomega, s);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "eps build launch: %s", hipGetErrorString(e));
+  for (int k0 = 0; k0 < npb; k0 += nb) {
+    const int nbk = std::min(nb, npb - k0);
+    e = gj_panel_launch(work, npb, nomega, k0, nbk, piv, h->d_status, s);
+    if (e == hipSuccess) e = gj_swap_extract_launch(work, wrow, npb, nomega, k0, nbk, piv, s);
+    if (e == hipSuccess) e = gj_update_launch(work, wrow, npb, nomega, k0, nbk, s);
+    if (e != hipSuccess) return fail(CHI0_EDEVICE, "Gauss-Jordan launch: %s", hipGetErrorString(e));
+  }
+  e = gj_finish_launch(work, static_cast<double2*>(eps_inv),
+                       (flags & CHI0_OUT_WC) ? static_cast<double2*>(wc) : nullptr, vsqrt, piv, perm,
+                       npb, nomega, s);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "Gauss-Jordan finish launch: %s", hipGetErrorString(e));
+  return CHI0_OK;
+}
+
+int chi0_sync(chi0_handle h) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  HIP_TRY(hipSetDevice(h->device));
+  HIP_TRY(hipDeviceSynchronize());
+  int32_t st = 0;
+  HIP_TRY(hipMemcpy(&st, h->d_status, sizeof(st), hipMemcpyDeviceToHost));
+  if (st) {
+    HIP_TRY(hipMemset(h->d_status, 0, sizeof(int32_t)));
+    return fail(CHI0_ESINGULAR, "a zero pivot was met while inverting eps");
+  }
+  return CHI0_OK;
+}
+
+int chi0_tile_count(chi0_precision prec) {
+  const int k = kind_of(prec);
+  return k < 0 ? fail(CHI0_EINVAL, "unknown precision") : herk_tile_count(k);
+}
+
+int chi0_tile_info(chi0_precision prec, int32_t tile, int32_t* tile_p, int32_t* tile_q,
+                   int32_t* kchunk, int32_t* flush_len) {
+  const int k = kind_of(prec);
+  if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
+  if (tile < 0 || tile >= herk_tile_count(k)) return fail(CHI0_EINVAL, "tile %d out of range", tile);
+  const TileConfig tc = herk_tile_config(k, tile);
+  if (tile_p) *tile_p = tc.tile;
+  if (tile_q) *tile_q = tc.tile;
+  if (kchunk) *kchunk = tc.kchunk;
+  if (flush_len) *flush_len = tc.flush;
+  return CHI0_OK;
+}
+
+int chi0_set_tile(chi0_handle h, chi0_precision prec, int32_t tile) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  const int k = kind_of(prec);
+  if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
+  if (tile < -1 || tile >= herk_tile_count(k)) return fail(CHI0_EINVAL, "tile %d out of range", tile);
+  h->tile_sel[k] = tile;
+  return CHI0_OK;
+}
+
+int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile) {
+  if (!h || !tile) return fail(CHI0_EINVAL, "NULL argument");
+  const int k = kind_of(prec);
+  if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
+  *tile = h->tile_sel[k] >= 0 ? h->tile_sel[k] : h->tile_tuned[k] >= 0 ? h->tile_tuned[k] : 0;
+  return CHI0_OK;
+}
+
+int chi0_autotune(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_ztype zt,
+                  chi0_precision prec, double delta_min, int32_t reps, int32_t* best,
+                  double* ms_out, void* hip_stream) {
+  int rc = validate_problems(probs, nprob, zt, prec, delta_min, 0);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (reps < 1) return fail(CHI0_EINVAL, "reps must be >= 1");
+  HIP_TRY(hipSetDevice(h->device));
+  const int k = kind_of(prec);
+  const int n = herk_tile_count(k);
+  if (n <= 0) return fail(CHI0_EUNSUPPORTED, "precision has no kernel in this build");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  int bi = 0;
+  double bms = 1e300;
+  const bool prof = h->profiling;
+  h->profiling = false;
+  for (int t = 0; t < n; ++t) {
+    rc = run_accumulate(h, probs, nprob, prec, delta_min, 0, s, t);  // warm-up + plan
+    if (rc) break;
+    hipEventRecord(a, s);
+    for (int r = 0; r < reps && !rc; ++r) rc = run_accumulate(h, probs, nprob, prec, delta_min, 0, s, t);
+    hipEventRecord(b, s);
+    if (rc) break;
+    if (hipEventSynchronize(b) != hipSuccess) { rc = fail(CHI0_EDEVICE, "autotune sync failed"); break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, a, b);
+    const double per = ms / reps;
+    if (ms_out) ms_out[t] = per;
+    if (per < bms) {
+      bms = per;
+      bi = t;
+    }
+  }
+  h->profiling = prof;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (rc) return rc;
+  h->tile_tuned[k] = bi;
+  if (best) *best = bi;
+  return CHI0_OK;
+}
+
+int chi0_profile_enable(chi0_handle h, int on) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  h->profiling = on != 0;
+  return CHI0_OK;
+}
+
+int chi0_profile_read(chi0_handle h, double* kernel_ms, int64_t* launches) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  for (auto& pr : h->prof_pending) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    h->prof_ms += ms;
+    h->prof_launches += 1;
+    h->event_pool.push_back(pr.first);
+    h->event_pool.push_back(pr.second);
+  }
+  h->prof_pending.clear();
+  if (kernel_ms) *kernel_ms = h->prof_ms;
+  if (launches) *launches = h->prof_launches;
+  h->prof_ms = 0.0;
+  h->prof_launches = 0;
+  return CHI0_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Shared host/device definitions of libchi0 (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chi0 {
+
+// One k-point (x spin) block as the kernels see it (device table entry).
+struct BlockDesc {
+  const void* z;            // [nocc][nunocc][npb] complex, row-major
+  const double* eps_occ;    // [nocc]
+  const double* eps_unocc;  // [nunocc]
+  double wk;
+  int32_t nocc;
+  int32_t nunocc;
+};
+
+// One q-point (device table entry).
+struct ProbDesc {
+  double2* chi0;            // [nomega][npb][npb] complex128 output
+  const double* omega;      // [nomega]
+  int32_t npb;
+  int32_t nomega;
+};
+
+// A unit of rank-K work: a contiguous range of pairs (from pair p0 of block
+// b0 to pair p1 (exclusive) of block b1, blocks in between complete; block
+// indices refer to the flat block table) contracted into one lower-triangle
+// tile (tp >= tq) of one frequency of one problem and written to FP64
+// partial slot `slot`.
+struct Unit {
+  int32_t prob;
+  int32_t iw;
+  int32_t tp;
+  int32_t tq;
+  int32_t b0;     // first block (flat block table index)
+  int32_t p0;     // first pair of block b0
+  int32_t b1;     // last block (inclusive)
+  int32_t p1;     // end pair (exclusive) of block b1
+  int32_t slot;
+  int32_t pad[3];
+};
+
+// Reduction job: the partial slots [slot0, slot0 + nslot) of one tile are
+// summed in order, negated, written to the lower triangle and mirrored.
+struct TileJob {
+  int32_t prob;
+  int32_t iw;
+  int32_t tp;
+  int32_t tq;
+  int32_t slot0;
+  int32_t nslot;
+};
+
+// Arguments of the persistent rank-K kernels.
+struct HerkArgs {
+  const Unit* units;
+  const int32_t* wg_offsets;  // [nwg + 1]: units of workgroup w are
+  const int32_t* wg_units;    // wg_units[wg_offsets[w] .. wg_offsets[w+1])
+  const BlockDesc* blocks;
+  const ProbDesc* probs;
+  double2* partials;          // [nslots][T][T] complex128
+  double delta_min;
+  int32_t flags;
+  int32_t flush_len;          // pairs per FP32 run (reduced-precision paths)
+};
+
+struct ReduceArgs {
+  const TileJob* jobs;
+  const ProbDesc* probs;
+  const double2* partials;
+  int32_t tile;               // T
+  int32_t accumulate;
+};
+
+// Kernel variants of the rank-K contraction.
+enum HerkKind { HERK_FP64 = 0, HERK_FP32 = 1, HERK_BF16X3 = 2 };
+
+struct TileConfig {
+  int32_t tile;      // T: tiles are T x T complex elements
+  int32_t kchunk;    // pairs staged in LDS per step
+  int32_t flush;     // FP32 run length in pairs (0: FP64 accumulation)
+  int32_t threads;   // workgroup size
+};
+
+// Host launchers (defined next to their kernels).
+int herk_tile_count(int kind);
+TileConfig herk_tile_config(int kind, int idx);
+int herk_max_wg_per_cu(int kind, int idx);
+hipError_t herk_launch(int kind, int idx, const HerkArgs& a, int nwg,
+                       hipStream_t s);
+hipError_t reduce_launch(const ReduceArgs& a, int njobs, hipStream_t s);
+
+hipError_t dielectric_build_launch(const double2* chi0, const double* vsqrt,
+                                   double2* work, double2* eps_out, int n,
+                                   int nomega, hipStream_t s);
+hipError_t gj_panel_launch(double2* work, int n, int nomega, int k0, int nb,
+                           int32_t* piv, int32_t* status, hipStream_t s);
+hipError_t gj_swap_extract_launch(double2* work, double2* wrow, int n,
+                                  int nomega, int k0, int nb,
+                                  const int32_t* piv, hipStream_t s);
+hipError_t gj_update_launch(double2* work, const double2* wrow, int n,
+                            int nomega, int k0, int nb, hipStream_t s);
+hipError_t gj_finish_launch(const double2* work, double2* eps_inv,
+                            double2* wc, const double* vsqrt,
+                            const int32_t* piv, int32_t* perm, int n,
+                            int nomega, hipStream_t s);
+int gj_panel_width();
+
+}  // namespace chi0

@@ -1,0 +1,338 @@
+// Dielectric step on gfx950: eps = 1 - diag(s) chi0 diag(s)
+// (Eq.(dielectricfunction)), its FP64 inverse by blocked Gauss-Jordan
+// elimination with partial pivoting (Algorithm "hrcxq" inverts eps for every
+// frequency), and W^c = diag(s) (eps^{-1} - 1) diag(s) (Eq.(wc)).
+//
+// The matrices of all frequencies are processed together (the batch index is
+// the last grid dimension).  Gauss-Jordan works in place on a workspace copy:
+// for each panel of nb columns
+//   1. gj_panel: the nb elimination steps restricted to the n x nb panel,
+//      pivot = entry of largest modulus at or below the diagonal; the panel
+//      ends up holding the combined elimination columns C;
+//   2. gj_swap_extract: the panel's row interchanges applied, in order, to
+//      every other column; the nb pivot rows copied out (W);
+//   3. gj_update: every other column j gets X[:, j] = X[:, j] (rows outside
+//      the panel) + C W[:, j]  -- a complex FP64 GEMM on the matrix cores.
+// Finally the columns are unscrambled (the interchanges applied in reverse
+// order to the column index).
+#include "common.h"
+
+namespace chi0 {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPanel = 32;     // nb
+constexpr int kPanelThreads = 1024;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+__global__ __launch_bounds__(256) void dielectric_build_kernel(
+    const double2* __restrict__ chi0, const double* __restrict__ s,
+    double2* __restrict__ work, double2* __restrict__ eps_out, int n, size_t total) {
+#pragma clang fp contract(off)
+  const size_t nn = static_cast<size_t>(n) * n;
+  for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < total;
+       e += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t r = e % nn;
+    const int i = static_cast<int>(r / n);
+    const int j = static_cast<int>(r - static_cast<size_t>(i) * n);
+    const double2 c = chi0[e];
+    const double si = s[i], sj = s[j];
+    double2 v;
+    v.x = (i == j ? 1.0 : 0.0) - (si * c.x) * sj;
+    v.y = -((si * c.y) * sj);
+    work[e] = v;
+    if (eps_out) eps_out[e] = v;
+  }
+}
+
+__global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(
+    double2* __restrict__ work, int n, int k0, int nb, int32_t* __restrict__ piv,
+    int32_t* __restrict__ status) {
+  constexpr int NW = kPanelThreads / 64;
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
+  __shared__ double2 rowk[kPanel];
+  __shared__ double2 s_d;
+  __shared__ int s_p;
+  const int mat = blockIdx.x;
+  double2* S = work + static_cast<size_t>(mat) * n * n;
+  int32_t* pv = piv + static_cast<size_t>(mat) * n;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+
+  for (int kk = 0; kk < nb; ++kk) {
+    const int k = k0 + kk;
+    // 1. pivot: largest |S[i][k]|^2 over i >= k (smallest index on ties)
+    double best = -1.0;
+    int bi = n;
+    for (int i = k + tid; i < n; i += kPanelThreads) {
+      const double2 v = S[static_cast<size_t>(i) * n + k];
+      const double m2 = v.x * v.x + v.y * v.y;
+      if (m2 > best) {
+        best = m2;
+        bi = i;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[wave] = best;
+      red_i[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double bv = red_v[0];
+      int bix = red_i[0];
+      for (int w = 1; w < NW; ++w)
+        if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bix)) {
+          bv = red_v[w];
+          bix = red_i[w];
+        }
+      if (bix >= n) bix = k;
+      if (!(bv > 0.0)) status[0] = 1;
+      s_p = bix;
+      pv[k] = bix;
+    }
+    __syncthreads();
+    const int p = s_p;
+    // 2. interchange rows k and p inside the panel
+    if (p != k && tid < nb) {
+      const size_t a0 = static_cast<size_t>(k) * n + k0 + tid;
+      const size_t a1 = static_cast<size_t>(p) * n + k0 + tid;
+      const double2 t0 = S[a0];
+      S[a0] = S[a1];
+      S[a1] = t0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double2 pvt = S[static_cast<size_t>(k) * n + k];
+      const double den = pvt.x * pvt.x + pvt.y * pvt.y;
+      s_d = double2{pvt.x / den, -pvt.y / den};
+    }
+    __syncthreads();
+    // 3. scale the pivot row (S[k][k] <- 1 first, so it ends up as 1/pivot)
+    if (tid < nb) {
+      const size_t a0 = static_cast<size_t>(k) * n + k0 + tid;
+      const double2 v = (k0 + tid == k) ? double2{1.0, 0.0} : S[a0];
+      const double2 r = cmul(v, s_d);
+      rowk[tid] = r;
+      S[a0] = r;
+    }
+    __syncthreads();
+    // 4. eliminate column k from every other row (S[i][k] <- 0 first)
+    for (int i = tid; i < n; i += kPanelThreads) {
+      if (i == k) continue;
+      double2* Si = S + static_cast<size_t>(i) * n + k0;
+      const double2 f = Si[kk];
+      for (int t = 0; t < nb; ++t) {
+        double2 x = (t == kk) ? double2{0.0, 0.0} : Si[t];
+        const double2 fr = cmul(f, rowk[t]);
+        x.x -= fr.x;
+        x.y -= fr.y;
+        Si[t] = x;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void gj_swap_extract_kernel(
+    double2* __restrict__ work, double2* __restrict__ wrow, int n, int k0, int nb,
+    const int32_t* __restrict__ piv) {
+  const int mat = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n || (j >= k0 && j < k0 + nb)) return;
+  double2* S = work + static_cast<size_t>(mat) * n * n;
+  const int32_t* pv = piv + static_cast<size_t>(mat) * n;
+  double2* W = wrow + static_cast<size_t>(mat) * kPanel * n;
+  for (int b = 0; b < nb; ++b) {
+    const int r = k0 + b;
+    const int p = pv[r];
+    if (p != r) {
+      const size_t a0 = static_cast<size_t>(r) * n + j;
+      const size_t a1 = static_cast<size_t>(p) * n + j;
+      const double2 t0 = S[a0];
+      S[a0] = S[a1];
+      S[a1] = t0;
+    }
+  }
+  for (int b = 0; b < nb; ++b) W[static_cast<size_t>(b) * n + j] = S[static_cast<size_t>(k0 + b) * n + j];
+}
+
+// X[i][j] = (i in panel rows ? 0 : X[i][j]) + sum_b C[i][b] W[b][j], j outside
+// the panel.  64 x 64 complex output tile per workgroup, 4 waves of 32 x 32,
+// FP64 16x16x4 MFMA with (re, im) stacked along the contraction index:
+//   Re += [Cr, Ci] . [Wr, -Wi],  Im += [Cr, Ci] . [Wi, Wr].
+__global__ __launch_bounds__(256) void gj_update_kernel(
+    double2* __restrict__ work, const double2* __restrict__ wrow, int n, int k0, int nb) {
+  constexpr int T = 64;
+  __shared__ double2 sC[kPanel][T];
+  __shared__ double2 sW[kPanel][T];
+  const int mat = blockIdx.z;
+  const int i0 = blockIdx.y * T;
+  const int j0 = blockIdx.x * T;
+  if (j0 + T > k0 && j0 < k0 + nb && j0 >= k0 && j0 + T <= k0 + nb) return;  // inside panel
+  double2* S = work + static_cast<size_t>(mat) * n * n;
+  const double2* W = wrow + static_cast<size_t>(mat) * kPanel * n;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kPanel * T; e += 256) {
+    const int b = e % kPanel;
+    const int i = e / kPanel;
+    double2 v = {0.0, 0.0};
+    if (b < nb && i0 + i < n) v = S[static_cast<size_t>(i0 + i) * n + k0 + b];
+    sC[b][i] = v;
+    const int bj = e / T;
+    const int jj = e % T;
+    double2 w = {0.0, 0.0};
+    if (bj < nb && j0 + jj < n) w = W[static_cast<size_t>(bj) * n + j0 + jj];
+    sW[bj][jj] = w;
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int m = lane & 15;
+  const int kk = lane >> 4;
+  const int prr = kk >> 1;
+  const bool isim = (kk & 1) != 0;
+  f64x4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      accR[a][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+      accI[a][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int st = 0; st < kPanel / 2; ++st) {
+    const int b = 2 * st + prr;
+    double av[2], wr_[2], wi_[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double2 x = sC[b][wr * 32 + a * 16 + m];
+      av[a] = isim ? x.y : x.x;
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double2 y = sW[b][wc * 32 + c * 16 + m];
+      wr_[c] = isim ? -y.y : y.x;
+      wi_[c] = isim ? y.x : y.y;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        accR[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], wr_[c], accR[a][c], 0, 0, 0);
+        accI[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], wi_[c], accI[a][c], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + kk + 4 * r;  // f64 16x16x4 result rows
+        const int j = j0 + wc * 32 + c * 16 + m;
+        if (i >= n || j >= n || (j >= k0 && j < k0 + nb)) continue;
+        const size_t ad = static_cast<size_t>(i) * n + j;
+        double2 x = (i >= k0 && i < k0 + nb) ? double2{0.0, 0.0} : S[ad];
+        x.x += accR[a][c][r];
+        x.y += accI[a][c][r];
+        S[ad] = x;
+      }
+}
+
+__global__ void gj_perm_kernel(const int32_t* __restrict__ piv, int32_t* __restrict__ perm, int n) {
+  const int mat = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const int32_t* pv = piv + static_cast<size_t>(mat) * n;
+  int32_t* ix = perm + static_cast<size_t>(mat) * n;
+  for (int j = 0; j < n; ++j) ix[j] = j;
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = pv[k];
+    const int32_t t = ix[k];
+    ix[k] = ix[p];
+    ix[p] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void gj_finish_kernel(
+    const double2* __restrict__ work, double2* __restrict__ eps_inv, double2* __restrict__ wc,
+    const double* __restrict__ s, const int32_t* __restrict__ perm, int n) {
+#pragma clang fp contract(off)
+  const int mat = blockIdx.z;
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const size_t base = static_cast<size_t>(mat) * n * n + static_cast<size_t>(i) * n;
+  const int src = perm[static_cast<size_t>(mat) * n + j];
+  const double2 x = work[base + src];
+  eps_inv[base + j] = x;
+  if (wc) {
+    const double si = s[i], sj = s[j];
+    double2 w;
+    w.x = (si * (x.x - (i == j ? 1.0 : 0.0))) * sj;
+    w.y = (si * x.y) * sj;
+    wc[base + j] = w;
+  }
+}
+
+}  // namespace
+
+int gj_panel_width() { return kPanel; }
+
+hipError_t dielectric_build_launch(const double2* chi0, const double* vsqrt, double2* work,
+                                   double2* eps_out, int n, int nomega, hipStream_t s) {
+  const size_t total = static_cast<size_t>(n) * n * nomega;
+  size_t nblk = (total + 255) / 256;
+  if (nblk > 65536) nblk = 65536;
+  hipLaunchKernelGGL(dielectric_build_kernel, dim3(static_cast<unsigned>(nblk)), dim3(256), 0, s,
+                     chi0, vsqrt, work, eps_out, n, total);
+  return hipGetLastError();
+}
+
+hipError_t gj_panel_launch(double2* work, int n, int nomega, int k0, int nb, int32_t* piv,
+                           int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(gj_panel_kernel, dim3(nomega), dim3(kPanelThreads), 0, s, work, n, k0, nb,
+                     piv, status);
+  return hipGetLastError();
+}
+
+hipError_t gj_swap_extract_launch(double2* work, double2* wrow, int n, int nomega, int k0, int nb,
+                                  const int32_t* piv, hipStream_t s) {
+  hipLaunchKernelGGL(gj_swap_extract_kernel, dim3((n + 255) / 256, nomega), dim3(256), 0, s, work,
+                     wrow, n, k0, nb, piv);
+  return hipGetLastError();
+}
+
+hipError_t gj_update_launch(double2* work, const double2* wrow, int n, int nomega, int k0, int nb,
+                            hipStream_t s) {
+  const int nt = (n + 63) / 64;
+  hipLaunchKernelGGL(gj_update_kernel, dim3(nt, nt, nomega), dim3(256), 0, s, work, wrow, n, k0,
+                     nb);
+  return hipGetLastError();
+}
+
+hipError_t gj_finish_launch(const double2* work, double2* eps_inv, double2* wc,
+                            const double* vsqrt, const int32_t* piv, int32_t* perm, int n,
+                            int nomega, hipStream_t s) {
+  hipLaunchKernelGGL(gj_perm_kernel, dim3(nomega), dim3(64), 0, s, piv, perm, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gj_finish_kernel, dim3((n + 255) / 256, n, nomega), dim3(256), 0, s, work,
+                     eps_inv, wc, vsqrt, perm, n);
+  return hipGetLastError();
+}
+
+}  // namespace chi0

@@ -1,0 +1,164 @@
+// FP64 weighted Hermitian rank-K update on gfx950 matrix cores.
+//
+// For one unit (problem, frequency, lower-triangle tile (tp, tq), block range)
+// the kernel accumulates, in FP64,
+//   S[P][Q] = sum_pairs c * conj(Z[pair][P]) * Z[pair][Q],
+//   c = w_k * 2 D / (D^2 + omega^2) >= 0,
+// over the tile's T x T complex entries; chi0 = -S (Eq.(polfx) at i*omega).
+// The complex product is four real products stacked along the contraction
+// index of v_mfma_f64_16x16x4f64: k-slots (re, im) of two pairs per MFMA,
+//   Re S += [ar, ai] . [br, bi],   Im S += [ar, ai] . [bi, -br].
+// The pair weight scales the Q-side operand as it is staged into LDS.
+#include "common.h"
+#include "herk_common.h"
+
+namespace chi0 {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int T, int KC>
+__global__ __launch_bounds__(256) void herk_fp64_kernel(HerkArgs a) {
+  static_assert(T % 32 == 0 && KC % 2 == 0, "tile shape");
+  constexpr int NT = 256;
+  constexpr int WT = T / 2;        // wave sub-tile (2 x 2 waves)
+  constexpr int NB = WT / 16;      // 16x16 MFMA blocks per wave side
+  __shared__ double2 sA[KC][T];
+  __shared__ double2 sB[KC][T];
+  __shared__ double sW[KC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int m = lane & 15;
+  const int kk = lane >> 4;
+  const int prr = kk >> 1;          // pair of the k-step held by this lane
+  const bool isim = (kk & 1) != 0;  // real or imaginary k-slot
+
+  const int beg = a.wg_offsets[blockIdx.x];
+  const int end = a.wg_offsets[blockIdx.x + 1];
+  for (int ui = beg; ui < end; ++ui) {
+    const Unit u = a.units[a.wg_units[ui]];
+    const ProbDesc pd = a.probs[u.prob];
+    const int npb = pd.npb;
+    const double om = pd.omega[u.iw];
+    const double w2 = om * om;
+    const int colP0 = u.tp * T;
+    const int colQ0 = u.tq * T;
+
+    f64x4 accR[NB][NB], accI[NB][NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        accR[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        accI[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      }
+
+    for (int b = u.b0; b <= u.b1; ++b) {
+      const BlockDesc bd = a.blocks[b];
+      const int pbeg = (b == u.b0) ? u.p0 : 0;
+      const int K = (b == u.b1) ? u.p1 : bd.nocc * bd.nunocc;  // end pair
+      const double2* z = static_cast<const double2*>(bd.z);
+      for (int p0 = pbeg; p0 < K; p0 += KC) {
+        if (tid < KC) sW[tid] = pair_weight(bd, p0 + tid, K, w2, a.delta_min);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < KC * T / NT; ++i) {
+          const int e = tid + i * NT;
+          const int r = e / T;
+          const int c = e % T;
+          const int p = p0 + r;
+          double2 va = {0.0, 0.0}, vb = {0.0, 0.0};
+          if (p < K) {
+            const size_t row = static_cast<size_t>(p) * npb;
+            if (colP0 + c < npb) va = z[row + colP0 + c];
+            if (colQ0 + c < npb) vb = z[row + colQ0 + c];
+          }
+          const double s = sW[r];
+          vb.x *= s;
+          vb.y *= s;
+          sA[r][c] = va;
+          sB[r][c] = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < KC / 2; ++st) {
+          const int pair = 2 * st + prr;
+          double av[NB], br[NB], bi[NB];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            const double2 x = sA[pair][wr * WT + i * 16 + m];
+            av[i] = isim ? x.y : x.x;
+          }
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const double2 y = sB[pair][wc * WT + j * 16 + m];
+            br[j] = isim ? y.y : y.x;
+            bi[j] = isim ? -y.x : y.y;
+          }
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], br[j], accR[i][j], 0, 0, 0);
+              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bi[j], accI[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+      }
+    }
+
+    // Result layout of 16x16x4 f64: lane holds column (lane % 16) of rows
+    // (lane / 16) + 4 r, r = 0..3.
+    double2* out = a.partials + static_cast<size_t>(u.slot) * T * T;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wr * WT + i * 16 + kk + 4 * r;
+          const int col = wc * WT + j * 16 + m;
+          out[row * T + col] = double2{accR[i][j][r], accI[i][j][r]};
+        }
+  }
+}
+
+}  // namespace
+
+// Tile table of the FP64 path.
+static const TileConfig kFp64Tiles[] = {
+    {64, 16, 0, 256},
+    {32, 16, 0, 256},
+};
+
+int herk_fp64_tile_count() { return sizeof(kFp64Tiles) / sizeof(kFp64Tiles[0]); }
+TileConfig herk_fp64_tile(int idx) { return kFp64Tiles[idx]; }
+
+hipError_t herk_fp64_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
+  switch (idx) {
+    case 0:
+      hipLaunchKernelGGL((herk_fp64_kernel<64, 16>), dim3(nwg), dim3(256), 0, s, a);
+      break;
+    case 1:
+      hipLaunchKernelGGL((herk_fp64_kernel<32, 16>), dim3(nwg), dim3(256), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int herk_fp64_max_wg_per_cu(int idx) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (idx == 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_kernel<64, 16>, 256, 0);
+  else if (idx == 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_kernel<32, 16>, 256, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
+}  // namespace chi0

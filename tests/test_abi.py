@@ -1,0 +1,132 @@
+"""The C ABI library loads and exports what include/chi0.h declares; host-side
+argument validation (no GPU work: every call here fails validation, or meets
+a NULL handle, before any device call)."""
+import ctypes
+import re
+from ctypes import byref, c_double, c_int32, c_void_p
+
+import pytest
+
+import paper_2506_03477_amd as pkg
+from paper_2506_03477_amd import _lib as L
+
+
+def test_exports_every_declared_function():
+    lib = pkg.load()
+    names = pkg.header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.chi0_version() >= 10000
+
+
+def test_status_strings():
+    lib = pkg.load()
+    for code in (0, -1, -2, -3, -5, -6):
+        assert lib.chi0_status_string(code).decode() != "unknown status"
+    assert lib.chi0_status_string(42).decode() == "unknown status"
+
+
+def test_tile_tables():
+    lib = pkg.load()
+    assert lib.chi0_tile_count(0) >= 1
+    a, b, c, d = c_int32(), c_int32(), c_int32(), c_int32()
+    assert lib.chi0_tile_info(0, 0, byref(a), byref(b), byref(c), byref(d)) == 0
+    assert a.value == b.value and a.value % 16 == 0 and c.value > 0
+    assert lib.chi0_tile_info(0, 999, byref(a), byref(b), byref(c), byref(d)) == L.CHI0_EINVAL
+    assert lib.chi0_tile_count(7) == L.CHI0_EINVAL
+
+
+FAKE = 0x10000  # never dereferenced: validation rejects before any device call
+
+
+def _problem(npb=8, nomega=2, nblocks=1, nocc=2, nunocc=3, z=FAKE, chi0=FAKE, omega=FAKE,
+             wk=0.5):
+    blocks = (L.chi0_block * max(1, nblocks))()
+    for i in range(nblocks):
+        blocks[i].nocc, blocks[i].nunocc = nocc, nunocc
+        blocks[i].z = z
+        blocks[i].eps_occ = FAKE
+        blocks[i].eps_unocc = FAKE
+        blocks[i].wk = wk
+    p = (L.chi0_problem * 1)()
+    p[0].npb, p[0].nblocks = npb, nblocks
+    p[0].blocks = ctypes.cast(blocks, ctypes.POINTER(L.chi0_block))
+    p[0].nomega, p[0].omega, p[0].chi0 = nomega, omega, chi0
+    return p, blocks
+
+
+def _acc(p, zt=0, prec=0, dmin=0.0, flags=0, nprob=1):
+    lib = pkg.load()
+    rc = lib.chi0_accumulate(None, p, nprob, zt, prec, dmin, flags, None)
+    return rc, lib.chi0_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(npb=0), "npb"),
+    (dict(nomega=0), "nomega"),
+    (dict(nocc=-1), "negative"),
+    (dict(z=None), "z is NULL"),
+    (dict(z=FAKE + 8), "aligned"),
+    (dict(chi0=None), "chi0 is NULL"),
+    (dict(chi0=FAKE + 4), "aligned"),
+    (dict(omega=None), "omega is NULL"),
+    (dict(wk=-1.0), "wk"),
+    (dict(wk=float("nan")), "wk"),
+])
+def test_validation_rejects(kw, needle):
+    p, keep = _problem(**kw)
+    rc, msg = _acc(p)
+    assert rc == L.CHI0_EINVAL and needle in msg, (rc, msg)
+
+
+def test_validation_flags_precision_and_handle():
+    p, keep = _problem()
+    assert _acc(p, dmin=-1.0)[0] == L.CHI0_EINVAL
+    assert _acc(p, dmin=float("inf"))[0] == L.CHI0_EINVAL
+    assert _acc(p, flags=64)[0] == L.CHI0_EINVAL
+    assert _acc(p, prec=9)[0] == L.CHI0_EINVAL
+    assert _acc(p, zt=1, prec=0)[0] == L.CHI0_EUNSUPPORTED       # FP64 needs complex128
+    assert _acc(p, zt=0, prec=2)[0] == L.CHI0_EUNSUPPORTED       # BF16x3 needs complex64
+    assert _acc(p, nprob=-1)[0] == L.CHI0_EINVAL
+    rc, msg = _acc(p)                                            # valid, but no handle
+    assert rc == L.CHI0_EINVAL and "handle" in msg
+    # an empty block needs no pointers
+    p2, keep2 = _problem(nocc=0, z=None)
+    rc, msg = _acc(p2)
+    assert "handle" in msg
+
+
+def test_validation_overlapping_outputs():
+    lib = pkg.load()
+    b = (L.chi0_block * 1)()
+    p = (L.chi0_problem * 2)()
+    for i in range(2):
+        p[i].npb, p[i].nblocks, p[i].blocks = 4, 0, ctypes.cast(b, ctypes.POINTER(L.chi0_block))
+        p[i].nomega, p[i].omega = 1, FAKE
+    p[0].chi0 = FAKE
+    p[1].chi0 = FAKE + 16 * 8
+    rc = lib.chi0_accumulate(None, p, 2, 0, 0, 0.0, 0, None)
+    assert rc == L.CHI0_EINVAL and "overlap" in lib.chi0_last_error().decode()
+
+
+def test_dielectric_validation():
+    lib = pkg.load()
+    f = lib.dielectric_invert
+    assert f(None, 0, 1, FAKE, FAKE, None, FAKE * 2, None, 0, None) == L.CHI0_EINVAL
+    assert f(None, 4, 0, FAKE, FAKE, None, FAKE * 2, None, 0, None) == L.CHI0_EINVAL
+    assert f(None, 4, 1, None, FAKE, None, FAKE * 2, None, 0, None) == L.CHI0_EINVAL
+    assert f(None, 4, 1, FAKE, FAKE, None, FAKE * 2, None, 8, None) == L.CHI0_EINVAL  # wc NULL
+    assert f(None, 4, 1, FAKE, FAKE, None, FAKE + 16, None, 0, None) == L.CHI0_EINVAL  # alias
+    assert f(None, 4, 1, FAKE, FAKE, None, FAKE * 2, None, 1, None) == L.CHI0_EINVAL  # flag
+    rc = f(None, 4, 1, FAKE, FAKE, None, FAKE * 2, None, 0, None)
+    assert rc == L.CHI0_EINVAL and "handle" in lib.chi0_last_error().decode()
+
+
+def test_null_handle_calls():
+    lib = pkg.load()
+    assert lib.chi0_destroy(None) == 0
+    assert lib.chi0_sync(None) == L.CHI0_EINVAL
+    assert lib.chi0_set_tile(None, 0, 0) == L.CHI0_EINVAL
+    assert lib.chi0_profile_enable(None, 1) == L.CHI0_EINVAL
+    assert lib.chi0_create(None, 0) == L.CHI0_EINVAL
