@@ -1,0 +1,238 @@
+"""Benchmark: one q-point of chi0(q, i omega) (all frequencies) plus the FP64
+dielectric inverse, on one MI355X.
+
+A step = chi0_accumulate (every frequency of the q-point) + dielectric_invert,
+on synthetic inputs already resident in HBM.  Prints one JSON line.
+
+Default workload: npb = 2048, nk = 16, nocc = 200, nunocc = 1200, 12
+Gauss-Legendre imaginary frequencies, complex64 Z (62.9 GB), BF16x3 split
+path; the FP64 path is timed once on the same workload (complex128 Z) for the
+FP64-vs-split comparison.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+MFMA_DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}
+SPLIT_FACTOR = {"fp64": 1, "fp32": 1, "bf16x3": 3}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def zherk_flops(npb, npairs, nomega):
+    """Algorithmic flops of chi0 for one q-point: a Hermitian rank-K update
+    per frequency, 8 real flops per complex multiply-add on the lower
+    triangle including the diagonal."""
+    return 4.0 * npairs * npb * (npb + 1) * nomega
+
+
+def inverse_flops(npb, nomega):
+    """Complex LU + inverse (Gauss-Jordan) flops: 8 n^3 real per matrix."""
+    return 8.0 * npb ** 3 * nomega
+
+
+def executed_mfma_flops(npb, npairs, nomega, tile, prec):
+    """Matrix-core flops actually issued: full T x T lower-triangle tiles (the
+    diagonal tiles are computed whole), 8 real flops per complex MAC, times
+    the number of split products."""
+    nt = -(-npb // tile)
+    return 8.0 * npairs * (nt * (nt + 1) // 2) * tile * tile * nomega * SPLIT_FACTOR[prec]
+
+
+def cpu_baseline(wl, target_s=15.0):
+    """Time the oracle on a bounded sample of the workload (first occupied
+    states of the first block, all product-basis functions, all frequencies)
+    and return its throughput in the metric's unit."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle
+
+    blk = wl.blocks(0)[0]
+    eo, eu = wl.energies(blk)
+
+    def run(nocc_s):
+        sub = blk.__class__(q=blk.q, spin=blk.spin, k=blk.k, nocc=nocc_s, nunocc=blk.nunocc,
+                            wk=blk.wk, bid=blk.bid)
+        z = wl.z_block(sub)            # the first nocc_s occupied rows of the block
+        t0 = time.perf_counter()
+        oracle.chi0_ref([(z, eo[:nocc_s], eu, blk.wk)], wl.npb, wl.omega, wl.delta_min)
+        return time.perf_counter() - t0
+
+    t1 = run(1)                        # probe, then one timed run of ~target_s
+    nocc_s = int(min(blk.nocc, max(1, round(target_s / max(t1, 1e-4)))))
+    t_meas = run(nocc_s) if nocc_s > 1 else t1
+    flops = zherk_flops(wl.npb, nocc_s * blk.nunocc, wl.nomega)
+    threads = 0
+    for info in threadpool_info():
+        if info.get("user_api") == "blas":
+            threads = max(threads, int(info.get("num_threads", 0)))
+    return {"value": flops / t_meas / 1e12, "unit": "TFLOP/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{nocc_s} occupied x {blk.nunocc} unoccupied states of one k-block, "
+                      f"npb={wl.npb}, all {wl.nomega} frequencies (FP64 chi0 only, "
+                      f"{t_meas:.1f} s)",
+            "seconds": t_meas}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=2, help="synthetic workload index (0-4)")
+    ap.add_argument("--precision", default=None, help="fp64 | fp32 | bf16x3 (default: the "
+                    "workload's split path)")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay chi0 from a hipGraph")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2506_03477_amd import Block, Context, Problem
+    from synth import workload
+    from synth.gpu import device_workload
+
+    wl = workload(args.workload)
+    prec = args.precision or wl.paths[0]
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = Context(0)
+    if ctx.tile_count(prec) <= 0:
+        raise SystemExit(f"precision {prec} has no kernel in this build")
+    ztype = "c128" if prec == "fp64" else "c64"
+
+    log(f"generating {wl.name} inputs ({ztype}) on the GPU")
+    t0 = time.time()
+    blks, omega, vsqrt = device_workload(wl, 0, dev, ztype=ztype)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f} s")
+    npairs = sum(b[4].npairs for b in blks)
+    chi = torch.empty((wl.nomega, wl.npb, wl.npb), dtype=torch.complex128, device=dev)
+    inv = torch.empty_like(chi)
+    prob = Problem([Block(z, eo, eu, wk) for z, eo, eu, wk, _ in blks], omega, chi)
+
+    def step():
+        ctx.chi0_accumulate([prob], precision=prec, delta_min=wl.delta_min, graph=args.graph)
+        ctx.dielectric_invert(vsqrt, chi, inv)
+
+    for i in range(args.warmup):
+        step()
+        ctx.sync()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ctx.profile_enable(not args.graph)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    chi_ms = 0.0
+    for i in range(args.steps):
+        e_a = torch.cuda.Event(enable_timing=True)
+        e_b = torch.cuda.Event(enable_timing=True)
+        e_a.record(stream)
+        ctx.chi0_accumulate([prob], precision=prec, delta_min=wl.delta_min, graph=args.graph)
+        e_b.record(stream)
+        ctx.dielectric_invert(vsqrt, chi, inv)
+        e_b.synchronize()
+        chi_ms += e_a.elapsed_time(e_b)
+        log(f"step {i + 1}/{args.steps}")
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ctx.sync()
+    total_ms = ev[0].elapsed_time(ev[1])
+    kern_ms, nlaunch = ctx.profile_read()
+    ms_per_step = total_ms / args.steps
+    tile = ctx.tile_info(prec, ctx.get_tile(prec))["tile_p"]
+
+    flops = zherk_flops(wl.npb, npairs, wl.nomega)
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    kern_avg_ms = kern_ms / nlaunch if nlaunch else None
+    roof = None
+    if kern_avg_ms:
+        ach = flops / (kern_avg_ms * 1e-3) / 1e12
+        exe = executed_mfma_flops(wl.npb, npairs, wl.nomega, tile, prec) / (kern_avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4), "traffic": None,
+                "kernel": f"herk_{prec}", "kernel_ms": round(kern_avg_ms, 3),
+                "executed_mfma_tflops": round(exe, 3),
+                "executed_mfma_frac": round(exe / PEAK_TFLOPS[prec], 4)}
+
+    extra = {"ms_per_q_chi0": round(chi_ms / args.steps, 3),
+             "ms_per_q_chi0_plus_inverse": round(ms_per_step, 3),
+             "tile": tile, "npairs": npairs}
+    if wl.paths and "fp64" in wl.paths and prec != "fp64" and not args.no_fp64_compare:
+        log("FP64 comparison: generating complex128 inputs")
+        del prob, blks
+        torch.cuda.empty_cache()
+        blks64, _, _ = device_workload(wl, 0, dev, ztype="c128")
+        prob64 = Problem([Block(z, eo, eu, wk) for z, eo, eu, wk, _ in blks64], omega, chi)
+        ctx.profile_enable(False)
+        ctx.chi0_accumulate([prob64], precision="fp64", delta_min=wl.delta_min)
+        ctx.sync()
+        log("FP64 comparison: plan built; timing one q-point")
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.chi0_accumulate([prob64], precision="fp64", delta_min=wl.delta_min)
+        b.record(stream)
+        b.synchronize()
+        fp64_ms = a.elapsed_time(b)
+        extra["fp64_ms_per_q_chi0"] = round(fp64_ms, 3)
+        extra["fp64_tflops"] = round(flops / (fp64_ms * 1e-3) / 1e12, 3)
+        extra["split_speedup_vs_fp64"] = round(fp64_ms / (chi_ms / args.steps), 3)
+        del prob64, blks64
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(wl)
+        log(f"oracle sample took {cpu.pop('seconds'):.1f} s")
+
+    out = {
+        "metric": "chi0 TFLOP/s and ms per q-point (all omega), FP64 vs split-precision at "
+                  "<=1e-6 rel err",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": MFMA_DTYPE[prec] if prec != "bf16x3" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "npb": wl.npb, "nk": wl.nk, "nspin": wl.nspin,
+                   "nocc": wl.nocc, "nunocc": wl.nunocc, "nomega": wl.nomega,
+                   "ztype": ztype, "path": prec,
+                   "step": "chi0 (all omega) + FP64 Gauss-Jordan inverse of eps"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

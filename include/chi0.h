@@ -174,6 +174,15 @@ int chi0_tile_info(chi0_precision prec, int32_t tile, int32_t* tile_p,
 int chi0_set_tile(chi0_handle h, chi0_precision prec, int32_t tile);
 int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile);
 
+/* FP32 run length of the reduced-precision paths: the number of pairs summed
+ * in FP32 before the partial sum is added into FP64.  By default it is
+ * 4 sqrt(K) pairs for a problem with K pairs (at least 64, at most the tile
+ * configuration's run length), which keeps the FP32 rounding of the chi0 sum
+ * near 1.4 units of FP32 roundoff, relative, for any K.  A value set here (a
+ * multiple of 16 in [16, 65536]) replaces that choice for every problem; 0
+ * restores it. */
+int chi0_set_flush(chi0_handle h, int32_t pairs);
+
 /* Autotuner: time every tile configuration of `prec` on the given problems
  * (their chi0 outputs are overwritten), keep the fastest as the handle's
  * default for `prec`, and return its index in *best (may be NULL).  Timings

@@ -75,6 +75,7 @@ def load() -> ctypes.CDLL:
         "chi0_tile_info": (c_int, [c_int, c_int32, POINTER(c_int32), POINTER(c_int32),
                                    POINTER(c_int32), POINTER(c_int32)]),
         "chi0_set_tile": (c_int, [vp, c_int, c_int32]),
+        "chi0_set_flush": (c_int, [vp, c_int32]),
         "chi0_get_tile": (c_int, [vp, c_int, POINTER(c_int32)]),
         "chi0_autotune": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
                                   c_int32, POINTER(c_int32), POINTER(c_double), vp]),
@@ -232,6 +233,9 @@ class Context:
 
     def set_tile(self, precision: str, tile: int) -> None:
         _check(self._lib.chi0_set_tile(self._h, PREC[precision], tile))
+
+    def set_flush(self, pairs: int) -> None:
+        _check(self._lib.chi0_set_flush(self._h, int(pairs)))
 
     def get_tile(self, precision: str) -> int:
         t = c_int32()

@@ -110,6 +110,7 @@ struct chi0_ctx {
   std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
   int tile_sel[3] = {-1, -1, -1};
   int tile_tuned[3] = {-1, -1, -1};
+  int flush_override = 0;
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
   std::vector<hipEvent_t> event_pool;
@@ -398,6 +399,20 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
   return CHI0_OK;
 }
 
+// FP32 run length for a problem.  A run of L pairs sums about 3 L / 8 MFMA
+// results per output in FP32; with R = K / L runs combined in FP64 the
+// relative rounding error of a positive sum is about u L / sqrt(8 K), so
+// L = 4 sqrt(K) keeps it near 1.4 u for every problem size (capped by the
+// tile configuration's run length, floored at 64 pairs).
+int32_t flush_length(const chi0_ctx* h, const TileConfig& tc, const chi0_problem& pr) {
+  if (h->flush_override > 0) return h->flush_override;
+  if (tc.flush <= 0) return 0;
+  double K = 0.0;
+  for (int b = 0; b < pr.nblocks; ++b) K += static_cast<double>(pr.blocks[b].nocc) * pr.blocks[b].nunocc;
+  int32_t L = static_cast<int32_t>(4.0 * std::sqrt(K)) / 16 * 16;
+  return std::max<int32_t>(64, std::min<int32_t>(tc.flush, L));
+}
+
 int staging_reserve(chi0_ctx* h, size_t bytes) {
   if (h->staging_pending) {
     HIP_TRY(hipEventSynchronize(h->staging_done));
@@ -449,6 +464,8 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
     ptab[p].omega = probs[p].omega;
     ptab[p].npb = probs[p].npb;
     ptab[p].nomega = probs[p].nomega;
+    ptab[p].flush = flush_length(h, pl->tc, probs[p]);
+    ptab[p].pad = 0;
     for (int b = 0; b < probs[p].nblocks; ++b) {
       const chi0_block& bl = probs[p].blocks[b];
       BlockDesc d;
@@ -481,7 +498,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   ha.partials = static_cast<double2*>(h->partials.p);
   ha.delta_min = delta_min;
   ha.flags = static_cast<int32_t>(flags);
-  ha.flush_len = pl->tc.flush;
+  ha.pad = 0;
   ReduceArgs ra;
   ra.jobs = static_cast<const TileJob*>(pl->d_jobs.p);
   ra.probs = ha.probs;
@@ -721,6 +738,14 @@ int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile) {
   const int k = kind_of(prec);
   if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
   *tile = h->tile_sel[k] >= 0 ? h->tile_sel[k] : h->tile_tuned[k] >= 0 ? h->tile_tuned[k] : 0;
+  return CHI0_OK;
+}
+
+int chi0_set_flush(chi0_handle h, int32_t pairs) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (pairs != 0 && (pairs < 16 || pairs > 65536 || pairs % 16 != 0))
+    return fail(CHI0_EINVAL, "flush length %d must be 0 or a multiple of 16 in [16, 65536]", pairs);
+  h->flush_override = pairs;
   return CHI0_OK;
 }
 

@@ -22,6 +22,8 @@ struct ProbDesc {
   const double* omega;      // [nomega]
   int32_t npb;
   int32_t nomega;
+  int32_t flush;            // FP32 run length in pairs (reduced-precision paths)
+  int32_t pad;
 };
 
 // A unit of rank-K work: a contiguous range of pairs (from pair p0 of block
@@ -63,7 +65,7 @@ struct HerkArgs {
   double2* partials;          // [nslots][T][T] complex128
   double delta_min;
   int32_t flags;
-  int32_t flush_len;          // pairs per FP32 run (reduced-precision paths)
+  int32_t pad;
 };
 
 struct ReduceArgs {

@@ -1,15 +1,471 @@
-// Reduced-precision rank-K kernels (FP32 and BF16x3).  Not yet available:
-// the tile tables are empty, so the API reports CHI0_EUNSUPPORTED.
+// Reduced-precision weighted Hermitian rank-K update on gfx950 matrix cores:
+// BF16x3 split products and FP32, both with FP32 runs flushed into FP64.
+//
+// Per unit (problem, frequency, lower tile (tp, tq), pair range) the kernels
+// accumulate S[P][Q] = sum_pairs conj(Z[pair][P]) * (c * Z[pair][Q]),
+// c = w_k 2 D / (D^2 + omega^2) (chi0 = -S, Eq.(polfx) at i*omega).
+// The pair weight scales the Q-side operand only, in FP32.
+//
+// BF16x3: every FP32 operand x is split into bf16 hi = rn(x) and
+// lo = rn(x - hi) (x - hi is exact in FP32); the product a * b is taken as
+// hi_a hi_b + hi_a lo_b + lo_a hi_b (optionally + lo_a lo_b) on
+// v_mfma_f32_32x32x16_bf16.  The complex product is stacked along the
+// contraction index: 8 pairs x (re, im) per MFMA,
+//   Re S += [ar, ai] . [br, bi],   Im S += [ar, ai] . [bi, -br],
+// where (bi, -br) is obtained from the packed (br, bi) by a 16-bit rotate and
+// a sign flip.
+//
+// FP32: v_mfma_f32_32x32x2f32 with the (re, im) of one pair as the two
+// contraction slots.
+//
+// Both kernels: 128 x 128 complex tiles, 4 waves of 64 x 64, operands staged
+// once per workgroup into double-buffered, XOR-swizzled LDS (the split / the
+// scaling happens while staging), one barrier per 16-pair stage, next
+// stage's global loads issued before the current stage's MFMAs.  Each
+// workgroup adds its FP32 accumulators into its FP64 partial tile in global
+// memory every `flush` pairs (per problem) and at the end of the unit, so no FP32 sum runs
+// over more than `flush` pairs.
 #include "common.h"
 #include "herk_common.h"
 
 namespace chi0 {
-int herk_fp32_tile_count() { return 0; }
-TileConfig herk_fp32_tile(int) { return TileConfig{0, 0, 0, 0}; }
-hipError_t herk_fp32_launch(int, const HerkArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
-int herk_fp32_max_wg_per_cu(int) { return 1; }
-int herk_bf16x3_tile_count() { return 0; }
-TileConfig herk_bf16x3_tile(int) { return TileConfig{0, 0, 0, 0}; }
-hipError_t herk_bf16x3_launch(int, const HerkArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
-int herk_bf16x3_max_wg_per_cu(int) { return 1; }
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kT = 128;   // tile edge (complex elements)
+constexpr int kKC = 16;   // pairs per stage
+constexpr int kNT = 256;  // threads
+
+// Pair cursor over a unit's range: block b, stage start p0, end of the
+// block's part of the range pend.
+struct Cursor {
+  int b;
+  int p0;
+  int pend;
+};
+
+__device__ __forceinline__ bool cursor_first(const Unit& u, const BlockDesc* blocks, Cursor& c) {
+  for (int b = u.b0; b <= u.b1; ++b) {
+    const int beg = (b == u.b0) ? u.p0 : 0;
+    const int end = (b == u.b1) ? u.p1 : blocks[b].nocc * blocks[b].nunocc;
+    if (beg < end) {
+      c.b = b;
+      c.p0 = beg;
+      c.pend = end;
+      return true;
+    }
+  }
+  return false;
+}
+
+__device__ __forceinline__ bool cursor_next(const Unit& u, const BlockDesc* blocks, Cursor& c) {
+  if (c.p0 + kKC < c.pend) {
+    c.p0 += kKC;
+    return true;
+  }
+  for (int b = c.b + 1; b <= u.b1; ++b) {
+    const int end = (b == u.b1) ? u.p1 : blocks[b].nocc * blocks[b].nunocc;
+    if (0 < end) {
+      c.b = b;
+      c.p0 = 0;
+      c.pend = end;
+      return true;
+    }
+  }
+  return false;
+}
+
+// LDS row = tile column (0..127), 16 dwords = 4 chunks of 4 pairs; chunk q of
+// row r lives at chunk q ^ ((r >> 2) & 3) (conflict-free 16-byte accesses).
+__device__ __forceinline__ int swz(int row, int q) {
+  return row * 16 + 4 * (q ^ ((row >> 2) & 3));
+}
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  bf16x2 v;
+  v[0] = static_cast<__bf16>(lo);
+  v[1] = static_cast<__bf16>(hi);
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ float bf16_lo_to_f32(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float bf16_hi_to_f32(uint32_t p) { return __uint_as_float(p & 0xFFFF0000u); }
+
+// (x_re, x_im) -> packed hi and lo bf16x2 words (re in the low half).
+__device__ __forceinline__ void split2(float re, float im, uint32_t& hi, uint32_t& lo) {
+  hi = pack_bf16x2(re, im);
+  lo = pack_bf16x2(re - bf16_lo_to_f32(hi), im - bf16_hi_to_f32(hi));
+}
+
+// (br, bi) packed -> (bi, -br) packed.
+__device__ __forceinline__ uint32_t rot_neg(uint32_t x) {
+  return __builtin_amdgcn_alignbit(x, x, 16) ^ 0x80000000u;
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ uint4 rot_neg4(uint4 v) {
+  return uint4{rot_neg(v.x), rot_neg(v.y), rot_neg(v.z), rot_neg(v.w)};
+}
+
+// Add (or store, when first) the 64 x 64 wave tile of FP32 accumulators into
+// the FP64 partial tile.  32x32 MFMA result layout: lane holds column
+// (lane % 32) of rows 8 (r / 4) + 4 (lane / 32) + (r % 4).
+__device__ __forceinline__ void flush_tile(double2* __restrict__ part, const f32x16 (&cr)[2][2],
+                                           const f32x16 (&ci)[2][2], int wr, int wc, int lane,
+                                           bool first) {
+  const int g = lane >> 5;
+  const int cl = lane & 31;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr * 64 + i * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+        const int col = wc * 64 + j * 32 + cl;
+        double2* p = part + row * kT + col;
+        double2 v = double2{static_cast<double>(cr[i][j][r]), static_cast<double>(ci[i][j][r])};
+        if (!first) {
+          const double2 o = *p;
+          v.x += o.x;
+          v.y += o.y;
+        }
+        *p = v;
+      }
+}
+
+template <bool LOLO>
+__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
+  __shared__ __attribute__((aligned(16))) uint32_t sAh[2][kT * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sAl[2][kT * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sBh[2][kT * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sBl[2][kT * 16];
+  __shared__ float sWgt[2][kKC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g8 = lane >> 5;
+  const int l32 = lane & 31;
+  // loader mapping: column c of the tile, pair groups gA and gA + 2
+  const int lc = tid & (kT - 1);
+  const int lg = tid >> 7;
+
+  const int beg = a.wg_offsets[blockIdx.x];
+  const int end = a.wg_offsets[blockIdx.x + 1];
+  for (int ui = beg; ui < end; ++ui) {
+    const Unit u = a.units[a.wg_units[ui]];
+    const ProbDesc pd = a.probs[u.prob];
+    const int npb = pd.npb;
+    const double om = pd.omega[u.iw];
+    const double w2 = om * om;
+    const int flush_stages = pd.flush > kKC ? pd.flush / kKC : 1;
+    const bool okP = u.tp * kT + lc < npb;
+    const bool okQ = u.tq * kT + lc < npb;
+    double2* part = a.partials + static_cast<size_t>(u.slot) * kT * kT;
+
+    f32x16 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = f32x16{0};
+        ci[i][j] = f32x16{0};
+      }
+    bool first_flush = true;
+    int since_flush = 0;
+
+    // raw operands of the stage being loaded: [group][pair in group]
+    float2 ra[2][4], rb[2][4];
+    Cursor cur;
+    bool have = cursor_first(u, a.blocks, cur);
+    __syncthreads();  // previous unit's last MFMAs are done with the LDS
+    auto load_stage = [&](const Cursor& c, int buf) {
+      const BlockDesc bd = a.blocks[c.b];
+      if (tid < kKC) sWgt[buf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
+      const float2* z = static_cast<const float2*>(bd.z);
+#pragma unroll
+      for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int p = c.p0 + 4 * (lg + 2 * gi) + e;
+          float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
+          if (p < c.pend) {
+            const float2* row = z + static_cast<size_t>(p) * npb;
+            if (okP) va = row[u.tp * kT + lc];
+            if (okQ) vb = row[u.tq * kT + lc];
+          }
+          ra[gi][e] = va;
+          rb[gi][e] = vb;
+        }
+    };
+    int buf = 0;
+    if (have) load_stage(cur, 0);
+    __syncthreads();  // weights of stage 0 visible
+    while (have) {
+      // stage the raw operands of this stage into LDS buffer `buf`
+#pragma unroll
+      for (int gi = 0; gi < 2; ++gi) {
+        const int q = lg + 2 * gi;
+        uint32_t ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          split2(ra[gi][e].x, ra[gi][e].y, ah[e], al[e]);
+          const float w = sWgt[buf][4 * q + e];
+          split2(rb[gi][e].x * w, rb[gi][e].y * w, bh[e], bl[e]);
+        }
+        const int o = swz(lc, q);
+        *reinterpret_cast<uint4*>(&sAh[buf][o]) = uint4{ah[0], ah[1], ah[2], ah[3]};
+        *reinterpret_cast<uint4*>(&sAl[buf][o]) = uint4{al[0], al[1], al[2], al[3]};
+        *reinterpret_cast<uint4*>(&sBh[buf][o]) = uint4{bh[0], bh[1], bh[2], bh[3]};
+        *reinterpret_cast<uint4*>(&sBl[buf][o]) = uint4{bl[0], bl[1], bl[2], bl[3]};
+      }
+      // next stage's loads (and weights) in flight during this stage's MFMAs
+      Cursor nxt = cur;
+      const bool more = cursor_next(u, a.blocks, nxt);
+      if (more) load_stage(nxt, buf ^ 1);
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const int q = 2 * ks + g8;
+        uint4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int row = wr * 64 + i * 32 + l32;
+          ah[i] = *reinterpret_cast<const uint4*>(&sAh[buf][swz(row, q)]);
+          al[i] = *reinterpret_cast<const uint4*>(&sAl[buf][swz(row, q)]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int row = wc * 64 + j * 32 + l32;
+          bh[j] = *reinterpret_cast<const uint4*>(&sBh[buf][swz(row, q)]);
+          bl[j] = *reinterpret_cast<const uint4*>(&sBl[buf][swz(row, q)]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const bf16x8 brh = as_bf16x8(bh[j]);
+          const bf16x8 brl = as_bf16x8(bl[j]);
+          const bf16x8 bih = as_bf16x8(rot_neg4(bh[j]));
+          const bf16x8 bil = as_bf16x8(rot_neg4(bl[j]));
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const bf16x8 aah = as_bf16x8(ah[i]);
+            const bf16x8 aal = as_bf16x8(al[i]);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, brh, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, bih, ci[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, brl, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, bil, ci[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, brh, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, bih, ci[i][j], 0, 0, 0);
+            if (LOLO) {
+              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, brl, cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, bil, ci[i][j], 0, 0, 0);
+            }
+          }
+        }
+      }
+      if (++since_flush >= flush_stages && more) {
+        flush_tile(part, cr, ci, wr, wc, lane, first_flush);
+        first_flush = false;
+        since_flush = 0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            cr[i][j] = f32x16{0};
+            ci[i][j] = f32x16{0};
+          }
+      }
+      cur = nxt;
+      have = more;
+      buf ^= 1;
+    }
+    flush_tile(part, cr, ci, wr, wc, lane, first_flush);
+  }
+}
+
+// FP32 path: v_mfma_f32_32x32x2f32, contraction slots (re, im) of one pair.
+// LDS holds the operands as complex64, rows = tile columns, 16 pairs per row
+// (8 chunks of 2 pairs, XOR-swizzled).
+__device__ __forceinline__ int swz32(int row, int q) {  // q: chunk of 2 pairs (16 B)
+  return row * 32 + 4 * (q ^ ((row >> 1) & 7));
+}
+
+__global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
+  __shared__ __attribute__((aligned(16))) float sA[2][kT * 32];
+  __shared__ __attribute__((aligned(16))) float sB[2][kT * 32];
+  __shared__ float sWgt[2][kKC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g = lane >> 5;  // contraction slot: 0 = re, 1 = im
+  const int l32 = lane & 31;
+  const int lc = tid & (kT - 1);
+  const int lg = tid >> 7;
+
+  const int beg = a.wg_offsets[blockIdx.x];
+  const int end = a.wg_offsets[blockIdx.x + 1];
+  for (int ui = beg; ui < end; ++ui) {
+    const Unit u = a.units[a.wg_units[ui]];
+    const ProbDesc pd = a.probs[u.prob];
+    const int npb = pd.npb;
+    const double om = pd.omega[u.iw];
+    const double w2 = om * om;
+    const int flush_stages = pd.flush > kKC ? pd.flush / kKC : 1;
+    const bool okP = u.tp * kT + lc < npb;
+    const bool okQ = u.tq * kT + lc < npb;
+    double2* part = a.partials + static_cast<size_t>(u.slot) * kT * kT;
+
+    f32x16 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = f32x16{0};
+        ci[i][j] = f32x16{0};
+      }
+    bool first_flush = true;
+    int since_flush = 0;
+    float2 ra[8], rb[8];  // pairs 8 lg .. 8 lg + 7 of the stage, column lc
+    Cursor cur;
+    bool have = cursor_first(u, a.blocks, cur);
+    __syncthreads();
+    auto load_stage = [&](const Cursor& c, int buf) {
+      const BlockDesc bd = a.blocks[c.b];
+      if (tid < kKC) sWgt[buf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
+      const float2* z = static_cast<const float2*>(bd.z);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int p = c.p0 + 8 * lg + e;
+        float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
+        if (p < c.pend) {
+          const float2* row = z + static_cast<size_t>(p) * npb;
+          if (okP) va = row[u.tp * kT + lc];
+          if (okQ) vb = row[u.tq * kT + lc];
+        }
+        ra[e] = va;
+        rb[e] = vb;
+      }
+    };
+    int buf = 0;
+    if (have) load_stage(cur, 0);
+    __syncthreads();
+    while (have) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int q = 4 * lg + h;  // chunk of pairs 2q, 2q + 1
+        const float w0 = sWgt[buf][2 * q];
+        const float w1 = sWgt[buf][2 * q + 1];
+        const int o = swz32(lc, q);
+        *reinterpret_cast<float4*>(&sA[buf][o]) =
+            float4{ra[2 * h].x, ra[2 * h].y, ra[2 * h + 1].x, ra[2 * h + 1].y};
+        *reinterpret_cast<float4*>(&sB[buf][o]) =
+            float4{rb[2 * h].x * w0, rb[2 * h].y * w0, rb[2 * h + 1].x * w1, rb[2 * h + 1].y * w1};
+      }
+      Cursor nxt = cur;
+      const bool more = cursor_next(u, a.blocks, nxt);
+      if (more) load_stage(nxt, buf ^ 1);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {  // two pairs per chunk
+        float4 av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          av[i] = *reinterpret_cast<const float4*>(&sA[buf][swz32(wr * 64 + i * 32 + l32, q)]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          bv[j] = *reinterpret_cast<const float4*>(&sB[buf][swz32(wc * 64 + j * 32 + l32, q)]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          float a0[2], b0r[2], b0i[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const float re = h ? av[i].z : av[i].x;
+            const float im = h ? av[i].w : av[i].y;
+            a0[i] = g ? im : re;
+          }
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const float re = h ? bv[j].z : bv[j].x;
+            const float im = h ? bv[j].w : bv[j].y;
+            b0r[j] = g ? im : re;
+            b0i[j] = g ? -re : im;
+          }
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0r[j], cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0i[j], ci[i][j], 0, 0, 0);
+            }
+        }
+      }
+      if (++since_flush >= flush_stages && more) {
+        flush_tile(part, cr, ci, wr, wc, lane, first_flush);
+        first_flush = false;
+        since_flush = 0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            cr[i][j] = f32x16{0};
+            ci[i][j] = f32x16{0};
+          }
+      }
+      cur = nxt;
+      have = more;
+      buf ^= 1;
+    }
+    flush_tile(part, cr, ci, wr, wc, lane, first_flush);
+  }
+}
+
+}  // namespace
+
+// Tile tables: {tile, pairs per stage, FP32 run length (pairs), threads}.
+static const TileConfig kBf16Tiles[] = {
+    {kT, kKC, 4096, kNT},
+    {kT, kKC, 4096, kNT},   // same tiles, lo*lo product added (CHI0_BF16_LOLO)
+};
+static const TileConfig kFp32Tiles[] = {
+    {kT, kKC, 4096, kNT},
+};
+
+int herk_bf16x3_tile_count() { return 1; }
+TileConfig herk_bf16x3_tile(int idx) { return kBf16Tiles[idx]; }
+hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
+  if (idx != 0) return hipErrorInvalidValue;
+  if (a.flags & 2)
+    hipLaunchKernelGGL(herk_bf16x3_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL(herk_bf16x3_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+int herk_bf16x3_max_wg_per_cu(int idx) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<false>, kNT, 0) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+int herk_fp32_tile_count() { return 1; }
+TileConfig herk_fp32_tile(int idx) { return kFp32Tiles[idx]; }
+hipError_t herk_fp32_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
+  if (idx != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(herk_fp32_kernel, dim3(nwg), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+int herk_fp32_max_wg_per_cu(int idx) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp32_kernel, kNT, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
 }  // namespace chi0

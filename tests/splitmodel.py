@@ -1,0 +1,55 @@
+"""Numpy model of the reduced-precision contractions, used to tell kernel
+mistakes apart from the rounding the precision choice itself implies.
+
+The model rounds exactly where the GPU paths round (FP32 weight, FP32 scaled
+operand, bf16 round-to-nearest-even hi / lo split) and then sums the products
+in FP64, so it differs from the GPU only by the FP32 accumulation of runs.
+Test infrastructure; not the oracle.
+"""
+import numpy as np
+
+import oracle
+
+
+def bf16_rne(x32):
+    """Round float32 values to bfloat16 (nearest, ties to even), as float32."""
+    b = np.asarray(x32, np.float32).view(np.uint32).astype(np.uint64)
+    r = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return r.astype(np.uint32).view(np.float32)
+
+
+def split(x32):
+    hi = bf16_rne(x32)
+    lo = bf16_rne((x32 - hi).astype(np.float32))
+    return hi.astype(np.float64), lo.astype(np.float64)
+
+
+def chi0_model(blocks, npb, omega, delta_min, path="bf16x3", lolo=False):
+    """blocks: (Z complex64 [nocc, nunocc, npb], eps_occ, eps_unocc, wk)."""
+    out = np.zeros((len(omega), npb, npb), np.complex128)
+    for z, eo, eu, wk in blocks:
+        nocc, nunocc, _ = z.shape
+        a = np.asarray(z, np.complex64).reshape(nocc * nunocc, npb)
+        d = oracle.pair_delta(eo, eu).reshape(-1)
+        keep = oracle.pair_included(d, delta_min)
+        for iw, w in enumerate(omega):
+            c = np.where(keep, -oracle.transition_weight(np.where(keep, d, 1.0), float(w), wk), 0.0)
+            c32 = c.astype(np.float32)[:, None]
+            br = (a.real.astype(np.float32) * c32).astype(np.float32)
+            bi = (a.imag.astype(np.float32) * c32).astype(np.float32)
+            ar = a.real.astype(np.float32)
+            ai = a.imag.astype(np.float32)
+            if path == "fp32":
+                ar64, ai64, br64, bi64 = (x.astype(np.float64) for x in (ar, ai, br, bi))
+                sr = ar64.T @ br64 + ai64.T @ bi64
+                si = ar64.T @ bi64 - ai64.T @ br64
+            else:
+                (arh, arl), (aih, ail) = split(ar), split(ai)
+                (brh, brl), (bih, bil) = split(br), split(bi)
+                terms = [(arh, aih, brh, bih), (arh, aih, brl, bil), (arl, ail, brh, bih)]
+                if lolo:
+                    terms.append((arl, ail, brl, bil))
+                sr = sum(x.T @ y + u.T @ v for x, u, y, v in terms)
+                si = sum(x.T @ v - u.T @ y for x, u, y, v in terms)
+            out[iw] -= sr + 1j * si
+    return out

@@ -1,0 +1,126 @@
+"""GPU parity of the reduced-precision paths (FP32 and BF16x3 split products,
+FP32 runs flushed into FP64) against the FP64 oracle at 1e-6 relative
+Frobenius error per frequency, and against a numpy model of the split
+arithmetic (which isolates kernel mistakes from the split's own error)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import (assert_hermitian_exact, device_problem, need_gpu, oracle_chi0,
+                        rel_fro)
+from paper_2506_03477_amd import Context, Problem
+from splitmodel import chi0_model
+from synth import workload
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _model(wl, path, lolo=False):
+    blocks = []
+    for blk in wl.blocks(0):
+        eo, eu = wl.energies(blk)
+        blocks.append((wl.z_block(blk), eo, eu, blk.wk))
+    return chi0_model(blocks, wl.npb, wl.omega, wl.delta_min, path, lolo)
+
+
+# The BF16x3 split represents each operand to 16 significant bits, so its
+# error relative to the oracle is about 4e-6 sqrt(npb / K) (K = number of
+# pairs): the cases keep K / npb >= 200, as in the workloads themselves
+# (K / npb = 1500 for npb = 2048).  FP32 has no such floor.
+CASES = {
+    "bf16x3": [
+        (0, dict(ztype="c64", nk=64)),                            # configs[0] shape, 64 k-points
+        (1, dict(npb=200, nk=4, ztype="c64")),                    # ragged npb, several tiles
+        (2, dict(npb=160, nk=2, nocc=40, nunocc=500)),            # configs[2] generator
+        (3, dict(nq=1, npb=130, nk=16)),                          # uneven blocks
+        (4, dict(npb=96, nk=4)),                                  # spins, intraband cut
+    ],
+    "fp32": [
+        (0, dict(ztype="c64")),
+        (1, dict(npb=200, nk=3, nocc=7, nunocc=45, ztype="c64")),
+        (2, dict(npb=300, nk=2, nocc=9, nunocc=120)),
+        (3, dict(nq=1, npb=130, nk=6)),
+        (4, dict(npb=96, nk=3)),
+    ],
+}
+
+
+@pytest.mark.parametrize("path,cfg,over", [(p, c, o) for p in CASES for c, o in CASES[p]])
+def test_lowp_parity(ctx, path, cfg, over):
+    wl = workload(cfg, **over)
+    _say(f"{path} parity {wl.name} {over}")
+    prob, _, _ = device_problem(wl)
+    ctx.chi0_accumulate([prob], precision=path, delta_min=wl.delta_min)
+    ctx.sync()
+    got = prob.chi0.cpu().numpy()
+    ref = oracle_chi0(wl)
+    err = rel_fro(got, ref)
+    mod = _model(wl, path)
+    err_model = rel_fro(got, mod)
+    _say(f"  vs oracle {err.max():.3e}  vs split model {err_model.max():.3e}  "
+         f"model vs oracle {rel_fro(mod, ref).max():.3e}")
+    assert np.all(err <= TOL), err
+    assert np.all(err_model <= 3e-7), err_model
+    assert_hermitian_exact(prob.chi0)
+
+
+def test_bf16_lolo_and_flush_lengths(ctx):
+    wl = workload(2, npb=160, nk=2, nocc=40, nunocc=500)
+    _say("bf16x3 lolo / flush lengths")
+    ref = oracle_chi0(wl)
+    prob, _, _ = device_problem(wl)
+    ctx.chi0_accumulate([prob], precision="bf16x3", lolo=True)
+    ctx.sync()
+    e_lolo = rel_fro(prob.chi0.cpu().numpy(), ref)
+    assert np.all(e_lolo <= TOL)
+    assert np.all(rel_fro(prob.chi0.cpu().numpy(), _model(wl, "bf16x3", lolo=True)) <= 3e-7)
+    outs = []
+    for fl in (16, 256, 0):
+        ctx.set_flush(fl)
+        ctx.chi0_accumulate([prob], precision="bf16x3")
+        ctx.sync()
+        outs.append(prob.chi0.clone())
+        e = rel_fro(prob.chi0.cpu().numpy(), ref)
+        _say(f"  flush {fl}: {e.max():.3e} (lolo {e_lolo.max():.3e})")
+        assert np.all(e <= TOL)
+    ctx.set_flush(0)
+    assert not torch.equal(outs[0], outs[2])   # the flush length changes the rounding
+
+
+def test_lowp_deterministic_graph_accumulate(ctx):
+    wl = workload(3, nq=1, npb=200, nk=16)
+    _say("bf16x3 determinism / graph / accumulate")
+    prob, _, _ = device_problem(wl)
+    ctx.chi0_accumulate([prob], precision="bf16x3")
+    first = prob.chi0.clone()
+    ctx.chi0_accumulate([prob], precision="bf16x3")
+    torch.cuda.synchronize()
+    assert torch.equal(first, prob.chi0)
+    for rep in range(3):
+        prob.chi0.zero_()
+        ctx.chi0_accumulate([prob], precision="bf16x3", graph=True)
+        torch.cuda.synchronize()
+        _ = torch.randn(4096, device="cuda").sum()
+        assert torch.equal(prob.chi0, first), rep
+    prob.chi0.copy_(first)
+    ctx.chi0_accumulate([prob], precision="bf16x3", accumulate=True)
+    ctx.sync()
+    assert np.all(rel_fro(prob.chi0.cpu().numpy(), 2 * first.cpu().numpy()) <= 1e-15)
+    assert_hermitian_exact(prob.chi0)
