@@ -147,6 +147,207 @@ __global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(
   }
 }
 
+// Register-resident panel for n <= 2048 (R = rows per thread, 1024 threads).
+// The panel's nb columns are processed as sub-panels of 8: a sub-panel lives
+// in registers (thread t owns rows t + 1024 r) through its 8 elimination
+// steps (pivot search by wave shuffles, row interchange and pivot-row
+// broadcast through LDS); it is then stored and its combined transformation
+// is applied to the other columns of the panel as a rank-8 update:
+//   y = (interchanges) x;   x <- y (rows outside the sub-panel) + C y[sub-panel rows].
+template <int R>
+__global__ __launch_bounds__(kPanelThreads) void gj_panel_reg_kernel(
+    double2* __restrict__ work, int n, int k0, int nb, int32_t* __restrict__ piv,
+    int32_t* __restrict__ status) {
+  constexpr int NT = kPanelThreads;
+  constexpr int NW = NT / 64;
+  constexpr int SB = 8;  // sub-panel width
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
+  __shared__ double2 swapP[SB], swapC[SB], rowk[SB];
+  __shared__ double2 wsub[SB][kPanel];
+  const int mat = blockIdx.x;
+  double2* S = work + static_cast<size_t>(mat) * n * n;
+  int32_t* pv = piv + static_cast<size_t>(mat) * n;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+
+  for (int j0 = 0; j0 < nb; j0 += SB) {
+    const int sw = min(SB, nb - j0);     // width of this sub-panel
+    const int c0 = k0 + j0;
+    double2 v[R][SB];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + NT * r;
+#pragma unroll
+      for (int t = 0; t < SB; ++t)
+        v[r][t] = (i < n && t < sw) ? S[static_cast<size_t>(i) * n + c0 + t] : double2{0.0, 0.0};
+    }
+    for (int s = 0; s < sw; ++s) {
+      const int c = c0 + s;
+      // 1. pivot: largest |x|^2 in column c over rows >= c (smallest index on ties)
+      double best = -1.0;
+      int bi = n;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + NT * r;
+        double2 x = double2{0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < SB; ++t)
+          if (t == s) x = v[r][t];
+        const double m2 = x.x * x.x + x.y * x.y;
+        if (i >= c && i < n && m2 > best) {
+          best = m2;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        red_v[wave] = best;
+        red_i[wave] = bi;
+      }
+      __syncthreads();
+      double bv = red_v[0];
+      int p = red_i[0];
+      for (int w = 1; w < NW; ++w)
+        if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < p)) {
+          bv = red_v[w];
+          p = red_i[w];
+        }
+      if (p >= n) p = c;
+      if (tid == 0) {
+        pv[c] = p;
+        if (!(bv > 0.0)) status[0] = 1;
+      }
+      // 2. interchange rows c and p (sub-panel registers)
+      const int oc = c % NT, rc = c / NT;
+      const int op = p % NT, rp = p / NT;
+      if (p != c) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (tid == op && r == rp)
+#pragma unroll
+            for (int t = 0; t < SB; ++t) swapP[t] = v[r][t];
+          if (tid == oc && r == rc)
+#pragma unroll
+            for (int t = 0; t < SB; ++t) swapC[t] = v[r][t];
+        }
+      }
+      __syncthreads();
+      if (p != c) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (tid == oc && r == rc)
+#pragma unroll
+            for (int t = 0; t < SB; ++t) v[r][t] = swapP[t];
+          if (tid == op && r == rp)
+#pragma unroll
+            for (int t = 0; t < SB; ++t) v[r][t] = swapC[t];
+        }
+      }
+      // 3. scale the pivot row (entry s <- 1 first, so it ends up 1/pivot)
+      if (tid == oc) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (r == rc) {
+            double2 pvt = double2{0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < SB; ++t)
+              if (t == s) pvt = v[r][t];
+            const double den = pvt.x * pvt.x + pvt.y * pvt.y;
+            const double2 d = double2{pvt.x / den, -pvt.y / den};
+#pragma unroll
+            for (int t = 0; t < SB; ++t) {
+              const double2 x = (t == s) ? double2{1.0, 0.0} : v[r][t];
+              v[r][t] = cmul(x, d);
+              rowk[t] = v[r][t];
+            }
+          }
+      }
+      __syncthreads();
+      // 4. eliminate column c from every other row (entry s <- 0 first)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + NT * r;
+        if (i == c || i >= n) continue;
+        double2 f = double2{0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < SB; ++t)
+          if (t == s) f = v[r][t];
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+          double2 x = (t == s) ? double2{0.0, 0.0} : v[r][t];
+          const double2 fr = cmul(f, rowk[t]);
+          x.x -= fr.x;
+          x.y -= fr.y;
+          v[r][t] = x;
+        }
+      }
+    }
+    // store the sub-panel
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + NT * r;
+      if (i < n)
+#pragma unroll
+        for (int t = 0; t < SB; ++t)
+          if (t < sw) S[static_cast<size_t>(i) * n + c0 + t] = v[r][t];
+    }
+    // apply the sub-panel to the other panel columns
+    const int nother = nb - sw;
+    if (nother > 0) {
+      if (tid < nother) {  // interchanges, in order, one column per thread
+        const int col = k0 + (tid < j0 ? tid : tid + sw);
+        for (int s = 0; s < sw; ++s) {
+          const int c = c0 + s;
+          const int p = pv[c];
+          if (p != c) {
+            const size_t a0 = static_cast<size_t>(c) * n + col;
+            const size_t a1 = static_cast<size_t>(p) * n + col;
+            const double2 t0 = S[a0];
+            S[a0] = S[a1];
+            S[a1] = t0;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < SB * nother) {
+        const int b = tid / nother;
+        const int o = tid % nother;
+        const int col = k0 + (o < j0 ? o : o + sw);
+        wsub[b][o] = (b < sw) ? S[static_cast<size_t>(c0 + b) * n + col] : double2{0.0, 0.0};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + NT * r;
+        if (i >= n) continue;
+        const bool inb = i >= c0 && i < c0 + sw;
+        for (int o = 0; o < nother; ++o) {
+          const int col = k0 + (o < j0 ? o : o + sw);
+          const size_t ad = static_cast<size_t>(i) * n + col;
+          double2 x = inb ? double2{0.0, 0.0} : S[ad];
+#pragma unroll
+          for (int b = 0; b < SB; ++b) {
+            const double2 fr = cmul(v[r][b], wsub[b][o]);
+            x.x += fr.x;
+            x.y += fr.y;
+          }
+          S[ad] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void gj_swap_extract_kernel(
     double2* __restrict__ work, double2* __restrict__ wrow, int n, int k0, int nb,
     const int32_t* __restrict__ piv) {
@@ -304,8 +505,15 @@ hipError_t dielectric_build_launch(const double2* chi0, const double* vsqrt, dou
 
 hipError_t gj_panel_launch(double2* work, int n, int nomega, int k0, int nb, int32_t* piv,
                            int32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(gj_panel_kernel, dim3(nomega), dim3(kPanelThreads), 0, s, work, n, k0, nb,
-                     piv, status);
+  if (n <= kPanelThreads)
+    hipLaunchKernelGGL(gj_panel_reg_kernel<1>, dim3(nomega), dim3(kPanelThreads), 0, s, work, n,
+                       k0, nb, piv, status);
+  else if (n <= 2 * kPanelThreads)
+    hipLaunchKernelGGL(gj_panel_reg_kernel<2>, dim3(nomega), dim3(kPanelThreads), 0, s, work, n,
+                       k0, nb, piv, status);
+  else
+    hipLaunchKernelGGL(gj_panel_kernel, dim3(nomega), dim3(kPanelThreads), 0, s, work, n, k0, nb,
+                       piv, status);
   return hipGetLastError();
 }
 

@@ -126,10 +126,169 @@ __global__ __launch_bounds__(256) void herk_fp64_kernel(HerkArgs a) {
   }
 }
 
+
+// Pipelined variant: 128 x 128 complex tiles, 4 waves of 64 x 64 (one
+// workgroup per CU, up to 512 registers per lane), 8 pairs per stage in
+// double-buffered LDS, next stage's global loads and weights issued before the
+// current stage's MFMAs, one barrier per stage.
+struct Cursor64 {
+  int b;
+  int p0;
+  int pend;
+};
+
+template <int KC>
+__device__ __forceinline__ bool cur_first(const Unit& u, const BlockDesc* blocks, Cursor64& c) {
+  for (int b = u.b0; b <= u.b1; ++b) {
+    const int beg = (b == u.b0) ? u.p0 : 0;
+    const int end = (b == u.b1) ? u.p1 : blocks[b].nocc * blocks[b].nunocc;
+    if (beg < end) {
+      c.b = b;
+      c.p0 = beg;
+      c.pend = end;
+      return true;
+    }
+  }
+  return false;
+}
+
+template <int KC>
+__device__ __forceinline__ bool cur_next(const Unit& u, const BlockDesc* blocks, Cursor64& c) {
+  if (c.p0 + KC < c.pend) {
+    c.p0 += KC;
+    return true;
+  }
+  for (int b = c.b + 1; b <= u.b1; ++b) {
+    const int end = (b == u.b1) ? u.p1 : blocks[b].nocc * blocks[b].nunocc;
+    if (0 < end) {
+      c.b = b;
+      c.p0 = 0;
+      c.pend = end;
+      return true;
+    }
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
+  constexpr int T = 128, KC = 8, NT = 256;
+  constexpr int NB = 4;  // 16x16 blocks per wave side (64 / 16)
+  __shared__ double2 sA[2][KC][T];
+  __shared__ double2 sB[2][KC][T];
+  __shared__ double sW[2][KC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int m = lane & 15;
+  const int kk = lane >> 4;
+  const int prr = kk >> 1;
+  const bool isim = (kk & 1) != 0;
+  const int lc = tid & (T - 1);   // loader: tile column
+  const int lg = tid >> 7;        // loader: pairs lg, lg + 2, lg + 4, lg + 6
+
+  const int beg = a.wg_offsets[blockIdx.x];
+  const int end = a.wg_offsets[blockIdx.x + 1];
+  for (int ui = beg; ui < end; ++ui) {
+    const Unit u = a.units[a.wg_units[ui]];
+    const ProbDesc pd = a.probs[u.prob];
+    const int npb = pd.npb;
+    const double om = pd.omega[u.iw];
+    const double w2 = om * om;
+    const bool okP = u.tp * T + lc < npb;
+    const bool okQ = u.tq * T + lc < npb;
+
+    f64x4 accR[NB][NB], accI[NB][NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        accR[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        accI[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      }
+    double2 ra[4], rb[4];
+    Cursor64 cur;
+    bool have = cur_first<KC>(u, a.blocks, cur);
+    __syncthreads();
+    auto load_stage = [&](const Cursor64& c, int buf) {
+      const BlockDesc bd = a.blocks[c.b];
+      if (tid < KC) sW[buf][tid] = pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min);
+      const double2* z = static_cast<const double2*>(bd.z);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int p = c.p0 + lg + 2 * e;
+        double2 va = double2{0.0, 0.0}, vb = double2{0.0, 0.0};
+        if (p < c.pend) {
+          const double2* row = z + static_cast<size_t>(p) * npb;
+          if (okP) va = row[u.tp * T + lc];
+          if (okQ) vb = row[u.tq * T + lc];
+        }
+        ra[e] = va;
+        rb[e] = vb;
+      }
+    };
+    int buf = 0;
+    if (have) load_stage(cur, 0);
+    __syncthreads();
+    while (have) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = lg + 2 * e;
+        const double w = sW[buf][r];
+        sA[buf][r][lc] = ra[e];
+        sB[buf][r][lc] = double2{rb[e].x * w, rb[e].y * w};
+      }
+      Cursor64 nxt = cur;
+      const bool more = cur_next<KC>(u, a.blocks, nxt);
+      if (more) load_stage(nxt, buf ^ 1);
+      __syncthreads();
+#pragma unroll
+      for (int st = 0; st < KC / 2; ++st) {
+        const int pair = 2 * st + prr;
+        double av[NB], br[NB], bi[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const double2 x = sA[buf][pair][wr * 64 + i * 16 + m];
+          av[i] = isim ? x.y : x.x;
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const double2 y = sB[buf][pair][wc * 64 + j * 16 + m];
+          br[j] = isim ? y.y : y.x;
+          bi[j] = isim ? -y.x : y.y;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], br[j], accR[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bi[j], accI[i][j], 0, 0, 0);
+          }
+      }
+      cur = nxt;
+      have = more;
+      buf ^= 1;
+    }
+    double2* out = a.partials + static_cast<size_t>(u.slot) * T * T;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wr * 64 + i * 16 + kk + 4 * r;
+          const int col = wc * 64 + j * 16 + m;
+          out[row * T + col] = double2{accR[i][j][r], accI[i][j][r]};
+        }
+  }
+}
+
 }  // namespace
 
 // Tile table of the FP64 path.
 static const TileConfig kFp64Tiles[] = {
+    {128, 8, 0, 256},   // pipelined, one workgroup per CU
     {64, 16, 0, 256},
     {32, 16, 0, 256},
 };
@@ -140,9 +299,12 @@ TileConfig herk_fp64_tile(int idx) { return kFp64Tiles[idx]; }
 hipError_t herk_fp64_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
   switch (idx) {
     case 0:
-      hipLaunchKernelGGL((herk_fp64_kernel<64, 16>), dim3(nwg), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(herk_fp64_pipe_kernel, dim3(nwg), dim3(256), 0, s, a);
       break;
     case 1:
+      hipLaunchKernelGGL((herk_fp64_kernel<64, 16>), dim3(nwg), dim3(256), 0, s, a);
+      break;
+    case 2:
       hipLaunchKernelGGL((herk_fp64_kernel<32, 16>), dim3(nwg), dim3(256), 0, s, a);
       break;
     default:
@@ -155,8 +317,10 @@ int herk_fp64_max_wg_per_cu(int idx) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   if (idx == 0)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_kernel<64, 16>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_pipe_kernel, 256, 0);
   else if (idx == 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_kernel<64, 16>, 256, 0);
+  else if (idx == 2)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_kernel<32, 16>, 256, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }

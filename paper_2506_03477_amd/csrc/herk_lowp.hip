@@ -18,7 +18,7 @@
 // FP32: v_mfma_f32_32x32x2f32 with the (re, im) of one pair as the two
 // contraction slots.
 //
-// Both kernels: 128 x 128 complex tiles, 4 waves of 64 x 64, operands staged
+// Both kernels: T x T complex tiles (T = 128 or 64), 4 waves of T/2 x T/2, operands staged
 // once per workgroup into double-buffered, XOR-swizzled LDS (the split / the
 // scaling happens while staging), one barrier per 16-pair stage, next
 // stage's global loads issued before the current stage's MFMAs.  Each
@@ -35,7 +35,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kT = 128;   // tile edge (complex elements)
 constexpr int kKC = 16;   // pairs per stage
 constexpr int kNT = 256;  // threads
 
@@ -78,7 +77,7 @@ __device__ __forceinline__ bool cursor_next(const Unit& u, const BlockDesc* bloc
   return false;
 }
 
-// LDS row = tile column (0..127), 16 dwords = 4 chunks of 4 pairs; chunk q of
+// LDS row = tile column (0..T-1), 16 dwords = 4 chunks of 4 pairs; chunk q of
 // row r lives at chunk q ^ ((r >> 2) & 3) (conflict-free 16-byte accesses).
 __device__ __forceinline__ int swz(int row, int q) {
   return row * 16 + 4 * (q ^ ((row >> 2) & 3));
@@ -111,23 +110,27 @@ __device__ __forceinline__ uint4 rot_neg4(uint4 v) {
   return uint4{rot_neg(v.x), rot_neg(v.y), rot_neg(v.z), rot_neg(v.w)};
 }
 
-// Add (or store, when first) the 64 x 64 wave tile of FP32 accumulators into
-// the FP64 partial tile.  32x32 MFMA result layout: lane holds column
+// Add (or store, when first) the (T/2) x (T/2) wave tile of FP32 accumulators
+// into the FP64 partial tile.  32x32 MFMA result layout: lane holds column
 // (lane % 32) of rows 8 (r / 4) + 4 (lane / 32) + (r % 4).
-__device__ __forceinline__ void flush_tile(double2* __restrict__ part, const f32x16 (&cr)[2][2],
-                                           const f32x16 (&ci)[2][2], int wr, int wc, int lane,
+template <int T, int NB>
+__device__ __forceinline__ void flush_tile(double2* __restrict__ part, const f32x16 (&cr)[NB][NB],
+                                           const f32x16 (&ci)[NB][NB], int wr, int wc, int lane,
                                            bool first) {
   const int g = lane >> 5;
   const int cl = lane & 31;
+  // Per-lane base offset, made opaque so that the 16 NB^2 element addresses
+  // are formed here instead of being hoisted (and kept live) across the
+  // stage loop.
+  int base = (wr * (T / 2) + 4 * g) * T + wc * (T / 2) + cl;
+  asm volatile("" : "+v"(base));
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = wr * 64 + i * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-        const int col = wc * 64 + j * 32 + cl;
-        double2* p = part + row * kT + col;
+        double2* p = part + base + (i * 32 + 8 * (r >> 2) + (r & 3)) * T + j * 32;
         double2 v = double2{static_cast<double>(cr[i][j][r]), static_cast<double>(ci[i][j][r])};
         if (!first) {
           const double2 o = *p;
@@ -138,12 +141,18 @@ __device__ __forceinline__ void flush_tile(double2* __restrict__ part, const f32
       }
 }
 
-template <bool LOLO>
+// BF16x3 kernel.  T = 128: waves of 64 x 64 (2 x 2 MFMA blocks); T = 64:
+// waves of 32 x 32.  The loader gives each thread one tile column and
+// T / 64 groups of 4 pairs.
+template <int T, bool LOLO>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
-  __shared__ __attribute__((aligned(16))) uint32_t sAh[2][kT * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sAl[2][kT * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sBh[2][kT * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sBl[2][kT * 16];
+  constexpr int NB = T / 64;          // 32x32 blocks per wave side
+  constexpr int LG = kNT / T;         // loader groups
+  constexpr int GPT = 4 / LG;         // pair groups (of 4) per thread
+  __shared__ __attribute__((aligned(16))) uint32_t sAh[2][T * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sAl[2][T * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sBh[2][T * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sBl[2][T * 16];
   __shared__ float sWgt[2][kKC];
 
   const int tid = threadIdx.x;
@@ -152,9 +161,8 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
   const int wr = wave >> 1, wc = wave & 1;
   const int g8 = lane >> 5;
   const int l32 = lane & 31;
-  // loader mapping: column c of the tile, pair groups gA and gA + 2
-  const int lc = tid & (kT - 1);
-  const int lg = tid >> 7;
+  const int lc = tid & (T - 1);
+  const int lg = tid / T;
 
   const int beg = a.wg_offsets[blockIdx.x];
   const int end = a.wg_offsets[blockIdx.x + 1];
@@ -165,23 +173,22 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
     const double om = pd.omega[u.iw];
     const double w2 = om * om;
     const int flush_stages = pd.flush > kKC ? pd.flush / kKC : 1;
-    const bool okP = u.tp * kT + lc < npb;
-    const bool okQ = u.tq * kT + lc < npb;
-    double2* part = a.partials + static_cast<size_t>(u.slot) * kT * kT;
+    const bool okP = u.tp * T + lc < npb;
+    const bool okQ = u.tq * T + lc < npb;
+    double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
 
-    f32x16 cr[2][2], ci[2][2];
+    f32x16 cr[NB][NB], ci[NB][NB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NB; ++j) {
         cr[i][j] = f32x16{0};
         ci[i][j] = f32x16{0};
       }
     bool first_flush = true;
     int since_flush = 0;
 
-    // raw operands of the stage being loaded: [group][pair in group]
-    float2 ra[2][4], rb[2][4];
+    float2 ra[GPT][4], rb[GPT][4];  // raw operands of the stage being loaded
     Cursor cur;
     bool have = cursor_first(u, a.blocks, cur);
     __syncthreads();  // previous unit's last MFMAs are done with the LDS
@@ -190,15 +197,15 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
       if (tid < kKC) sWgt[buf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
       const float2* z = static_cast<const float2*>(bd.z);
 #pragma unroll
-      for (int gi = 0; gi < 2; ++gi)
+      for (int gi = 0; gi < GPT; ++gi)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int p = c.p0 + 4 * (lg + 2 * gi) + e;
+          const int p = c.p0 + 4 * (lg + LG * gi) + e;
           float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
           if (p < c.pend) {
             const float2* row = z + static_cast<size_t>(p) * npb;
-            if (okP) va = row[u.tp * kT + lc];
-            if (okQ) vb = row[u.tq * kT + lc];
+            if (okP) va = row[u.tp * T + lc];
+            if (okQ) vb = row[u.tq * T + lc];
           }
           ra[gi][e] = va;
           rb[gi][e] = vb;
@@ -208,10 +215,11 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
     if (have) load_stage(cur, 0);
     __syncthreads();  // weights of stage 0 visible
     while (have) {
-      // stage the raw operands of this stage into LDS buffer `buf`
+      // stage this stage's operands into LDS buffer `buf`: split the P side,
+      // scale and split the Q side
 #pragma unroll
-      for (int gi = 0; gi < 2; ++gi) {
-        const int q = lg + 2 * gi;
+      for (int gi = 0; gi < GPT; ++gi) {
+        const int q = lg + LG * gi;
         uint32_t ah[4], al[4], bh[4], bl[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -233,50 +241,64 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
         const int q = 2 * ks + g8;
-        uint4 ah[2], al[2], bh[2], bl[2];
+        bf16x8 fah[NB], fal[NB], fbh[NB], fbl[NB], fih[NB], fil[NB];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int row = wr * 64 + i * 32 + l32;
-          ah[i] = *reinterpret_cast<const uint4*>(&sAh[buf][swz(row, q)]);
-          al[i] = *reinterpret_cast<const uint4*>(&sAl[buf][swz(row, q)]);
+        for (int i = 0; i < NB; ++i) {
+          const int row = wr * (T / 2) + i * 32 + l32;
+          fah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&sAh[buf][swz(row, q)]));
+          fal[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&sAl[buf][swz(row, q)]));
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int row = wc * 64 + j * 32 + l32;
-          bh[j] = *reinterpret_cast<const uint4*>(&sBh[buf][swz(row, q)]);
-          bl[j] = *reinterpret_cast<const uint4*>(&sBl[buf][swz(row, q)]);
+        for (int j = 0; j < NB; ++j) {
+          const int row = wc * (T / 2) + j * 32 + l32;
+          const uint4 bh = *reinterpret_cast<const uint4*>(&sBh[buf][swz(row, q)]);
+          const uint4 bl = *reinterpret_cast<const uint4*>(&sBl[buf][swz(row, q)]);
+          fbh[j] = as_bf16x8(bh);
+          fbl[j] = as_bf16x8(bl);
+          fih[j] = as_bf16x8(rot_neg4(bh));   // (bi, -br) for the imaginary part
+          fil[j] = as_bf16x8(rot_neg4(bl));
         }
+        // one product kind at a time over the accumulators, so dependent MFMAs
+        // on the same accumulator are 2 NB^2 instructions apart
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const bf16x8 brh = as_bf16x8(bh[j]);
-          const bf16x8 brl = as_bf16x8(bl[j]);
-          const bf16x8 bih = as_bf16x8(rot_neg4(bh[j]));
-          const bf16x8 bil = as_bf16x8(rot_neg4(bl[j]));
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const bf16x8 aah = as_bf16x8(ah[i]);
-            const bf16x8 aal = as_bf16x8(al[i]);
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, brh, cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, bih, ci[i][j], 0, 0, 0);
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, brl, cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aah, bil, ci[i][j], 0, 0, 0);
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, brh, cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, bih, ci[i][j], 0, 0, 0);
-            if (LOLO) {
-              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, brl, cr[i][j], 0, 0, 0);
-              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aal, bil, ci[i][j], 0, 0, 0);
-            }
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbh[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fih[j], ci[i][j], 0, 0, 0);
           }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbl[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fil[j], ci[i][j], 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbh[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fih[j], ci[i][j], 0, 0, 0);
+          }
+        if (LOLO) {
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbl[j], cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fil[j], ci[i][j], 0, 0, 0);
+            }
         }
       }
       if (++since_flush >= flush_stages && more) {
-        flush_tile(part, cr, ci, wr, wc, lane, first_flush);
+        flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
         first_flush = false;
         since_flush = 0;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < NB; ++j) {
             cr[i][j] = f32x16{0};
             ci[i][j] = f32x16{0};
           }
@@ -285,7 +307,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
       have = more;
       buf ^= 1;
     }
-    flush_tile(part, cr, ci, wr, wc, lane, first_flush);
+    flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
   }
 }
 
@@ -296,9 +318,13 @@ __device__ __forceinline__ int swz32(int row, int q) {  // q: chunk of 2 pairs (
   return row * 32 + 4 * (q ^ ((row >> 1) & 7));
 }
 
+template <int T>
 __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
-  __shared__ __attribute__((aligned(16))) float sA[2][kT * 32];
-  __shared__ __attribute__((aligned(16))) float sB[2][kT * 32];
+  constexpr int NB = T / 64;
+  constexpr int LG = kNT / T;         // loader groups
+  constexpr int PPT = kKC / LG;       // pairs per thread
+  __shared__ __attribute__((aligned(16))) float sA[2][T * 32];
+  __shared__ __attribute__((aligned(16))) float sB[2][T * 32];
   __shared__ float sWgt[2][kKC];
 
   const int tid = threadIdx.x;
@@ -307,8 +333,8 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
   const int wr = wave >> 1, wc = wave & 1;
   const int g = lane >> 5;  // contraction slot: 0 = re, 1 = im
   const int l32 = lane & 31;
-  const int lc = tid & (kT - 1);
-  const int lg = tid >> 7;
+  const int lc = tid & (T - 1);
+  const int lg = tid / T;
 
   const int beg = a.wg_offsets[blockIdx.x];
   const int end = a.wg_offsets[blockIdx.x + 1];
@@ -319,21 +345,21 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
     const double om = pd.omega[u.iw];
     const double w2 = om * om;
     const int flush_stages = pd.flush > kKC ? pd.flush / kKC : 1;
-    const bool okP = u.tp * kT + lc < npb;
-    const bool okQ = u.tq * kT + lc < npb;
-    double2* part = a.partials + static_cast<size_t>(u.slot) * kT * kT;
+    const bool okP = u.tp * T + lc < npb;
+    const bool okQ = u.tq * T + lc < npb;
+    double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
 
-    f32x16 cr[2][2], ci[2][2];
+    f32x16 cr[NB][NB], ci[NB][NB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NB; ++j) {
         cr[i][j] = f32x16{0};
         ci[i][j] = f32x16{0};
       }
     bool first_flush = true;
     int since_flush = 0;
-    float2 ra[8], rb[8];  // pairs 8 lg .. 8 lg + 7 of the stage, column lc
+    float2 ra[PPT], rb[PPT];  // pairs PPT lg .. PPT lg + PPT - 1, column lc
     Cursor cur;
     bool have = cursor_first(u, a.blocks, cur);
     __syncthreads();
@@ -342,13 +368,13 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
       if (tid < kKC) sWgt[buf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
       const float2* z = static_cast<const float2*>(bd.z);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int p = c.p0 + 8 * lg + e;
+      for (int e = 0; e < PPT; ++e) {
+        const int p = c.p0 + PPT * lg + e;
         float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
         if (p < c.pend) {
           const float2* row = z + static_cast<size_t>(p) * npb;
-          if (okP) va = row[u.tp * kT + lc];
-          if (okQ) vb = row[u.tq * kT + lc];
+          if (okP) va = row[u.tp * T + lc];
+          if (okQ) vb = row[u.tq * T + lc];
         }
         ra[e] = va;
         rb[e] = vb;
@@ -359,8 +385,8 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
     __syncthreads();
     while (have) {
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int q = 4 * lg + h;  // chunk of pairs 2q, 2q + 1
+      for (int h = 0; h < PPT / 2; ++h) {
+        const int q = (PPT / 2) * lg + h;  // chunk of pairs 2q, 2q + 1
         const float w0 = sWgt[buf][2 * q];
         const float w1 = sWgt[buf][2 * q + 1];
         const int o = swz32(lc, q);
@@ -375,46 +401,46 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 8; ++q) {  // two pairs per chunk
-        float4 av[2], bv[2];
+        float4 av[NB], bv[NB];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-          av[i] = *reinterpret_cast<const float4*>(&sA[buf][swz32(wr * 64 + i * 32 + l32, q)]);
+        for (int i = 0; i < NB; ++i)
+          av[i] = *reinterpret_cast<const float4*>(&sA[buf][swz32(wr * (T / 2) + i * 32 + l32, q)]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          bv[j] = *reinterpret_cast<const float4*>(&sB[buf][swz32(wc * 64 + j * 32 + l32, q)]);
+        for (int j = 0; j < NB; ++j)
+          bv[j] = *reinterpret_cast<const float4*>(&sB[buf][swz32(wc * (T / 2) + j * 32 + l32, q)]);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          float a0[2], b0r[2], b0i[2];
+          float a0[NB], b0r[NB], b0i[NB];
 #pragma unroll
-          for (int i = 0; i < 2; ++i) {
+          for (int i = 0; i < NB; ++i) {
             const float re = h ? av[i].z : av[i].x;
             const float im = h ? av[i].w : av[i].y;
             a0[i] = g ? im : re;
           }
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < NB; ++j) {
             const float re = h ? bv[j].z : bv[j].x;
             const float im = h ? bv[j].w : bv[j].y;
             b0r[j] = g ? im : re;
             b0i[j] = g ? -re : im;
           }
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < NB; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < NB; ++j) {
               cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0r[j], cr[i][j], 0, 0, 0);
               ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0i[j], ci[i][j], 0, 0, 0);
             }
         }
       }
       if (++since_flush >= flush_stages && more) {
-        flush_tile(part, cr, ci, wr, wc, lane, first_flush);
+        flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
         first_flush = false;
         since_flush = 0;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < NB; ++j) {
             cr[i][j] = f32x16{0};
             ci[i][j] = f32x16{0};
           }
@@ -423,49 +449,66 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
       have = more;
       buf ^= 1;
     }
-    flush_tile(part, cr, ci, wr, wc, lane, first_flush);
+    flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
   }
 }
 
 }  // namespace
 
-// Tile tables: {tile, pairs per stage, FP32 run length (pairs), threads}.
+// Tile tables: {tile, pairs per stage, cap of the FP32 run length (pairs),
+// threads}.  BF16X3 with CHI0_BF16_LOLO selects the variant adding lo*lo.
 static const TileConfig kBf16Tiles[] = {
-    {kT, kKC, 4096, kNT},
-    {kT, kKC, 4096, kNT},   // same tiles, lo*lo product added (CHI0_BF16_LOLO)
+    {128, kKC, 4096, kNT},
+    {64, kKC, 4096, kNT},
+    {128, kKC, 1024, kNT},
 };
 static const TileConfig kFp32Tiles[] = {
-    {kT, kKC, 4096, kNT},
+    {128, kKC, 4096, kNT},
+    {64, kKC, 4096, kNT},
 };
 
-int herk_bf16x3_tile_count() { return 1; }
+int herk_bf16x3_tile_count() { return sizeof(kBf16Tiles) / sizeof(kBf16Tiles[0]); }
 TileConfig herk_bf16x3_tile(int idx) { return kBf16Tiles[idx]; }
 hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
-  if (idx != 0) return hipErrorInvalidValue;
-  if (a.flags & 2)
-    hipLaunchKernelGGL(herk_bf16x3_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
-  else
-    hipLaunchKernelGGL(herk_bf16x3_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
+  if (idx < 0 || idx >= herk_bf16x3_tile_count()) return hipErrorInvalidValue;
+  const bool lolo = (a.flags & 2) != 0;
+  if (kBf16Tiles[idx].tile == 128) {
+    if (lolo)
+      hipLaunchKernelGGL((herk_bf16x3_kernel<128, true>), dim3(nwg), dim3(kNT), 0, s, a);
+    else
+      hipLaunchKernelGGL((herk_bf16x3_kernel<128, false>), dim3(nwg), dim3(kNT), 0, s, a);
+  } else {
+    if (lolo)
+      hipLaunchKernelGGL((herk_bf16x3_kernel<64, true>), dim3(nwg), dim3(kNT), 0, s, a);
+    else
+      hipLaunchKernelGGL((herk_bf16x3_kernel<64, false>), dim3(nwg), dim3(kNT), 0, s, a);
+  }
   return hipGetLastError();
 }
 int herk_bf16x3_max_wg_per_cu(int idx) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<false>, kNT, 0) != hipSuccess)
-    return 1;
-  return n > 0 ? n : 1;
+  hipError_t e = kBf16Tiles[idx].tile == 128
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false>, kNT, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<64, false>, kNT, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
 }
 
-int herk_fp32_tile_count() { return 1; }
+int herk_fp32_tile_count() { return sizeof(kFp32Tiles) / sizeof(kFp32Tiles[0]); }
 TileConfig herk_fp32_tile(int idx) { return kFp32Tiles[idx]; }
 hipError_t herk_fp32_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
-  if (idx != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(herk_fp32_kernel, dim3(nwg), dim3(kNT), 0, s, a);
+  if (idx < 0 || idx >= herk_fp32_tile_count()) return hipErrorInvalidValue;
+  if (kFp32Tiles[idx].tile == 128)
+    hipLaunchKernelGGL(herk_fp32_kernel<128>, dim3(nwg), dim3(kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL(herk_fp32_kernel<64>, dim3(nwg), dim3(kNT), 0, s, a);
   return hipGetLastError();
 }
 int herk_fp32_max_wg_per_cu(int idx) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp32_kernel, kNT, 0) != hipSuccess) return 1;
-  return n > 0 ? n : 1;
+  hipError_t e = kFp32Tiles[idx].tile == 128
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp32_kernel<128>, kNT, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp32_kernel<64>, kNT, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
 }
 
 }  // namespace chi0
