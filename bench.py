@@ -22,6 +22,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+KERNEL_SOURCE = {"fp64": "paper_2506_03477_amd/csrc/herk_fp64.hip",
+                 "fp32": "paper_2506_03477_amd/csrc/herk_lowp.hip",
+                 "bf16x3": "paper_2506_03477_amd/csrc/herk_lowp.hip"}
+KERNEL_NAME = {"fp64": "herk_fp64", "fp32": "herk_fp32", "bf16x3": "herk_bf16x3"}
+CALIB_BYTES = 1 << 30   # plain device copy used to calibrate the byte counters
 MFMA_DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}
 SPLIT_FACTOR = {"fp64": 1, "fp32": 1, "bf16x3": 3}
 
@@ -86,6 +91,71 @@ def cpu_baseline(wl, target_s=15.0):
             "seconds": t_meas}
 
 
+def source_sha(prec):
+    import hashlib
+    with open(os.path.join(ROOT, KERNEL_SOURCE[prec]), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_file(prec, workload_name):
+    return os.path.join(ROOT, "profiles", f"traffic_{KERNEL_NAME[prec]}_{workload_name}.json")
+
+
+def _dispatch_counters(db, counter):
+    """{kernel_name: [value per dispatch]} for one counter of a rocprofv3 --pmc run."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    out = {}
+    for name, val in con.execute("select kernel_name, value from counters_collection "
+                                 "where counter_name = ?", (counter,)):
+        out.setdefault(name, []).append(float(val))
+    return out
+
+
+def summarize_pmc(fetch_db, write_db, prec, workload_name, command):
+    """HBM bytes per launch of the rank-K kernel from FETCH_SIZE / WRITE_SIZE
+    runs (KiB per dispatch), each scaled by what the same counter reads for a
+    plain device copy of CALIB_BYTES (run by --copy-calibration)."""
+    res = {"kernel": KERNEL_NAME[prec], "workload": workload_name, "command": command,
+           "kernel_source_sha": source_sha(prec)}
+    for counter, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
+        per = _dispatch_counters(db, counter)
+        herk = [v for k, v in per.items() if KERNEL_NAME[prec] in k]
+        copy = [v for k, v in per.items() if "copy" in k.lower()]
+        herk_vals = [x for vs in herk for x in vs]
+        copy_vals = [x for vs in copy for x in vs]
+        if not herk_vals or not copy_vals:
+            raise SystemExit(f"{counter}: kernel or copy dispatches missing in {db}")
+        kib_copy = max(copy_vals)                 # the 1 GiB calibration copy
+        factor = (CALIB_BYTES / 1024.0) / kib_copy
+        kib = sum(herk_vals) / len(herk_vals)
+        res[counter] = {"kib_per_dispatch": kib, "copy_kib": kib_copy,
+                        "scale": factor, "bytes_per_launch": kib * 1024.0 * factor}
+    res["traffic_bytes_per_launch"] = (res["FETCH_SIZE"]["bytes_per_launch"] +
+                                       res["WRITE_SIZE"]["bytes_per_launch"])
+    path = traffic_file(prec, workload_name)
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(f"wrote {path}")
+
+
+def summarize_trace(db, out_path, command):
+    """Short text summary (per-kernel calls, total and mean duration) of a
+    rocprofv3 --kernel-trace run."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = list(con.execute("select name, total_calls, total_duration, average, percentage "
+                            "from top_kernels"))
+    with open(out_path, "w") as f:
+        f.write(f"# rocprofv3 kernel-trace summary\n\ncommand: `{command}`\n\n")
+        f.write("| kernel | calls | total ms | mean ms | % |\n|---|---|---|---|---|\n")
+        for name, calls, tot, avg, pct in rows:   # top_kernels durations are in microseconds
+            short = name.replace("(anonymous namespace)::", "").replace("void ", "")
+            short = short.split("(")[0][:90]
+            f.write(f"| {short} | {calls} | {tot / 1e3:.3f} | {avg / 1e3:.4f} | {pct:.2f} |\n")
+    print(f"wrote {out_path}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,7 +167,24 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay chi0 from a hipGraph")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (byte-counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write profiles/traffic_*.json from two rocprofv3 --pmc databases")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DB", "OUT"),
+                    help="write a text summary of a rocprofv3 --kernel-trace database")
+    ap.add_argument("--command", default="", help="profiled command (for the summaries)")
     args = ap.parse_args()
+
+    if args.summarize_pmc or args.summarize_trace:
+        from synth import workload as _wl
+        name = _wl(args.workload).name
+        if args.summarize_pmc:
+            summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1],
+                          args.precision or _wl(args.workload).paths[0], name, args.command)
+        if args.summarize_trace:
+            summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -120,6 +207,13 @@ def main():
         raise SystemExit(f"precision {prec} has no kernel in this build")
     ztype = "c128" if prec == "fp64" else "c64"
 
+    if args.copy_calibration:
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy done")
     log(f"generating {wl.name} inputs ({ztype}) on the GPU")
     t0 = time.time()
     blks, omega, vsqrt = device_workload(wl, 0, dev, ztype=ztype)
@@ -171,8 +265,17 @@ def main():
     if kern_avg_ms:
         ach = flops / (kern_avg_ms * 1e-3) / 1e12
         exe = executed_mfma_flops(wl.npb, npairs, wl.nomega, tile, prec) / (kern_avg_ms * 1e-3) / 1e12
+        traffic = None
+        tf = traffic_file(prec, wl.name)
+        if os.path.exists(tf):
+            with open(tf) as f:
+                t = json.load(f)
+            if t.get("kernel_source_sha") == source_sha(prec):
+                traffic = round(t["traffic_bytes_per_launch"])
         roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec],
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4), "traffic": traffic,
+                "algorithmic_bytes": int(npairs * wl.npb * (16 if prec == "fp64" else 8)
+                                         + wl.nomega * wl.npb * (wl.npb + 1) // 2 * 16),
                 "kernel": f"herk_{prec}", "kernel_ms": round(kern_avg_ms, 3),
                 "executed_mfma_tflops": round(exe, 3),
                 "executed_mfma_frac": round(exe / PEAK_TFLOPS[prec], 4)}

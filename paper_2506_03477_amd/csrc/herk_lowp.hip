@@ -36,6 +36,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kKC = 16;   // pairs per stage
+
+// Z is read through a global-address-space pointer (global_load rather than
+// flat_load); one complex64 = one 64-bit word.
+typedef const uint64_t __attribute__((address_space(1)))* gf2ptr;
+
+__device__ __forceinline__ float2 ld_c64(gf2ptr p) {
+  const uint64_t v = *p;
+  return float2{__uint_as_float(static_cast<uint32_t>(v)), __uint_as_float(static_cast<uint32_t>(v >> 32))};
+}
 constexpr int kNT = 256;  // threads
 
 // Pair cursor over a unit's range: block b, stage start p0, end of the
@@ -185,8 +194,6 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
         cr[i][j] = f32x16{0};
         ci[i][j] = f32x16{0};
       }
-    bool first_flush = true;
-    int since_flush = 0;
 
     float2 ra[GPT][4], rb[GPT][4];  // raw operands of the stage being loaded
     Cursor cur;
@@ -195,7 +202,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
     auto load_stage = [&](const Cursor& c, int buf) {
       const BlockDesc bd = a.blocks[c.b];
       if (tid < kKC) sWgt[buf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
-      const float2* z = static_cast<const float2*>(bd.z);
+      const gf2ptr z = (gf2ptr)(bd.z);
 #pragma unroll
       for (int gi = 0; gi < GPT; ++gi)
 #pragma unroll
@@ -203,9 +210,9 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
           const int p = c.p0 + 4 * (lg + LG * gi) + e;
           float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
           if (p < c.pend) {
-            const float2* row = z + static_cast<size_t>(p) * npb;
-            if (okP) va = row[u.tp * T + lc];
-            if (okQ) vb = row[u.tq * T + lc];
+            const gf2ptr row = z + static_cast<size_t>(p) * npb;
+            if (okP) va = ld_c64(row + u.tp * T + lc);
+            if (okQ) vb = ld_c64(row + u.tq * T + lc);
           }
           ra[gi][e] = va;
           rb[gi][e] = vb;
@@ -214,7 +221,12 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
     int buf = 0;
     if (have) load_stage(cur, 0);
     __syncthreads();  // weights of stage 0 visible
+    // Outer loop: one FP32 run of at most flush_stages stages, then the flush
+    // into FP64.  The inner stage loop carries no flush code, so the
+    // accumulators stay in place across it.
+    bool first_flush = true;
     while (have) {
+    for (int ns = 0; ns < flush_stages && have; ++ns) {
       // stage this stage's operands into LDS buffer `buf`: split the P side,
       // scale and split the Q side
 #pragma unroll
@@ -291,23 +303,21 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
             }
         }
       }
-      if (++since_flush >= flush_stages && more) {
-        flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
-        first_flush = false;
-        since_flush = 0;
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            cr[i][j] = f32x16{0};
-            ci[i][j] = f32x16{0};
-          }
-      }
       cur = nxt;
       have = more;
       buf ^= 1;
     }
     flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
+    first_flush = false;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        cr[i][j] = f32x16{0};
+        ci[i][j] = f32x16{0};
+      }
+    }
+    if (first_flush) flush_tile<T, NB>(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
   }
 }
 
@@ -357,8 +367,6 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
         cr[i][j] = f32x16{0};
         ci[i][j] = f32x16{0};
       }
-    bool first_flush = true;
-    int since_flush = 0;
     float2 ra[PPT], rb[PPT];  // pairs PPT lg .. PPT lg + PPT - 1, column lc
     Cursor cur;
     bool have = cursor_first(u, a.blocks, cur);
@@ -366,15 +374,15 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
     auto load_stage = [&](const Cursor& c, int buf) {
       const BlockDesc bd = a.blocks[c.b];
       if (tid < kKC) sWgt[buf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
-      const float2* z = static_cast<const float2*>(bd.z);
+      const gf2ptr z = (gf2ptr)(bd.z);
 #pragma unroll
       for (int e = 0; e < PPT; ++e) {
         const int p = c.p0 + PPT * lg + e;
         float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
         if (p < c.pend) {
-          const float2* row = z + static_cast<size_t>(p) * npb;
-          if (okP) va = row[u.tp * T + lc];
-          if (okQ) vb = row[u.tq * T + lc];
+          const gf2ptr row = z + static_cast<size_t>(p) * npb;
+          if (okP) va = ld_c64(row + u.tp * T + lc);
+          if (okQ) vb = ld_c64(row + u.tq * T + lc);
         }
         ra[e] = va;
         rb[e] = vb;
@@ -383,7 +391,9 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
     int buf = 0;
     if (have) load_stage(cur, 0);
     __syncthreads();
+    bool first_flush = true;
     while (have) {
+    for (int ns = 0; ns < flush_stages && have; ++ns) {
 #pragma unroll
       for (int h = 0; h < PPT / 2; ++h) {
         const int q = (PPT / 2) * lg + h;  // chunk of pairs 2q, 2q + 1
@@ -433,23 +443,21 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
             }
         }
       }
-      if (++since_flush >= flush_stages && more) {
-        flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
-        first_flush = false;
-        since_flush = 0;
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            cr[i][j] = f32x16{0};
-            ci[i][j] = f32x16{0};
-          }
-      }
       cur = nxt;
       have = more;
       buf ^= 1;
     }
     flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
+    first_flush = false;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        cr[i][j] = f32x16{0};
+        ci[i][j] = f32x16{0};
+      }
+    }
+    if (first_flush) flush_tile<T, NB>(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
   }
 }
 
