@@ -200,6 +200,19 @@ int chi0_autotune(chi0_handle h, const chi0_problem* probs, int32_t nprob,
 int chi0_profile_enable(chi0_handle h, int on);
 int chi0_profile_read(chi0_handle h, double* kernel_ms, int64_t* launches);
 
+/* Host-only inspection of the work decomposition chi0_accumulate would use
+ * for these problem shapes with `nwg` persistent workgroups and tile
+ * configuration `tile` (no device call; only npb, nomega, nblocks and the
+ * blocks' nocc / nunocc are read).  Returns the number of units and of tile
+ * jobs; when units_out is not NULL (capacity units_cap units), writes 10
+ * int32 per unit: problem, frequency, tile row, tile column, first block,
+ * first pair, last block, end pair (exclusive), partial slot, workgroup.
+ * load_max / load_mean give the planned per-workgroup cost (pairs). */
+int chi0_plan_inspect(const chi0_problem* probs, int32_t nprob, chi0_precision prec,
+                      int32_t tile, int32_t nwg, int32_t* nunits, int32_t* njobs,
+                      int32_t* units_out, int32_t units_cap, double* load_max,
+                      double* load_mean);
+
 /* ABI version (major * 10000 + minor * 100 + patch). */
 int chi0_version(void);
 

@@ -79,6 +79,9 @@ def load() -> ctypes.CDLL:
         "chi0_get_tile": (c_int, [vp, c_int, POINTER(c_int32)]),
         "chi0_autotune": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
                                   c_int32, POINTER(c_int32), POINTER(c_double), vp]),
+        "chi0_plan_inspect": (c_int, [POINTER(chi0_problem), c_int32, c_int, c_int32, c_int32,
+                                      POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                      c_int32, POINTER(c_double), POINTER(c_double)]),
         "chi0_profile_enable": (c_int, [vp, c_int]),
         "chi0_profile_read": (c_int, [vp, POINTER(c_double), POINTER(c_int64)]),
     }

@@ -224,7 +224,7 @@ int upload_sync(DevBuf& d, const std::vector<T>& v) {
   return CHI0_OK;
 }
 
-// Work decomposition.
+// Work decomposition (host only).
 //  * Every (problem, frequency, lower tile) is split into s_p contiguous
 //    ranges of the problem's pairs (blocks concatenated); s_p is chosen so
 //    that there are several units per workgroup.
@@ -236,18 +236,17 @@ int upload_sync(DevBuf& d, const std::vector<T>& v) {
 //  * Logical workgroups are placed XCD-major: consecutive logical
 //    workgroups share an XCD (workgroups are dispatched round-robin over the
 //    8 XCDs), so units that read the same Z columns share an L2.
-int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem* probs,
-               int nprob) {
-  const TileConfig tc = herk_tile_config(kind, tile_idx);
-  const int T = tc.tile;
-  const int wg_per_cu = std::max(1, herk_max_wg_per_cu(kind, tile_idx));
-  const int nwg = h->ncu * wg_per_cu;
-  pl.kind = kind;
-  pl.tile_idx = tile_idx;
-  pl.tc = tc;
-  pl.nwg = nwg;
-  pl.nprob = nprob;
+struct HostPlan {
+  std::vector<Unit> units;
+  std::vector<TileJob> jobs;
+  std::vector<int32_t> wg_off, wg_units;
+  std::vector<double> cost;
+  std::vector<double> wg_load;
+  int nblocks_total = 0;
+};
 
+void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int nprob, HostPlan& hp) {
+  const int T = tc.tile;
   struct P {
     int npb, nomega, nt, ntl, b0, nb;
     int64_t K;
@@ -272,7 +271,7 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
     bflat += q.nb;
     work += static_cast<double>(q.nomega) * q.ntl * static_cast<double>(q.K);
   }
-  pl.nblocks_total = bflat;
+  hp.nblocks_total = bflat;
 
   // target pairs per unit: ~8 units per workgroup, at least 1024 pairs, and
   // partial storage bounded
@@ -288,10 +287,6 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
   };
   while (count_units(per_unit) * slot_bytes > max_partial_bytes) per_unit *= 1.5;
 
-  std::vector<Unit> units;
-  std::vector<TileJob> jobs;
-  std::vector<double> cost;
-  // ranges per problem
   struct Range { int b0, p0, b1, p1; int64_t n; };
   std::vector<std::vector<Range>> ranges(nprob);
   for (int p = 0; p < nprob; ++p) {
@@ -303,7 +298,7 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
       Range rg{};
       rg.n = g1 - g0;
       if (q.nb == 0) {
-        rg.b0 = q.b0; rg.p0 = 0; rg.b1 = q.b0 - 1; rg.p1 = 0;  // empty: loop does nothing
+        rg.b0 = q.b0; rg.p0 = 0; rg.b1 = q.b0 - 1; rg.p1 = 0;  // empty: no block visited
       } else {
         int bb = static_cast<int>(std::upper_bound(q.cum.begin(), q.cum.end(), g0) - q.cum.begin()) - 1;
         bb = std::min(bb, q.nb - 1);
@@ -326,30 +321,30 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
     for (int iw = 0; iw < q.nomega; ++iw)
       for (int tp = 0; tp < q.nt; ++tp)
         for (int tq = 0; tq <= tp; ++tq) {
-          TileJob j{p, iw, tp, tq, static_cast<int32_t>(units.size()),
+          TileJob j{p, iw, tp, tq, static_cast<int32_t>(hp.units.size()),
                     static_cast<int32_t>(ranges[p].size())};
-          jobs.push_back(j);
+          hp.jobs.push_back(j);
           for (size_t r = 0; r < ranges[p].size(); ++r) {
             const Range& rg = ranges[p][r];
             Unit u{};
             u.prob = p; u.iw = iw; u.tp = tp; u.tq = tq;
             u.b0 = rg.b0; u.p0 = rg.p0; u.b1 = rg.b1; u.p1 = rg.p1;
-            u.slot = static_cast<int32_t>(units.size());
-            units.push_back(u);
+            u.slot = static_cast<int32_t>(hp.units.size());
+            hp.units.push_back(u);
             unit_range_idx.push_back(static_cast<int>(r));
             // cost: pairs rounded up to staging chunks per block touched, plus a
             // fixed per-unit cost (zeroing and writing the tile)
-            const double nblk = rg.b1 - rg.b0 + 1;
-            cost.push_back(static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0);
+            const double nblk = std::max(0, rg.b1 - rg.b0 + 1);
+            hp.cost.push_back(static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0);
           }
         }
   }
   // locality order: (problem, range, tile, frequency)
-  std::vector<int> order(units.size());
+  std::vector<int> order(hp.units.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const Unit& ua = units[a];
-    const Unit& ub = units[b];
+    const Unit& ua = hp.units[a];
+    const Unit& ub = hp.units[b];
     if (ua.prob != ub.prob) return ua.prob < ub.prob;
     if (unit_range_idx[a] != unit_range_idx[b]) return unit_range_idx[a] < unit_range_idx[b];
     if (ua.tp != ub.tp) return ua.tp < ub.tp;
@@ -358,15 +353,17 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
   });
   // greedy list scheduling over logical workgroups
   std::vector<std::vector<int>> lists(nwg);
+  std::vector<double> load(nwg, 0.0);
   typedef std::pair<double, int> Slot;
   std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
   for (int w = 0; w < nwg; ++w) heap.push(Slot(0.0, w));
   for (int id : order) {
-    Slot s = heap.top();
+    Slot sl = heap.top();
     heap.pop();
-    lists[s.second].push_back(id);
-    s.first += cost[id];
-    heap.push(s);
+    lists[sl.second].push_back(id);
+    sl.first += hp.cost[id];
+    load[sl.second] = sl.first;
+    heap.push(sl);
   }
   // logical -> physical placement (XCD-major)
   const int nxcd = 8;
@@ -378,23 +375,42 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
     for (int L = 0; L < nwg; ++L) phys_of[L] = L;
   }
   std::vector<std::vector<int>> plists(nwg);
-  for (int L = 0; L < nwg; ++L) plists[phys_of[L]] = std::move(lists[L]);
-  std::vector<int32_t> off(nwg + 1, 0), flat;
-  flat.reserve(units.size());
-  for (int w = 0; w < nwg; ++w) {
-    off[w] = static_cast<int32_t>(flat.size());
-    for (int id : plists[w]) flat.push_back(id);
+  hp.wg_load.assign(nwg, 0.0);
+  for (int L = 0; L < nwg; ++L) {
+    plists[phys_of[L]] = std::move(lists[L]);
+    hp.wg_load[phys_of[L]] = load[L];
   }
-  off[nwg] = static_cast<int32_t>(flat.size());
+  hp.wg_off.assign(nwg + 1, 0);
+  hp.wg_units.clear();
+  hp.wg_units.reserve(hp.units.size());
+  for (int w = 0; w < nwg; ++w) {
+    hp.wg_off[w] = static_cast<int32_t>(hp.wg_units.size());
+    for (int id : plists[w]) hp.wg_units.push_back(id);
+  }
+  hp.wg_off[nwg] = static_cast<int32_t>(hp.wg_units.size());
+}
 
-  pl.nunits = static_cast<int>(units.size());
-  pl.njobs = static_cast<int>(jobs.size());
+int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem* probs,
+               int nprob) {
+  const TileConfig tc = herk_tile_config(kind, tile_idx);
+  const int wg_per_cu = std::max(1, herk_max_wg_per_cu(kind, tile_idx));
+  const int nwg = h->ncu * wg_per_cu;
+  pl.kind = kind;
+  pl.tile_idx = tile_idx;
+  pl.tc = tc;
+  pl.nwg = nwg;
+  pl.nprob = nprob;
+  HostPlan hp;
+  plan_host(tc, nwg, probs, nprob, hp);
+  pl.nblocks_total = hp.nblocks_total;
+  pl.nunits = static_cast<int>(hp.units.size());
+  pl.njobs = static_cast<int>(hp.jobs.size());
   int rc;
-  if ((rc = upload_sync(pl.d_units, units))) return rc;
-  if ((rc = upload_sync(pl.d_wg_off, off))) return rc;
-  if ((rc = upload_sync(pl.d_wg_units, flat))) return rc;
-  if ((rc = upload_sync(pl.d_jobs, jobs))) return rc;
-  if ((rc = pl.d_blocks.reserve(std::max(1, bflat) * sizeof(BlockDesc), nullptr))) return rc;
+  if ((rc = upload_sync(pl.d_units, hp.units))) return rc;
+  if ((rc = upload_sync(pl.d_wg_off, hp.wg_off))) return rc;
+  if ((rc = upload_sync(pl.d_wg_units, hp.wg_units))) return rc;
+  if ((rc = upload_sync(pl.d_jobs, hp.jobs))) return rc;
+  if ((rc = pl.d_blocks.reserve(std::max(1, hp.nblocks_total) * sizeof(BlockDesc), nullptr))) return rc;
   if ((rc = pl.d_probs.reserve(std::max(1, nprob) * sizeof(ProbDesc), nullptr))) return rc;
   return CHI0_OK;
 }
@@ -791,6 +807,51 @@ int chi0_autotune(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_
   if (rc) return rc;
   h->tile_tuned[k] = bi;
   if (best) *best = bi;
+  return CHI0_OK;
+}
+
+int chi0_plan_inspect(const chi0_problem* probs, int32_t nprob, chi0_precision prec,
+                      int32_t tile, int32_t nwg, int32_t* nunits, int32_t* njobs,
+                      int32_t* units_out, int32_t units_cap, double* load_max,
+                      double* load_mean) {
+  if (nprob < 0 || (nprob > 0 && !probs)) return fail(CHI0_EINVAL, "bad problem list");
+  if (nwg < 1) return fail(CHI0_EINVAL, "nwg must be >= 1");
+  const int k = kind_of(prec);
+  if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
+  if (tile < 0 || tile >= herk_tile_count(k)) return fail(CHI0_EINVAL, "tile %d out of range", tile);
+  for (int p = 0; p < nprob; ++p) {
+    if (probs[p].npb < 1 || probs[p].nomega < 1 || probs[p].nblocks < 0 ||
+        (probs[p].nblocks > 0 && !probs[p].blocks))
+      return fail(CHI0_EINVAL, "problem %d: bad shape", p);
+    for (int b = 0; b < probs[p].nblocks; ++b)
+      if (probs[p].blocks[b].nocc < 0 || probs[p].blocks[b].nunocc < 0)
+        return fail(CHI0_EINVAL, "problem %d block %d: negative size", p, b);
+  }
+  HostPlan hp;
+  plan_host(herk_tile_config(k, tile), nwg, probs, nprob, hp);
+  if (nunits) *nunits = static_cast<int32_t>(hp.units.size());
+  if (njobs) *njobs = static_cast<int32_t>(hp.jobs.size());
+  if (units_out) {
+    if (units_cap < static_cast<int32_t>(hp.units.size()))
+      return fail(CHI0_EINVAL, "units_out holds %d units, %zu needed", units_cap, hp.units.size());
+    // per unit: prob, iw, tp, tq, b0, p0, b1, p1, slot, workgroup
+    std::vector<int32_t> owner(hp.units.size(), -1);
+    for (int w = 0; w < nwg; ++w)
+      for (int i = hp.wg_off[w]; i < hp.wg_off[w + 1]; ++i) owner[hp.wg_units[i]] = w;
+    for (size_t u = 0; u < hp.units.size(); ++u) {
+      const Unit& x = hp.units[u];
+      int32_t* o = units_out + 10 * u;
+      o[0] = x.prob; o[1] = x.iw; o[2] = x.tp; o[3] = x.tq; o[4] = x.b0;
+      o[5] = x.p0; o[6] = x.b1; o[7] = x.p1; o[8] = x.slot; o[9] = owner[u];
+    }
+  }
+  double mx = 0.0, sum = 0.0;
+  for (double v : hp.wg_load) {
+    mx = std::max(mx, v);
+    sum += v;
+  }
+  if (load_max) *load_max = mx;
+  if (load_mean) *load_mean = hp.wg_load.empty() ? 0.0 : sum / hp.wg_load.size();
   return CHI0_OK;
 }
 

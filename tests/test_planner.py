@@ -1,0 +1,138 @@
+"""Host logic: the work decomposition of chi0_accumulate (host-only
+chi0_plan_inspect, no device call) covers every pair of every (problem,
+frequency, lower tile) exactly once, in order, with one workgroup per unit
+and a balanced load."""
+import ctypes
+from ctypes import byref, c_double, c_int32
+
+import numpy as np
+import pytest
+
+import paper_2506_03477_amd as pkg
+from paper_2506_03477_amd import _lib as L
+from synth import workload
+
+FAKE = 0x10000
+
+
+def _problems(shapes):
+    """shapes: list of (npb, nomega, [(nocc, nunocc), ...])"""
+    keep = []
+    arr = (L.chi0_problem * len(shapes))()
+    for i, (npb, nomega, blocks) in enumerate(shapes):
+        b = (L.chi0_block * max(1, len(blocks)))()
+        for j, (no, nu) in enumerate(blocks):
+            b[j].nocc, b[j].nunocc, b[j].z, b[j].eps_occ, b[j].eps_unocc, b[j].wk = \
+                no, nu, FAKE, FAKE, FAKE, 1.0
+        keep.append(b)
+        arr[i].npb, arr[i].nblocks = npb, len(blocks)
+        arr[i].blocks = ctypes.cast(b, ctypes.POINTER(L.chi0_block))
+        arr[i].nomega, arr[i].omega, arr[i].chi0 = nomega, FAKE, FAKE
+    return arr, keep
+
+
+def _inspect(shapes, prec, tile, nwg):
+    lib = pkg.load()
+    arr, keep = _problems(shapes)
+    nu, nj = c_int32(), c_int32()
+    assert lib.chi0_plan_inspect(arr, len(shapes), prec, tile, nwg, byref(nu), byref(nj), None, 0,
+                                 None, None) == 0
+    buf = (c_int32 * (10 * max(1, nu.value)))()
+    lmax, lmean = c_double(), c_double()
+    assert lib.chi0_plan_inspect(arr, len(shapes), prec, tile, nwg, byref(nu), byref(nj), buf,
+                                 nu.value, byref(lmax), byref(lmean)) == 0
+    units = np.frombuffer(buf, dtype=np.int32)[:10 * nu.value].reshape(-1, 10)
+    return units, nj.value, lmax.value, lmean.value
+
+
+def _check(shapes, prec, tile, nwg):
+    lib = pkg.load()
+    T = c_int32()
+    assert lib.chi0_tile_info(prec, tile, byref(T), None, None, None) == 0
+    T = T.value
+    units, njobs, lmax, lmean = _inspect(shapes, prec, tile, nwg)
+    # flat block offsets and cumulative pairs
+    flat0, cums = [], []
+    f = 0
+    for npb, nomega, blocks in shapes:
+        flat0.append(f)
+        f += len(blocks)
+        cums.append(np.concatenate([[0], np.cumsum([no * nu for no, nu in blocks])]).astype(np.int64))
+    expected_jobs = sum(nomega * ((npb + T - 1) // T) * ((npb + T - 1) // T + 1) // 2
+                        for npb, nomega, _ in shapes)
+    assert njobs == expected_jobs
+    assert np.array_equal(np.sort(units[:, 8]), np.arange(len(units)))     # slots unique
+    assert np.all((units[:, 9] >= 0) & (units[:, 9] < nwg))                 # one owner each
+    jobs = {}
+    for u in units:
+        p, iw, tp, tq, b0, p0, b1, p1, slot, w = (int(x) for x in u)
+        npb, nomega, blocks = shapes[p]
+        nt = (npb + T - 1) // T
+        assert 0 <= iw < nomega and 0 <= tq <= tp < nt
+        cum = cums[p]
+        if b1 < b0:                        # problem without blocks
+            g0 = g1 = 0
+        else:
+            lb0, lb1 = b0 - flat0[p], b1 - flat0[p]
+            assert 0 <= lb0 <= lb1 < len(blocks)
+            assert 0 <= p0 <= cum[lb0 + 1] - cum[lb0] and 0 <= p1 <= cum[lb1 + 1] - cum[lb1]
+            g0, g1 = cum[lb0] + p0, cum[lb1] + p1
+            assert g1 >= g0
+        jobs.setdefault((p, iw, tp, tq), []).append((slot, g0, g1))
+    assert len(jobs) == expected_jobs
+    for (p, iw, tp, tq), lst in jobs.items():
+        lst.sort()
+        slots = [s for s, _, _ in lst]
+        assert slots == list(range(slots[0], slots[0] + len(slots)))       # contiguous slots
+        pos = 0
+        for _, g0, g1 in lst:                                               # exact cover, in order
+            assert g0 == pos
+            pos = g1
+        assert pos == cums[p][-1]
+    return lmax, lmean
+
+
+def _shapes_of(wl, nq=None):
+    out = []
+    for q in range(nq or wl.nq):
+        out.append((wl.npb, wl.nomega, [(b.nocc, b.nunocc) for b in wl.blocks(q)]))
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("nwg", [1, 7, 256])
+def test_cover_small_and_edge_shapes(prec, nwg):
+    lib = pkg.load()
+    shapes = [
+        (1, 1, [(1, 1)]),
+        (129, 3, [(0, 5), (3, 0), (7, 11), (0, 0), (2, 300)]),   # empty blocks inside
+        (64, 2, []),                                             # no blocks
+        (300, 1, [(0, 0)]),                                      # blocks but no pairs
+        (200, 4, [(40, 300)] * 3),
+    ]
+    for tile in range(lib.chi0_tile_count(prec)):
+        _check(shapes, prec, tile, nwg)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+def test_cover_workloads_and_balance(cfg):
+    wl = workload(cfg)
+    shapes = _shapes_of(wl)
+    prec = {0: 0, 1: 1, 2: 2, 3: 1, 4: 2}[cfg]
+    lmax, lmean = _check(shapes, prec, 0, 256)
+    if cfg in (2, 3, 4):          # enough work for 256 persistent workgroups
+        assert lmax / lmean < 1.1, (lmax, lmean)
+
+
+def test_inspect_rejects_bad_input():
+    lib = pkg.load()
+    arr, keep = _problems([(0, 1, [])])
+    assert lib.chi0_plan_inspect(arr, 1, 0, 0, 4, None, None, None, 0, None, None) == L.CHI0_EINVAL
+    arr, keep = _problems([(8, 1, [(1, 1)])])
+    assert lib.chi0_plan_inspect(arr, 1, 0, 99, 4, None, None, None, 0, None, None) == L.CHI0_EINVAL
+    assert lib.chi0_plan_inspect(arr, 1, 0, 0, 0, None, None, None, 0, None, None) == L.CHI0_EINVAL
+    nu = c_int32()
+    assert lib.chi0_plan_inspect(arr, 1, 0, 0, 4, byref(nu), None, None, 0, None, None) == 0
+    buf = (c_int32 * 10)()
+    if nu.value > 1:
+        assert lib.chi0_plan_inspect(arr, 1, 0, 0, 4, None, None, buf, 1, None, None) == L.CHI0_EINVAL
