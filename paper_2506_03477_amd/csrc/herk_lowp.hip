@@ -104,6 +104,9 @@ __device__ __forceinline__ float bf16_hi_to_f32(uint32_t p) { return __uint_as_f
 
 // (x_re, x_im) -> packed hi and lo bf16x2 words (re in the low half).
 __device__ __forceinline__ void split2(float re, float im, uint32_t& hi, uint32_t& lo) {
+  // no contraction: re, im are the FP32-rounded operands (for the scaled
+  // side, the rounded product), and x - hi is exact in FP32
+#pragma clang fp contract(off)
   hi = pack_bf16x2(re, im);
   lo = pack_bf16x2(re - bf16_lo_to_f32(hi), im - bf16_hi_to_f32(hi));
 }
@@ -321,6 +324,205 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
   }
 }
 
+// Software-pipelined BF16x3 kernel (T = 128).  Stage s (16 pairs):
+//   1. issue the global loads (and weights) of stage s + 2 into register set
+//      s % 2 (freed when stage s was staged into LDS one stage earlier);
+//   2. the MFMAs of stage s (LDS buffer s % 2) and the staging of stage s + 1
+//      (register set (s + 1) % 2 -> LDS buffer (s + 1) % 2) in one basic
+//      block, so the split / scale VALU work overlaps the matrix cores;
+//   3. one barrier.
+// The stage loop is unrolled by two so every buffer index is a constant.
+template <bool LOLO>
+__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
+  constexpr int T = 128, NB = 2, LG = 2, GPT = 2;
+  __shared__ __attribute__((aligned(16))) uint32_t sAh[2][T * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sAl[2][T * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sBh[2][T * 16];
+  __shared__ __attribute__((aligned(16))) uint32_t sBl[2][T * 16];
+  __shared__ float sWgt[2][kKC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g8 = lane >> 5;
+  const int l32 = lane & 31;
+  const int lc = tid & (T - 1);
+  const int lg = tid / T;
+
+  const int beg = a.wg_offsets[blockIdx.x];
+  const int end = a.wg_offsets[blockIdx.x + 1];
+  for (int ui = beg; ui < end; ++ui) {
+    const Unit u = a.units[a.wg_units[ui]];
+    const ProbDesc pd = a.probs[u.prob];
+    const int npb = pd.npb;
+    const double om = pd.omega[u.iw];
+    const double w2 = om * om;
+    const int flush_pairs = pd.flush > 2 * kKC ? pd.flush / (2 * kKC) : 1;  // stage pairs per run
+    const bool okP = u.tp * T + lc < npb;
+    const bool okQ = u.tq * T + lc < npb;
+    double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
+
+    f32x16 cr[NB][NB], ci[NB][NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        cr[i][j] = f32x16{0};
+        ci[i][j] = f32x16{0};
+      }
+    float2 ra0[GPT][4], rb0[GPT][4], ra1[GPT][4], rb1[GPT][4];
+
+    auto load_stage = [&](const Cursor& c, float2 (&ra)[GPT][4], float2 (&rb)[GPT][4], int wbuf) {
+      const BlockDesc bd = a.blocks[c.b];
+      if (tid < kKC) sWgt[wbuf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
+      const gf2ptr z = (gf2ptr)(bd.z);
+#pragma unroll
+      for (int gi = 0; gi < GPT; ++gi)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int p = c.p0 + 4 * (lg + LG * gi) + e;
+          float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
+          if (p < c.pend) {
+            const gf2ptr row = z + static_cast<size_t>(p) * npb;
+            if (okP) va = ld_c64(row + u.tp * T + lc);
+            if (okQ) vb = ld_c64(row + u.tq * T + lc);
+          }
+          ra[gi][e] = va;
+          rb[gi][e] = vb;
+        }
+    };
+    auto stage_lds = [&](const float2 (&ra)[GPT][4], const float2 (&rb)[GPT][4], int buf) {
+#pragma unroll
+      for (int gi = 0; gi < GPT; ++gi) {
+        const int q = lg + LG * gi;
+        uint32_t ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          split2(ra[gi][e].x, ra[gi][e].y, ah[e], al[e]);
+          const float w = sWgt[buf][4 * q + e];
+          split2(rb[gi][e].x * w, rb[gi][e].y * w, bh[e], bl[e]);
+        }
+        const int o = swz(lc, q);
+        *reinterpret_cast<uint4*>(&sAh[buf][o]) = uint4{ah[0], ah[1], ah[2], ah[3]};
+        *reinterpret_cast<uint4*>(&sAl[buf][o]) = uint4{al[0], al[1], al[2], al[3]};
+        *reinterpret_cast<uint4*>(&sBh[buf][o]) = uint4{bh[0], bh[1], bh[2], bh[3]};
+        *reinterpret_cast<uint4*>(&sBl[buf][o]) = uint4{bl[0], bl[1], bl[2], bl[3]};
+      }
+    };
+    auto mfma_stage = [&](int buf) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const int q = 2 * ks + g8;
+        bf16x8 fah[NB], fal[NB], fbh[NB], fbl[NB], fih[NB], fil[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int row = wr * (T / 2) + i * 32 + l32;
+          fah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&sAh[buf][swz(row, q)]));
+          fal[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&sAl[buf][swz(row, q)]));
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int row = wc * (T / 2) + j * 32 + l32;
+          const uint4 bh = *reinterpret_cast<const uint4*>(&sBh[buf][swz(row, q)]);
+          const uint4 bl = *reinterpret_cast<const uint4*>(&sBl[buf][swz(row, q)]);
+          fbh[j] = as_bf16x8(bh);
+          fbl[j] = as_bf16x8(bl);
+          fih[j] = as_bf16x8(rot_neg4(bh));
+          fil[j] = as_bf16x8(rot_neg4(bl));
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbh[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fih[j], ci[i][j], 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbl[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fil[j], ci[i][j], 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbh[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fih[j], ci[i][j], 0, 0, 0);
+          }
+        if (LOLO) {
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbl[j], cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fil[j], ci[i][j], 0, 0, 0);
+            }
+        }
+      }
+    };
+
+    // Interleave hint for the MFMA + staging block: each MFMA is followed by
+    // a few VALU instructions of the staging (split / scale / rotate), so the
+    // vector ALU works while the matrix core is busy.
+    auto interleave = [&]() {
+#pragma unroll
+      for (int k = 0; k < (LOLO ? 64 : 48); ++k) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // 1 MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);   // 5 VALU
+      }
+    };
+
+    // pipeline state: stages s (in LDS), s + 1 (in registers), s + 2 (next load)
+    Cursor c_s, c_1, c_2;
+    bool h_s = cursor_first(u, a.blocks, c_s);
+    c_1 = c_s;
+    bool h_1 = h_s && cursor_next(u, a.blocks, c_1);
+    __syncthreads();  // previous unit's last MFMAs are done with the LDS
+    if (h_s) load_stage(c_s, ra0, rb0, 0);
+    if (h_1) load_stage(c_1, ra1, rb1, 1);
+    __syncthreads();  // weights of stages 0 and 1 visible
+    if (h_s) stage_lds(ra0, rb0, 0);
+    __syncthreads();
+    bool first_flush = true;
+    while (h_s) {
+      for (int np = 0; np < flush_pairs && h_s; ++np) {
+        // ---- even stage: LDS 0, registers set 1 -> LDS 1, loads -> set 0
+        c_2 = c_1;
+        bool h_2 = h_1 && cursor_next(u, a.blocks, c_2);
+        if (h_2) load_stage(c_2, ra0, rb0, 0);
+        mfma_stage(0);
+        stage_lds(ra1, rb1, 1);   // stale data when !h_1: never read
+        interleave();
+        __syncthreads();
+        c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
+        if (!h_s) break;
+        // ---- odd stage: LDS 1, registers set 0 -> LDS 0, loads -> set 1
+        c_2 = c_1;
+        h_2 = h_1 && cursor_next(u, a.blocks, c_2);
+        if (h_2) load_stage(c_2, ra1, rb1, 1);
+        mfma_stage(1);
+        stage_lds(ra0, rb0, 0);
+        interleave();
+        __syncthreads();
+        c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
+      }
+      flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
+      first_flush = false;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          cr[i][j] = f32x16{0};
+          ci[i][j] = f32x16{0};
+        }
+    }
+    if (first_flush) flush_tile<T, NB>(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
+  }
+}
+
 // FP32 path: v_mfma_f32_32x32x2f32, contraction slots (re, im) of one pair.
 // LDS holds the operands as complex64, rows = tile columns, 16 pairs per row
 // (8 chunks of 2 pairs, XOR-swizzled).
@@ -466,9 +668,10 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
 // Tile tables: {tile, pairs per stage, cap of the FP32 run length (pairs),
 // threads}.  BF16X3 with CHI0_BF16_LOLO selects the variant adding lo*lo.
 static const TileConfig kBf16Tiles[] = {
-    {128, kKC, 4096, kNT},
+    {128, kKC, 4096, kNT},   // software-pipelined kernel
+    {128, kKC, 4096, kNT},   // staging and MFMAs in sequence
     {64, kKC, 4096, kNT},
-    {128, kKC, 1024, kNT},
+    {128, kKC, 1024, kNT},   // pipelined, shorter FP32 runs
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT},
@@ -480,7 +683,13 @@ TileConfig herk_bf16x3_tile(int idx) { return kBf16Tiles[idx]; }
 hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
   if (idx < 0 || idx >= herk_bf16x3_tile_count()) return hipErrorInvalidValue;
   const bool lolo = (a.flags & 2) != 0;
-  if (kBf16Tiles[idx].tile == 128) {
+  const bool pipe = idx == 0 || idx == 3;
+  if (pipe) {
+    if (lolo)
+      hipLaunchKernelGGL(herk_bf16x3_pipe_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
+    else
+      hipLaunchKernelGGL(herk_bf16x3_pipe_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
+  } else if (kBf16Tiles[idx].tile == 128) {
     if (lolo)
       hipLaunchKernelGGL((herk_bf16x3_kernel<128, true>), dim3(nwg), dim3(kNT), 0, s, a);
     else
@@ -495,9 +704,13 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
 }
 int herk_bf16x3_max_wg_per_cu(int idx) {
   int n = 0;
-  hipError_t e = kBf16Tiles[idx].tile == 128
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false>, kNT, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<64, false>, kNT, 0);
+  hipError_t e;
+  if (idx == 0 || idx == 3)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_pipe_kernel<false>, kNT, 0);
+  else if (kBf16Tiles[idx].tile == 128)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false>, kNT, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<64, false>, kNT, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
