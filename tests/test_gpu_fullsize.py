@@ -16,32 +16,28 @@ from synth import workload
 
 pytestmark = pytest.mark.gpu
 
-# entries: diagonal, tile corners and ragged boundaries, far off-diagonal
-ENTRIES = [(0, 0), (1, 0), (127, 127), (128, 127), (128, 128), (255, 1), (1000, 999),
-           (1024, 0), (2047, 2047), (2047, 0), (1500, 700), (64, 63), (513, 511), (2046, 129)]
+# entries: diagonal, tile corners and ragged boundaries, far off-diagonal;
+# the diagonal entries of every index involved are sampled too (they set the
+# natural scale of each entry).
+PAIRS = [(1, 0), (128, 127), (255, 1), (1000, 999), (1024, 0), (2047, 0), (1500, 700), (64, 63),
+         (513, 511), (2046, 129), (2047, 2046)]
+INDICES = sorted({i for e in PAIRS for i in e} | {0, 127, 128, 2047})
+ENTRIES = [(i, i) for i in INDICES] + PAIRS
+def _normalized_errors(got, ent):
+    """|got_IJ - ref_IJ| / (sqrt(|ref_II ref_JJ|) + 1e-20 |ref_00|), per frequency.
 
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
-
-
-def _oracle_entries(wl):
-    cols = sorted({i for e in ENTRIES for i in e})
-    col_index = {c: k for k, c in enumerate(cols)}
-
-    def gen():
-        for blk in wl.blocks(0):
-            eo, eu = wl.energies(blk)
-            yield wl.z_elements(blk, np.arange(blk.npairs), np.array(cols)), eo, eu, blk.wk
-    return oracle.chi0_entries(gen(), ENTRIES, col_index, wl.omega, wl.delta_min)
-
-
-def _normalized_errors(chi, ref_entries, ref_diag):
+    The scale of an entry is the geometric mean of its diagonal entries (a
+    positive semidefinite sum bounds |S_IJ| by it).  With Z decaying as
+    exp(-I/32), entries with I + J above ~2800 are below the FP32 range and
+    the reduced-precision paths return 0 for them; the absolute floor
+    1e-20 |chi0_00| (far below anything that moves the relative Frobenius
+    error) keeps such entries from dominating the check."""
+    pos = {e: k for k, e in enumerate(ENTRIES)}
+    d00 = np.abs(ent[:, pos[(0, 0)]])
     errs = []
     for k, (i, j) in enumerate(ENTRIES):
-        scale = np.sqrt(np.abs(ref_diag[:, i]) * np.abs(ref_diag[:, j]))
-        errs.append(np.abs(chi[:, i, j] - ref_entries[:, k]) / scale)
+        scale = np.sqrt(np.abs(ent[:, pos[(i, i)]]) * np.abs(ent[:, pos[(j, j)]])) + 1e-20 * d00
+        errs.append(np.abs(got[:, k] - ent[:, k]) / scale)
     return np.array(errs)
 
 
@@ -67,14 +63,7 @@ def test_fullsize_sampled_entries(ref, path, tol):
     idx_i = torch.tensor([i for i, _ in ENTRIES], device=chi.device)
     idx_j = torch.tensor([j for _, j in ENTRIES], device=chi.device)
     got = chi[:, idx_i, idx_j].cpu().numpy()                   # [nomega, nentries]
-    diag = torch.diagonal(chi, dim1=1, dim2=2).cpu().numpy()
-    ref_diag = {i: ent[:, k] for k, (i, j) in enumerate(ENTRIES) if i == j}
-    errs = []
-    for k, (i, j) in enumerate(ENTRIES):
-        di = ref_diag.get(i, diag[:, i])
-        dj = ref_diag.get(j, diag[:, j])
-        errs.append(np.abs(got[:, k] - ent[:, k]) / np.sqrt(np.abs(di) * np.abs(dj)))
-    errs = np.array(errs)
+    errs = _normalized_errors(got, ent)
     _say(f"  max normalized entry error {errs.max():.3e} (tol {tol})")
     assert errs.max() <= tol, errs
     if path == "bf16x3":
