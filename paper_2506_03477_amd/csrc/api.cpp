@@ -100,6 +100,7 @@ struct chi0_ctx {
   int device = 0;
   int ncu = 0;
   DevBuf partials;
+  DevBuf wts;           // pair weights of the current call
   DevBuf gj_work, gj_wrow, gj_piv, gj_perm;
   uint64_t ws_gen = 1;
   int32_t* d_status = nullptr;
@@ -470,18 +471,37 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   const int T = pl->tc.tile;
   int rc = h->partials.reserve(static_cast<size_t>(pl->nunits) * T * T * sizeof(double2), &h->ws_gen);
   if (rc) return rc;
+  const int nblocks_total = pl->nblocks_total;
+
+  // pair weights: [nomega][ktot] per problem, float (FP64 path: double)
+  const size_t wsize = kind == HERK_FP64 ? sizeof(double) : sizeof(float);
+  size_t wbytes = 0;
+  int kmax = 0;
+  for (int p = 0; p < nprob; ++p) {
+    int64_t kt = 0;
+    for (int b = 0; b < probs[p].nblocks; ++b) {
+      const int64_t k = static_cast<int64_t>(probs[p].blocks[b].nocc) * probs[p].blocks[b].nunocc;
+      kt += k;
+      kmax = std::max<int>(kmax, static_cast<int>(k));
+    }
+    wbytes += ((static_cast<size_t>(kt) * probs[p].nomega * wsize + 255) / 256) * 256;
+  }
+  if ((rc = h->wts.reserve(std::max<size_t>(wbytes, 256), &h->ws_gen))) return rc;
 
   // per-call tables (pointers change between calls) via pinned staging
   std::vector<BlockDesc> bt;
   bt.reserve(pl->nblocks_total);
   std::vector<ProbDesc> ptab(nprob);
+  size_t woff = 0;
   for (int p = 0; p < nprob; ++p) {
     ptab[p].chi0 = static_cast<double2*>(probs[p].chi0);
     ptab[p].omega = probs[p].omega;
+    ptab[p].wts = static_cast<char*>(h->wts.p) + woff;
     ptab[p].npb = probs[p].npb;
     ptab[p].nomega = probs[p].nomega;
     ptab[p].flush = flush_length(h, pl->tc, probs[p]);
     ptab[p].pad = 0;
+    int64_t base = 0;
     for (int b = 0; b < probs[p].nblocks; ++b) {
       const chi0_block& bl = probs[p].blocks[b];
       BlockDesc d;
@@ -491,8 +511,14 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
       d.wk = bl.wk;
       d.nocc = bl.nocc;
       d.nunocc = bl.nunocc;
+      d.pair_base = base;
+      d.prob = p;
+      d.pad = 0;
+      base += static_cast<int64_t>(bl.nocc) * bl.nunocc;
       bt.push_back(d);
     }
+    ptab[p].ktot = base;
+    woff += ((static_cast<size_t>(base) * probs[p].nomega * wsize + 255) / 256) * 256;
   }
   const size_t bt_bytes = bt.size() * sizeof(BlockDesc);
   const size_t pt_bytes = ptab.size() * sizeof(ProbDesc);
@@ -546,6 +572,8 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
       HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess)
+        e = pair_weights_launch(ha.blocks, ha.probs, nblocks_total, kmax, delta_min, kind == HERK_FP64, cs);
       if (e == hipSuccess) e = herk_launch(kind, pl->tile_idx, ha, pl->nwg, cs);
       if (e == hipSuccess) e = reduce_launch(ra, pl->njobs, cs);
       hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -566,6 +594,9 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
     return CHI0_OK;
   }
 
+  hipError_t ew = pair_weights_launch(ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
+                                      kind == HERK_FP64, stream);
+  if (ew != hipSuccess) return fail(CHI0_EDEVICE, "pair-weight launch: %s", hipGetErrorString(ew));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->profiling) {
     e0 = get_event(h);
@@ -633,6 +664,7 @@ int chi0_destroy(chi0_handle h) {
   hipDeviceSynchronize();
   h->plans.clear();
   h->partials.release();
+  h->wts.release();
   h->gj_work.release();
   h->gj_wrow.release();
   h->gj_piv.release();

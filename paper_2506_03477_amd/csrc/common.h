@@ -14,12 +14,17 @@ struct BlockDesc {
   double wk;
   int32_t nocc;
   int32_t nunocc;
+  int64_t pair_base;        // first pair of this block in its problem's pair list
+  int32_t prob;             // problem index
+  int32_t pad;
 };
 
 // One q-point (device table entry).
 struct ProbDesc {
   double2* chi0;            // [nomega][npb][npb] complex128 output
   const double* omega;      // [nomega]
+  void* wts;                // [nomega][ktot] pair weights (float, or double for FP64)
+  int64_t ktot;             // pairs of the problem (all blocks)
   int32_t npb;
   int32_t nomega;
   int32_t flush;            // FP32 run length in pairs (reduced-precision paths)
@@ -87,6 +92,8 @@ struct TileConfig {
 };
 
 // Host launchers (defined next to their kernels).
+hipError_t pair_weights_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
+                               int kmax, double delta_min, bool f64, hipStream_t s);
 int herk_tile_count(int kind);
 TileConfig herk_tile_config(int kind, int idx);
 int herk_max_wg_per_cu(int kind, int idx);

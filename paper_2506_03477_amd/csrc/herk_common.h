@@ -21,6 +21,62 @@ __device__ __forceinline__ double pair_weight(const BlockDesc& bd, int p, int K,
   return bd.wk * 2.0 * d / (d * d + w2);
 }
 
+// Read-only tables are read through the constant address space: they do not
+// change during a launch, so uniform reads become scalar loads that do not
+// wait behind the vector memory traffic.
+template <class X>
+__device__ __forceinline__ X ld_const(const X* p, int i) {
+  return ((const X __attribute__((address_space(4)))*)(p))[i];
+}
+
+__device__ __forceinline__ int block_pairs(const BlockDesc* blocks, int b) {
+  const BlockDesc* bp = blocks + b;
+  const int* f = reinterpret_cast<const int*>(&bp->nocc);
+  return ld_const(f, 0) * ld_const(f, 1);
+}
+
+// Pair cursor over a unit's range: block b, stage start p0, end of the
+// block's part of the range pend.  Uniform across the workgroup.
+struct Cursor {
+  int b;
+  int p0;
+  int pend;
+};
+
+__device__ __forceinline__ bool cursor_first(const Unit& u, const BlockDesc* blocks, Cursor& c) {
+  for (int b = u.b0; b <= u.b1; ++b) {
+    const int beg = (b == u.b0) ? u.p0 : 0;
+    const int end = (b == u.b1) ? u.p1 : block_pairs(blocks, b);
+    if (beg < end) {
+      c.b = b;
+      c.p0 = beg;
+      c.pend = end;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Advances c by one stage of KC pairs; returns false (leaving c on the last
+// stage) when the unit has no further stage.
+template <int KC>
+__device__ __forceinline__ bool cursor_next(const Unit& u, const BlockDesc* blocks, Cursor& c) {
+  if (c.p0 + KC < c.pend) {
+    c.p0 += KC;
+    return true;
+  }
+  for (int b = c.b + 1; b <= u.b1; ++b) {
+    const int end = (b == u.b1) ? u.p1 : block_pairs(blocks, b);
+    if (0 < end) {
+      c.b = b;
+      c.p0 = 0;
+      c.pend = end;
+      return true;
+    }
+  }
+  return false;
+}
+
 // Host-side dispatch tables of the three precision paths.
 int herk_fp64_tile_count();
 TileConfig herk_fp64_tile(int idx);

@@ -129,53 +129,48 @@ __global__ __launch_bounds__(256) void herk_fp64_kernel(HerkArgs a) {
 
 // Pipelined variant: 128 x 128 complex tiles, 4 waves of 64 x 64 (one
 // workgroup per CU, up to 512 registers per lane), 8 pairs per stage in
-// double-buffered LDS, next stage's global loads and weights issued before the
-// current stage's MFMAs, one barrier per stage.
-struct Cursor64 {
-  int b;
-  int p0;
-  int pend;
-};
+// double-buffered LDS, next stage's Z and (precomputed) weight loads issued
+// unconditionally before the current stage's MFMAs, one barrier per stage.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef const dvec2 __attribute__((address_space(1)))* gd2ptr;
+typedef const double __attribute__((address_space(1)))* gdptr;
 
-template <int KC>
-__device__ __forceinline__ bool cur_first(const Unit& u, const BlockDesc* blocks, Cursor64& c) {
-  for (int b = u.b0; b <= u.b1; ++b) {
-    const int beg = (b == u.b0) ? u.p0 : 0;
-    const int end = (b == u.b1) ? u.p1 : blocks[b].nocc * blocks[b].nunocc;
-    if (beg < end) {
-      c.b = b;
-      c.p0 = beg;
-      c.pend = end;
-      return true;
-    }
+// Operand and weight loads of one stage for one thread (pairs p0 + poff[k],
+// tile columns cP / cQ), issued unconditionally with clamped addresses; bit k
+// of the returned mask says whether pair k exists.
+template <int NP>
+__device__ __forceinline__ uint32_t load_pairs64(const HerkArgs& a, const ProbDesc& pd, int iw,
+                                                 const Cursor& c, const int (&poff)[NP], int npb,
+                                                 int cP, int cQ, double2 (&ra)[NP],
+                                                 double2 (&rb)[NP], double (&rw)[NP]) {
+  const int b = __builtin_amdgcn_readfirstlane(c.b);
+  const BlockDesc* bp = a.blocks + b;
+  const gd2ptr z = (gd2ptr)(ld_const(&bp->z, 0));
+  const int64_t pbase = ld_const(&bp->pair_base, 0);
+  const gdptr w = (gdptr)(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int p = c.p0 + poff[k];
+    const bool valid = p < c.pend;
+    const int pc = valid ? p : c.pend - 1;
+    mask |= valid ? (1u << k) : 0u;
+    const gd2ptr row = z + static_cast<size_t>(pc) * npb;
+    const dvec2 va = row[cP];
+    const dvec2 vb = row[cQ];
+    ra[k] = double2{va.x, va.y};
+    rb[k] = double2{vb.x, vb.y};
+    rw[k] = w[pc];
   }
-  return false;
-}
-
-template <int KC>
-__device__ __forceinline__ bool cur_next(const Unit& u, const BlockDesc* blocks, Cursor64& c) {
-  if (c.p0 + KC < c.pend) {
-    c.p0 += KC;
-    return true;
-  }
-  for (int b = c.b + 1; b <= u.b1; ++b) {
-    const int end = (b == u.b1) ? u.p1 : blocks[b].nocc * blocks[b].nunocc;
-    if (0 < end) {
-      c.b = b;
-      c.p0 = 0;
-      c.pend = end;
-      return true;
-    }
-  }
-  return false;
+  return mask;
 }
 
 __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
   constexpr int T = 128, KC = 8, NT = 256;
   constexpr int NB = 4;  // 16x16 blocks per wave side (64 / 16)
+  constexpr int NP = 4;  // pairs per thread per stage
   __shared__ double2 sA[2][KC][T];
   __shared__ double2 sB[2][KC][T];
-  __shared__ double sW[2][KC];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -187,6 +182,9 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
   const bool isim = (kk & 1) != 0;
   const int lc = tid & (T - 1);   // loader: tile column
   const int lg = tid >> 7;        // loader: pairs lg, lg + 2, lg + 4, lg + 6
+  int poff[NP];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) poff[e] = lg + 2 * e;
 
   const int beg = a.wg_offsets[blockIdx.x];
   const int end = a.wg_offsets[blockIdx.x + 1];
@@ -194,10 +192,9 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
     const Unit u = a.units[a.wg_units[ui]];
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
-    const double om = pd.omega[u.iw];
-    const double w2 = om * om;
     const bool okP = u.tp * T + lc < npb;
     const bool okQ = u.tq * T + lc < npb;
+    const int cP = okP ? u.tp * T + lc : 0, cQ = okQ ? u.tq * T + lc : 0;
 
     f64x4 accR[NB][NB], accI[NB][NB];
 #pragma unroll
@@ -207,41 +204,26 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
         accR[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
         accI[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
       }
-    double2 ra[4], rb[4];
-    Cursor64 cur;
-    bool have = cur_first<KC>(u, a.blocks, cur);
+    double2 ra[NP], rb[NP];
+    double rw[NP];
+    uint32_t mk = 0;
+    Cursor cur;
+    bool have = cursor_first(u, a.blocks, cur);
     __syncthreads();
-    auto load_stage = [&](const Cursor64& c, int buf) {
-      const BlockDesc bd = a.blocks[c.b];
-      if (tid < KC) sW[buf][tid] = pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min);
-      const double2* z = static_cast<const double2*>(bd.z);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int p = c.p0 + lg + 2 * e;
-        double2 va = double2{0.0, 0.0}, vb = double2{0.0, 0.0};
-        if (p < c.pend) {
-          const double2* row = z + static_cast<size_t>(p) * npb;
-          if (okP) va = row[u.tp * T + lc];
-          if (okQ) vb = row[u.tq * T + lc];
-        }
-        ra[e] = va;
-        rb[e] = vb;
-      }
-    };
+    if (have) mk = load_pairs64<NP>(a, pd, u.iw, cur, poff, npb, cP, cQ, ra, rb, rw);
     int buf = 0;
-    if (have) load_stage(cur, 0);
-    __syncthreads();
     while (have) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < NP; ++e) {
         const int r = lg + 2 * e;
-        const double w = sW[buf][r];
-        sA[buf][r][lc] = ra[e];
+        const bool v = (mk >> e) & 1u;
+        const double w = (v && okQ) ? rw[e] : 0.0;
+        sA[buf][r][lc] = (v && okP) ? ra[e] : double2{0.0, 0.0};
         sB[buf][r][lc] = double2{rb[e].x * w, rb[e].y * w};
       }
-      Cursor64 nxt = cur;
-      const bool more = cur_next<KC>(u, a.blocks, nxt);
-      if (more) load_stage(nxt, buf ^ 1);
+      Cursor nxt = cur;
+      const bool more = cursor_next<KC>(u, a.blocks, nxt);
+      mk = load_pairs64<NP>(a, pd, u.iw, nxt, poff, npb, cP, cQ, ra, rb, rw);
       __syncthreads();
 #pragma unroll
       for (int st = 0; st < KC / 2; ++st) {

@@ -4,7 +4,8 @@
 // Per unit (problem, frequency, lower tile (tp, tq), pair range) the kernels
 // accumulate S[P][Q] = sum_pairs conj(Z[pair][P]) * (c * Z[pair][Q]),
 // c = w_k 2 D / (D^2 + omega^2) (chi0 = -S, Eq.(polfx) at i*omega).
-// The pair weight scales the Q-side operand only, in FP32.
+// The pair weight (precomputed per pair and frequency) scales the Q-side
+// operand only, in FP32.
 //
 // BF16x3: every FP32 operand x is split into bf16 hi = rn(x) and
 // lo = rn(x - hi) (x - hi is exact in FP32); the product a * b is taken as
@@ -18,10 +19,11 @@
 // FP32: v_mfma_f32_32x32x2f32 with the (re, im) of one pair as the two
 // contraction slots.
 //
-// Both kernels: T x T complex tiles (T = 128 or 64), 4 waves of T/2 x T/2, operands staged
-// once per workgroup into double-buffered, XOR-swizzled LDS (the split / the
-// scaling happens while staging), one barrier per 16-pair stage, next
-// stage's global loads issued before the current stage's MFMAs.  Each
+// All kernels: T x T complex tiles (T = 128 or 64), 4 waves of T/2 x T/2,
+// operands staged once per workgroup into double-buffered, XOR-swizzled LDS
+// (the split / the scaling happens while staging), one barrier per 16-pair
+// stage, later stages' global loads (Z and the precomputed pair weights)
+// issued before the current stage's MFMAs.  Each
 // workgroup adds its FP32 accumulators into its FP64 partial tile in global
 // memory every `flush` pairs (per problem) and at the end of the unit, so no FP32 sum runs
 // over more than `flush` pairs.
@@ -37,53 +39,49 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kKC = 16;   // pairs per stage
 
+constexpr int kNT = 256;  // threads
+
 // Z is read through a global-address-space pointer (global_load rather than
 // flat_load); one complex64 = one 64-bit word.
 typedef const uint64_t __attribute__((address_space(1)))* gf2ptr;
+
+typedef const float __attribute__((address_space(1)))* gfptr;
 
 __device__ __forceinline__ float2 ld_c64(gf2ptr p) {
   const uint64_t v = *p;
   return float2{__uint_as_float(static_cast<uint32_t>(v)), __uint_as_float(static_cast<uint32_t>(v >> 32))};
 }
-constexpr int kNT = 256;  // threads
 
-// Pair cursor over a unit's range: block b, stage start p0, end of the
-// block's part of the range pend.
-struct Cursor {
-  int b;
-  int p0;
-  int pend;
-};
-
-__device__ __forceinline__ bool cursor_first(const Unit& u, const BlockDesc* blocks, Cursor& c) {
-  for (int b = u.b0; b <= u.b1; ++b) {
-    const int beg = (b == u.b0) ? u.p0 : 0;
-    const int end = (b == u.b1) ? u.p1 : blocks[b].nocc * blocks[b].nunocc;
-    if (beg < end) {
-      c.b = b;
-      c.p0 = beg;
-      c.pend = end;
-      return true;
-    }
+// Operand and weight loads of one stage for one thread: NP pairs
+// p0 + poff[k] of the current block, tile columns colP / colQ.  Every load is
+// issued unconditionally with its address clamped into the block and the
+// matrix; bit k of the returned mask says whether pair k exists, and the
+// consumer zeroes the other operands when it stages them.  The loads of a
+// stage thus form one straight-line group that is only waited for when the
+// stage is staged, one or two stages later.
+template <int NP>
+__device__ __forceinline__ uint32_t load_pairs(const HerkArgs& a, const ProbDesc& pd, int iw,
+                                               const Cursor& c, const int (&poff)[NP], int npb,
+                                               int cP, int cQ, float2 (&ra)[NP], float2 (&rb)[NP],
+                                               float (&rw)[NP]) {
+  const int b = __builtin_amdgcn_readfirstlane(c.b);
+  const BlockDesc* bp = a.blocks + b;
+  const gf2ptr z = (gf2ptr)(ld_const(&bp->z, 0));
+  const int64_t pbase = ld_const(&bp->pair_base, 0);
+  const gfptr w = (gfptr)(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int p = c.p0 + poff[k];
+    const bool valid = p < c.pend;
+    const int pc = valid ? p : c.pend - 1;
+    mask |= valid ? (1u << k) : 0u;
+    const gf2ptr row = z + static_cast<size_t>(pc) * npb;
+    ra[k] = ld_c64(row + cP);
+    rb[k] = ld_c64(row + cQ);
+    rw[k] = w[pc];
   }
-  return false;
-}
-
-__device__ __forceinline__ bool cursor_next(const Unit& u, const BlockDesc* blocks, Cursor& c) {
-  if (c.p0 + kKC < c.pend) {
-    c.p0 += kKC;
-    return true;
-  }
-  for (int b = c.b + 1; b <= u.b1; ++b) {
-    const int end = (b == u.b1) ? u.p1 : blocks[b].nocc * blocks[b].nunocc;
-    if (0 < end) {
-      c.b = b;
-      c.p0 = 0;
-      c.pend = end;
-      return true;
-    }
-  }
-  return false;
+  return mask;
 }
 
 // LDS row = tile column (0..T-1), 16 dwords = 4 chunks of 4 pairs; chunk q of
@@ -153,19 +151,127 @@ __device__ __forceinline__ void flush_tile(double2* __restrict__ part, const f32
       }
 }
 
-// BF16x3 kernel.  T = 128: waves of 64 x 64 (2 x 2 MFMA blocks); T = 64:
-// waves of 32 x 32.  The loader gives each thread one tile column and
-// T / 64 groups of 4 pairs.
+template <int NB>
+__device__ __forceinline__ void zero_acc(f32x16 (&cr)[NB][NB], f32x16 (&ci)[NB][NB]) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      cr[i][j] = f32x16{0};
+      ci[i][j] = f32x16{0};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3
+// ---------------------------------------------------------------------------
+
+// LDS of the BF16x3 kernels: bf16 hi / lo planes of both operands, two buffers.
+template <int T>
+struct Bf16Lds {
+  uint32_t ah[2][T * 16];
+  uint32_t al[2][T * 16];
+  uint32_t bh[2][T * 16];
+  uint32_t bl[2][T * 16];
+};
+
+// Stage one thread's 4 GPT pairs into LDS buffer `buf`: split the P side,
+// scale (by the pair weight) and split the Q side.  Thread owns tile column
+// lc and pair groups q = lg + LG gi (4 pairs each).
+template <int T, int GPT, int LG>
+__device__ __forceinline__ void bf16_stage(Bf16Lds<T>& L, int buf, int lc, int lg,
+                                           const float2 (&ra)[4 * GPT], const float2 (&rb)[4 * GPT],
+                                           const float (&rw)[4 * GPT], uint32_t mask, bool okP,
+                                           bool okQ) {
+#pragma unroll
+  for (int gi = 0; gi < GPT; ++gi) {
+    const int q = lg + LG * gi;
+    uint32_t ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * gi + e;
+      const bool v = (mask >> k) & 1u;
+      const float2 x = (v && okP) ? ra[k] : float2{0.f, 0.f};
+      const float wq = (v && okQ) ? rw[k] : 0.f;
+      split2(x.x, x.y, ah[e], al[e]);
+      split2(rb[k].x * wq, rb[k].y * wq, bh[e], bl[e]);
+    }
+    const int o = swz(lc, q);
+    *reinterpret_cast<uint4*>(&L.ah[buf][o]) = uint4{ah[0], ah[1], ah[2], ah[3]};
+    *reinterpret_cast<uint4*>(&L.al[buf][o]) = uint4{al[0], al[1], al[2], al[3]};
+    *reinterpret_cast<uint4*>(&L.bh[buf][o]) = uint4{bh[0], bh[1], bh[2], bh[3]};
+    *reinterpret_cast<uint4*>(&L.bl[buf][o]) = uint4{bl[0], bl[1], bl[2], bl[3]};
+  }
+}
+
+// The 2 k-steps (8 pairs each) of one stage from LDS buffer `buf`.  One
+// product kind at a time over the accumulators, so dependent MFMAs on the
+// same accumulator are 2 NB^2 instructions apart.
+template <int T, int NB, bool LOLO>
+__device__ __forceinline__ void bf16_mfma(const Bf16Lds<T>& L, int buf, int wr, int wc, int g8,
+                                          int l32, f32x16 (&cr)[NB][NB], f32x16 (&ci)[NB][NB]) {
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    const int q = 2 * ks + g8;
+    bf16x8 fah[NB], fal[NB], fbh[NB], fbl[NB], fih[NB], fil[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int row = wr * (T / 2) + i * 32 + l32;
+      fah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.ah[buf][swz(row, q)]));
+      fal[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.al[buf][swz(row, q)]));
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int row = wc * (T / 2) + j * 32 + l32;
+      const uint4 bh = *reinterpret_cast<const uint4*>(&L.bh[buf][swz(row, q)]);
+      const uint4 bl = *reinterpret_cast<const uint4*>(&L.bl[buf][swz(row, q)]);
+      fbh[j] = as_bf16x8(bh);
+      fbl[j] = as_bf16x8(bl);
+      fih[j] = as_bf16x8(rot_neg4(bh));   // (bi, -br) for the imaginary part
+      fil[j] = as_bf16x8(rot_neg4(bl));
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbh[j], cr[i][j], 0, 0, 0);
+        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fih[j], ci[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbl[j], cr[i][j], 0, 0, 0);
+        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fil[j], ci[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbh[j], cr[i][j], 0, 0, 0);
+        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fih[j], ci[i][j], 0, 0, 0);
+      }
+    if (LOLO) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbl[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fil[j], ci[i][j], 0, 0, 0);
+        }
+    }
+  }
+}
+
+// BF16x3 kernel, staging and MFMAs in sequence.  T = 128: waves of 64 x 64
+// (2 x 2 MFMA blocks); T = 64: waves of 32 x 32.
 template <int T, bool LOLO>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
   constexpr int NB = T / 64;          // 32x32 blocks per wave side
   constexpr int LG = kNT / T;         // loader groups
   constexpr int GPT = 4 / LG;         // pair groups (of 4) per thread
-  __shared__ __attribute__((aligned(16))) uint32_t sAh[2][T * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sAl[2][T * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sBh[2][T * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sBl[2][T * 16];
-  __shared__ float sWgt[2][kKC];
+  constexpr int NP = 4 * GPT;         // pairs per thread per stage
+  __shared__ __attribute__((aligned(16))) Bf16Lds<T> L;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -175,6 +281,11 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
   const int l32 = lane & 31;
   const int lc = tid & (T - 1);
   const int lg = tid / T;
+  int poff[NP];
+#pragma unroll
+  for (int gi = 0; gi < GPT; ++gi)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) poff[4 * gi + e] = 4 * (lg + LG * gi) + e;
 
   const int beg = a.wg_offsets[blockIdx.x];
   const int end = a.wg_offsets[blockIdx.x + 1];
@@ -182,164 +293,58 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
     const Unit u = a.units[a.wg_units[ui]];
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
-    const double om = pd.omega[u.iw];
-    const double w2 = om * om;
     const int flush_stages = pd.flush > kKC ? pd.flush / kKC : 1;
     const bool okP = u.tp * T + lc < npb;
     const bool okQ = u.tq * T + lc < npb;
     double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
 
     f32x16 cr[NB][NB], ci[NB][NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        cr[i][j] = f32x16{0};
-        ci[i][j] = f32x16{0};
-      }
-
-    float2 ra[GPT][4], rb[GPT][4];  // raw operands of the stage being loaded
+    zero_acc<NB>(cr, ci);
+    float2 ra[NP], rb[NP];
+    float rw[NP];
+    uint32_t mk = 0;
+    const int cP = okP ? u.tp * T + lc : 0, cQ = okQ ? u.tq * T + lc : 0;
     Cursor cur;
     bool have = cursor_first(u, a.blocks, cur);
     __syncthreads();  // previous unit's last MFMAs are done with the LDS
-    auto load_stage = [&](const Cursor& c, int buf) {
-      const BlockDesc bd = a.blocks[c.b];
-      if (tid < kKC) sWgt[buf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
-      const gf2ptr z = (gf2ptr)(bd.z);
-#pragma unroll
-      for (int gi = 0; gi < GPT; ++gi)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int p = c.p0 + 4 * (lg + LG * gi) + e;
-          float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
-          if (p < c.pend) {
-            const gf2ptr row = z + static_cast<size_t>(p) * npb;
-            if (okP) va = ld_c64(row + u.tp * T + lc);
-            if (okQ) vb = ld_c64(row + u.tq * T + lc);
-          }
-          ra[gi][e] = va;
-          rb[gi][e] = vb;
-        }
-    };
+    if (have) mk = load_pairs<NP>(a, pd, u.iw, cur, poff, npb, cP, cQ, ra, rb, rw);
     int buf = 0;
-    if (have) load_stage(cur, 0);
-    __syncthreads();  // weights of stage 0 visible
-    // Outer loop: one FP32 run of at most flush_stages stages, then the flush
-    // into FP64.  The inner stage loop carries no flush code, so the
-    // accumulators stay in place across it.
     bool first_flush = true;
     while (have) {
-    for (int ns = 0; ns < flush_stages && have; ++ns) {
-      // stage this stage's operands into LDS buffer `buf`: split the P side,
-      // scale and split the Q side
-#pragma unroll
-      for (int gi = 0; gi < GPT; ++gi) {
-        const int q = lg + LG * gi;
-        uint32_t ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          split2(ra[gi][e].x, ra[gi][e].y, ah[e], al[e]);
-          const float w = sWgt[buf][4 * q + e];
-          split2(rb[gi][e].x * w, rb[gi][e].y * w, bh[e], bl[e]);
-        }
-        const int o = swz(lc, q);
-        *reinterpret_cast<uint4*>(&sAh[buf][o]) = uint4{ah[0], ah[1], ah[2], ah[3]};
-        *reinterpret_cast<uint4*>(&sAl[buf][o]) = uint4{al[0], al[1], al[2], al[3]};
-        *reinterpret_cast<uint4*>(&sBh[buf][o]) = uint4{bh[0], bh[1], bh[2], bh[3]};
-        *reinterpret_cast<uint4*>(&sBl[buf][o]) = uint4{bl[0], bl[1], bl[2], bl[3]};
+      for (int ns = 0; ns < flush_stages && have; ++ns) {
+        bf16_stage<T, GPT, LG>(L, buf, lc, lg, ra, rb, rw, mk, okP, okQ);
+        // next stage's loads in flight during this stage's MFMAs (the cursor
+        // stays on a valid stage when there is no next one)
+        Cursor nxt = cur;
+        const bool more = cursor_next<kKC>(u, a.blocks, nxt);
+        mk = load_pairs<NP>(a, pd, u.iw, nxt, poff, npb, cP, cQ, ra, rb, rw);
+        __syncthreads();
+        bf16_mfma<T, NB, LOLO>(L, buf, wr, wc, g8, l32, cr, ci);
+        cur = nxt;
+        have = more;
+        buf ^= 1;
       }
-      // next stage's loads (and weights) in flight during this stage's MFMAs
-      Cursor nxt = cur;
-      const bool more = cursor_next(u, a.blocks, nxt);
-      if (more) load_stage(nxt, buf ^ 1);
-      __syncthreads();
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const int q = 2 * ks + g8;
-        bf16x8 fah[NB], fal[NB], fbh[NB], fbl[NB], fih[NB], fil[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          const int row = wr * (T / 2) + i * 32 + l32;
-          fah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&sAh[buf][swz(row, q)]));
-          fal[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&sAl[buf][swz(row, q)]));
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int row = wc * (T / 2) + j * 32 + l32;
-          const uint4 bh = *reinterpret_cast<const uint4*>(&sBh[buf][swz(row, q)]);
-          const uint4 bl = *reinterpret_cast<const uint4*>(&sBl[buf][swz(row, q)]);
-          fbh[j] = as_bf16x8(bh);
-          fbl[j] = as_bf16x8(bl);
-          fih[j] = as_bf16x8(rot_neg4(bh));   // (bi, -br) for the imaginary part
-          fil[j] = as_bf16x8(rot_neg4(bl));
-        }
-        // one product kind at a time over the accumulators, so dependent MFMAs
-        // on the same accumulator are 2 NB^2 instructions apart
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbh[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fih[j], ci[i][j], 0, 0, 0);
-          }
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbl[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fil[j], ci[i][j], 0, 0, 0);
-          }
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbh[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fih[j], ci[i][j], 0, 0, 0);
-          }
-        if (LOLO) {
-#pragma unroll
-          for (int i = 0; i < NB; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbl[j], cr[i][j], 0, 0, 0);
-              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fil[j], ci[i][j], 0, 0, 0);
-            }
-        }
-      }
-      cur = nxt;
-      have = more;
-      buf ^= 1;
-    }
-    flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
-    first_flush = false;
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        cr[i][j] = f32x16{0};
-        ci[i][j] = f32x16{0};
-      }
+      flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
+      first_flush = false;
+      zero_acc<NB>(cr, ci);
     }
     if (first_flush) flush_tile<T, NB>(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
   }
 }
 
 // Software-pipelined BF16x3 kernel (T = 128).  Stage s (16 pairs):
-//   1. issue the global loads (and weights) of stage s + 2 into register set
-//      s % 2 (freed when stage s was staged into LDS one stage earlier);
+//   1. issue the global loads of stage s + 2 into register set s % 2 (freed
+//      when stage s was staged into LDS one stage earlier);
 //   2. the MFMAs of stage s (LDS buffer s % 2) and the staging of stage s + 1
 //      (register set (s + 1) % 2 -> LDS buffer (s + 1) % 2) in one basic
-//      block, so the split / scale VALU work overlaps the matrix cores;
+//      block, with scheduling hints interleaving one MFMA with five VALU
+//      instructions, so the split / scale work overlaps the matrix cores;
 //   3. one barrier.
 // The stage loop is unrolled by two so every buffer index is a constant.
 template <bool LOLO>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
-  constexpr int T = 128, NB = 2, LG = 2, GPT = 2;
-  __shared__ __attribute__((aligned(16))) uint32_t sAh[2][T * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sAl[2][T * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sBh[2][T * 16];
-  __shared__ __attribute__((aligned(16))) uint32_t sBl[2][T * 16];
-  __shared__ float sWgt[2][kKC];
+  constexpr int T = 128, NB = 2, LG = 2, GPT = 2, NP = 8;
+  __shared__ __attribute__((aligned(16))) Bf16Lds<T> L;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -349,6 +354,11 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
   const int l32 = lane & 31;
   const int lc = tid & (T - 1);
   const int lg = tid / T;
+  int poff[NP];
+#pragma unroll
+  for (int gi = 0; gi < GPT; ++gi)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) poff[4 * gi + e] = 4 * (lg + LG * gi) + e;
 
   const int beg = a.wg_offsets[blockIdx.x];
   const int end = a.wg_offsets[blockIdx.x + 1];
@@ -356,117 +366,18 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
     const Unit u = a.units[a.wg_units[ui]];
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
-    const double om = pd.omega[u.iw];
-    const double w2 = om * om;
     const int flush_pairs = pd.flush > 2 * kKC ? pd.flush / (2 * kKC) : 1;  // stage pairs per run
     const bool okP = u.tp * T + lc < npb;
     const bool okQ = u.tq * T + lc < npb;
+    const int cP = okP ? u.tp * T + lc : 0, cQ = okQ ? u.tq * T + lc : 0;
     double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
 
     f32x16 cr[NB][NB], ci[NB][NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        cr[i][j] = f32x16{0};
-        ci[i][j] = f32x16{0};
-      }
-    float2 ra0[GPT][4], rb0[GPT][4], ra1[GPT][4], rb1[GPT][4];
+    zero_acc<NB>(cr, ci);
+    float2 ra0[NP], rb0[NP], ra1[NP], rb1[NP];
+    float rw0[NP], rw1[NP];
+    uint32_t mk0 = 0, mk1 = 0;
 
-    auto load_stage = [&](const Cursor& c, float2 (&ra)[GPT][4], float2 (&rb)[GPT][4], int wbuf) {
-      const BlockDesc bd = a.blocks[c.b];
-      if (tid < kKC) sWgt[wbuf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
-      const gf2ptr z = (gf2ptr)(bd.z);
-#pragma unroll
-      for (int gi = 0; gi < GPT; ++gi)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int p = c.p0 + 4 * (lg + LG * gi) + e;
-          float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
-          if (p < c.pend) {
-            const gf2ptr row = z + static_cast<size_t>(p) * npb;
-            if (okP) va = ld_c64(row + u.tp * T + lc);
-            if (okQ) vb = ld_c64(row + u.tq * T + lc);
-          }
-          ra[gi][e] = va;
-          rb[gi][e] = vb;
-        }
-    };
-    auto stage_lds = [&](const float2 (&ra)[GPT][4], const float2 (&rb)[GPT][4], int buf) {
-#pragma unroll
-      for (int gi = 0; gi < GPT; ++gi) {
-        const int q = lg + LG * gi;
-        uint32_t ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          split2(ra[gi][e].x, ra[gi][e].y, ah[e], al[e]);
-          const float w = sWgt[buf][4 * q + e];
-          split2(rb[gi][e].x * w, rb[gi][e].y * w, bh[e], bl[e]);
-        }
-        const int o = swz(lc, q);
-        *reinterpret_cast<uint4*>(&sAh[buf][o]) = uint4{ah[0], ah[1], ah[2], ah[3]};
-        *reinterpret_cast<uint4*>(&sAl[buf][o]) = uint4{al[0], al[1], al[2], al[3]};
-        *reinterpret_cast<uint4*>(&sBh[buf][o]) = uint4{bh[0], bh[1], bh[2], bh[3]};
-        *reinterpret_cast<uint4*>(&sBl[buf][o]) = uint4{bl[0], bl[1], bl[2], bl[3]};
-      }
-    };
-    auto mfma_stage = [&](int buf) {
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const int q = 2 * ks + g8;
-        bf16x8 fah[NB], fal[NB], fbh[NB], fbl[NB], fih[NB], fil[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          const int row = wr * (T / 2) + i * 32 + l32;
-          fah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&sAh[buf][swz(row, q)]));
-          fal[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&sAl[buf][swz(row, q)]));
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int row = wc * (T / 2) + j * 32 + l32;
-          const uint4 bh = *reinterpret_cast<const uint4*>(&sBh[buf][swz(row, q)]);
-          const uint4 bl = *reinterpret_cast<const uint4*>(&sBl[buf][swz(row, q)]);
-          fbh[j] = as_bf16x8(bh);
-          fbl[j] = as_bf16x8(bl);
-          fih[j] = as_bf16x8(rot_neg4(bh));
-          fil[j] = as_bf16x8(rot_neg4(bl));
-        }
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbh[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fih[j], ci[i][j], 0, 0, 0);
-          }
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbl[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fil[j], ci[i][j], 0, 0, 0);
-          }
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbh[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fih[j], ci[i][j], 0, 0, 0);
-          }
-        if (LOLO) {
-#pragma unroll
-          for (int i = 0; i < NB; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbl[j], cr[i][j], 0, 0, 0);
-              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fil[j], ci[i][j], 0, 0, 0);
-            }
-        }
-      }
-    };
-
-    // Interleave hint for the MFMA + staging block: each MFMA is followed by
-    // a few VALU instructions of the staging (split / scale / rotate), so the
-    // vector ALU works while the matrix core is busy.
     auto interleave = [&]() {
 #pragma unroll
       for (int k = 0; k < (LOLO ? 64 : 48); ++k) {
@@ -475,57 +386,56 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
       }
     };
 
-    // pipeline state: stages s (in LDS), s + 1 (in registers), s + 2 (next load)
+    // pipeline state: stage s (staged in LDS), s + 1 (in registers),
+    // s + 2 (being loaded).  Cursors stay on a valid stage when the unit has
+    // no further stage, so every load reads valid memory.
     Cursor c_s, c_1, c_2;
     bool h_s = cursor_first(u, a.blocks, c_s);
     c_1 = c_s;
-    bool h_1 = h_s && cursor_next(u, a.blocks, c_1);
+    bool h_1 = h_s && cursor_next<kKC>(u, a.blocks, c_1);
     __syncthreads();  // previous unit's last MFMAs are done with the LDS
-    if (h_s) load_stage(c_s, ra0, rb0, 0);
-    if (h_1) load_stage(c_1, ra1, rb1, 1);
-    __syncthreads();  // weights of stages 0 and 1 visible
-    if (h_s) stage_lds(ra0, rb0, 0);
+    if (h_s) {
+      mk0 = load_pairs<NP>(a, pd, u.iw, c_s, poff, npb, cP, cQ, ra0, rb0, rw0);
+      mk1 = load_pairs<NP>(a, pd, u.iw, c_1, poff, npb, cP, cQ, ra1, rb1, rw1);
+      bf16_stage<T, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0, okP, okQ);
+    }
     __syncthreads();
     bool first_flush = true;
     while (h_s) {
       for (int np = 0; np < flush_pairs && h_s; ++np) {
-        // ---- even stage: LDS 0, registers set 1 -> LDS 1, loads -> set 0
+        // ---- even stage: LDS 0, register set 1 -> LDS 1, loads -> set 0
         c_2 = c_1;
-        bool h_2 = h_1 && cursor_next(u, a.blocks, c_2);
-        if (h_2) load_stage(c_2, ra0, rb0, 0);
-        mfma_stage(0);
-        stage_lds(ra1, rb1, 1);   // stale data when !h_1: never read
+        bool h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
+        mk0 = load_pairs<NP>(a, pd, u.iw, c_2, poff, npb, cP, cQ, ra0, rb0, rw0);
+        bf16_mfma<T, NB, LOLO>(L, 0, wr, wc, g8, l32, cr, ci);
+        bf16_stage<T, GPT, LG>(L, 1, lc, lg, ra1, rb1, rw1, mk1, okP, okQ);   // unused when !h_1
         interleave();
         __syncthreads();
         c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
         if (!h_s) break;
-        // ---- odd stage: LDS 1, registers set 0 -> LDS 0, loads -> set 1
+        // ---- odd stage: LDS 1, register set 0 -> LDS 0, loads -> set 1
         c_2 = c_1;
-        h_2 = h_1 && cursor_next(u, a.blocks, c_2);
-        if (h_2) load_stage(c_2, ra1, rb1, 1);
-        mfma_stage(1);
-        stage_lds(ra0, rb0, 0);
+        h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
+        mk1 = load_pairs<NP>(a, pd, u.iw, c_2, poff, npb, cP, cQ, ra1, rb1, rw1);
+        bf16_mfma<T, NB, LOLO>(L, 1, wr, wc, g8, l32, cr, ci);
+        bf16_stage<T, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0, okP, okQ);
         interleave();
         __syncthreads();
         c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
       }
       flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
       first_flush = false;
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          cr[i][j] = f32x16{0};
-          ci[i][j] = f32x16{0};
-        }
+      zero_acc<NB>(cr, ci);
     }
     if (first_flush) flush_tile<T, NB>(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
   }
 }
 
-// FP32 path: v_mfma_f32_32x32x2f32, contraction slots (re, im) of one pair.
-// LDS holds the operands as complex64, rows = tile columns, 16 pairs per row
+// ---------------------------------------------------------------------------
+// FP32: v_mfma_f32_32x32x2f32, contraction slots (re, im) of one pair.  LDS
+// holds the operands as complex64, rows = tile columns, 16 pairs per row
 // (8 chunks of 2 pairs, XOR-swizzled).
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ int swz32(int row, int q) {  // q: chunk of 2 pairs (16 B)
   return row * 32 + 4 * (q ^ ((row >> 1) & 7));
 }
@@ -537,7 +447,6 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
   constexpr int PPT = kKC / LG;       // pairs per thread
   __shared__ __attribute__((aligned(16))) float sA[2][T * 32];
   __shared__ __attribute__((aligned(16))) float sB[2][T * 32];
-  __shared__ float sWgt[2][kKC];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -547,6 +456,9 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
   const int l32 = lane & 31;
   const int lc = tid & (T - 1);
   const int lg = tid / T;
+  int poff[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) poff[e] = PPT * lg + e;
 
   const int beg = a.wg_offsets[blockIdx.x];
   const int end = a.wg_offsets[blockIdx.x + 1];
@@ -554,110 +466,83 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
     const Unit u = a.units[a.wg_units[ui]];
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
-    const double om = pd.omega[u.iw];
-    const double w2 = om * om;
     const int flush_stages = pd.flush > kKC ? pd.flush / kKC : 1;
     const bool okP = u.tp * T + lc < npb;
     const bool okQ = u.tq * T + lc < npb;
     double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
 
     f32x16 cr[NB][NB], ci[NB][NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        cr[i][j] = f32x16{0};
-        ci[i][j] = f32x16{0};
-      }
-    float2 ra[PPT], rb[PPT];  // pairs PPT lg .. PPT lg + PPT - 1, column lc
+    zero_acc<NB>(cr, ci);
+    float2 ra[PPT], rb[PPT];
+    float rw[PPT];
+    uint32_t mk = 0;
+    const int cP = okP ? u.tp * T + lc : 0, cQ = okQ ? u.tq * T + lc : 0;
     Cursor cur;
     bool have = cursor_first(u, a.blocks, cur);
     __syncthreads();
-    auto load_stage = [&](const Cursor& c, int buf) {
-      const BlockDesc bd = a.blocks[c.b];
-      if (tid < kKC) sWgt[buf][tid] = static_cast<float>(pair_weight(bd, c.p0 + tid, c.pend, w2, a.delta_min));
-      const gf2ptr z = (gf2ptr)(bd.z);
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int p = c.p0 + PPT * lg + e;
-        float2 va = float2{0.f, 0.f}, vb = float2{0.f, 0.f};
-        if (p < c.pend) {
-          const gf2ptr row = z + static_cast<size_t>(p) * npb;
-          if (okP) va = ld_c64(row + u.tp * T + lc);
-          if (okQ) vb = ld_c64(row + u.tq * T + lc);
-        }
-        ra[e] = va;
-        rb[e] = vb;
-      }
-    };
+    if (have) mk = load_pairs<PPT>(a, pd, u.iw, cur, poff, npb, cP, cQ, ra, rb, rw);
     int buf = 0;
-    if (have) load_stage(cur, 0);
-    __syncthreads();
     bool first_flush = true;
     while (have) {
-    for (int ns = 0; ns < flush_stages && have; ++ns) {
+      for (int ns = 0; ns < flush_stages && have; ++ns) {
 #pragma unroll
-      for (int h = 0; h < PPT / 2; ++h) {
-        const int q = (PPT / 2) * lg + h;  // chunk of pairs 2q, 2q + 1
-        const float w0 = sWgt[buf][2 * q];
-        const float w1 = sWgt[buf][2 * q + 1];
-        const int o = swz32(lc, q);
-        *reinterpret_cast<float4*>(&sA[buf][o]) =
-            float4{ra[2 * h].x, ra[2 * h].y, ra[2 * h + 1].x, ra[2 * h + 1].y};
-        *reinterpret_cast<float4*>(&sB[buf][o]) =
-            float4{rb[2 * h].x * w0, rb[2 * h].y * w0, rb[2 * h + 1].x * w1, rb[2 * h + 1].y * w1};
-      }
-      Cursor nxt = cur;
-      const bool more = cursor_next(u, a.blocks, nxt);
-      if (more) load_stage(nxt, buf ^ 1);
-      __syncthreads();
+        for (int h = 0; h < PPT / 2; ++h) {
+          const int q = (PPT / 2) * lg + h;  // chunk of pairs 2q, 2q + 1
+          const bool v0 = (mk >> (2 * h)) & 1u, v1 = (mk >> (2 * h + 1)) & 1u;
+          const float w0 = (v0 && okQ) ? rw[2 * h] : 0.f;
+          const float w1 = (v1 && okQ) ? rw[2 * h + 1] : 0.f;
+          const float2 x0 = (v0 && okP) ? ra[2 * h] : float2{0.f, 0.f};
+          const float2 x1 = (v1 && okP) ? ra[2 * h + 1] : float2{0.f, 0.f};
+          const int o = swz32(lc, q);
+          *reinterpret_cast<float4*>(&sA[buf][o]) = float4{x0.x, x0.y, x1.x, x1.y};
+          *reinterpret_cast<float4*>(&sB[buf][o]) =
+              float4{rb[2 * h].x * w0, rb[2 * h].y * w0, rb[2 * h + 1].x * w1, rb[2 * h + 1].y * w1};
+        }
+        Cursor nxt = cur;
+        const bool more = cursor_next<kKC>(u, a.blocks, nxt);
+        mk = load_pairs<PPT>(a, pd, u.iw, nxt, poff, npb, cP, cQ, ra, rb, rw);
+        __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {  // two pairs per chunk
-        float4 av[NB], bv[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i)
-          av[i] = *reinterpret_cast<const float4*>(&sA[buf][swz32(wr * (T / 2) + i * 32 + l32, q)]);
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          bv[j] = *reinterpret_cast<const float4*>(&sB[buf][swz32(wc * (T / 2) + j * 32 + l32, q)]);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          float a0[NB], b0r[NB], b0i[NB];
-#pragma unroll
-          for (int i = 0; i < NB; ++i) {
-            const float re = h ? av[i].z : av[i].x;
-            const float im = h ? av[i].w : av[i].y;
-            a0[i] = g ? im : re;
-          }
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            const float re = h ? bv[j].z : bv[j].x;
-            const float im = h ? bv[j].w : bv[j].y;
-            b0r[j] = g ? im : re;
-            b0i[j] = g ? -re : im;
-          }
+        for (int q = 0; q < 8; ++q) {  // two pairs per chunk
+          float4 av[NB], bv[NB];
 #pragma unroll
           for (int i = 0; i < NB; ++i)
+            av[i] = *reinterpret_cast<const float4*>(&sA[buf][swz32(wr * (T / 2) + i * 32 + l32, q)]);
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            bv[j] = *reinterpret_cast<const float4*>(&sB[buf][swz32(wc * (T / 2) + j * 32 + l32, q)]);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            float a0[NB], b0r[NB], b0i[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+              const float re = h ? av[i].z : av[i].x;
+              const float im = h ? av[i].w : av[i].y;
+              a0[i] = g ? im : re;
+            }
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0r[j], cr[i][j], 0, 0, 0);
-              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0i[j], ci[i][j], 0, 0, 0);
+              const float re = h ? bv[j].z : bv[j].x;
+              const float im = h ? bv[j].w : bv[j].y;
+              b0r[j] = g ? im : re;
+              b0i[j] = g ? -re : im;
             }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+              for (int j = 0; j < NB; ++j) {
+                cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0r[j], cr[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[i], b0i[j], ci[i][j], 0, 0, 0);
+              }
+          }
         }
+        cur = nxt;
+        have = more;
+        buf ^= 1;
       }
-      cur = nxt;
-      have = more;
-      buf ^= 1;
-    }
-    flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
-    first_flush = false;
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        cr[i][j] = f32x16{0};
-        ci[i][j] = f32x16{0};
-      }
+      flush_tile<T, NB>(part, cr, ci, wr, wc, lane, first_flush);
+      first_flush = false;
+      zero_acc<NB>(cr, ci);
     }
     if (first_flush) flush_tile<T, NB>(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
   }
