@@ -134,21 +134,27 @@ __device__ __forceinline__ void flush_tile(double2* __restrict__ part, const f32
   // stage loop.
   int base = (wr * (T / 2) + 4 * g) * T + wc * (T / 2) + cl;
   asm volatile("" : "+v"(base));
+  // One 32x32 block at a time: its 16 old values are loaded as one group
+  // before any of them is added and stored, so a flush waits for memory
+  // NB^2 times rather than once per element.
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
+    for (int j = 0; j < NB; ++j) {
+      double2* blk = part + base + i * 32 * T + j * 32;
+      double2 o[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        double2* p = part + base + (i * 32 + 8 * (r >> 2) + (r & 3)) * T + j * 32;
-        double2 v = double2{static_cast<double>(cr[i][j][r]), static_cast<double>(ci[i][j][r])};
-        if (!first) {
-          const double2 o = *p;
-          v.x += o.x;
-          v.y += o.y;
-        }
-        *p = v;
+      for (int r = 0; r < 16; ++r) o[r] = double2{0.0, 0.0};
+      if (!first) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[r] = blk[(8 * (r >> 2) + (r & 3)) * T];
       }
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        blk[(8 * (r >> 2) + (r & 3)) * T] =
+            double2{static_cast<double>(cr[i][j][r]) + o[r].x,
+                    static_cast<double>(ci[i][j][r]) + o[r].y};
+    }
 }
 
 template <int NB>
@@ -264,9 +270,11 @@ __device__ __forceinline__ void bf16_mfma(const Bf16Lds<T>& L, int buf, int wr, 
 }
 
 // BF16x3 kernel, staging and MFMAs in sequence.  T = 128: waves of 64 x 64
-// (2 x 2 MFMA blocks); T = 64: waves of 32 x 32.
-template <int T, bool LOLO>
-__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_kernel(HerkArgs a) {
+// (2 x 2 MFMA blocks); T = 64: waves of 32 x 32.  OCC = workgroups per CU
+// the register allocation must allow (2: at most 256 registers per lane, so
+// two workgroups' barriers and memory waits can hide each other).
+template <int T, bool LOLO, int OCC>
+__global__ __launch_bounds__(kNT, OCC) void herk_bf16x3_kernel(HerkArgs a) {
   constexpr int NB = T / 64;          // 32x32 blocks per wave side
   constexpr int LG = kNT / T;         // loader groups
   constexpr int GPT = 4 / LG;         // pair groups (of 4) per thread
@@ -553,10 +561,11 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
 // Tile tables: {tile, pairs per stage, cap of the FP32 run length (pairs),
 // threads}.  BF16X3 with CHI0_BF16_LOLO selects the variant adding lo*lo.
 static const TileConfig kBf16Tiles[] = {
-    {128, kKC, 4096, kNT},   // software-pipelined kernel
-    {128, kKC, 4096, kNT},   // staging and MFMAs in sequence
-    {64, kKC, 4096, kNT},
-    {128, kKC, 1024, kNT},   // pipelined, shorter FP32 runs
+    {128, kKC, 4096, kNT},   // 0: software-pipelined kernel
+    {128, kKC, 4096, kNT},   // 1: staging and MFMAs in sequence
+    {64, kKC, 4096, kNT},    // 2
+    {128, kKC, 1024, kNT},   // 3: pipelined, shorter FP32 runs
+    {128, kKC, 4096, kNT},   // 4: in sequence, two workgroups per CU
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT},
@@ -565,37 +574,49 @@ static const TileConfig kFp32Tiles[] = {
 
 int herk_bf16x3_tile_count() { return sizeof(kBf16Tiles) / sizeof(kBf16Tiles[0]); }
 TileConfig herk_bf16x3_tile(int idx) { return kBf16Tiles[idx]; }
+template <int T, int OCC>
+static void launch_bf16_seq(bool lolo, const HerkArgs& a, int nwg, hipStream_t s) {
+  if (lolo)
+    hipLaunchKernelGGL((herk_bf16x3_kernel<T, true, OCC>), dim3(nwg), dim3(kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL((herk_bf16x3_kernel<T, false, OCC>), dim3(nwg), dim3(kNT), 0, s, a);
+}
+
 hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
   if (idx < 0 || idx >= herk_bf16x3_tile_count()) return hipErrorInvalidValue;
   const bool lolo = (a.flags & 2) != 0;
-  const bool pipe = idx == 0 || idx == 3;
-  if (pipe) {
-    if (lolo)
-      hipLaunchKernelGGL(herk_bf16x3_pipe_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
-    else
-      hipLaunchKernelGGL(herk_bf16x3_pipe_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
-  } else if (kBf16Tiles[idx].tile == 128) {
-    if (lolo)
-      hipLaunchKernelGGL((herk_bf16x3_kernel<128, true>), dim3(nwg), dim3(kNT), 0, s, a);
-    else
-      hipLaunchKernelGGL((herk_bf16x3_kernel<128, false>), dim3(nwg), dim3(kNT), 0, s, a);
-  } else {
-    if (lolo)
-      hipLaunchKernelGGL((herk_bf16x3_kernel<64, true>), dim3(nwg), dim3(kNT), 0, s, a);
-    else
-      hipLaunchKernelGGL((herk_bf16x3_kernel<64, false>), dim3(nwg), dim3(kNT), 0, s, a);
+  switch (idx) {
+    case 0:
+    case 3:
+      if (lolo)
+        hipLaunchKernelGGL(herk_bf16x3_pipe_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
+      else
+        hipLaunchKernelGGL(herk_bf16x3_pipe_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
+      break;
+    case 1: launch_bf16_seq<128, 1>(lolo, a, nwg, s); break;
+    case 2: launch_bf16_seq<64, 1>(lolo, a, nwg, s); break;
+    default: launch_bf16_seq<128, 2>(lolo, a, nwg, s); break;
   }
   return hipGetLastError();
 }
 int herk_bf16x3_max_wg_per_cu(int idx) {
   int n = 0;
   hipError_t e;
-  if (idx == 0 || idx == 3)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_pipe_kernel<false>, kNT, 0);
-  else if (kBf16Tiles[idx].tile == 128)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false>, kNT, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<64, false>, kNT, 0);
+  switch (idx) {
+    case 0:
+    case 3:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_pipe_kernel<false>, kNT, 0);
+      break;
+    case 1:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false, 1>, kNT, 0);
+      break;
+    case 2:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<64, false, 1>, kNT, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false, 2>, kNT, 0);
+      break;
+  }
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

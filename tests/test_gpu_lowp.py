@@ -124,3 +124,28 @@ def test_lowp_deterministic_graph_accumulate(ctx):
     ctx.sync()
     assert np.all(rel_fro(prob.chi0.cpu().numpy(), 2 * first.cpu().numpy()) <= 1e-15)
     assert_hermitian_exact(prob.chi0)
+
+
+@pytest.mark.parametrize("path", ["bf16x3", "fp32"])
+def test_every_tile_configuration(ctx, path):
+    """Every kernel variant of the autotuner's table meets the same bar (a
+    ragged npb spanning several tiles of either size, uneven blocks)."""
+    wl = workload(3, nq=1, npb=200, nk=16)
+    ref = oracle_chi0(wl)
+    mod = _model(wl, path)
+    prob, _, _ = device_problem(wl)
+    outs = []
+    for tile in range(ctx.tile_count(path)):
+        ctx.set_tile(path, tile)
+        _say(f"{path} tile {tile} {ctx.tile_info(path, tile)}")
+        ctx.chi0_accumulate([prob], precision=path)
+        ctx.sync()
+        got = prob.chi0.cpu().numpy()
+        e, em = rel_fro(got, ref), rel_fro(got, mod)
+        _say(f"  vs oracle {e.max():.3e}  vs split model {em.max():.3e}")
+        assert np.all(e <= TOL), e
+        assert np.all(em <= 3e-7), em
+        assert_hermitian_exact(prob.chi0)
+        outs.append(prob.chi0.clone())
+    ctx.set_tile(path, -1)
+    _say("  bitwise equal to tile 0: " + str([bool(torch.equal(outs[0], o)) for o in outs]))
