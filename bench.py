@@ -288,7 +288,21 @@ def main():
                 "executed_mfma_tflops": round(exe, 3),
                 "executed_mfma_frac": round(exe / PEAK_TFLOPS[prec], 4)}
 
+    inv_ms = {}
+    for method in ("gj", "hpd"):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for chi, inv in zip(chis, invs):
+            ctx.dielectric_invert(vsqrt, chi, inv, method=method)
+        b.record(stream)
+        b.synchronize()
+        ctx.sync()
+        inv_ms[method] = round(a.elapsed_time(b) / wl.nq, 3)
+    log(f"inverse ms per q: {inv_ms}")
+
     extra = {"ms_per_q_chi0": round(chi_ms / args.steps / wl.nq, 3),
+             "ms_per_q_inverse_gj": inv_ms["gj"], "ms_per_q_inverse_hpd": inv_ms["hpd"],
              "ms_per_q_chi0_plus_inverse": round(ms_per_step / wl.nq, 3),
              "nq_per_step": wl.nq, "tile": tile, "npairs": npairs}
     if wl.paths and "fp64" in wl.paths and prec != "fp64" and not args.no_fp64_compare:

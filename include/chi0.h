@@ -46,6 +46,8 @@ typedef enum {
   CHI0_EINVAL = -1,        /* invalid argument                                */
   CHI0_ENOMEM = -2,        /* device workspace allocation failed              */
   CHI0_EDEVICE = -3,       /* HIP runtime / kernel launch failure             */
+  CHI0_ENOTHPD = -4,       /* eps is not Hermitian positive definite (a
+                              non-positive pivot in CHI0_INV_HPD)             */
   CHI0_ESINGULAR = -5,     /* exact zero pivot met while inverting eps        */
   CHI0_EUNSUPPORTED = -6   /* valid but unsupported combination               */
 } chi0_status;
@@ -77,9 +79,21 @@ enum {
                               keyed by the problem shapes                     */
 };
 
-/* dielectric_invert flags */
+/* dielectric_invert flags: one inversion method (the low two bits) or'd
+ * with the output options */
 enum {
   CHI0_INV_GJ = 0,         /* blocked Gauss-Jordan with partial pivoting      */
+  CHI0_INV_HPD = 1,        /* eps Hermitian positive definite (it is, since
+                              chi0 is negative semidefinite): blocked
+                              symmetric Gauss-Jordan sweeps without pivoting on
+                              the lower triangle, half the work of
+                              CHI0_INV_GJ; eps_inv is mirrored from the lower
+                              triangle (exactly Hermitian, real diagonal); a
+                              non-positive pivot makes chi0_sync() return
+                              CHI0_ENOTHPD                                    */
+  CHI0_INV_HPD_FALLBACK_GJ = 2, /* CHI0_INV_HPD, then (synchronising the
+                              stream) CHI0_INV_GJ if a pivot was not positive */
+  CHI0_INV_METHOD_MASK = 3,
   CHI0_OUT_WC = 8          /* also write W^c                                  */
 };
 
@@ -137,23 +151,28 @@ int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob,
 /* Dielectric step for one q-point (Eq.(dielectricfunction), Eq.(wc);
  * Algorithm "hrcxq" builds eps, inverts it, forms W^c):
  *   eps[w] = 1 - diag(vsqrt) chi0[w] diag(vsqrt), eps_inv[w] = eps[w]^{-1}
- * by blocked Gauss-Jordan elimination with partial pivoting in FP64, and
+ * in FP64 by the method in the low two flag bits (CHI0_INV_GJ: blocked
+ * Gauss-Jordan elimination with partial pivoting, which reads all of eps;
+ * CHI0_INV_HPD: symmetric sweeps, which read its lower triangle only), and
  * W^c[w] = diag(vsqrt) (eps_inv[w] - 1) diag(vsqrt) when CHI0_OUT_WC is set.
  *   vsqrt   DEVICE [npb] double, > 0
  *   chi0    DEVICE [nomega][npb][npb] complex128 (input, not modified)
  *   eps     DEVICE out, same shape, or NULL
  *   eps_inv DEVICE out, same shape (must not alias chi0 or eps)
  *   wc      DEVICE out, same shape, used iff CHI0_OUT_WC (else may be NULL)
- * A zero pivot makes chi0_sync() return CHI0_ESINGULAR (eps_inv is then
- * undefined for that frequency). */
+ * A zero pivot makes chi0_sync() return CHI0_ESINGULAR, a non-positive
+ * pivot of CHI0_INV_HPD CHI0_ENOTHPD (eps_inv is then undefined for that
+ * frequency).  CHI0_INV_HPD_FALLBACK_GJ waits for the stream before it
+ * returns and reports neither for a matrix the fallback inverted. */
 int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega,
                       const double* vsqrt, const void* chi0, void* eps,
                       void* eps_inv, void* wc, uint32_t flags,
                       void* hip_stream);
 
 /* Wait for all work the handle enqueued, then report deferred failures:
- * CHI0_EDEVICE for a runtime error, CHI0_ESINGULAR for a zero pivot since the
- * previous chi0_sync(). */
+ * CHI0_EDEVICE for a runtime error, CHI0_ESINGULAR for a zero pivot and
+ * CHI0_ENOTHPD for a non-positive CHI0_INV_HPD pivot since the previous
+ * chi0_sync(). */
 int chi0_sync(chi0_handle h);
 
 /* Static description of a status code. */

@@ -24,7 +24,10 @@ What it computes (all complex128 / float64):
 * eps[I, J] = delta_IJ - s_I chi0[I, J] s_J with s_I = sqrt(v_I),
   Eq.(dielectricfunction).
 * eps^{-1}: Gauss-Jordan elimination with partial pivoting on [eps | 1]
-  (textbook), or LAPACK's inverse as a library primitive for large matrices.
+  (textbook), the Cholesky route for Hermitian positive definite eps
+  (eps = L L^H, then L Y = 1 and L^H X = Y by substitution; eps is HPD
+  because chi0 is negative semidefinite), or LAPACK's inverse as a library
+  primitive for large matrices.
 * W^c[I, J] = s_I (eps^{-1} - 1)[I, J] s_J, Eq.(wc).
 
 Parity pins for every function live in ``tests/test_oracle_pins.py``; none of
@@ -245,6 +248,42 @@ def inverse_gauss_jordan(a: np.ndarray) -> np.ndarray:
     return aug[:, n:]
 
 
+class NotHPD(np.linalg.LinAlgError):
+    """A Cholesky pivot was not positive: the matrix is not Hermitian
+    positive definite (numerically)."""
+
+
+def cholesky_lower(a: np.ndarray) -> np.ndarray:
+    """Textbook column-by-column Cholesky factor L (lower, real positive
+    diagonal) with a = L L^H, reading only the lower triangle of a."""
+    a = np.array(a, dtype=np.complex128)
+    n = a.shape[0]
+    low = np.zeros_like(a)
+    for j in range(n):
+        d = a[j, j].real - np.sum(np.abs(low[j, :j]) ** 2)
+        if not d > 0.0:
+            raise NotHPD(f"pivot {j} = {d}")
+        low[j, j] = np.sqrt(d)
+        low[j + 1:, j] = (a[j + 1:, j] - low[j + 1:, :j] @ low[j, :j].conj()) / low[j, j]
+    return low
+
+
+def inverse_cholesky(a: np.ndarray) -> np.ndarray:
+    """Inverse of a Hermitian positive definite matrix via a = L L^H: forward
+    substitution L Y = 1, then back substitution L^H X = Y."""
+    low = cholesky_lower(a)
+    n = low.shape[0]
+    y = np.zeros((n, n), np.complex128)
+    eye = np.eye(n, dtype=np.complex128)
+    for i in range(n):
+        y[i] = (eye[i] - low[i, :i] @ y[:i]) / low[i, i]
+    up = low.conj().T
+    x = np.zeros((n, n), np.complex128)
+    for i in range(n - 1, -1, -1):
+        x[i] = (y[i] - up[i, i + 1:] @ x[i + 1:]) / up[i, i]
+    return x
+
+
 def inverse(eps: np.ndarray, method: str = "gauss_jordan") -> np.ndarray:
     """Inverse of each frequency's matrix; eps is [nomega, n, n] or [n, n]."""
     eps = np.asarray(eps, np.complex128)
@@ -253,6 +292,8 @@ def inverse(eps: np.ndarray, method: str = "gauss_jordan") -> np.ndarray:
         eps = eps[None]
     if method == "gauss_jordan":
         out = np.stack([inverse_gauss_jordan(e) for e in eps])
+    elif method == "cholesky":
+        out = np.stack([inverse_cholesky(e) for e in eps])
     elif method == "lapack":
         out = np.linalg.inv(eps)
     else:

@@ -5,9 +5,9 @@ The computation lives in libchi0.so (hand-written HIP kernels behind the C ABI
 of include/chi0.h); this package is its ctypes binding.
 """
 from ._lib import (Block, Problem, Context, Chi0Error, load, header_functions, PREC, ZTYPE,
-                   CHI0_OK, CHI0_EINVAL, CHI0_ENOMEM, CHI0_EDEVICE, CHI0_ESINGULAR,
-                   CHI0_EUNSUPPORTED)
+                   CHI0_OK, CHI0_EINVAL, CHI0_ENOMEM, CHI0_EDEVICE, CHI0_ENOTHPD,
+                   CHI0_ESINGULAR, CHI0_EUNSUPPORTED)
 
 __all__ = ["Block", "Problem", "Context", "Chi0Error", "load", "header_functions", "PREC",
            "ZTYPE", "CHI0_OK", "CHI0_EINVAL", "CHI0_ENOMEM", "CHI0_EDEVICE",
-           "CHI0_ESINGULAR", "CHI0_EUNSUPPORTED"]
+           "CHI0_ENOTHPD", "CHI0_ESINGULAR", "CHI0_EUNSUPPORTED"]

@@ -21,6 +21,7 @@ CHI0_OK = 0
 CHI0_EINVAL = -1
 CHI0_ENOMEM = -2
 CHI0_EDEVICE = -3
+CHI0_ENOTHPD = -4
 CHI0_ESINGULAR = -5
 CHI0_EUNSUPPORTED = -6
 
@@ -30,6 +31,9 @@ CHI0_ACCUMULATE = 1
 CHI0_BF16_LOLO = 2
 CHI0_USE_GRAPH = 4
 CHI0_INV_GJ = 0
+CHI0_INV_HPD = 1
+CHI0_INV_HPD_FALLBACK_GJ = 2
+INV_METHOD = {"gj": CHI0_INV_GJ, "hpd": CHI0_INV_HPD, "hpd_fallback_gj": CHI0_INV_HPD_FALLBACK_GJ}
 CHI0_OUT_WC = 8
 
 
@@ -212,10 +216,11 @@ class Context:
                                          _stream_ptr(stream)))
 
     # -- dielectric ----------------------------------------------------------
-    def dielectric_invert(self, vsqrt, chi0, eps_inv, eps=None, wc=None, stream=None) -> None:
+    def dielectric_invert(self, vsqrt, chi0, eps_inv, eps=None, wc=None, method: str = "gj",
+                          stream=None) -> None:
         import torch
         nomega, npb, _ = chi0.shape
-        flags = CHI0_OUT_WC if wc is not None else 0
+        flags = (CHI0_OUT_WC if wc is not None else 0) | INV_METHOD[method]
         _check(self._lib.dielectric_invert(
             self._h, npb, nomega, _dev_ptr(vsqrt, torch.float64, "vsqrt"),
             _dev_ptr(chi0, torch.complex128, "chi0"), _dev_ptr(eps, torch.complex128, "eps"),

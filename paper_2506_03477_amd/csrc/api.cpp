@@ -102,6 +102,7 @@ struct chi0_ctx {
   DevBuf partials;
   DevBuf wts;           // pair weights of the current call
   DevBuf gj_work, gj_wrow, gj_piv, gj_perm;
+  DevBuf hpd_p, hpd_c, hpd_dinv;  // HPD inverse: kept panel, new panel, D^{-1}
   uint64_t ws_gen = 1;
   int32_t* d_status = nullptr;
   void* staging = nullptr;  // pinned host staging for table uploads
@@ -626,6 +627,7 @@ const char* chi0_status_string(int s) {
     case CHI0_EINVAL: return "invalid argument";
     case CHI0_ENOMEM: return "device allocation failed";
     case CHI0_EDEVICE: return "HIP device or launch failure";
+    case CHI0_ENOTHPD: return "eps is not Hermitian positive definite";
     case CHI0_ESINGULAR: return "zero pivot while inverting eps";
     case CHI0_EUNSUPPORTED: return "unsupported combination";
   }
@@ -669,6 +671,9 @@ int chi0_destroy(chi0_handle h) {
   h->gj_wrow.release();
   h->gj_piv.release();
   h->gj_perm.release();
+  h->hpd_p.release();
+  h->hpd_c.release();
+  h->hpd_dinv.release();
   if (h->d_status) hipFree(h->d_status);
   if (h->staging) hipHostFree(h->staging);
   if (h->staging_done) hipEventDestroy(h->staging_done);
@@ -697,7 +702,11 @@ int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* 
                       void* hip_stream) {
   if (npb < 1) return fail(CHI0_EINVAL, "npb = %d < 1", npb);
   if (nomega < 1) return fail(CHI0_EINVAL, "nomega = %d < 1", nomega);
-  if (flags & ~static_cast<uint32_t>(CHI0_OUT_WC)) return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  if (flags & ~static_cast<uint32_t>(CHI0_OUT_WC | CHI0_INV_METHOD_MASK))
+    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  const uint32_t method = flags & CHI0_INV_METHOD_MASK;
+  if (method != CHI0_INV_GJ && method != CHI0_INV_HPD && method != CHI0_INV_HPD_FALLBACK_GJ)
+    return fail(CHI0_EINVAL, "unknown inversion method %u", method);
   if (!vsqrt || !chi0 || !eps_inv) return fail(CHI0_EINVAL, "vsqrt, chi0 and eps_inv must be non-NULL");
   if ((flags & CHI0_OUT_WC) && !wc) return fail(CHI0_EINVAL, "CHI0_OUT_WC set but wc is NULL");
   if (!aligned(chi0, 16) || !aligned(eps_inv, 16) || (eps && !aligned(eps, 16)) ||
@@ -714,19 +723,49 @@ int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* 
   if (!h) return fail(CHI0_EINVAL, "handle is NULL");
   HIP_TRY(hipSetDevice(h->device));
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const int nb = gj_panel_width();
+  double2* wc_out = (flags & CHI0_OUT_WC) ? static_cast<double2*>(wc) : nullptr;
   int rc;
   if ((rc = h->gj_work.reserve(bytes, &h->ws_gen))) return rc;
-  if ((rc = h->gj_wrow.reserve(static_cast<size_t>(nomega) * nb * npb * 16, &h->ws_gen))) return rc;
-  if ((rc = h->gj_piv.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
-  if ((rc = h->gj_perm.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
   double2* work = static_cast<double2*>(h->gj_work.p);
-  double2* wrow = static_cast<double2*>(h->gj_wrow.p);
-  int32_t* piv = static_cast<int32_t*>(h->gj_piv.p);
-  int32_t* perm = static_cast<int32_t*>(h->gj_perm.p);
   hipError_t e = dielectric_build_launch(static_cast<const double2*>(chi0), vsqrt, work,
                                          static_cast<double2*>(eps), npb, nomega, s);
   if (e != hipSuccess) return fail(CHI0_EDEVICE, "eps build launch: %s", hipGetErrorString(e));
+
+  if (method != CHI0_INV_GJ) {
+    const int nb = hpd_block_width();
+    if ((rc = h->hpd_p.reserve(static_cast<size_t>(nomega) * npb * nb * 16, &h->ws_gen))) return rc;
+    if ((rc = h->hpd_c.reserve(static_cast<size_t>(nomega) * npb * nb * 16, &h->ws_gen))) return rc;
+    if ((rc = h->hpd_dinv.reserve(static_cast<size_t>(nomega) * nb * nb * 16, &h->ws_gen))) return rc;
+    double2* pb = static_cast<double2*>(h->hpd_p.p);
+    double2* cb = static_cast<double2*>(h->hpd_c.p);
+    double2* di = static_cast<double2*>(h->hpd_dinv.p);
+    const bool fallback = method == CHI0_INV_HPD_FALLBACK_GJ;
+    e = hpd_status_clear_launch(h->d_status, s);
+    for (int k0 = 0; k0 < npb && e == hipSuccess; k0 += nb)
+      e = hpd_step_launch(work, di, pb, cb, npb, nomega, k0, std::min(nb, npb - k0), h->d_status,
+                          !fallback, s);
+    if (e == hipSuccess)
+      e = hpd_finish_launch(work, static_cast<double2*>(eps_inv), wc_out, vsqrt, npb, nomega, s);
+    if (e != hipSuccess) return fail(CHI0_EDEVICE, "HPD inverse launch: %s", hipGetErrorString(e));
+    if (!fallback) return CHI0_OK;
+    // fallback: wait for this call's sweeps and redo the pivoted inverse if
+    // a pivot was not positive
+    int32_t st[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(st, h->d_status, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!st[1]) return CHI0_OK;
+    e = dielectric_build_launch(static_cast<const double2*>(chi0), vsqrt, work, nullptr, npb,
+                                nomega, s);
+    if (e != hipSuccess) return fail(CHI0_EDEVICE, "eps build launch: %s", hipGetErrorString(e));
+  }
+
+  const int nb = gj_panel_width();
+  if ((rc = h->gj_wrow.reserve(static_cast<size_t>(nomega) * nb * npb * 16, &h->ws_gen))) return rc;
+  if ((rc = h->gj_piv.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
+  if ((rc = h->gj_perm.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
+  double2* wrow = static_cast<double2*>(h->gj_wrow.p);
+  int32_t* piv = static_cast<int32_t*>(h->gj_piv.p);
+  int32_t* perm = static_cast<int32_t*>(h->gj_perm.p);
   for (int k0 = 0; k0 < npb; k0 += nb) {
     const int nbk = std::min(nb, npb - k0);
     e = gj_panel_launch(work, npb, nomega, k0, nbk, piv, h->d_status, s);
@@ -734,9 +773,8 @@ int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* 
     if (e == hipSuccess) e = gj_update_launch(work, wrow, npb, nomega, k0, nbk, s);
     if (e != hipSuccess) return fail(CHI0_EDEVICE, "Gauss-Jordan launch: %s", hipGetErrorString(e));
   }
-  e = gj_finish_launch(work, static_cast<double2*>(eps_inv),
-                       (flags & CHI0_OUT_WC) ? static_cast<double2*>(wc) : nullptr, vsqrt, piv, perm,
-                       npb, nomega, s);
+  e = gj_finish_launch(work, static_cast<double2*>(eps_inv), wc_out, vsqrt, piv, perm, npb, nomega,
+                       s);
   if (e != hipSuccess) return fail(CHI0_EDEVICE, "Gauss-Jordan finish launch: %s", hipGetErrorString(e));
   return CHI0_OK;
 }
@@ -745,11 +783,14 @@ int chi0_sync(chi0_handle h) {
   if (!h) return fail(CHI0_EINVAL, "handle is NULL");
   HIP_TRY(hipSetDevice(h->device));
   HIP_TRY(hipDeviceSynchronize());
-  int32_t st = 0;
-  HIP_TRY(hipMemcpy(&st, h->d_status, sizeof(st), hipMemcpyDeviceToHost));
-  if (st) {
-    HIP_TRY(hipMemset(h->d_status, 0, sizeof(int32_t)));
-    return fail(CHI0_ESINGULAR, "a zero pivot was met while inverting eps");
+  // status words: [0] zero pivot (Gauss-Jordan), [1] this call's HPD sweeps
+  // met a non-positive pivot, [2] the same, reported here
+  int32_t st[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpy(st, h->d_status, sizeof(st), hipMemcpyDeviceToHost));
+  if (st[0] || st[2]) {
+    HIP_TRY(hipMemset(h->d_status, 0, sizeof(st)));
+    if (st[0]) return fail(CHI0_ESINGULAR, "a zero pivot was met while inverting eps");
+    return fail(CHI0_ENOTHPD, "a non-positive pivot was met: eps is not Hermitian positive definite");
   }
   return CHI0_OK;
 }

@@ -117,4 +117,13 @@ hipError_t gj_finish_launch(const double2* work, double2* eps_inv,
                             int nomega, hipStream_t s);
 int gj_panel_width();
 
+// Hermitian positive definite inverse (symmetric Gauss-Jordan sweeps).
+int hpd_block_width();
+hipError_t hpd_status_clear_launch(int32_t* status, hipStream_t s);
+hipError_t hpd_step_launch(double2* work, double2* dinv, double2* pbuf, double2* cbuf, int n,
+                           int nomega, int k0, int nb, int32_t* status, bool report,
+                           hipStream_t s);
+hipError_t hpd_finish_launch(const double2* work, double2* eps_inv, double2* wc,
+                             const double* vsqrt, int n, int nomega, hipStream_t s);
+
 }  // namespace chi0

@@ -54,7 +54,7 @@ def pin_golden(orc):
             eps = orc.dielectric(chi[None], s)[0]
             if not _close(eps, _frac_mat(case["eps"]), 1e-15):
                 fails.append(f"golden eps: {eps}")
-            for method in ("gauss_jordan", "lapack"):
+            for method in ("gauss_jordan", "cholesky", "lapack"):
                 inv = orc.inverse(eps, method)
                 if not _close(inv, _frac_mat(case["eps_inv"]), 1e-15):
                     fails.append(f"golden eps_inv ({method}): {inv}")
@@ -148,7 +148,7 @@ def pin_single_transition(orc):
         if not _close(eps, np.eye(npb) + g * np.outer(a, a.conj()), 4e-15):
             fails.append(f"single transition eps omega={w}")
         inv_ref = np.eye(npb) - g * np.outer(a, a.conj()) / (1.0 + g * np.vdot(a, a).real)
-        for method in ("gauss_jordan", "lapack"):
+        for method in ("gauss_jordan", "cholesky", "lapack"):
             inv = orc.inverse(eps, method)
             if not _close(inv, inv_ref, 1e-14):
                 fails.append(f"single transition eps_inv {method} omega={w}")
@@ -287,9 +287,11 @@ def pin_structure(orc):
 
 
 def pin_inverse(orc):
-    """Inverse: Gauss-Jordan and LAPACK agree; residual bounded by kappa*u;
-    matrices that need pivoting (zero / tiny leading entry) are inverted
-    exactly; permutation matrix inverse is its transpose."""
+    """Inverse: Gauss-Jordan, Cholesky and LAPACK agree; residual bounded by
+    kappa*u; matrices that need pivoting (zero / tiny leading entry) are
+    inverted exactly; permutation matrix inverse is its transpose; the
+    Cholesky factor reproduces its matrix, an indefinite matrix is rejected
+    and a complex 2x2 HPD matrix has its closed-form inverse."""
     fails = []
     p = np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]], complex)
     if not _close(orc.inverse(p, "gauss_jordan"), p.T, 0.0):
@@ -309,6 +311,29 @@ def pin_inverse(orc):
         fails.append("GJ vs LAPACK")
     if np.linalg.norm(e @ gj - np.eye(n)) > 64 * n * kappa * U:
         fails.append("GJ residual")
+    ch = orc.inverse(e, "cholesky")
+    if np.linalg.norm(ch - la) / np.linalg.norm(la) > 64 * kappa * U:
+        fails.append("Cholesky vs LAPACK")
+    # the factor itself: L L^H reproduces e, L is lower with a positive diagonal
+    low = orc.cholesky_lower(e)
+    if np.linalg.norm(low @ low.conj().T - e) > 64 * n * U * np.linalg.norm(e):
+        fails.append("Cholesky factor L L^H != e")
+    if np.any(np.triu(low, 1) != 0) or np.any(np.diag(low).real <= 0) or \
+            np.any(np.diag(low).imag != 0):
+        fails.append("Cholesky factor shape")
+    # an indefinite Hermitian matrix is rejected; a 2x2 HPD matrix with a
+    # complex off-diagonal entry has the closed-form inverse
+    # [[d, -b], [-conj(b), a]] / (a d - |b|^2)
+    bad = np.array([[1.0, 2.0], [2.0, 1.0]], complex)
+    try:
+        orc.inverse(bad, "cholesky")
+        fails.append("indefinite matrix accepted")
+    except orc.NotHPD:
+        pass
+    a2 = np.array([[4.0, 1.0 + 2.0j], [1.0 - 2.0j, 3.0]])
+    ref2 = np.array([[3.0, -1.0 - 2.0j], [-1.0 + 2.0j, 4.0]]) / 7.0
+    if not _close(orc.inverse(a2, "cholesky"), ref2, 1e-15):
+        fails.append(f"2x2 closed form: {orc.inverse(a2, 'cholesky')}")
     return fails
 
 

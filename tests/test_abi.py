@@ -118,7 +118,12 @@ def test_dielectric_validation():
     assert f(None, 4, 1, None, FAKE, None, FAKE * 2, None, 0, None) == L.CHI0_EINVAL
     assert f(None, 4, 1, FAKE, FAKE, None, FAKE * 2, None, 8, None) == L.CHI0_EINVAL  # wc NULL
     assert f(None, 4, 1, FAKE, FAKE, None, FAKE + 16, None, 0, None) == L.CHI0_EINVAL  # alias
-    assert f(None, 4, 1, FAKE, FAKE, None, FAKE * 2, None, 1, None) == L.CHI0_EINVAL  # flag
+    for bad in (3, 16, 4):                                                           # flags
+        assert f(None, 4, 1, FAKE, FAKE, None, FAKE * 2, None, bad, None) == L.CHI0_EINVAL
+        assert "flag" in lib.chi0_last_error().decode() or "method" in lib.chi0_last_error().decode()
+    for method in (L.CHI0_INV_GJ, L.CHI0_INV_HPD, L.CHI0_INV_HPD_FALLBACK_GJ):     # valid: handle
+        assert f(None, 4, 1, FAKE, FAKE, None, FAKE * 2, None, method, None) == L.CHI0_EINVAL
+        assert "handle" in lib.chi0_last_error().decode()
     rc = f(None, 4, 1, FAKE, FAKE, None, FAKE * 2, None, 0, None)
     assert rc == L.CHI0_EINVAL and "handle" in lib.chi0_last_error().decode()
 

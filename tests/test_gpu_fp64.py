@@ -9,7 +9,7 @@ import torch
 import oracle
 from gpu_common import (assert_hermitian_exact, device_problem, need_gpu, oracle_chi0,
                         rel_fro)
-from paper_2506_03477_amd import Block, Chi0Error, Context, Problem, CHI0_ESINGULAR
+from paper_2506_03477_amd import Block, Chi0Error, Context, Problem, CHI0_ENOTHPD, CHI0_ESINGULAR
 from synth import workload
 from synth.gpu import z_block_device
 
@@ -191,3 +191,99 @@ def test_dielectric_singular(ctx):
         ctx.sync()
     assert ei.value.code == CHI0_ESINGULAR
     ctx.sync()                                      # status is cleared once reported
+
+
+def _nsd_chi0(n, nomega, seed):
+    """A negative semidefinite Hermitian chi0 (-A^H diag(c) A, c > 0) of
+    rank min(n, 3n/2) per frequency, and the Coulomb square roots 1/(1+I)."""
+    rng = np.random.default_rng(seed)
+    k = max(1, 3 * n // 2)
+    out = np.empty((nomega, n, n), np.complex128)
+    for iw in range(nomega):
+        a = rng.standard_normal((k, n)) + 1j * rng.standard_normal((k, n))
+        c = rng.uniform(0.1, 2.0, k) / (1.0 + iw)
+        out[iw] = -(a.conj().T * c) @ a
+    return out, 1.0 / (1.0 + np.arange(n, dtype=np.float64))
+
+
+def _check_hpd_inverse(eps, inv, eps_o, tag):
+    u = np.finfo(float).eps / 2
+    inv_ref = oracle.inverse(eps_o, "cholesky")
+    n = eps.shape[-1]
+    for iw in range(eps.shape[0]):
+        kappa = np.linalg.cond(eps_o[iw])
+        tol = max(TOL_FP64, 64 * kappa * u)
+        e = rel_fro(inv[iw], inv_ref[iw])
+        res = np.linalg.norm(eps[iw] @ inv[iw] - np.eye(n)) / np.sqrt(n)
+        _say(f"  {tag} iw={iw} kappa={kappa:.3g} inv rel={e:.3g} residual={res:.3g}")
+        assert e <= tol
+        assert res <= 64 * n * kappa * u
+        assert np.array_equal(inv[iw], inv[iw].conj().T)     # mirrored: exactly Hermitian
+        assert np.all(np.diag(inv[iw]).imag == 0)
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 100, 130])
+def test_dielectric_hpd_sizes(ctx, n):
+    """Hermitian positive definite inverse (symmetric sweeps) at block-
+    ragged sizes, against the oracle's Cholesky inverse."""
+    _say(f"dielectric hpd n={n}")
+    chi_h, s_h = _nsd_chi0(n, 3, seed=n)
+    chi = torch.from_numpy(chi_h).cuda()
+    s = torch.from_numpy(s_h).cuda()
+    eps = torch.empty_like(chi)
+    inv = torch.empty_like(chi)
+    wc = torch.empty_like(chi)
+    ctx.dielectric_invert(s, chi, inv, eps=eps, wc=wc, method="hpd")
+    ctx.sync()
+    eps_o = oracle.dielectric(chi_h, s_h)
+    assert np.array_equal(eps.cpu().numpy(), eps_o)
+    _check_hpd_inverse(eps.cpu().numpy(), inv.cpu().numpy(), eps_o, f"n={n}")
+    assert np.array_equal(wc.cpu().numpy(), oracle.screened_wc(inv.cpu().numpy(), s_h))
+
+
+@pytest.mark.parametrize("cfg,over", [(0, {}), (1, dict(npb=150, nk=2, nocc=8, nunocc=40))])
+def test_dielectric_hpd_parity(ctx, cfg, over):
+    wl = workload(cfg, **over)
+    _say(f"dielectric hpd {wl.name}")
+    prob, vsqrt, _ = device_problem(wl)
+    ctx.chi0_accumulate([prob], delta_min=wl.delta_min)
+    eps = torch.empty_like(prob.chi0)
+    inv = torch.empty_like(prob.chi0)
+    inv_gj = torch.empty_like(prob.chi0)
+    ctx.dielectric_invert(vsqrt, prob.chi0, inv, eps=eps, method="hpd")
+    ctx.dielectric_invert(vsqrt, prob.chi0, inv_gj, method="gj")
+    ctx.sync()
+    s = wl.vsqrt()
+    eps_o = oracle.dielectric(oracle_chi0(wl), s)
+    _check_hpd_inverse(eps.cpu().numpy(), inv.cpu().numpy(), eps_o, wl.name)
+    u = np.finfo(float).eps / 2
+    for iw in range(wl.nomega):
+        kappa = np.linalg.cond(eps_o[iw])
+        assert rel_fro(inv.cpu().numpy()[iw], inv_gj.cpu().numpy()[iw]) <= max(TOL_FP64, 64 * kappa * u)
+
+
+def test_dielectric_hpd_rejects_indefinite(ctx):
+    """An indefinite eps is reported (CHI0_ENOTHPD); the fallback method
+    returns the pivoted Gauss-Jordan inverse instead, bit for bit."""
+    _say("dielectric hpd indefinite / fallback")
+    n = 40
+    chi_h, s_h = _nsd_chi0(n, 2, seed=7)
+    chi_h[0] = -chi_h[0] * 50.0                       # eps = 1 - 50 s A^H c A s: indefinite
+    chi = torch.from_numpy(chi_h).cuda()
+    s = torch.from_numpy(s_h).cuda()
+    inv = torch.empty_like(chi)
+    ctx.dielectric_invert(s, chi, inv, method="hpd")
+    with pytest.raises(Chi0Error) as ei:
+        ctx.sync()
+    assert ei.value.code == CHI0_ENOTHPD
+    ctx.sync()                                        # cleared once reported
+    inv_fb = torch.empty_like(chi)
+    inv_gj = torch.empty_like(chi)
+    ctx.dielectric_invert(s, chi, inv_fb, method="hpd_fallback_gj")
+    ctx.dielectric_invert(s, chi, inv_gj, method="gj")
+    ctx.sync()                                        # the fallback reports nothing
+    assert torch.equal(inv_fb, inv_gj)
+    eps_o = oracle.dielectric(chi_h, s_h)
+    ref = oracle.inverse(eps_o, "lapack")
+    for iw in range(2):
+        assert rel_fro(inv_gj.cpu().numpy()[iw], ref[iw]) <= 1e-10

@@ -74,6 +74,25 @@ def _gj_no_pivot(a):
     return aug[:, n:]
 
 
+def _chol_no_conj(a):
+    """Cholesky factor with the conjugation of the row dropped."""
+    a = np.array(a, dtype=np.complex128)
+    n = a.shape[0]
+    low = np.zeros_like(a)
+    for j in range(n):
+        d = a[j, j].real - np.sum(np.abs(low[j, :j]) ** 2)
+        if not d > 0.0:
+            raise orc.NotHPD(f"pivot {j}")
+        low[j, j] = np.sqrt(d)
+        low[j + 1:, j] = (a[j + 1:, j] - low[j + 1:, :j] @ low[j, :j]) / low[j, j]
+    return low
+
+
+def _chol_upper_read(a):
+    """Cholesky factor reading the upper triangle as if it were the lower."""
+    return orc.__dict__["_orig_cholesky_lower"](np.array(a).T)
+
+
 def _wc_no_minus_one(eps_inv, vsqrt):
     s = np.asarray(vsqrt)
     d = np.asarray(eps_inv)
@@ -99,6 +118,8 @@ MUTATIONS = {
     "dielectric_plus": ("dielectric", _dielectric_plus),
     "dielectric_one_side": ("dielectric", _dielectric_one_side),
     "gj_no_pivot": ("inverse_gauss_jordan", _gj_no_pivot),
+    "chol_no_conj": ("cholesky_lower", _chol_no_conj),
+    "chol_upper_read": ("cholesky_lower", _chol_upper_read),
     "wc_no_minus_one": ("screened_wc", _wc_no_minus_one),
     "drop_last_block": ("chi0_ref", _ref_drop_last_block),
 }
@@ -107,6 +128,7 @@ MUTATIONS = {
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_mutation_is_caught(name, monkeypatch):
     attr, fn = MUTATIONS[name]
+    monkeypatch.setattr(orc, "_orig_cholesky_lower", orc.cholesky_lower, raising=False)
     monkeypatch.setattr(orc, attr, fn)
     res = pins.run_all(orc)
     caught = [k for k, v in res.items() if v]
