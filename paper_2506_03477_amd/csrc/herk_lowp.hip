@@ -52,34 +52,48 @@ __device__ __forceinline__ float2 ld_c64(gf2ptr p) {
   return float2{__uint_as_float(static_cast<uint32_t>(v)), __uint_as_float(static_cast<uint32_t>(v >> 32))};
 }
 
+// Byte offset of a tile column within a Z row; a column beyond npb reads
+// column 0 instead (its products are never used).
+__device__ __forceinline__ uint32_t col_offset(int col, int npb) {
+  return static_cast<uint32_t>(col < npb ? col : 0) * 8u;
+}
+
 // Operand and weight loads of one stage for one thread: NP pairs
-// p0 + poff[k] of the current block, tile columns colP / colQ.  Every load is
-// issued unconditionally with its address clamped into the block and the
-// matrix; bit k of the returned mask says whether pair k exists, and the
-// consumer zeroes the other operands when it stages them.  The loads of a
-// stage thus form one straight-line group that is only waited for when the
-// stage is staged, one or two stages later.
+// p0 + poff[k] of the current block, tile column byte offsets offP / offQ.
+// Every kernel gives all lanes of a wave the same pair offsets, so the pair
+// rows, their validity and their weights are wave-uniform: the row address
+// and the weight live in scalar registers (the weight comes through the
+// scalar cache) and a lane only adds its fixed column offset.  Loads are
+// issued unconditionally with the row clamped into the block; bit k of the
+// returned (uniform) mask says whether pair k exists, and the consumer gives
+// a missing pair weight 0.  The loads of a stage thus form one straight-line
+// group that is only waited for when the stage is staged.
 template <int NP>
 __device__ __forceinline__ uint32_t load_pairs(const HerkArgs& a, const ProbDesc& pd, int iw,
                                                const Cursor& c, const int (&poff)[NP], int npb,
-                                               int cP, int cQ, float2 (&ra)[NP], float2 (&rb)[NP],
-                                               float (&rw)[NP]) {
+                                               uint32_t offP, uint32_t offQ, float2 (&ra)[NP],
+                                               float2 (&rb)[NP], float (&rw)[NP]) {
+  typedef const char __attribute__((address_space(1)))* gcptr;
   const int b = __builtin_amdgcn_readfirstlane(c.b);
+  const int p0 = __builtin_amdgcn_readfirstlane(c.p0);
+  const int last = __builtin_amdgcn_readfirstlane(c.pend) - 1 - p0;  // last valid offset
   const BlockDesc* bp = a.blocks + b;
-  const gf2ptr z = (gf2ptr)(ld_const(&bp->z, 0));
+  const uint32_t row_bytes = static_cast<uint32_t>(npb) * 8u;
+  // stage base: row p0 of the block, and its weights
+  const gcptr z = (gcptr)(ld_const(&bp->z, 0)) + static_cast<size_t>(p0) * row_bytes;
   const int64_t pbase = ld_const(&bp->pair_base, 0);
-  const gfptr w = (gfptr)(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase;
+  const float* w = static_cast<const float*>(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase + p0;
   uint32_t mask = 0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    const int p = c.p0 + poff[k];
-    const bool valid = p < c.pend;
-    const int pc = valid ? p : c.pend - 1;
+    const int o = __builtin_amdgcn_readfirstlane(poff[k]);
+    const bool valid = o <= last;
+    const int oc = valid ? o : last;
     mask |= valid ? (1u << k) : 0u;
-    const gf2ptr row = z + static_cast<size_t>(pc) * npb;
-    ra[k] = ld_c64(row + cP);
-    rb[k] = ld_c64(row + cQ);
-    rw[k] = w[pc];
+    const gcptr row = z + static_cast<uint32_t>(oc) * row_bytes;
+    ra[k] = ld_c64((gf2ptr)(row + offP));
+    rb[k] = ld_c64((gf2ptr)(row + offQ));
+    rw[k] = ld_const(w, oc);
   }
   return mask;
 }
@@ -172,23 +186,27 @@ __device__ __forceinline__ void zero_acc(f32x16 (&cr)[NB][NB], f32x16 (&ci)[NB][
 // BF16x3
 // ---------------------------------------------------------------------------
 
-// LDS of the BF16x3 kernels: bf16 hi / lo planes of both operands, two buffers.
+// LDS of the BF16x3 kernels: bf16 hi / lo planes of both operands, and of
+// the Q side rotated to (im, -re) for the imaginary part, two buffers.
 template <int T>
 struct Bf16Lds {
   uint32_t ah[2][T * 16];
   uint32_t al[2][T * 16];
   uint32_t bh[2][T * 16];
   uint32_t bl[2][T * 16];
+  uint32_t bih[2][T * 16];
+  uint32_t bil[2][T * 16];
 };
 
 // Stage one thread's 4 GPT pairs into LDS buffer `buf`: split the P side,
-// scale (by the pair weight) and split the Q side.  Thread owns tile column
-// lc and pair groups q = lg + LG gi (4 pairs each).
+// scale (by the pair weight, 0 for a missing pair) and split the Q side, and
+// store the Q side also rotated.  Thread owns tile column lc and pair groups
+// q = lg + LG gi (4 pairs each).  Columns beyond npb hold real (clamped)
+// data whose products land in tile rows / columns the reduction ignores.
 template <int T, int GPT, int LG>
 __device__ __forceinline__ void bf16_stage(Bf16Lds<T>& L, int buf, int lc, int lg,
                                            const float2 (&ra)[4 * GPT], const float2 (&rb)[4 * GPT],
-                                           const float (&rw)[4 * GPT], uint32_t mask, bool okP,
-                                           bool okQ) {
+                                           const float (&rw)[4 * GPT], uint32_t mask) {
 #pragma unroll
   for (int gi = 0; gi < GPT; ++gi) {
     const int q = lg + LG * gi;
@@ -196,10 +214,8 @@ __device__ __forceinline__ void bf16_stage(Bf16Lds<T>& L, int buf, int lc, int l
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int k = 4 * gi + e;
-      const bool v = (mask >> k) & 1u;
-      const float2 x = (v && okP) ? ra[k] : float2{0.f, 0.f};
-      const float wq = (v && okQ) ? rw[k] : 0.f;
-      split2(x.x, x.y, ah[e], al[e]);
+      const float wq = ((mask >> k) & 1u) ? rw[k] : 0.f;
+      split2(ra[k].x, ra[k].y, ah[e], al[e]);
       split2(rb[k].x * wq, rb[k].y * wq, bh[e], bl[e]);
     }
     const int o = swz(lc, q);
@@ -207,6 +223,8 @@ __device__ __forceinline__ void bf16_stage(Bf16Lds<T>& L, int buf, int lc, int l
     *reinterpret_cast<uint4*>(&L.al[buf][o]) = uint4{al[0], al[1], al[2], al[3]};
     *reinterpret_cast<uint4*>(&L.bh[buf][o]) = uint4{bh[0], bh[1], bh[2], bh[3]};
     *reinterpret_cast<uint4*>(&L.bl[buf][o]) = uint4{bl[0], bl[1], bl[2], bl[3]};
+    *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(uint4{bh[0], bh[1], bh[2], bh[3]});
+    *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(uint4{bl[0], bl[1], bl[2], bl[3]});
   }
 }
 
@@ -229,12 +247,10 @@ __device__ __forceinline__ void bf16_mfma(const Bf16Lds<T>& L, int buf, int wr, 
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int row = wc * (T / 2) + j * 32 + l32;
-      const uint4 bh = *reinterpret_cast<const uint4*>(&L.bh[buf][swz(row, q)]);
-      const uint4 bl = *reinterpret_cast<const uint4*>(&L.bl[buf][swz(row, q)]);
-      fbh[j] = as_bf16x8(bh);
-      fbl[j] = as_bf16x8(bl);
-      fih[j] = as_bf16x8(rot_neg4(bh));   // (bi, -br) for the imaginary part
-      fil[j] = as_bf16x8(rot_neg4(bl));
+      fbh[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bh[buf][swz(row, q)]));
+      fbl[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bl[buf][swz(row, q)]));
+      fih[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bih[buf][swz(row, q)]));  // (bi, -br)
+      fil[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bil[buf][swz(row, q)]));
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i)
@@ -302,8 +318,6 @@ __global__ __launch_bounds__(kNT, OCC) void herk_bf16x3_kernel(HerkArgs a) {
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
     const int flush_stages = pd.flush > kKC ? pd.flush / kKC : 1;
-    const bool okP = u.tp * T + lc < npb;
-    const bool okQ = u.tq * T + lc < npb;
     double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
 
     f32x16 cr[NB][NB], ci[NB][NB];
@@ -311,7 +325,7 @@ __global__ __launch_bounds__(kNT, OCC) void herk_bf16x3_kernel(HerkArgs a) {
     float2 ra[NP], rb[NP];
     float rw[NP];
     uint32_t mk = 0;
-    const int cP = okP ? u.tp * T + lc : 0, cQ = okQ ? u.tq * T + lc : 0;
+    const uint32_t cP = col_offset(u.tp * T + lc, npb), cQ = col_offset(u.tq * T + lc, npb);
     Cursor cur;
     bool have = cursor_first(u, a.blocks, cur);
     __syncthreads();  // previous unit's last MFMAs are done with the LDS
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(kNT, OCC) void herk_bf16x3_kernel(HerkArgs a) {
     bool first_flush = true;
     while (have) {
       for (int ns = 0; ns < flush_stages && have; ++ns) {
-        bf16_stage<T, GPT, LG>(L, buf, lc, lg, ra, rb, rw, mk, okP, okQ);
+        bf16_stage<T, GPT, LG>(L, buf, lc, lg, ra, rb, rw, mk);
         // next stage's loads in flight during this stage's MFMAs (the cursor
         // stays on a valid stage when there is no next one)
         Cursor nxt = cur;
@@ -375,9 +389,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
     const int flush_pairs = pd.flush > 2 * kKC ? pd.flush / (2 * kKC) : 1;  // stage pairs per run
-    const bool okP = u.tp * T + lc < npb;
-    const bool okQ = u.tq * T + lc < npb;
-    const int cP = okP ? u.tp * T + lc : 0, cQ = okQ ? u.tq * T + lc : 0;
+    const uint32_t cP = col_offset(u.tp * T + lc, npb), cQ = col_offset(u.tq * T + lc, npb);
     double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
 
     f32x16 cr[NB][NB], ci[NB][NB];
@@ -405,7 +417,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
     if (h_s) {
       mk0 = load_pairs<NP>(a, pd, u.iw, c_s, poff, npb, cP, cQ, ra0, rb0, rw0);
       mk1 = load_pairs<NP>(a, pd, u.iw, c_1, poff, npb, cP, cQ, ra1, rb1, rw1);
-      bf16_stage<T, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0, okP, okQ);
+      bf16_stage<T, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0);
     }
     __syncthreads();
     bool first_flush = true;
@@ -416,7 +428,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
         bool h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
         mk0 = load_pairs<NP>(a, pd, u.iw, c_2, poff, npb, cP, cQ, ra0, rb0, rw0);
         bf16_mfma<T, NB, LOLO>(L, 0, wr, wc, g8, l32, cr, ci);
-        bf16_stage<T, GPT, LG>(L, 1, lc, lg, ra1, rb1, rw1, mk1, okP, okQ);   // unused when !h_1
+        bf16_stage<T, GPT, LG>(L, 1, lc, lg, ra1, rb1, rw1, mk1);   // unused when !h_1
         interleave();
         __syncthreads();
         c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
@@ -426,7 +438,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
         h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
         mk1 = load_pairs<NP>(a, pd, u.iw, c_2, poff, npb, cP, cQ, ra1, rb1, rw1);
         bf16_mfma<T, NB, LOLO>(L, 1, wr, wc, g8, l32, cr, ci);
-        bf16_stage<T, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0, okP, okQ);
+        bf16_stage<T, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0);
         interleave();
         __syncthreads();
         c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
@@ -475,8 +487,6 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
     const int flush_stages = pd.flush > kKC ? pd.flush / kKC : 1;
-    const bool okP = u.tp * T + lc < npb;
-    const bool okQ = u.tq * T + lc < npb;
     double2* part = a.partials + static_cast<size_t>(u.slot) * T * T;
 
     f32x16 cr[NB][NB], ci[NB][NB];
@@ -484,7 +494,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
     float2 ra[PPT], rb[PPT];
     float rw[PPT];
     uint32_t mk = 0;
-    const int cP = okP ? u.tp * T + lc : 0, cQ = okQ ? u.tq * T + lc : 0;
+    const uint32_t cP = col_offset(u.tp * T + lc, npb), cQ = col_offset(u.tq * T + lc, npb);
     Cursor cur;
     bool have = cursor_first(u, a.blocks, cur);
     __syncthreads();
@@ -496,11 +506,10 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
 #pragma unroll
         for (int h = 0; h < PPT / 2; ++h) {
           const int q = (PPT / 2) * lg + h;  // chunk of pairs 2q, 2q + 1
-          const bool v0 = (mk >> (2 * h)) & 1u, v1 = (mk >> (2 * h + 1)) & 1u;
-          const float w0 = (v0 && okQ) ? rw[2 * h] : 0.f;
-          const float w1 = (v1 && okQ) ? rw[2 * h + 1] : 0.f;
-          const float2 x0 = (v0 && okP) ? ra[2 * h] : float2{0.f, 0.f};
-          const float2 x1 = (v1 && okP) ? ra[2 * h + 1] : float2{0.f, 0.f};
+          const float w0 = ((mk >> (2 * h)) & 1u) ? rw[2 * h] : 0.f;
+          const float w1 = ((mk >> (2 * h + 1)) & 1u) ? rw[2 * h + 1] : 0.f;
+          const float2 x0 = ra[2 * h];
+          const float2 x1 = ra[2 * h + 1];
           const int o = swz32(lc, q);
           *reinterpret_cast<float4*>(&sA[buf][o]) = float4{x0.x, x0.y, x1.x, x1.y};
           *reinterpret_cast<float4*>(&sB[buf][o]) =
