@@ -135,32 +135,40 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef const dvec2 __attribute__((address_space(1)))* gd2ptr;
 typedef const double __attribute__((address_space(1)))* gdptr;
 
-// Operand and weight loads of one stage for one thread (pairs p0 + poff[k],
-// tile columns cP / cQ), issued unconditionally with clamped addresses; bit k
-// of the returned mask says whether pair k exists.
+// Operand and weight loads of one stage for one thread: pairs p0 + poff[k]
+// (the same for every lane of a wave, so rows, validity and weights are
+// wave-uniform and live in scalar registers), tile column byte offsets offP /
+// offQ (a column beyond npb reads column 0; its products are never used).
+// Loads are issued unconditionally with the row clamped into the block; bit
+// k of the returned mask says whether pair k exists (a missing pair gets
+// weight 0).
 template <int NP>
 __device__ __forceinline__ uint32_t load_pairs64(const HerkArgs& a, const ProbDesc& pd, int iw,
                                                  const Cursor& c, const int (&poff)[NP], int npb,
-                                                 int cP, int cQ, double2 (&ra)[NP],
+                                                 uint32_t offP, uint32_t offQ, double2 (&ra)[NP],
                                                  double2 (&rb)[NP], double (&rw)[NP]) {
+  typedef const char __attribute__((address_space(1)))* gcptr;
   const int b = __builtin_amdgcn_readfirstlane(c.b);
+  const int p0 = __builtin_amdgcn_readfirstlane(c.p0);
+  const int last = __builtin_amdgcn_readfirstlane(c.pend) - 1 - p0;
   const BlockDesc* bp = a.blocks + b;
-  const gd2ptr z = (gd2ptr)(ld_const(&bp->z, 0));
+  const uint32_t row_bytes = static_cast<uint32_t>(npb) * 16u;
+  const gcptr z = (gcptr)(ld_const(&bp->z, 0)) + static_cast<size_t>(p0) * row_bytes;
   const int64_t pbase = ld_const(&bp->pair_base, 0);
-  const gdptr w = (gdptr)(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase;
+  const double* w = static_cast<const double*>(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase + p0;
   uint32_t mask = 0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    const int p = c.p0 + poff[k];
-    const bool valid = p < c.pend;
-    const int pc = valid ? p : c.pend - 1;
+    const int o = __builtin_amdgcn_readfirstlane(poff[k]);
+    const bool valid = o <= last;
+    const int oc = valid ? o : last;
     mask |= valid ? (1u << k) : 0u;
-    const gd2ptr row = z + static_cast<size_t>(pc) * npb;
-    const dvec2 va = row[cP];
-    const dvec2 vb = row[cQ];
+    const gcptr row = z + static_cast<uint32_t>(oc) * row_bytes;
+    const dvec2 va = *(gd2ptr)(row + offP);
+    const dvec2 vb = *(gd2ptr)(row + offQ);
     ra[k] = double2{va.x, va.y};
     rb[k] = double2{vb.x, vb.y};
-    rw[k] = w[pc];
+    rw[k] = ld_const(w, oc);
   }
   return mask;
 }
@@ -192,9 +200,8 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
     const Unit u = a.units[a.wg_units[ui]];
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
-    const bool okP = u.tp * T + lc < npb;
-    const bool okQ = u.tq * T + lc < npb;
-    const int cP = okP ? u.tp * T + lc : 0, cQ = okQ ? u.tq * T + lc : 0;
+    const uint32_t cP = static_cast<uint32_t>(u.tp * T + lc < npb ? u.tp * T + lc : 0) * 16u;
+    const uint32_t cQ = static_cast<uint32_t>(u.tq * T + lc < npb ? u.tq * T + lc : 0) * 16u;
 
     f64x4 accR[NB][NB], accI[NB][NB];
 #pragma unroll
@@ -216,9 +223,8 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
 #pragma unroll
       for (int e = 0; e < NP; ++e) {
         const int r = lg + 2 * e;
-        const bool v = (mk >> e) & 1u;
-        const double w = (v && okQ) ? rw[e] : 0.0;
-        sA[buf][r][lc] = (v && okP) ? ra[e] : double2{0.0, 0.0};
+        const double w = ((mk >> e) & 1u) ? rw[e] : 0.0;
+        sA[buf][r][lc] = ra[e];
         sB[buf][r][lc] = double2{rb[e].x * w, rb[e].y * w};
       }
       Cursor nxt = cur;
