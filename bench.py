@@ -156,6 +156,27 @@ def summarize_trace(db, out_path, command):
     print(f"wrote {out_path}")
 
 
+def summarize_counters(db, out_path, command):
+    """Per-kernel mean of every counter of a rocprofv3 --pmc run (text)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = {}
+    for name, counter, val in con.execute("select kernel_name, counter_name, value "
+                                          "from counters_collection"):
+        short = name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        rows.setdefault(short[:80], {}).setdefault(counter, []).append(float(val))
+    counters = sorted({c for r in rows.values() for c in r})
+    with open(out_path, "w") as f:
+        f.write(f"# rocprofv3 counters (mean per dispatch)\n\ncommand: `{command}`\n\n")
+        f.write("| kernel | dispatches | " + " | ".join(counters) + " |\n")
+        f.write("|---|---|" + "---|" * len(counters) + "\n")
+        for k, r in sorted(rows.items()):
+            n = max(len(v) for v in r.values())
+            vals = [f"{sum(r[c]) / len(r[c]):.4g}" if c in r else "" for c in counters]
+            f.write(f"| {k} | {n} | " + " | ".join(vals) + " |\n")
+    print(f"wrote {out_path}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,9 +194,14 @@ def main():
                     help="write profiles/traffic_*.json from two rocprofv3 --pmc databases")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DB", "OUT"),
                     help="write a text summary of a rocprofv3 --kernel-trace database")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_DB", "OUT"),
+                    help="write a text table of every counter of a rocprofv3 --pmc database")
     ap.add_argument("--command", default="", help="profiled command (for the summaries)")
     args = ap.parse_args()
 
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.command)
+        return
     if args.summarize_pmc or args.summarize_trace:
         from synth import workload as _wl
         name = _wl(args.workload).name

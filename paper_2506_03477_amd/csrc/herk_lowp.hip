@@ -186,16 +186,19 @@ __device__ __forceinline__ void zero_acc(f32x16 (&cr)[NB][NB], f32x16 (&ci)[NB][
 // BF16x3
 // ---------------------------------------------------------------------------
 
-// LDS of the BF16x3 kernels: bf16 hi / lo planes of both operands, and of
-// the Q side rotated to (im, -re) for the imaginary part, two buffers.
-template <int T>
+// LDS of the BF16x3 kernels: bf16 hi / lo planes of both operands, two
+// buffers; with ROT also the Q side rotated to (im, -re) for the imaginary
+// part (staged once instead of rotated by every wave at every k-step, at
+// the price of 50% more LDS).
+template <int T, bool ROT>
 struct Bf16Lds {
+  static constexpr int kRot = ROT ? 2 : 0;
   uint32_t ah[2][T * 16];
   uint32_t al[2][T * 16];
   uint32_t bh[2][T * 16];
   uint32_t bl[2][T * 16];
-  uint32_t bih[2][T * 16];
-  uint32_t bil[2][T * 16];
+  uint32_t bih[kRot][T * 16];
+  uint32_t bil[kRot][T * 16];
 };
 
 // Stage one thread's 4 GPT pairs into LDS buffer `buf`: split the P side,
@@ -203,8 +206,8 @@ struct Bf16Lds {
 // store the Q side also rotated.  Thread owns tile column lc and pair groups
 // q = lg + LG gi (4 pairs each).  Columns beyond npb hold real (clamped)
 // data whose products land in tile rows / columns the reduction ignores.
-template <int T, int GPT, int LG>
-__device__ __forceinline__ void bf16_stage(Bf16Lds<T>& L, int buf, int lc, int lg,
+template <int T, bool ROT, int GPT, int LG>
+__device__ __forceinline__ void bf16_stage(Bf16Lds<T, ROT>& L, int buf, int lc, int lg,
                                            const float2 (&ra)[4 * GPT], const float2 (&rb)[4 * GPT],
                                            const float (&rw)[4 * GPT], uint32_t mask) {
 #pragma unroll
@@ -223,16 +226,18 @@ __device__ __forceinline__ void bf16_stage(Bf16Lds<T>& L, int buf, int lc, int l
     *reinterpret_cast<uint4*>(&L.al[buf][o]) = uint4{al[0], al[1], al[2], al[3]};
     *reinterpret_cast<uint4*>(&L.bh[buf][o]) = uint4{bh[0], bh[1], bh[2], bh[3]};
     *reinterpret_cast<uint4*>(&L.bl[buf][o]) = uint4{bl[0], bl[1], bl[2], bl[3]};
-    *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(uint4{bh[0], bh[1], bh[2], bh[3]});
-    *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(uint4{bl[0], bl[1], bl[2], bl[3]});
+    if constexpr (ROT) {
+      *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(uint4{bh[0], bh[1], bh[2], bh[3]});
+      *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(uint4{bl[0], bl[1], bl[2], bl[3]});
+    }
   }
 }
 
 // The 2 k-steps (8 pairs each) of one stage from LDS buffer `buf`.  One
 // product kind at a time over the accumulators, so dependent MFMAs on the
 // same accumulator are 2 NB^2 instructions apart.
-template <int T, int NB, bool LOLO>
-__device__ __forceinline__ void bf16_mfma(const Bf16Lds<T>& L, int buf, int wr, int wc, int g8,
+template <int T, bool ROT, int NB, bool LOLO>
+__device__ __forceinline__ void bf16_mfma(const Bf16Lds<T, ROT>& L, int buf, int wr, int wc, int g8,
                                           int l32, f32x16 (&cr)[NB][NB], f32x16 (&ci)[NB][NB]) {
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
@@ -247,10 +252,17 @@ __device__ __forceinline__ void bf16_mfma(const Bf16Lds<T>& L, int buf, int wr, 
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int row = wc * (T / 2) + j * 32 + l32;
-      fbh[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bh[buf][swz(row, q)]));
-      fbl[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bl[buf][swz(row, q)]));
-      fih[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bih[buf][swz(row, q)]));  // (bi, -br)
-      fil[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bil[buf][swz(row, q)]));
+      const uint4 bh = *reinterpret_cast<const uint4*>(&L.bh[buf][swz(row, q)]);
+      const uint4 bl = *reinterpret_cast<const uint4*>(&L.bl[buf][swz(row, q)]);
+      fbh[j] = as_bf16x8(bh);
+      fbl[j] = as_bf16x8(bl);
+      if constexpr (ROT) {  // (bi, -br) for the imaginary part
+        fih[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bih[buf][swz(row, q)]));
+        fil[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bil[buf][swz(row, q)]));
+      } else {
+        fih[j] = as_bf16x8(rot_neg4(bh));
+        fil[j] = as_bf16x8(rot_neg4(bl));
+      }
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i)
@@ -295,7 +307,8 @@ __global__ __launch_bounds__(kNT, OCC) void herk_bf16x3_kernel(HerkArgs a) {
   constexpr int LG = kNT / T;         // loader groups
   constexpr int GPT = 4 / LG;         // pair groups (of 4) per thread
   constexpr int NP = 4 * GPT;         // pairs per thread per stage
-  __shared__ __attribute__((aligned(16))) Bf16Lds<T> L;
+  constexpr bool ROT = OCC == 1;      // two workgroups per CU: no rotated planes
+  __shared__ __attribute__((aligned(16))) Bf16Lds<T, ROT> L;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -334,14 +347,14 @@ __global__ __launch_bounds__(kNT, OCC) void herk_bf16x3_kernel(HerkArgs a) {
     bool first_flush = true;
     while (have) {
       for (int ns = 0; ns < flush_stages && have; ++ns) {
-        bf16_stage<T, GPT, LG>(L, buf, lc, lg, ra, rb, rw, mk);
+        bf16_stage<T, ROT, GPT, LG>(L, buf, lc, lg, ra, rb, rw, mk);
         // next stage's loads in flight during this stage's MFMAs (the cursor
         // stays on a valid stage when there is no next one)
         Cursor nxt = cur;
         const bool more = cursor_next<kKC>(u, a.blocks, nxt);
         mk = load_pairs<NP>(a, pd, u.iw, nxt, poff, npb, cP, cQ, ra, rb, rw);
         __syncthreads();
-        bf16_mfma<T, NB, LOLO>(L, buf, wr, wc, g8, l32, cr, ci);
+        bf16_mfma<T, ROT, NB, LOLO>(L, buf, wr, wc, g8, l32, cr, ci);
         cur = nxt;
         have = more;
         buf ^= 1;
@@ -366,7 +379,8 @@ __global__ __launch_bounds__(kNT, OCC) void herk_bf16x3_kernel(HerkArgs a) {
 template <bool LOLO>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
   constexpr int T = 128, NB = 2, LG = 2, GPT = 2, NP = 8;
-  __shared__ __attribute__((aligned(16))) Bf16Lds<T> L;
+  constexpr bool ROT = true;
+  __shared__ __attribute__((aligned(16))) Bf16Lds<T, ROT> L;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -417,7 +431,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
     if (h_s) {
       mk0 = load_pairs<NP>(a, pd, u.iw, c_s, poff, npb, cP, cQ, ra0, rb0, rw0);
       mk1 = load_pairs<NP>(a, pd, u.iw, c_1, poff, npb, cP, cQ, ra1, rb1, rw1);
-      bf16_stage<T, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0);
+      bf16_stage<T, ROT, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0);
     }
     __syncthreads();
     bool first_flush = true;
@@ -427,8 +441,8 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
         c_2 = c_1;
         bool h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
         mk0 = load_pairs<NP>(a, pd, u.iw, c_2, poff, npb, cP, cQ, ra0, rb0, rw0);
-        bf16_mfma<T, NB, LOLO>(L, 0, wr, wc, g8, l32, cr, ci);
-        bf16_stage<T, GPT, LG>(L, 1, lc, lg, ra1, rb1, rw1, mk1);   // unused when !h_1
+        bf16_mfma<T, ROT, NB, LOLO>(L, 0, wr, wc, g8, l32, cr, ci);
+        bf16_stage<T, ROT, GPT, LG>(L, 1, lc, lg, ra1, rb1, rw1, mk1);   // unused when !h_1
         interleave();
         __syncthreads();
         c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
@@ -437,8 +451,8 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
         c_2 = c_1;
         h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
         mk1 = load_pairs<NP>(a, pd, u.iw, c_2, poff, npb, cP, cQ, ra1, rb1, rw1);
-        bf16_mfma<T, NB, LOLO>(L, 1, wr, wc, g8, l32, cr, ci);
-        bf16_stage<T, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0);
+        bf16_mfma<T, ROT, NB, LOLO>(L, 1, wr, wc, g8, l32, cr, ci);
+        bf16_stage<T, ROT, GPT, LG>(L, 0, lc, lg, ra0, rb0, rw0, mk0);
         interleave();
         __syncthreads();
         c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
