@@ -101,6 +101,7 @@ struct chi0_ctx {
   int ncu = 0;
   DevBuf partials;
   DevBuf wts;           // pair weights of the current call
+  DevBuf zsplit;        // pre-split P-side planes of the current call
   DevBuf gj_work, gj_wrow, gj_piv, gj_perm;
   DevBuf hpd_p, hpd_c, hpd_dinv;  // HPD inverse: kept panel, new panel, D^{-1}
   uint64_t ws_gen = 1;
@@ -247,12 +248,24 @@ struct HostPlan {
   int nblocks_total = 0;
 };
 
+// Lower-triangle tiles of a TP x TQ tiling of an npb x npb matrix: tile
+// (tp, tq) is needed iff it holds an entry on or below the diagonal.
+void lower_tiles(int npb, int TP, int TQ, std::vector<std::pair<int, int>>& out) {
+  out.clear();
+  const int ntp = (npb + TP - 1) / TP;
+  for (int tp = 0; tp < ntp; ++tp) {
+    const int last_row = std::min((tp + 1) * TP, npb) - 1;
+    for (int tq = 0; tq * TQ <= last_row; ++tq) out.emplace_back(tp, tq);
+  }
+}
+
 void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int nprob, HostPlan& hp) {
-  const int T = tc.tile;
+  const int TP = tc.tile, TQ = tc.tile_q;
   struct P {
-    int npb, nomega, nt, ntl, b0, nb;
+    int npb, nomega, ntl, b0, nb;
     int64_t K;
     std::vector<int64_t> cum;  // cumulative pairs at block starts
+    std::vector<std::pair<int, int>> tiles;
   };
   std::vector<P> ps(nprob);
   int bflat = 0;
@@ -261,8 +274,8 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
     P& q = ps[p];
     q.npb = probs[p].npb;
     q.nomega = probs[p].nomega;
-    q.nt = (q.npb + T - 1) / T;
-    q.ntl = q.nt * (q.nt + 1) / 2;
+    lower_tiles(q.npb, TP, TQ, q.tiles);
+    q.ntl = static_cast<int>(q.tiles.size());
     q.b0 = bflat;
     q.nb = probs[p].nblocks;
     q.cum.resize(q.nb + 1);
@@ -279,7 +292,7 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
   // partial storage bounded
   const double min_pairs = 1024.0;
   double per_unit = std::max(min_pairs, work / (8.0 * nwg));
-  const double slot_bytes = static_cast<double>(T) * T * 16.0;
+  const double slot_bytes = static_cast<double>(TP) * TQ * 16.0;
   const double max_partial_bytes = 6.0e9;
   auto count_units = [&](double pu) {
     double n = 0;
@@ -295,8 +308,19 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
     P& q = ps[p];
     int64_t s = std::max<int64_t>(1, std::llround(std::ceil(static_cast<double>(q.K) / per_unit)));
     if (q.K == 0) s = 1;
+    // range boundaries fall on multiples of the staging chunk within their
+    // block, so every stage of a unit is a whole, aligned chunk of a block
+    // (or that block's tail)
+    auto align = [&](int64_t g) {
+      if (q.nb == 0 || g <= 0 || g >= q.K) return std::max<int64_t>(0, std::min(g, q.K));
+      int bb = static_cast<int>(std::upper_bound(q.cum.begin(), q.cum.end(), g) - q.cum.begin()) - 1;
+      bb = std::min(bb, q.nb - 1);
+      const int64_t kb = q.cum[bb + 1] - q.cum[bb];
+      const int64_t loc = std::min(kb, (g - q.cum[bb] + tc.kchunk / 2) / tc.kchunk * tc.kchunk);
+      return q.cum[bb] + loc;
+    };
     for (int64_t r = 0; r < s; ++r) {
-      const int64_t g0 = q.K * r / s, g1 = q.K * (r + 1) / s;
+      const int64_t g0 = align(q.K * r / s), g1 = align(q.K * (r + 1) / s);
       Range rg{};
       rg.n = g1 - g0;
       if (q.nb == 0) {
@@ -321,25 +345,25 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
   for (int p = 0; p < nprob; ++p) {
     P& q = ps[p];
     for (int iw = 0; iw < q.nomega; ++iw)
-      for (int tp = 0; tp < q.nt; ++tp)
-        for (int tq = 0; tq <= tp; ++tq) {
-          TileJob j{p, iw, tp, tq, static_cast<int32_t>(hp.units.size()),
-                    static_cast<int32_t>(ranges[p].size())};
-          hp.jobs.push_back(j);
-          for (size_t r = 0; r < ranges[p].size(); ++r) {
-            const Range& rg = ranges[p][r];
-            Unit u{};
-            u.prob = p; u.iw = iw; u.tp = tp; u.tq = tq;
-            u.b0 = rg.b0; u.p0 = rg.p0; u.b1 = rg.b1; u.p1 = rg.p1;
-            u.slot = static_cast<int32_t>(hp.units.size());
-            hp.units.push_back(u);
-            unit_range_idx.push_back(static_cast<int>(r));
-            // cost: pairs rounded up to staging chunks per block touched, plus a
-            // fixed per-unit cost (zeroing and writing the tile)
-            const double nblk = std::max(0, rg.b1 - rg.b0 + 1);
-            hp.cost.push_back(static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0);
-          }
+      for (const auto& t : q.tiles) {
+        const int tp = t.first, tq = t.second;
+        TileJob j{p, iw, tp, tq, static_cast<int32_t>(hp.units.size()),
+                  static_cast<int32_t>(ranges[p].size())};
+        hp.jobs.push_back(j);
+        for (size_t r = 0; r < ranges[p].size(); ++r) {
+          const Range& rg = ranges[p][r];
+          Unit u{};
+          u.prob = p; u.iw = iw; u.tp = tp; u.tq = tq;
+          u.b0 = rg.b0; u.p0 = rg.p0; u.b1 = rg.b1; u.p1 = rg.p1;
+          u.slot = static_cast<int32_t>(hp.units.size());
+          hp.units.push_back(u);
+          unit_range_idx.push_back(static_cast<int>(r));
+          // cost: pairs rounded up to staging chunks per block touched, plus a
+          // fixed per-unit cost (zeroing and writing the tile)
+          const double nblk = std::max(0, rg.b1 - rg.b0 + 1);
+          hp.cost.push_back(static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0);
         }
+      }
   }
   // locality order: (problem, range, tile, frequency)
   std::vector<int> order(hp.units.size());
@@ -469,8 +493,8 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
     pl = it->second.get();
   }
   if (pl->nunits == 0) return CHI0_OK;
-  const int T = pl->tc.tile;
-  int rc = h->partials.reserve(static_cast<size_t>(pl->nunits) * T * T * sizeof(double2), &h->ws_gen);
+  const int TP = pl->tc.tile, TQ = pl->tc.tile_q;
+  int rc = h->partials.reserve(static_cast<size_t>(pl->nunits) * TP * TQ * sizeof(double2), &h->ws_gen);
   if (rc) return rc;
   const int nblocks_total = pl->nblocks_total;
 
@@ -489,11 +513,29 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   }
   if ((rc = h->wts.reserve(std::max<size_t>(wbytes, 256), &h->ws_gen))) return rc;
 
+  // pre-split P-side planes (kernels that read them only)
+  const bool presplit = pl->tc.presplit != 0;
+  size_t zbytes = 0;
+  int64_t max_groups = 0;
+  int max_npb = 0;
+  if (presplit) {
+    for (int p = 0; p < nprob; ++p)
+      for (int b = 0; b < probs[p].nblocks; ++b) {
+        const int64_t G = presplit_groups(static_cast<int64_t>(probs[p].blocks[b].nocc) *
+                                          probs[p].blocks[b].nunocc);
+        const size_t plane = ((static_cast<size_t>(G) * probs[p].npb * 16 + 255) / 256) * 256;
+        zbytes += 2 * plane;
+        max_groups = std::max(max_groups, G);
+        max_npb = std::max(max_npb, probs[p].npb);
+      }
+    if ((rc = h->zsplit.reserve(std::max<size_t>(zbytes, 256), &h->ws_gen))) return rc;
+  }
+
   // per-call tables (pointers change between calls) via pinned staging
   std::vector<BlockDesc> bt;
   bt.reserve(pl->nblocks_total);
   std::vector<ProbDesc> ptab(nprob);
-  size_t woff = 0;
+  size_t woff = 0, zoff = 0;
   for (int p = 0; p < nprob; ++p) {
     ptab[p].chi0 = static_cast<double2*>(probs[p].chi0);
     ptab[p].omega = probs[p].omega;
@@ -515,6 +557,15 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
       d.pair_base = base;
       d.prob = p;
       d.pad = 0;
+      d.zs = nullptr;
+      d.zs_plane = 0;
+      if (presplit) {
+        const int64_t G = presplit_groups(static_cast<int64_t>(bl.nocc) * bl.nunocc);
+        const size_t plane = ((static_cast<size_t>(G) * probs[p].npb * 16 + 255) / 256) * 256;
+        d.zs = static_cast<char*>(h->zsplit.p) + zoff;
+        d.zs_plane = static_cast<int64_t>(plane);
+        zoff += 2 * plane;
+      }
       base += static_cast<int64_t>(bl.nocc) * bl.nunocc;
       bt.push_back(d);
     }
@@ -546,7 +597,9 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   ra.jobs = static_cast<const TileJob*>(pl->d_jobs.p);
   ra.probs = ha.probs;
   ra.partials = ha.partials;
-  ra.tile = T;
+  ra.tile_p = TP;
+  ra.tile_q = TQ;
+  ra.pad = 0;
   ra.accumulate = (flags & CHI0_ACCUMULATE) ? 1 : 0;
 
   const bool use_graph = (flags & CHI0_USE_GRAPH) && !h->profiling;
@@ -575,6 +628,8 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
       hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess)
         e = pair_weights_launch(ha.blocks, ha.probs, nblocks_total, kmax, delta_min, kind == HERK_FP64, cs);
+      if (e == hipSuccess && presplit)
+        e = presplit_launch(ha.blocks, ha.probs, nblocks_total, max_groups, max_npb, cs);
       if (e == hipSuccess) e = herk_launch(kind, pl->tile_idx, ha, pl->nwg, cs);
       if (e == hipSuccess) e = reduce_launch(ra, pl->njobs, cs);
       hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -598,6 +653,10 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   hipError_t ew = pair_weights_launch(ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
                                       kind == HERK_FP64, stream);
   if (ew != hipSuccess) return fail(CHI0_EDEVICE, "pair-weight launch: %s", hipGetErrorString(ew));
+  if (presplit) {
+    ew = presplit_launch(ha.blocks, ha.probs, nblocks_total, max_groups, max_npb, stream);
+    if (ew != hipSuccess) return fail(CHI0_EDEVICE, "pre-split launch: %s", hipGetErrorString(ew));
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->profiling) {
     e0 = get_event(h);
@@ -667,6 +726,7 @@ int chi0_destroy(chi0_handle h) {
   h->plans.clear();
   h->partials.release();
   h->wts.release();
+  h->zsplit.release();
   h->gj_work.release();
   h->gj_wrow.release();
   h->gj_piv.release();
@@ -807,7 +867,7 @@ int chi0_tile_info(chi0_precision prec, int32_t tile, int32_t* tile_p, int32_t* 
   if (tile < 0 || tile >= herk_tile_count(k)) return fail(CHI0_EINVAL, "tile %d out of range", tile);
   const TileConfig tc = herk_tile_config(k, tile);
   if (tile_p) *tile_p = tc.tile;
-  if (tile_q) *tile_q = tc.tile;
+  if (tile_q) *tile_q = tc.tile_q;
   if (kchunk) *kchunk = tc.kchunk;
   if (flush_len) *flush_len = tc.flush;
   return CHI0_OK;

@@ -17,6 +17,11 @@ struct BlockDesc {
   int64_t pair_base;        // first pair of this block in its problem's pair list
   int32_t prob;             // problem index
   int32_t pad;
+  // BF16 hi / lo planes of Z split once per call (only for kernels that read
+  // the P side pre-split): plane[g][col][4] words, g = group of 4 pairs,
+  // padded with zero pairs to whole 16-pair stages; lo = hi + zs_plane bytes.
+  void* zs;
+  int64_t zs_plane;
 };
 
 // One q-point (device table entry).
@@ -77,21 +82,30 @@ struct ReduceArgs {
   const TileJob* jobs;
   const ProbDesc* probs;
   const double2* partials;
-  int32_t tile;               // T
+  int32_t tile_p;             // tile rows
+  int32_t tile_q;             // tile columns
   int32_t accumulate;
+  int32_t pad;
 };
 
 // Kernel variants of the rank-K contraction.
 enum HerkKind { HERK_FP64 = 0, HERK_FP32 = 1, HERK_BF16X3 = 2 };
 
 struct TileConfig {
-  int32_t tile;      // T: tiles are T x T complex elements
+  int32_t tile;      // tile rows (P side), complex elements
   int32_t kchunk;    // pairs staged in LDS per step
   int32_t flush;     // FP32 run length in pairs (0: FP64 accumulation)
   int32_t threads;   // workgroup size
+  int32_t tile_q;    // tile columns (Q side); tile = tile_q or tile = 2 tile_q
+  int32_t presplit;  // 1: the kernel reads the P side from BlockDesc::zs
 };
 
+// Groups of 4 pairs in a block's pre-split planes (whole 16-pair stages).
+__host__ __device__ inline int64_t presplit_groups(int64_t pairs) { return (pairs + 15) / 16 * 4; }
+
 // Host launchers (defined next to their kernels).
+hipError_t presplit_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
+                           int64_t max_groups, int max_npb, hipStream_t s);
 hipError_t pair_weights_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
                                int kmax, double delta_min, bool f64, hipStream_t s);
 int herk_tile_count(int kind);

@@ -276,9 +276,9 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
 
 // Tile table of the FP64 path.
 static const TileConfig kFp64Tiles[] = {
-    {128, 8, 0, 256},   // pipelined, one workgroup per CU
-    {64, 16, 0, 256},
-    {32, 16, 0, 256},
+    {128, 8, 0, 256, 128},   // pipelined, one workgroup per CU
+    {64, 16, 0, 256, 64},
+    {32, 16, 0, 256, 32},
 };
 
 int herk_fp64_tile_count() { return sizeof(kFp64Tiles) / sizeof(kFp64Tiles[0]); }

@@ -466,6 +466,304 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Tall tiles: 256 (P) x 128 (Q), P side pre-split.  The Q side (scaled and
+// split per frequency) is shared by twice as many P rows as in a square
+// tile, and the P side arrives already split (presplit.hip) and goes from
+// memory straight into LDS (global_load_lds, no registers, no vector ALU),
+// so the only staging arithmetic left is the Q side's.  Each wave's
+// 128 x 64 sub-tile (4 x 2 blocks, 256 FP32 accumulators per lane) does 48
+// MFMAs per 16 fragment reads.
+// ---------------------------------------------------------------------------
+struct Bf16TallLds {
+  uint32_t ah[2][256 * 16];
+  uint32_t al[2][256 * 16];
+  uint32_t bh[2][128 * 16];
+  uint32_t bl[2][128 * 16];
+  uint32_t bih[2][128 * 16];
+  uint32_t bil[2][128 * 16];
+};
+
+// Q-side loads of one stage: column offQ of the 8 pairs 4 (lg + 2 gi) + e,
+// and their weights (wave-uniform rows, see load_pairs).
+__device__ __forceinline__ uint32_t tall_load_q(const HerkArgs& a, const ProbDesc& pd, int iw,
+                                                const Cursor& c, int lg, int npb, uint32_t offQ,
+                                                float2 (&rb)[8], float (&rw)[8]) {
+  typedef const char __attribute__((address_space(1)))* gcptr;
+  const int b = __builtin_amdgcn_readfirstlane(c.b);
+  const int p0 = __builtin_amdgcn_readfirstlane(c.p0);
+  const int last = __builtin_amdgcn_readfirstlane(c.pend) - 1 - p0;
+  const int g = __builtin_amdgcn_readfirstlane(lg);
+  const BlockDesc* bp = a.blocks + b;
+  const uint32_t row_bytes = static_cast<uint32_t>(npb) * 8u;
+  const gcptr z = (gcptr)(ld_const(&bp->z, 0)) + static_cast<size_t>(p0) * row_bytes;
+  const int64_t pbase = ld_const(&bp->pair_base, 0);
+  const float* w = static_cast<const float*>(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase + p0;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int o = 4 * (g + 2 * (k >> 2)) + (k & 3);
+    const bool valid = o <= last;
+    const int oc = valid ? o : last;
+    mask |= valid ? (1u << k) : 0u;
+    rb[k] = ld_c64((gf2ptr)(z + static_cast<uint32_t>(oc) * row_bytes + offQ));
+    rw[k] = ld_const(w, oc);
+  }
+  return mask;
+}
+
+// P side of one stage (16 pairs, starting at a multiple of 16 within the
+// block) from the pre-split planes: thread t loads tile row t's four 16-byte
+// chunks (4 pairs each) of the hi and of the lo plane, column offset offP.
+// No arithmetic: the words go to LDS as they are (tall_stage_p).
+__device__ __forceinline__ void tall_load_p(const HerkArgs& a, const Cursor& c, int npb,
+                                            uint32_t offP, uint4 (&ph)[4], uint4 (&pl)[4]) {
+  typedef const char __attribute__((address_space(1)))* gcptr;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  typedef const u32x4 __attribute__((address_space(1)))* gu4ptr;
+  const int b = __builtin_amdgcn_readfirstlane(c.b);
+  const int p0 = __builtin_amdgcn_readfirstlane(c.p0);
+  const BlockDesc* bp = a.blocks + b;
+  const size_t chunk_bytes = static_cast<size_t>(npb) * 16;
+  const gcptr hi = (gcptr)(ld_const(&bp->zs, 0)) + static_cast<size_t>(p0 >> 2) * chunk_bytes;
+  const gcptr lo = hi + ld_const(&bp->zs_plane, 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t o = static_cast<uint32_t>(q) * static_cast<uint32_t>(chunk_bytes) + offP;
+    const u32x4 h = *(gu4ptr)(hi + o);
+    const u32x4 l = *(gu4ptr)(lo + o);
+    ph[q] = uint4{h.x, h.y, h.z, h.w};
+    pl[q] = uint4{l.x, l.y, l.z, l.w};
+  }
+}
+
+__device__ __forceinline__ void tall_stage_p(Bf16TallLds& L, int buf, int lp, const uint4 (&ph)[4],
+                                             const uint4 (&pl)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int o = swz(lp, q);
+    *reinterpret_cast<uint4*>(&L.ah[buf][o]) = ph[q];
+    *reinterpret_cast<uint4*>(&L.al[buf][o]) = pl[q];
+  }
+}
+
+// Q side of one stage into LDS buffer `buf`: column lq, pair chunks lg and
+// lg + 2, scaled (0 for a missing pair), split and rotated.
+__device__ __forceinline__ void tall_stage_q(Bf16TallLds& L, int buf, int lq, int lg,
+                                             const float2 (&rb)[8], const float (&rw)[8],
+                                             uint32_t mask) {
+#pragma unroll
+  for (int gi = 0; gi < 2; ++gi) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * gi + e;
+      const float wq = ((mask >> k) & 1u) ? rw[k] : 0.f;
+      split2(rb[k].x * wq, rb[k].y * wq, h[e], l[e]);
+    }
+    const int o = swz(lq, lg + 2 * gi);
+    const uint4 vh = uint4{h[0], h[1], h[2], h[3]};
+    const uint4 vl = uint4{l[0], l[1], l[2], l[3]};
+    *reinterpret_cast<uint4*>(&L.bh[buf][o]) = vh;
+    *reinterpret_cast<uint4*>(&L.bl[buf][o]) = vl;
+    *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(vh);
+    *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(vl);
+  }
+}
+
+// The 2 k-steps of one stage for a wave's 128 x 64 sub-tile.
+template <bool LOLO>
+__device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr, int wc, int g8,
+                                          int l32, f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    const int q = 2 * ks + g8;
+    bf16x8 fah[4], fal[4], fbh[2], fbl[2], fih[2], fil[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wr * 128 + i * 32 + l32;
+      fah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.ah[buf][swz(row, q)]));
+      fal[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.al[buf][swz(row, q)]));
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = wc * 64 + j * 32 + l32;
+      fbh[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bh[buf][swz(row, q)]));
+      fbl[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bl[buf][swz(row, q)]));
+      fih[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bih[buf][swz(row, q)]));
+      fil[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bil[buf][swz(row, q)]));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbh[j], cr[i][j], 0, 0, 0);
+        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fih[j], ci[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbl[j], cr[i][j], 0, 0, 0);
+        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fil[j], ci[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbh[j], cr[i][j], 0, 0, 0);
+        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fih[j], ci[i][j], 0, 0, 0);
+      }
+    if (LOLO) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbl[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fil[j], ci[i][j], 0, 0, 0);
+        }
+    }
+  }
+}
+
+// Add (or store, when first) a wave's 128 x 64 accumulators into the FP64
+// partial tile (256 x 128, row-major); 16 old values are loaded as a group.
+__device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32x16 (&cr)[4][2],
+                                           const f32x16 (&ci)[4][2], int wr, int wc, int lane,
+                                           bool first) {
+  constexpr int TQ = 128;
+  const int g = lane >> 5;
+  const int cl = lane & 31;
+  int base = (wr * 128 + 4 * g) * TQ + wc * 64 + cl;
+  asm volatile("" : "+v"(base));
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      double2* blk = part + base + i * 32 * TQ + j * 32;
+      double2 o[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[r] = double2{0.0, 0.0};
+      if (!first) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[r] = blk[(8 * (r >> 2) + (r & 3)) * TQ];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        blk[(8 * (r >> 2) + (r & 3)) * TQ] =
+            double2{static_cast<double>(cr[i][j][r]) + o[r].x,
+                    static_cast<double>(ci[i][j][r]) + o[r].y};
+    }
+}
+
+// Software-pipelined tall-tile kernel.  Stage s (buffer s % 2):
+//   1. the P loads of stage s + 1 (one register set) and the Q loads of stage
+//      s + 2 (register set s % 2);
+//   2. the MFMAs of stage s and the Q staging of stage s + 1 (register set
+//      (s + 1) % 2) in one block with interleaving hints;
+//   3. the P staging of stage s + 1 (its loads have had the MFMA phase to
+//      land), then one barrier.
+template <bool LOLO>
+__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
+  constexpr int TP = 256, TQ = 128;
+  __shared__ __attribute__((aligned(16))) Bf16TallLds L;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g8 = lane >> 5;
+  const int l32 = lane & 31;
+  const int lp = tid;              // P row of the tile
+  const int lq = tid & (TQ - 1);   // Q column
+  const int lg = tid >> 7;         // Q pair group (wave-uniform)
+
+  const int beg = a.wg_offsets[blockIdx.x];
+  const int end = a.wg_offsets[blockIdx.x + 1];
+  for (int ui = beg; ui < end; ++ui) {
+    const Unit u = a.units[a.wg_units[ui]];
+    const ProbDesc pd = a.probs[u.prob];
+    const int npb = pd.npb;
+    const int flush_pairs = pd.flush > 2 * kKC ? pd.flush / (2 * kKC) : 1;
+    const uint32_t cQ = col_offset(u.tq * TQ + lq, npb);
+    const uint32_t cP = (u.tp * TP + lp < npb ? static_cast<uint32_t>(u.tp * TP + lp) : 0u) * 16u;
+    double2* part = a.partials + static_cast<size_t>(u.slot) * TP * TQ;
+
+    f32x16 cr[4][2], ci[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = f32x16{0};
+        ci[i][j] = f32x16{0};
+      }
+    float2 rb0[8], rb1[8];
+    float rw0[8], rw1[8];
+    uint4 ph[4], pl[4];
+    uint32_t mk0 = 0, mk1 = 0;
+
+    auto interleave = [&]() {
+#pragma unroll
+      for (int k = 0; k < (LOLO ? 128 : 96); ++k) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // 1 MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // 2 VALU
+      }
+    };
+
+    Cursor c_s, c_1, c_2;
+    bool h_s = cursor_first(u, a.blocks, c_s);
+    c_1 = c_s;
+    bool h_1 = h_s && cursor_next<kKC>(u, a.blocks, c_1);
+    __syncthreads();  // previous unit's last MFMAs are done with the LDS
+    if (h_s) {
+      tall_load_p(a, c_s, npb, cP, ph, pl);
+      mk0 = tall_load_q(a, pd, u.iw, c_s, lg, npb, cQ, rb0, rw0);
+      mk1 = tall_load_q(a, pd, u.iw, c_1, lg, npb, cQ, rb1, rw1);
+      tall_stage_p(L, 0, lp, ph, pl);
+      tall_stage_q(L, 0, lq, lg, rb0, rw0, mk0);
+    }
+    __syncthreads();
+    bool first_flush = true;
+    while (h_s) {
+      for (int np = 0; np < flush_pairs && h_s; ++np) {
+        // ---- even stage: LDS 0; stage s + 1 -> LDS 1
+        c_2 = c_1;
+        bool h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
+        tall_load_p(a, c_1, npb, cP, ph, pl);                     // unused when !h_1
+        mk0 = tall_load_q(a, pd, u.iw, c_2, lg, npb, cQ, rb0, rw0);
+        tall_mfma<LOLO>(L, 0, wr, wc, g8, l32, cr, ci);
+        tall_stage_q(L, 1, lq, lg, rb1, rw1, mk1);
+        interleave();
+        tall_stage_p(L, 1, lp, ph, pl);
+        __syncthreads();
+        c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
+        if (!h_s) break;
+        // ---- odd stage: LDS 1; stage s + 1 -> LDS 0
+        c_2 = c_1;
+        h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
+        tall_load_p(a, c_1, npb, cP, ph, pl);
+        mk1 = tall_load_q(a, pd, u.iw, c_2, lg, npb, cQ, rb1, rw1);
+        tall_mfma<LOLO>(L, 1, wr, wc, g8, l32, cr, ci);
+        tall_stage_q(L, 0, lq, lg, rb0, rw0, mk0);
+        interleave();
+        tall_stage_p(L, 0, lp, ph, pl);
+        __syncthreads();
+        c_s = c_1; h_s = h_1; c_1 = c_2; h_1 = h_2;
+      }
+      tall_flush(part, cr, ci, wr, wc, lane, first_flush);
+      first_flush = false;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = f32x16{0};
+          ci[i][j] = f32x16{0};
+        }
+    }
+    if (first_flush) tall_flush(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP32: v_mfma_f32_32x32x2f32, contraction slots (re, im) of one pair.  LDS
 // holds the operands as complex64, rows = tile columns, 16 pairs per row
 // (8 chunks of 2 pairs, XOR-swizzled).
@@ -584,15 +882,16 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
 // Tile tables: {tile, pairs per stage, cap of the FP32 run length (pairs),
 // threads}.  BF16X3 with CHI0_BF16_LOLO selects the variant adding lo*lo.
 static const TileConfig kBf16Tiles[] = {
-    {128, kKC, 4096, kNT},   // 0: software-pipelined kernel
-    {128, kKC, 4096, kNT},   // 1: staging and MFMAs in sequence
-    {64, kKC, 4096, kNT},    // 2
-    {128, kKC, 1024, kNT},   // 3: pipelined, shorter FP32 runs
-    {128, kKC, 4096, kNT},   // 4: in sequence, two workgroups per CU
+    {128, kKC, 4096, kNT, 128},   // 0: software-pipelined kernel
+    {128, kKC, 4096, kNT, 128},   // 1: staging and MFMAs in sequence
+    {64, kKC, 4096, kNT, 64},     // 2
+    {128, kKC, 1024, kNT, 128},   // 3: pipelined, shorter FP32 runs
+    {128, kKC, 4096, kNT, 128},   // 4: in sequence, two workgroups per CU
+    {256, kKC, 4096, kNT, 128, 1},   // 5: pipelined, tall 256 x 128 tiles, P pre-split
 };
 static const TileConfig kFp32Tiles[] = {
-    {128, kKC, 4096, kNT},
-    {64, kKC, 4096, kNT},
+    {128, kKC, 4096, kNT, 128},
+    {64, kKC, 4096, kNT, 64},
 };
 
 int herk_bf16x3_tile_count() { return sizeof(kBf16Tiles) / sizeof(kBf16Tiles[0]); }
@@ -618,7 +917,13 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
       break;
     case 1: launch_bf16_seq<128, 1>(lolo, a, nwg, s); break;
     case 2: launch_bf16_seq<64, 1>(lolo, a, nwg, s); break;
-    default: launch_bf16_seq<128, 2>(lolo, a, nwg, s); break;
+    case 4: launch_bf16_seq<128, 2>(lolo, a, nwg, s); break;
+    default:
+      if (lolo)
+        hipLaunchKernelGGL(herk_bf16x3_tall_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
+      else
+        hipLaunchKernelGGL(herk_bf16x3_tall_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
+      break;
   }
   return hipGetLastError();
 }
@@ -636,8 +941,11 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
     case 2:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<64, false, 1>, kNT, 0);
       break;
-    default:
+    case 4:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false, 2>, kNT, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall_kernel<false>, kNT, 0);
       break;
   }
   return e == hipSuccess && n > 0 ? n : 1;

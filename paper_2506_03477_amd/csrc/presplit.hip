@@ -1,0 +1,72 @@
+// BF16 hi / lo split of the unscaled P-side operand, once per call.
+//
+// The P side of the rank-K update (conj(Z_P) without the pair weight) does
+// not depend on the frequency, so kernels that read it pre-split save the
+// split in every (tile, frequency) unit.  For every block, group g of four
+// pairs and product-basis column c, the four pairs' (re, im) values are
+// rounded to bf16 hi = RNE(x) and lo = RNE(x - hi) (x - hi is exact in FP32)
+// and stored as 16-byte chunks
+//   hi plane: zs + (g * npb + c) * 16,  lo plane: the same + zs_plane,
+// each 32-bit word holding (re, im) of one pair, re in the low half; pairs
+// beyond the block's end (padding to whole 16-pair stages) are zero.
+#include "common.h"
+#include "herk_common.h"
+
+namespace chi0 {
+namespace {
+
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  bf16x2 v;
+  v[0] = static_cast<__bf16>(lo);
+  v[1] = static_cast<__bf16>(hi);
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+__global__ __launch_bounds__(256) void presplit_kernel(const BlockDesc* __restrict__ blocks,
+                                                       const ProbDesc* __restrict__ probs,
+                                                       int block0) {
+#pragma clang fp contract(off)
+  const BlockDesc bd = blocks[block0 + blockIdx.z];
+  const int npb = probs[bd.prob].npb;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= npb) return;
+  const int64_t K = static_cast<int64_t>(bd.nocc) * bd.nunocc;
+  const int64_t G = presplit_groups(K);
+  const float2* z = static_cast<const float2*>(bd.z);
+  char* hi_plane = static_cast<char*>(bd.zs);
+  char* lo_plane = hi_plane + bd.zs_plane;
+  for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t p = 4 * g + e;
+      const float2 x = p < K ? z[p * npb + c] : float2{0.f, 0.f};
+      h[e] = pack2(x.x, x.y);
+      const float hr = __uint_as_float(h[e] << 16);
+      const float hm = __uint_as_float(h[e] & 0xFFFF0000u);
+      l[e] = pack2(x.x - hr, x.y - hm);
+    }
+    const size_t off = (static_cast<size_t>(g) * npb + c) * 16;
+    *reinterpret_cast<uint4*>(hi_plane + off) = uint4{h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<uint4*>(lo_plane + off) = uint4{l[0], l[1], l[2], l[3]};
+  }
+}
+
+}  // namespace
+
+hipError_t presplit_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
+                           int64_t max_groups, int max_npb, hipStream_t s) {
+  if (nblocks <= 0 || max_groups <= 0 || max_npb <= 0) return hipSuccess;
+  const unsigned gy = static_cast<unsigned>(max_groups < 4096 ? max_groups : 4096);
+  for (int b0 = 0; b0 < nblocks; b0 += 65535) {
+    const int nb = nblocks - b0 < 65535 ? nblocks - b0 : 65535;
+    hipLaunchKernelGGL(presplit_kernel, dim3((max_npb + 255) / 256, gy, nb), dim3(256), 0, s,
+                       blocks, probs, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace chi0

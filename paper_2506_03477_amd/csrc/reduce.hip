@@ -14,21 +14,22 @@ namespace {
 
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   const TileJob j = a.jobs[blockIdx.y];
-  const int T = a.tile;
+  const int TP = a.tile_p, TQ = a.tile_q;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= T * T) return;
-  const int row = e / T;
-  const int col = e - row * T;
+  if (e >= TP * TQ) return;
+  const int row = e / TQ;
+  const int col = e - row * TQ;
   const ProbDesc pd = a.probs[j.prob];
   const int npb = pd.npb;
-  const int I = j.tp * T + row;
-  const int J = j.tq * T + col;
+  const int I = j.tp * TP + row;
+  const int J = j.tq * TQ + col;
   if (I >= npb || J >= npb) return;
-  if (j.tp == j.tq && row < col) return;  // mirrored from the lower half
+  if (J > I) return;  // upper triangle: mirrored from the lower half
   double re = 0.0, im = 0.0;
-  const double2* src = a.partials + static_cast<size_t>(j.slot0) * T * T + e;
+  const size_t slot = static_cast<size_t>(TP) * TQ;
+  const double2* src = a.partials + static_cast<size_t>(j.slot0) * slot + e;
   for (int s = 0; s < j.nslot; ++s) {
-    const double2 v = src[static_cast<size_t>(s) * T * T];
+    const double2 v = src[static_cast<size_t>(s) * slot];
     re += v.x;
     im += v.y;
   }
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
 hipError_t reduce_launch(const ReduceArgs& a, int njobs, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   const int nthr = 256;
-  const int nx = (a.tile * a.tile + nthr - 1) / nthr;
+  const int nx = (a.tile_p * a.tile_q + nthr - 1) / nthr;
   hipLaunchKernelGGL(reduce_kernel, dim3(nx, njobs), dim3(nthr), 0, s, a);
   return hipGetLastError();
 }

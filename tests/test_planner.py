@@ -47,9 +47,10 @@ def _inspect(shapes, prec, tile, nwg):
 
 def _check(shapes, prec, tile, nwg):
     lib = pkg.load()
-    T = c_int32()
-    assert lib.chi0_tile_info(prec, tile, byref(T), None, None, None) == 0
-    T = T.value
+    TP, TQ, KC = c_int32(), c_int32(), c_int32()
+    assert lib.chi0_tile_info(prec, tile, byref(TP), byref(TQ), byref(KC), None) == 0
+    TP, TQ, KC = TP.value, TQ.value, KC.value
+    assert TP % TQ == 0
     units, njobs, lmax, lmean = _inspect(shapes, prec, tile, nwg)
     # flat block offsets and cumulative pairs
     flat0, cums = [], []
@@ -58,8 +59,17 @@ def _check(shapes, prec, tile, nwg):
         flat0.append(f)
         f += len(blocks)
         cums.append(np.concatenate([[0], np.cumsum([no * nu for no, nu in blocks])]).astype(np.int64))
-    expected_jobs = sum(nomega * ((npb + T - 1) // T) * ((npb + T - 1) // T + 1) // 2
-                        for npb, nomega, _ in shapes)
+    def lower_tile_count(npb):
+        # tiles holding an entry on or below the diagonal, counted entry-wise
+        seen = set()
+        for i in range(0, npb, max(1, min(TP, TQ) // 4)):
+            for j in range(0, i + 1, max(1, min(TP, TQ) // 4)):
+                seen.add((i // TP, j // TQ))
+        for i in range(npb):                      # the diagonal itself
+            seen.add((i // TP, i // TQ))
+        return len(seen)
+
+    expected_jobs = sum(nomega * lower_tile_count(npb) for npb, nomega, _ in shapes)
     assert njobs == expected_jobs
     assert np.array_equal(np.sort(units[:, 8]), np.arange(len(units)))     # slots unique
     assert np.all((units[:, 9] >= 0) & (units[:, 9] < nwg))                 # one owner each
@@ -67,8 +77,8 @@ def _check(shapes, prec, tile, nwg):
     for u in units:
         p, iw, tp, tq, b0, p0, b1, p1, slot, w = (int(x) for x in u)
         npb, nomega, blocks = shapes[p]
-        nt = (npb + T - 1) // T
-        assert 0 <= iw < nomega and 0 <= tq <= tp < nt
+        assert 0 <= iw < nomega and 0 <= tp * TP < npb and 0 <= tq * TQ < npb
+        assert tq * TQ <= min((tp + 1) * TP, npb) - 1        # holds a lower-triangle entry
         cum = cums[p]
         if b1 < b0:                        # problem without blocks
             g0 = g1 = 0
@@ -76,6 +86,8 @@ def _check(shapes, prec, tile, nwg):
             lb0, lb1 = b0 - flat0[p], b1 - flat0[p]
             assert 0 <= lb0 <= lb1 < len(blocks)
             assert 0 <= p0 <= cum[lb0 + 1] - cum[lb0] and 0 <= p1 <= cum[lb1 + 1] - cum[lb1]
+            # stages are whole, aligned chunks of a block
+            assert p0 % KC == 0 or p0 == cum[lb0 + 1] - cum[lb0]
             g0, g1 = cum[lb0] + p0, cum[lb1] + p1
             assert g1 >= g0
         jobs.setdefault((p, iw, tp, tq), []).append((slot, g0, g1))
