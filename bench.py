@@ -47,12 +47,21 @@ def inverse_flops(npb, nomega):
     return 8.0 * npb ** 3 * nomega
 
 
-def executed_mfma_flops(npb, npairs, nomega, tile, prec):
-    """Matrix-core flops actually issued: full T x T lower-triangle tiles (the
-    diagonal tiles are computed whole), 8 real flops per complex MAC, times
-    the number of split products."""
-    nt = -(-npb // tile)
-    return 8.0 * npairs * (nt * (nt + 1) // 2) * tile * tile * nomega * SPLIT_FACTOR[prec]
+def lower_tile_count(npb, tp, tq):
+    """Tiles of a tp x tq tiling holding an entry on or below the diagonal."""
+    n = 0
+    for r in range(-(-npb // tp)):
+        last_row = min((r + 1) * tp, npb) - 1
+        n += last_row // tq + 1
+    return n
+
+
+def executed_mfma_flops(npb, npairs, nomega, tile_p, tile_q, prec):
+    """Matrix-core flops actually issued: whole tp x tq tiles holding
+    lower-triangle entries (tiles on the diagonal are computed whole), 8 real
+    flops per complex MAC, times the number of split products."""
+    return (8.0 * npairs * lower_tile_count(npb, tile_p, tile_q) * tile_p * tile_q * nomega
+            * SPLIT_FACTOR[prec])
 
 
 def cpu_baseline(wl, target_s=15.0):
@@ -188,6 +197,8 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay chi0 from a hipGraph")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="tile configuration index (default: the library's default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (byte-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -231,6 +242,8 @@ def main():
     ctx = Context(0)
     if ctx.tile_count(prec) <= 0:
         raise SystemExit(f"precision {prec} has no kernel in this build")
+    if args.tile >= 0:
+        ctx.set_tile(prec, args.tile)
     ztype = "c128" if prec == "fp64" else "c64"
 
     if args.copy_calibration:
@@ -290,7 +303,8 @@ def main():
     total_ms = ev[0].elapsed_time(ev[1])
     kern_ms, nlaunch = ctx.profile_read()
     ms_per_step = total_ms / args.steps
-    tile = ctx.tile_info(prec, ctx.get_tile(prec))["tile_p"]
+    tinfo = ctx.tile_info(prec, ctx.get_tile(prec))
+    tile = tinfo["tile_p"]
 
     flops = zherk_flops(wl.npb, npairs, wl.nomega)
     value = flops / (ms_per_step * 1e-3) / 1e12
@@ -298,7 +312,8 @@ def main():
     roof = None
     if kern_avg_ms:
         ach = flops / (kern_avg_ms * 1e-3) / 1e12
-        exe = executed_mfma_flops(wl.npb, npairs, wl.nomega, tile, prec) / (kern_avg_ms * 1e-3) / 1e12
+        exe = executed_mfma_flops(wl.npb, npairs, wl.nomega, tinfo["tile_p"], tinfo["tile_q"],
+                                  prec) / (kern_avg_ms * 1e-3) / 1e12
         traffic = None
         tf = traffic_file(prec, wl.name)
         if os.path.exists(tf):
@@ -330,7 +345,8 @@ def main():
     extra = {"ms_per_q_chi0": round(chi_ms / args.steps / wl.nq, 3),
              "ms_per_q_inverse_gj": inv_ms["gj"], "ms_per_q_inverse_hpd": inv_ms["hpd"],
              "ms_per_q_chi0_plus_inverse": round(ms_per_step / wl.nq, 3),
-             "nq_per_step": wl.nq, "tile": tile, "npairs": npairs}
+             "nq_per_step": wl.nq, "tile": [tinfo["tile_p"], tinfo["tile_q"]],
+             "tile_index": ctx.get_tile(prec), "npairs": npairs}
     if wl.paths and "fp64" in wl.paths and prec != "fp64" and not args.no_fp64_compare:
         log("FP64 comparison: generating complex128 inputs")
         del probs, blks
