@@ -173,26 +173,33 @@ __device__ __forceinline__ uint32_t load_pairs64(const HerkArgs& a, const ProbDe
   return mask;
 }
 
-__global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
-  constexpr int T = 128, KC = 8, NT = 256;
-  constexpr int NB = 4;  // 16x16 blocks per wave side (64 / 16)
-  constexpr int NP = 4;  // pairs per thread per stage
+// NW = 4: 2 x 2 waves of 64 x 64 (one wave per SIMD, 256 accumulator
+// registers); NW = 8: 2 x 4 waves of 64 x 32 (two waves per SIMD, so one
+// wave's MFMAs can issue while the other waits).
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
+  constexpr int T = 128, KC = 8, NT = 64 * NW;
+  constexpr int WC = NW / 2;          // wave columns
+  constexpr int NBI = 4;              // 16x16 blocks per wave: 64 rows
+  constexpr int NBJ = T / WC / 16;    // and T / WC columns
+  constexpr int LG = NT / T;          // loader pair groups
+  constexpr int NP = KC / LG;         // pairs per thread per stage
   __shared__ double2 sA[2][KC][T];
   __shared__ double2 sB[2][KC][T];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WC, wc = wave % WC;
   const int m = lane & 15;
   const int kk = lane >> 4;
   const int prr = kk >> 1;
   const bool isim = (kk & 1) != 0;
   const int lc = tid & (T - 1);   // loader: tile column
-  const int lg = tid >> 7;        // loader: pairs lg, lg + 2, lg + 4, lg + 6
+  const int lg = tid / T;         // loader: pairs lg, lg + LG, ... (wave-uniform)
   int poff[NP];
 #pragma unroll
-  for (int e = 0; e < NP; ++e) poff[e] = lg + 2 * e;
+  for (int e = 0; e < NP; ++e) poff[e] = lg + LG * e;
 
   const int beg = a.wg_offsets[blockIdx.x];
   const int end = a.wg_offsets[blockIdx.x + 1];
@@ -203,11 +210,11 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
     const uint32_t cP = static_cast<uint32_t>(u.tp * T + lc < npb ? u.tp * T + lc : 0) * 16u;
     const uint32_t cQ = static_cast<uint32_t>(u.tq * T + lc < npb ? u.tq * T + lc : 0) * 16u;
 
-    f64x4 accR[NB][NB], accI[NB][NB];
+    f64x4 accR[NBI][NBJ], accI[NBI][NBJ];
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
+    for (int i = 0; i < NBI; ++i)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
+      for (int j = 0; j < NBJ; ++j) {
         accR[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
         accI[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
       }
@@ -222,7 +229,7 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
     while (have) {
 #pragma unroll
       for (int e = 0; e < NP; ++e) {
-        const int r = lg + 2 * e;
+        const int r = lg + LG * e;
         const double w = ((mk >> e) & 1u) ? rw[e] : 0.0;
         sA[buf][r][lc] = ra[e];
         sB[buf][r][lc] = double2{rb[e].x * w, rb[e].y * w};
@@ -234,22 +241,22 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
 #pragma unroll
       for (int st = 0; st < KC / 2; ++st) {
         const int pair = 2 * st + prr;
-        double av[NB], br[NB], bi[NB];
+        double av[NBI], br[NBJ], bi[NBJ];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
+        for (int i = 0; i < NBI; ++i) {
           const double2 x = sA[buf][pair][wr * 64 + i * 16 + m];
           av[i] = isim ? x.y : x.x;
         }
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const double2 y = sB[buf][pair][wc * 64 + j * 16 + m];
+        for (int j = 0; j < NBJ; ++j) {
+          const double2 y = sB[buf][pair][wc * (T / WC) + j * 16 + m];
           br[j] = isim ? y.y : y.x;
           bi[j] = isim ? -y.x : y.y;
         }
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
+        for (int i = 0; i < NBI; ++i)
 #pragma unroll
-          for (int j = 0; j < NB; ++j) {
+          for (int j = 0; j < NBJ; ++j) {
             accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], br[j], accR[i][j], 0, 0, 0);
             accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bi[j], accI[i][j], 0, 0, 0);
           }
@@ -260,13 +267,13 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
     }
     double2* out = a.partials + static_cast<size_t>(u.slot) * T * T;
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
+    for (int i = 0; i < NBI; ++i)
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
+      for (int j = 0; j < NBJ; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = wr * 64 + i * 16 + kk + 4 * r;
-          const int col = wc * 64 + j * 16 + m;
+          const int col = wc * (T / WC) + j * 16 + m;
           out[row * T + col] = double2{accR[i][j][r], accI[i][j][r]};
         }
   }
@@ -276,9 +283,10 @@ __global__ __launch_bounds__(256, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
 
 // Tile table of the FP64 path.
 static const TileConfig kFp64Tiles[] = {
-    {128, 8, 0, 256, 128},   // pipelined, one workgroup per CU
-    {64, 16, 0, 256, 64},
-    {32, 16, 0, 256, 32},
+    {128, 8, 0, 256, 128},   // 0: pipelined, 4 waves of 64 x 64
+    {64, 16, 0, 256, 64},    // 1
+    {32, 16, 0, 256, 32},    // 2
+    {128, 8, 0, 512, 128},   // 3: pipelined, 8 waves of 64 x 32 (two per SIMD)
 };
 
 int herk_fp64_tile_count() { return sizeof(kFp64Tiles) / sizeof(kFp64Tiles[0]); }
@@ -287,7 +295,10 @@ TileConfig herk_fp64_tile(int idx) { return kFp64Tiles[idx]; }
 hipError_t herk_fp64_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
   switch (idx) {
     case 0:
-      hipLaunchKernelGGL(herk_fp64_pipe_kernel, dim3(nwg), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(herk_fp64_pipe_kernel<4>, dim3(nwg), dim3(256), 0, s, a);
+      break;
+    case 3:
+      hipLaunchKernelGGL(herk_fp64_pipe_kernel<8>, dim3(nwg), dim3(512), 0, s, a);
       break;
     case 1:
       hipLaunchKernelGGL((herk_fp64_kernel<64, 16>), dim3(nwg), dim3(256), 0, s, a);
@@ -305,7 +316,9 @@ int herk_fp64_max_wg_per_cu(int idx) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   if (idx == 0)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_pipe_kernel, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_pipe_kernel<4>, 256, 0);
+  else if (idx == 3)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_pipe_kernel<8>, 512, 0);
   else if (idx == 1)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_kernel<64, 16>, 256, 0);
   else if (idx == 2)
