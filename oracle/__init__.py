@@ -9,3 +9,4 @@ from .chi0_oracle import (chi0_ref, chi0_brute, chi0_exact, chi0_entries,
                           chi0_block, chi0_workload, dielectric, inverse,
                           inverse_gauss_jordan, screened_wc, transition_weight,
                           pair_delta, pair_included, rel_fro, workload_blocks)
+from .sigx_oracle import sigx_block, sigx_brute, sigx_exact, sigx_ref  # noqa: F401
