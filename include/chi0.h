@@ -148,6 +148,40 @@ int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob,
                     chi0_ztype zt, chi0_precision prec, double delta_min,
                     uint32_t flags, void* hip_stream);
 
+/* Exchange self-energy (Eq.(sigx)) of one q-point, one k-point block:
+ *   Sigma^x[n][m] = - sum_blocks w_k sum_{n' occ} sum_mu
+ *                   conj(Z[n'][mu][n]) v[mu] Z[n'][mu][m]
+ * with Z[n'][mu][n] the matrix element of Eq.(defz) between product-basis
+ * function mu of k and the states (q-k, n') and (q, n). */
+typedef struct {
+  int32_t nocc;            /* occupied intermediate states n', >= 0          */
+  int32_t nmu;             /* product-basis functions mu, >= 0               */
+  const void* z;           /* DEVICE [nocc][nmu][nqp] complex, row-major (n
+                              contiguous), 16-byte aligned; may be NULL when
+                              nocc * nmu == 0                                 */
+  const double* v;         /* DEVICE [nmu] Coulomb eigenvalues v_mu(k) >= 0   */
+  double wk;               /* k-point weight, finite, >= 0 (1 for the bare
+                              Brillouin-zone sum)                             */
+} sigx_block;
+
+typedef struct {
+  int32_t nqp;             /* quasiparticle states n, m, >= 1                 */
+  int32_t nblocks;         /* >= 0                                            */
+  const sigx_block* blocks;/* HOST [nblocks]                                  */
+  void* sigx;              /* DEVICE out [nqp][nqp] complex128, written as an
+                              exactly Hermitian matrix, 16-byte aligned       */
+} sigx_problem;
+
+/* Sigma^x for `nprob` q-points in one persistent launch: the same weighted
+ * Hermitian rank-K update as chi0_accumulate (rows (n', mu) with weight
+ * w_k v_mu, one output matrix per problem), on the same FP64 / FP32 / BF16x3
+ * matrix-core paths, FP64 cross-block reduction, planner and tile table.
+ * zt / prec / flags as for chi0_accumulate (CHI0_ACCUMULATE,
+ * CHI0_BF16_LOLO, CHI0_USE_GRAPH). */
+int sigx_accumulate(chi0_handle h, const sigx_problem* probs, int32_t nprob,
+                    chi0_ztype zt, chi0_precision prec, uint32_t flags,
+                    void* hip_stream);
+
 /* Dielectric step for one q-point (Eq.(dielectricfunction), Eq.(wc);
  * Algorithm "hrcxq" builds eps, inverts it, forms W^c):
  *   eps[w] = 1 - diag(vsqrt) chi0[w] diag(vsqrt), eps_inv[w] = eps[w]^{-1}

@@ -47,6 +47,16 @@ class chi0_problem(ctypes.Structure):
                 ("nomega", c_int32), ("omega", c_void_p), ("chi0", c_void_p)]
 
 
+class sigx_block(ctypes.Structure):
+    _fields_ = [("nocc", c_int32), ("nmu", c_int32), ("z", c_void_p), ("v", c_void_p),
+                ("wk", c_double)]
+
+
+class sigx_problem(ctypes.Structure):
+    _fields_ = [("nqp", c_int32), ("nblocks", c_int32), ("blocks", POINTER(sigx_block)),
+                ("sigx", c_void_p)]
+
+
 class Chi0Error(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libchi0 error {code}: {msg}")
@@ -75,6 +85,7 @@ def load() -> ctypes.CDLL:
                                     c_uint32, vp]),
         "dielectric_invert": (c_int, [vp, c_int32, c_int32, vp, vp, vp, vp, vp, c_uint32, vp]),
         "chi0_sync": (c_int, [vp]),
+        "sigx_accumulate": (c_int, [vp, POINTER(sigx_problem), c_int32, c_int, c_int, c_uint32, vp]),
         "chi0_tile_count": (c_int, [c_int]),
         "chi0_tile_info": (c_int, [c_int, c_int32, POINTER(c_int32), POINTER(c_int32),
                                    POINTER(c_int32), POINTER(c_int32)]),
@@ -146,6 +157,54 @@ class Problem:
         return int(self.chi0.shape[-1])
 
 
+@dataclass
+class SigxBlock:
+    """One k-point of the exchange self-energy: z [nocc, nmu, nqp] complex
+    device tensor, v [nmu] float64 device tensor (Coulomb eigenvalues), wk."""
+    z: object
+    v: object
+    wk: float
+
+
+@dataclass
+class SigxProblem:
+    """One q-point: blocks and the [nqp, nqp] complex128 output."""
+    blocks: List[SigxBlock]
+    sigx: object
+
+    @property
+    def nqp(self) -> int:
+        return int(self.sigx.shape[-1])
+
+
+def _marshal_sigx(problems: Sequence[SigxProblem]):
+    import torch
+    keep = []
+    arr = (sigx_problem * len(problems))()
+    for i, p in enumerate(problems):
+        nqp, nqp2 = p.sigx.shape
+        if nqp != nqp2:
+            raise ValueError("sigx must be [nqp, nqp]")
+        barr = (sigx_block * max(1, len(p.blocks)))()
+        for j, b in enumerate(p.blocks):
+            nmu = int(b.v.numel())
+            has_z = b.z is not None and b.z.numel() > 0
+            nocc = int(b.z.shape[0]) if has_z else 0
+            if has_z and tuple(b.z.shape) != (nocc, nmu, nqp):
+                raise ValueError(f"block {j}: z shape {tuple(b.z.shape)} != {(nocc, nmu, nqp)}")
+            barr[j].nocc = nocc
+            barr[j].nmu = nmu
+            barr[j].z = _dev_ptr(b.z, what="z") if has_z else None
+            barr[j].v = _dev_ptr(b.v, torch.float64, "v") if nmu else None
+            barr[j].wk = float(b.wk)
+        keep.append(barr)
+        arr[i].nqp = nqp
+        arr[i].nblocks = len(p.blocks)
+        arr[i].blocks = ctypes.cast(barr, POINTER(sigx_block))
+        arr[i].sigx = _dev_ptr(p.sigx, torch.complex128, "sigx")
+    return arr, keep
+
+
 def _marshal(problems: Sequence[Problem]):
     import torch
     keep = []
@@ -213,6 +272,22 @@ class Context:
             (CHI0_USE_GRAPH if graph else 0)
         _check(self._lib.chi0_accumulate(self._h, arr, len(problems), _ztype_of(problems),
                                          PREC[precision], float(delta_min), flags,
+                                         _stream_ptr(stream)))
+
+    # -- exchange self-energy --------------------------------------------------
+    def sigx_accumulate(self, problems: Sequence[SigxProblem], precision: str = "fp64",
+                        accumulate: bool = False, lolo: bool = False, graph: bool = False,
+                        stream=None) -> None:
+        import torch
+        arr, keep = _marshal_sigx(problems)
+        zt = ZTYPE["c128"]
+        for p in problems:
+            for b in p.blocks:
+                if b.z is not None and b.z.numel():
+                    zt = ZTYPE["c128"] if b.z.dtype == torch.complex128 else ZTYPE["c64"]
+        flags = (CHI0_ACCUMULATE if accumulate else 0) | (CHI0_BF16_LOLO if lolo else 0) | \
+            (CHI0_USE_GRAPH if graph else 0)
+        _check(self._lib.sigx_accumulate(self._h, arr, len(problems), zt, PREC[precision], flags,
                                          _stream_ptr(stream)))
 
     # -- dielectric ----------------------------------------------------------

@@ -146,6 +146,54 @@ hipEvent_t get_event(chi0_ctx* h) {
   return e;
 }
 
+int validate_sigx(const sigx_problem* probs, int32_t nprob, chi0_ztype zt, chi0_precision prec,
+                  uint32_t flags) {
+  if (nprob < 0) return fail(CHI0_EINVAL, "nprob = %d < 0", nprob);
+  if (nprob > 0 && !probs) return fail(CHI0_EINVAL, "probs is NULL");
+  if (prec != CHI0_PREC_FP64 && prec != CHI0_PREC_FP32 && prec != CHI0_PREC_BF16X3)
+    return fail(CHI0_EINVAL, "unknown precision %d", static_cast<int>(prec));
+  if (zt != CHI0_Z_C128 && zt != CHI0_Z_C64)
+    return fail(CHI0_EINVAL, "unknown Z type %d", static_cast<int>(zt));
+  if (flags & ~static_cast<uint32_t>(CHI0_ACCUMULATE | CHI0_BF16_LOLO | CHI0_USE_GRAPH))
+    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  for (int p = 0; p < nprob; ++p) {
+    const sigx_problem& pr = probs[p];
+    if (pr.nqp < 1) return fail(CHI0_EINVAL, "problem %d: nqp = %d < 1", p, pr.nqp);
+    if (pr.nblocks < 0) return fail(CHI0_EINVAL, "problem %d: nblocks = %d < 0", p, pr.nblocks);
+    if (pr.nblocks > 0 && !pr.blocks) return fail(CHI0_EINVAL, "problem %d: blocks is NULL", p);
+    if (!pr.sigx) return fail(CHI0_EINVAL, "problem %d: sigx is NULL", p);
+    if (!aligned(pr.sigx, 16)) return fail(CHI0_EINVAL, "problem %d: sigx not 16-byte aligned", p);
+    for (int b = 0; b < pr.nblocks; ++b) {
+      const sigx_block& bl = pr.blocks[b];
+      if (bl.nocc < 0 || bl.nmu < 0)
+        return fail(CHI0_EINVAL, "problem %d block %d: negative nocc/nmu", p, b);
+      const int64_t K = static_cast<int64_t>(bl.nocc) * bl.nmu;
+      if (K > 0x7fffffffLL)
+        return fail(CHI0_EINVAL, "problem %d block %d: more than 2^31-1 rows", p, b);
+      if (!std::isfinite(bl.wk) || bl.wk < 0.0)
+        return fail(CHI0_EINVAL, "problem %d block %d: wk must be finite and >= 0", p, b);
+      if (K > 0) {
+        if (!bl.z) return fail(CHI0_EINVAL, "problem %d block %d: z is NULL", p, b);
+        if (!aligned(bl.z, 16))
+          return fail(CHI0_EINVAL, "problem %d block %d: z not 16-byte aligned", p, b);
+        if (!bl.v) return fail(CHI0_EINVAL, "problem %d block %d: v is NULL", p, b);
+      }
+    }
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(pr.sigx);
+    const uintptr_t a1 = a0 + static_cast<uintptr_t>(pr.nqp) * pr.nqp * 16;
+    for (int q = 0; q < p; ++q) {
+      const uintptr_t b0 = reinterpret_cast<uintptr_t>(probs[q].sigx);
+      const uintptr_t b1 = b0 + static_cast<uintptr_t>(probs[q].nqp) * probs[q].nqp * 16;
+      if (a0 < b1 && b0 < a1) return fail(CHI0_EINVAL, "problems %d and %d: outputs overlap", q, p);
+    }
+  }
+  const bool need128 = prec == CHI0_PREC_FP64;
+  if (need128 != (zt == CHI0_Z_C128))
+    return fail(CHI0_EUNSUPPORTED, "precision %d needs Z type %s", static_cast<int>(prec),
+                need128 ? "CHI0_Z_C128" : "CHI0_Z_C64");
+  return CHI0_OK;
+}
+
 int validate_problems(const chi0_problem* probs, int32_t nprob, chi0_ztype zt,
                       chi0_precision prec, double delta_min, uint32_t flags) {
   if (nprob < 0) return fail(CHI0_EINVAL, "nprob = %d < 0", nprob);
@@ -469,8 +517,19 @@ int staging_reserve(chi0_ctx* h, size_t bytes) {
   return CHI0_OK;
 }
 
+// Row weights of a call: the chi0 transition weights (Eq.(polfx) at i omega)
+// or, for the exchange self-energy, w_k v_mu (Eq.(sigx)).
+enum WeightMode { kWeightsChi0 = 0, kWeightsCoulomb = 1 };
+
+hipError_t weights_launch(int mode, const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
+                          int kmax, double delta_min, bool f64, hipStream_t s) {
+  return mode == kWeightsCoulomb ? coulomb_weights_launch(blocks, probs, nblocks, kmax, f64, s)
+                                 : pair_weights_launch(blocks, probs, nblocks, kmax, delta_min, f64, s);
+}
+
 int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_precision prec,
-                   double delta_min, uint32_t flags, hipStream_t stream, int tile_override) {
+                   double delta_min, uint32_t flags, hipStream_t stream, int tile_override,
+                   int mode = kWeightsChi0) {
   const int kind = kind_of(prec);
   const int ntile = herk_tile_count(kind);
   if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this build", prec);
@@ -608,7 +667,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
     // only reused with the same values, so they join the key
     const int gi = ra.accumulate;
     char kb[96];
-    snprintf(kb, sizeof(kb), "#g%d/%a/%u", gi, delta_min, flags);
+    snprintf(kb, sizeof(kb), "#g%d/%a/%u/m%d", gi, delta_min, flags, mode);
     const std::string gkey = key + kb;
     auto git = h->plans.find(gkey);
     Plan* gp = nullptr;
@@ -627,7 +686,8 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess)
-        e = pair_weights_launch(ha.blocks, ha.probs, nblocks_total, kmax, delta_min, kind == HERK_FP64, cs);
+        e = weights_launch(mode, ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
+                           kind == HERK_FP64, cs);
       if (e == hipSuccess && presplit)
         e = presplit_launch(ha.blocks, ha.probs, nblocks_total, max_groups, max_npb, cs);
       if (e == hipSuccess) e = herk_launch(kind, pl->tile_idx, ha, pl->nwg, cs);
@@ -650,8 +710,8 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
     return CHI0_OK;
   }
 
-  hipError_t ew = pair_weights_launch(ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
-                                      kind == HERK_FP64, stream);
+  hipError_t ew = weights_launch(mode, ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
+                                 kind == HERK_FP64, stream);
   if (ew != hipSuccess) return fail(CHI0_EDEVICE, "pair-weight launch: %s", hipGetErrorString(ew));
   if (presplit) {
     ew = presplit_launch(ha.blocks, ha.probs, nblocks_total, max_groups, max_npb, stream);
@@ -744,6 +804,40 @@ int chi0_destroy(chi0_handle h) {
   for (auto e : h->event_pool) hipEventDestroy(e);
   delete h;
   return CHI0_OK;
+}
+
+int sigx_accumulate(chi0_handle h, const sigx_problem* probs, int32_t nprob, chi0_ztype zt,
+                    chi0_precision prec, uint32_t flags, void* hip_stream) {
+  int rc = validate_sigx(probs, nprob, zt, prec, flags);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (nprob == 0) return CHI0_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  // the exchange sum is the same weighted Hermitian rank-K update: rows
+  // (n', mu) of nqp values, weight w_k v_mu, one "frequency", output -S
+  std::vector<chi0_problem> cp(nprob);
+  std::vector<std::vector<chi0_block>> cb(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    cb[p].resize(std::max(1, probs[p].nblocks));
+    for (int b = 0; b < probs[p].nblocks; ++b) {
+      const sigx_block& s = probs[p].blocks[b];
+      chi0_block& d = cb[p][b];
+      d.nocc = s.nocc;
+      d.nunocc = s.nmu;
+      d.z = s.z;
+      d.eps_occ = nullptr;
+      d.eps_unocc = s.v;
+      d.wk = s.wk;
+    }
+    cp[p].npb = probs[p].nqp;
+    cp[p].nblocks = probs[p].nblocks;
+    cp[p].blocks = cb[p].data();
+    cp[p].nomega = 1;
+    cp[p].omega = nullptr;
+    cp[p].chi0 = probs[p].sigx;
+  }
+  return run_accumulate(h, cp.data(), nprob, prec, 0.0, flags, static_cast<hipStream_t>(hip_stream),
+                        -1, kWeightsCoulomb);
 }
 
 int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_ztype zt,

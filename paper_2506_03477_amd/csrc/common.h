@@ -104,6 +104,8 @@ struct TileConfig {
 __host__ __device__ inline int64_t presplit_groups(int64_t pairs) { return (pairs + 15) / 16 * 4; }
 
 // Host launchers (defined next to their kernels).
+hipError_t coulomb_weights_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
+                                  int kmax, bool f64, hipStream_t s);
 hipError_t presplit_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
                            int64_t max_groups, int max_npb, hipStream_t s);
 hipError_t pair_weights_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,

@@ -26,7 +26,33 @@ __global__ __launch_bounds__(256) void pair_weights_kernel(const BlockDesc* __re
   }
 }
 
+// Exchange self-energy rows (Eq.(sigx)): row p = n' nmu + mu of a block has
+// weight w_k v[mu]; the block's nunocc is nmu and eps_unocc holds v.
+template <class W>
+__global__ __launch_bounds__(256) void coulomb_weights_kernel(const BlockDesc* __restrict__ blocks,
+                                                              const ProbDesc* __restrict__ probs) {
+  const BlockDesc bd = blocks[blockIdx.y];
+  const int K = bd.nocc * bd.nunocc;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= K) return;
+  const ProbDesc pd = probs[bd.prob];
+  W* out = static_cast<W*>(pd.wts) + bd.pair_base + p;
+  const double w = bd.wk * bd.eps_unocc[p % bd.nunocc];
+  for (int iw = 0; iw < pd.nomega; ++iw) out[static_cast<size_t>(iw) * pd.ktot] = static_cast<W>(w);
+}
+
 }  // namespace
+
+hipError_t coulomb_weights_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
+                                  int kmax, bool f64, hipStream_t s) {
+  if (nblocks <= 0 || kmax <= 0) return hipSuccess;
+  const dim3 grid((kmax + 255) / 256, nblocks);
+  if (f64)
+    hipLaunchKernelGGL(coulomb_weights_kernel<double>, grid, dim3(256), 0, s, blocks, probs);
+  else
+    hipLaunchKernelGGL(coulomb_weights_kernel<float>, grid, dim3(256), 0, s, blocks, probs);
+  return hipGetLastError();
+}
 
 hipError_t pair_weights_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks, int kmax,
                                double delta_min, bool f64, hipStream_t s) {

@@ -23,6 +23,26 @@ PAIRS = [(1, 0), (128, 127), (255, 1), (1000, 999), (1024, 0), (2047, 0), (1500,
          (513, 511), (2046, 129), (2047, 2046)]
 INDICES = sorted({i for e in PAIRS for i in e} | {0, 127, 128, 2047})
 ENTRIES = [(i, i) for i in INDICES] + PAIRS
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_entries(wl):
+    """Oracle values of ENTRIES, [nomega, len(ENTRIES)], from the Z columns
+    of the sampled indices only."""
+    cols = sorted({i for e in ENTRIES for i in e})
+    col_index = {c: k for k, c in enumerate(cols)}
+
+    def gen():
+        for blk in wl.blocks(0):
+            eo, eu = wl.energies(blk)
+            yield wl.z_elements(blk, np.arange(blk.npairs), np.array(cols)), eo, eu, blk.wk
+    return oracle.chi0_entries(gen(), ENTRIES, col_index, wl.omega, wl.delta_min)
+
+
 def _normalized_errors(got, ent):
     """|got_IJ - ref_IJ| / (sqrt(|ref_II ref_JJ|) + 1e-20 |ref_00|), per frequency.
 
@@ -43,16 +63,24 @@ def _normalized_errors(got, ent):
 
 @pytest.fixture(scope="module")
 def ref():
+    """Oracle entries per Z type (the FP64 path reads complex128 Z, the
+    reduced-precision paths the complex64-rounded values)."""
     need_gpu()
-    wl = workload(2)
-    _say("oracle: sampled entries of the npb=2048 workload")
-    return wl, _oracle_entries(wl)
+    cache = {}
+
+    def get(ztype):
+        if ztype not in cache:
+            wl = workload(2, ztype=ztype)
+            _say(f"oracle: sampled entries of the npb=2048 workload ({ztype})")
+            cache[ztype] = (wl, _oracle_entries(wl))
+        return cache[ztype]
+    return get
 
 
 @pytest.mark.parametrize("path,tol", [("bf16x3", 1e-6), ("fp64", 1e-12)])
 def test_fullsize_sampled_entries(ref, path, tol):
-    wl, ent = ref
     ztype = "c128" if path == "fp64" else "c64"
+    wl, ent = ref(ztype)
     _say(f"full size {wl.name} {path}")
     ctx = Context(0)
     prob, vsqrt, _ = device_problem(wl, ztype=ztype)
