@@ -182,6 +182,13 @@ class Workload:
                                  ulo + (uhi - ulo) * uu[nf_u:]])
         return np.sort(eo), np.sort(eu)
 
+    def coulomb(self, blk: Block) -> np.ndarray:
+        """Coulomb eigenvalues for the exchange workloads (whose blocks have
+        nunocc = number of product-basis functions mu): v_mu = (1 + mu)^(-2/3),
+        the 1/|G|^2 decay of plane-wave-like functions ordered by |G|, with
+        |G|^2 growing as mu^(2/3)."""
+        return (1.0 + np.arange(blk.nunocc, dtype=np.float64)) ** (-2.0 / 3.0)
+
     # ----------------------------------------------------------------------- Z
     def z_elements(self, blk: Block, pair_index: np.ndarray,
                    cols: np.ndarray) -> np.ndarray:
@@ -244,6 +251,14 @@ def workload(cfg: int, **overrides) -> Workload:
                       ztype="c64", delta_min=1e-4, occ_range=(-0.8, 0.0),
                       unocc_range=(0.0, 3.0), metallic=True,
                       paths=("bf16x3", "fp64"))
+    elif cfg == 5:
+        # Exchange self-energy (Eq.(sigx)) at the (InAs)4(GaSb)4 sizes of the
+        # paper's system-size table: nqp = 287 quasiparticle states (the Z
+        # columns), 92 occupied intermediate states n' (nocc) and 2097
+        # product-basis functions mu (nunocc) per k-point, 16 k-points.
+        wl = Workload(name="sigx_nqp287_nocc92_npb2097", cfg=5, npb=287, nq=1, nspin=1,
+                      nk=16, nocc=92, nunocc=2097, omega=(0.0,), ztype="c128",
+                      paths=("fp64", "fp32", "bf16x3"))
     else:
         raise ValueError(f"unknown workload {cfg}")
     if overrides:

@@ -24,6 +24,40 @@ def split(x32):
     return hi.astype(np.float64), lo.astype(np.float64)
 
 
+def weighted_model(rows, weights, path="bf16x3", lolo=False):
+    """-sum_r w_r conj(Z_r)^T Z_r with the GPU's rounding (FP32 weight on the
+    Q side, bf16 split), summed in FP64.  rows: complex64 [K, n]."""
+    a = np.asarray(rows, np.complex64)
+    c32 = np.asarray(weights, np.float64).astype(np.float32)[:, None]
+    br = (a.real.astype(np.float32) * c32).astype(np.float32)
+    bi = (a.imag.astype(np.float32) * c32).astype(np.float32)
+    ar = a.real.astype(np.float32)
+    ai = a.imag.astype(np.float32)
+    if path == "fp32":
+        ar64, ai64, br64, bi64 = (x.astype(np.float64) for x in (ar, ai, br, bi))
+        sr = ar64.T @ br64 + ai64.T @ bi64
+        si = ar64.T @ bi64 - ai64.T @ br64
+    else:
+        (arh, arl), (aih, ail) = split(ar), split(ai)
+        (brh, brl), (bih, bil) = split(br), split(bi)
+        terms = [(arh, aih, brh, bih), (arh, aih, brl, bil), (arl, ail, brh, bih)]
+        if lolo:
+            terms.append((arl, ail, brl, bil))
+        sr = sum(x.T @ y + u.T @ v for x, u, y, v in terms)
+        si = sum(x.T @ v - u.T @ y for x, u, y, v in terms)
+    return -(sr + 1j * si)
+
+
+def sigx_model(blocks, nqp, path="bf16x3"):
+    """blocks: (Z complex64 [nocc, nmu, nqp], v [nmu], wk) of Eq.(sigx)."""
+    out = np.zeros((nqp, nqp), np.complex128)
+    for z, v, wk in blocks:
+        nocc, nmu, _ = z.shape
+        out += weighted_model(np.asarray(z).reshape(nocc * nmu, nqp),
+                              np.tile(np.asarray(v, np.float64) * wk, nocc), path)
+    return out
+
+
 def chi0_model(blocks, npb, omega, delta_min, path="bf16x3", lolo=False):
     """blocks: (Z complex64 [nocc, nunocc, npb], eps_occ, eps_unocc, wk)."""
     out = np.zeros((len(omega), npb, npb), np.complex128)

@@ -1,0 +1,132 @@
+"""GPU parity of the exchange self-energy (Eq.(sigx), sigx_accumulate)
+against the CPU oracle: every precision path, every tile configuration,
+ragged sizes, empty blocks, accumulate mode and graph replay."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.sigx_oracle import sigx_ref, sigx_workload_blocks
+from gpu_common import assert_hermitian_exact, need_gpu, rel_fro
+from splitmodel import sigx_model
+from paper_2506_03477_amd import Context, SigxBlock, SigxProblem
+from synth import workload
+from synth.gpu import z_block_device
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _device_sigx(wl, ztype):
+    blocks = []
+    for blk in wl.blocks(0):
+        z = z_block_device(wl, blk, "cuda", ztype=ztype)
+        v = torch.from_numpy(wl.coulomb(blk)).cuda()
+        blocks.append(SigxBlock(z, v, blk.wk))
+    out = torch.empty((wl.npb, wl.npb), dtype=torch.complex128, device="cuda")
+    return SigxProblem(blocks, out)
+
+
+def _oracle(wl, ztype):
+    return sigx_ref(sigx_workload_blocks(wl.replace(ztype=ztype)), wl.npb)
+
+
+def _bf16_tol(wl):
+    """BF16x3 split error: each operand keeps 16 significant bits, so a
+    weighted sum of K_eff = (sum w)^2 / sum w^2 effective rows has relative
+    Frobenius error ~ 4e-6 sqrt(nqp / K_eff); the bound used is twice that,
+    and never below the 1e-6 of the chi0 path."""
+    w = np.concatenate([np.tile(wl.coulomb(b), b.nocc) * b.wk for b in wl.blocks(0)])
+    keff = w.sum() ** 2 / np.sum(w * w)
+    return max(1e-6, 8e-6 * np.sqrt(wl.npb / keff))
+
+
+# The small cases keep K_eff / nqp large enough for the BF16x3 bound to stay
+# near 1e-6.
+CASES = [
+    dict(npb=64, nk=3, nocc=6, nunocc=400),        # one tile
+    dict(npb=130, nk=2, nocc=9, nunocc=1500),      # ragged, several tiles
+    dict(npb=287, nk=1, nocc=23, nunocc=2097),     # paper-size columns and mu, fewer n'
+]
+
+
+@pytest.mark.parametrize("path", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("over", CASES)
+def test_sigx_parity(ctx, path, over):
+    wl = workload(5, **over)
+    ztype = "c128" if path == "fp64" else "c64"
+    _say(f"sigx {path} {over}")
+    prob = _device_sigx(wl, ztype)
+    ctx.sigx_accumulate([prob], precision=path)
+    ctx.sync()
+    got = prob.sigx.cpu().numpy()
+    ref = _oracle(wl, ztype)
+    err = rel_fro(got[None], ref[None])[0]
+    tol = _bf16_tol(wl) if path == "bf16x3" else TOL[path]
+    _say(f"  vs oracle {err:.3e} (tol {tol:.2e})")
+    assert err <= tol
+    if path != "fp64":      # the model of the rounding isolates kernel mistakes
+        mod = sigx_model(sigx_workload_blocks(wl.replace(ztype="c64")), wl.npb, path)
+        em = rel_fro(got[None], mod[None])[0]
+        _say(f"  vs split model {em:.3e}")
+        assert em <= 3e-7
+    assert_hermitian_exact(prob.sigx)
+    ev = np.linalg.eigvalsh(got)
+    assert ev.max() <= 1e-10 * np.abs(ev).max()          # negative semidefinite
+
+
+@pytest.mark.parametrize("path", ["fp64", "bf16x3"])
+def test_sigx_every_tile_and_modes(ctx, path):
+    wl = workload(5, npb=200, nk=2, nocc=7, nunocc=1200)
+    ztype = "c128" if path == "fp64" else "c64"
+    ref = _oracle(wl, ztype)
+    prob = _device_sigx(wl, ztype)
+    for tile in range(ctx.tile_count(path)):
+        ctx.set_tile(path, tile)
+        ctx.sigx_accumulate([prob], precision=path)
+        ctx.sync()
+        err = rel_fro(prob.sigx.cpu().numpy()[None], ref[None])[0]
+        _say(f"sigx {path} tile {tile} {ctx.tile_info(path, tile)}: {err:.3e}")
+        assert err <= (_bf16_tol(wl) if path == "bf16x3" else TOL[path])
+    ctx.set_tile(path, -1)
+    # accumulate mode doubles, graph replays reproduce the eager result
+    ctx.sigx_accumulate([prob], precision=path)
+    first = prob.sigx.clone()
+    ctx.sigx_accumulate([prob], precision=path, accumulate=True)
+    ctx.sync()
+    assert rel_fro(prob.sigx.cpu().numpy()[None], 2 * first.cpu().numpy()[None])[0] <= 1e-15
+    for rep in range(3):
+        prob.sigx.zero_()
+        ctx.sigx_accumulate([prob], precision=path, graph=True)
+        torch.cuda.synchronize()
+        _ = torch.randn(4096, device="cuda").sum()
+        assert torch.equal(prob.sigx, first), rep
+
+
+def test_sigx_empty_blocks_and_two_problems(ctx):
+    """Blocks without rows contribute nothing; two q-points in one call."""
+    wl = workload(5, npb=96, nk=2, nocc=5, nunocc=300)
+    p1 = _device_sigx(wl, "c128")
+    empty = SigxBlock(torch.empty((0, 0, 96), dtype=torch.complex128, device="cuda"),
+                      torch.empty((0,), dtype=torch.float64, device="cuda"), 1.0)
+    p1.blocks.insert(1, empty)
+    wl2 = workload(5, npb=33, nk=1, nocc=3, nunocc=50)
+    p2 = _device_sigx(wl2, "c128")
+    ctx.sigx_accumulate([p1, p2], precision="fp64")
+    ctx.sync()
+    assert rel_fro(p1.sigx.cpu().numpy()[None], _oracle(wl, "c128")[None])[0] <= 1e-12
+    assert rel_fro(p2.sigx.cpu().numpy()[None], _oracle(wl2, "c128")[None])[0] <= 1e-12
