@@ -186,6 +186,103 @@ def summarize_counters(db, out_path, command):
     print(f"wrote {out_path}")
 
 
+def sigx_cpu_baseline(wl, target_s=10.0):
+    """The exchange oracle on a bounded sample: the first n' rows of one k-point."""
+    from threadpoolctl import threadpool_info
+
+    from oracle.sigx_oracle import sigx_ref
+
+    blk = wl.blocks(0)[0]
+    v = wl.coulomb(blk)
+
+    def run(nocc_s):
+        sub = blk.__class__(q=blk.q, spin=blk.spin, k=blk.k, nocc=nocc_s, nunocc=blk.nunocc,
+                            wk=blk.wk, bid=blk.bid)
+        z = wl.z_block(sub)
+        t0 = time.perf_counter()
+        sigx_ref([(z, v, blk.wk)], wl.npb)
+        return time.perf_counter() - t0
+
+    t1 = run(1)
+    nocc_s = int(min(blk.nocc, max(1, round(target_s / max(t1, 1e-4)))))
+    t_meas = run(nocc_s) if nocc_s > 1 else t1
+    flops = zherk_flops(wl.npb, nocc_s * blk.nunocc, 1)
+    threads = 0
+    for info in threadpool_info():
+        if info.get("user_api") == "blas":
+            threads = max(threads, int(info.get("num_threads", 0)))
+    return {"value": flops / t_meas / 1e12, "unit": "TFLOP/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{nocc_s} occupied x {blk.nunocc} product-basis rows of one k-point, "
+                      f"nqp={wl.npb} ({t_meas:.1f} s)"}
+
+
+def bench_sigx(args):
+    """Exchange self-energy (Eq.(sigx)) of one q-point: one JSON line."""
+    import torch
+
+    from paper_2506_03477_amd import Context, SigxBlock, SigxProblem
+    from synth import workload
+    from synth.gpu import z_block_device
+
+    wl = workload(5)
+    prec = args.precision or "fp64"
+    ztype = "c128" if prec == "fp64" else "c64"
+    torch.cuda.set_device(0)
+    ctx = Context(0)
+    if args.tile >= 0:
+        ctx.set_tile(prec, args.tile)
+    log(f"generating {wl.name} inputs ({ztype}) on the GPU")
+    blocks = []
+    for blk in wl.blocks(0):
+        z = z_block_device(wl, blk, "cuda", ztype=ztype)
+        blocks.append(SigxBlock(z, torch.from_numpy(wl.coulomb(blk)).cuda(), blk.wk))
+    out = torch.empty((wl.npb, wl.npb), dtype=torch.complex128, device="cuda")
+    prob = SigxProblem(blocks, out)
+    rows = sum(b.npairs for b in wl.blocks(0))
+    for _ in range(args.warmup):
+        ctx.sigx_accumulate([prob], precision=prec)
+    ctx.sync()
+    ctx.profile_enable(True)
+    ctx.profile_read()
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(args.steps):
+        ctx.sigx_accumulate([prob], precision=prec)
+    b.record(stream)
+    b.synchronize()
+    ctx.sync()
+    ms = a.elapsed_time(b) / args.steps
+    kern_ms, n = ctx.profile_read()
+    kern_avg = kern_ms / n if n else None
+    flops = zherk_flops(wl.npb, rows, 1)
+    tinfo = ctx.tile_info(prec, ctx.get_tile(prec))
+    roof = None
+    if kern_avg:
+        ach = flops / (kern_avg * 1e-3) / 1e12
+        exe = executed_mfma_flops(wl.npb, rows, 1, tinfo["tile_p"], tinfo["tile_q"], prec) / \
+            (kern_avg * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4), "traffic": None,
+                "kernel": f"herk_{prec}", "kernel_ms": round(kern_avg, 3),
+                "executed_mfma_tflops": round(exe, 3),
+                "executed_mfma_frac": round(exe / PEAK_TFLOPS[prec], 4)}
+    cpu = None if args.no_cpu_baseline else sigx_cpu_baseline(wl)
+    print(json.dumps({
+        "metric": "Sigma^x TFLOP/s per q-point (exchange self-energy, Eq. sigx)",
+        "value": round(flops / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": MFMA_DTYPE[prec] if prec != "bf16x3" else "bf16x3", "data": "synthetic",
+        "config": {"workload": wl.name, "nqp": wl.npb, "nk": wl.nk, "nocc": wl.nocc,
+                   "nmu": wl.nunocc, "ztype": ztype, "path": prec,
+                   "tile": [tinfo["tile_p"], tinfo["tile_q"]]},
+        "roofline": roof, "cpu_baseline": cpu}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +305,8 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_DB", "OUT"),
                     help="write a text table of every counter of a rocprofv3 --pmc database")
     ap.add_argument("--command", default="", help="profiled command (for the summaries)")
+    ap.add_argument("--sigx", action="store_true",
+                    help="time the exchange self-energy (Eq. sigx) instead of chi0")
     args = ap.parse_args()
 
     if args.summarize_counters:
@@ -223,6 +322,9 @@ def main():
             summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
         return
 
+    if args.sigx and args.gpus == 1:
+        bench_sigx(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described in DESIGN.md, not built)"}))
