@@ -8,7 +8,8 @@
 // The complex product is four real products stacked along the contraction
 // index of v_mfma_f64_16x16x4f64: k-slots (re, im) of two pairs per MFMA,
 //   Re S += [ar, ai] . [br, bi],   Im S += [ar, ai] . [bi, -br].
-// The pair weight scales the Q-side operand as it is staged into LDS.
+// The pair weight (precomputed per call, pair_weights_kernel) scales the
+// Q-side operand as it is staged into LDS.
 #include "common.h"
 #include "herk_common.h"
 
@@ -42,8 +43,7 @@ __global__ __launch_bounds__(256) void herk_fp64_kernel(HerkArgs a) {
     const Unit u = a.units[a.wg_units[ui]];
     const ProbDesc pd = a.probs[u.prob];
     const int npb = pd.npb;
-    const double om = pd.omega[u.iw];
-    const double w2 = om * om;
+    const double* wts = static_cast<const double*>(pd.wts) + static_cast<size_t>(u.iw) * pd.ktot;
     const int colP0 = u.tp * T;
     const int colQ0 = u.tq * T;
 
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void herk_fp64_kernel(HerkArgs a) {
       const int K = (b == u.b1) ? u.p1 : bd.nocc * bd.nunocc;  // end pair
       const double2* z = static_cast<const double2*>(bd.z);
       for (int p0 = pbeg; p0 < K; p0 += KC) {
-        if (tid < KC) sW[tid] = pair_weight(bd, p0 + tid, K, w2, a.delta_min);
+        if (tid < KC) sW[tid] = p0 + tid < K ? wts[bd.pair_base + p0 + tid] : 0.0;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < KC * T / NT; ++i) {

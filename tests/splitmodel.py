@@ -24,6 +24,19 @@ def split(x32):
     return hi.astype(np.float64), lo.astype(np.float64)
 
 
+def mirror_lower(m):
+    """The GPU computes the lower triangle (row index on the unscaled,
+    conjugated side) and mirrors it with conjugation, imaginary diagonal 0;
+    the model returns the same Hermitian matrix from its lower triangle
+    (its upper triangle has the two sides' roundings swapped)."""
+    m = np.asarray(m)
+    lo = np.tril(m)
+    out = lo + np.conj(np.swapaxes(np.tril(lo, -1), -1, -2))
+    d = np.einsum("...ii->...i", out)
+    d.imag[...] = 0.0
+    return out
+
+
 def weighted_model(rows, weights, path="bf16x3", lolo=False):
     """-sum_r w_r conj(Z_r)^T Z_r with the GPU's rounding (FP32 weight on the
     Q side, bf16 split), summed in FP64.  rows: complex64 [K, n]."""
@@ -55,7 +68,7 @@ def sigx_model(blocks, nqp, path="bf16x3"):
         nocc, nmu, _ = z.shape
         out += weighted_model(np.asarray(z).reshape(nocc * nmu, nqp),
                               np.tile(np.asarray(v, np.float64) * wk, nocc), path)
-    return out
+    return mirror_lower(out)
 
 
 def chi0_model(blocks, npb, omega, delta_min, path="bf16x3", lolo=False):
@@ -86,4 +99,4 @@ def chi0_model(blocks, npb, omega, delta_min, path="bf16x3", lolo=False):
                 sr = sum(x.T @ y + u.T @ v for x, u, y, v in terms)
                 si = sum(x.T @ v - u.T @ y for x, u, y, v in terms)
             out[iw] -= sr + 1j * si
-    return out
+    return mirror_lower(out)
