@@ -230,23 +230,23 @@ def workload(cfg: int, **overrides) -> Workload:
     gl12 = tuple(float(x) for x in gauss_legendre_imag_axis(12))
     gl16 = tuple(float(x) for x in gauss_legendre_imag_axis(16))
     if cfg == 0:
-        wl = Workload(name="cfg0_npb64", cfg=0, npb=64, nq=1, nspin=1, nk=8,
+        wl = Workload(name="npb64_nk8_8x32_4w", cfg=0, npb=64, nq=1, nspin=1, nk=8,
                       nocc=8, nunocc=32, omega=(0.1, 0.5, 2.0, 8.0), ztype="c128",
                       unocc_range=(0.05, 3.0), paths=("fp64",))
     elif cfg == 1:
-        wl = Workload(name="cfg1_npb512", cfg=1, npb=512, nq=1, nspin=1, nk=64,
+        wl = Workload(name="npb512_nk64_40x300_12w", cfg=1, npb=512, nq=1, nspin=1, nk=64,
                       nocc=40, nunocc=300, omega=gl12, ztype="c128",
                       unocc_range=(0.03, 3.0), paths=("fp64", "fp32"))
     elif cfg == 2:
-        wl = Workload(name="cfg2_npb2048", cfg=2, npb=2048, nq=1, nspin=1, nk=16,
+        wl = Workload(name="npb2048_nk16_200x1200_12w", cfg=2, npb=2048, nq=1, nspin=1, nk=16,
                       nocc=200, nunocc=1200, omega=gl12, ztype="c64",
                       unocc_range=(0.05, 3.0), paths=("bf16x3", "fp64"))
     elif cfg == 3:
-        wl = Workload(name="cfg3_batched_npb384", cfg=3, npb=384, nq=32, nspin=1,
+        wl = Workload(name="32q_npb384_nk16_ragged_12w", cfg=3, npb=384, nq=32, nspin=1,
                       nk=16, nocc=(16, 64), nunocc=(100, 400), omega=gl12,
                       ztype="c64", unocc_range=(0.05, 3.0), paths=("fp32",))
     elif cfg == 4:
-        wl = Workload(name="cfg4_spin_metal_npb1024", cfg=4, npb=1024, nq=1,
+        wl = Workload(name="spin2_metal_npb1024_nk128_16w", cfg=4, npb=1024, nq=1,
                       nspin=2, nk=128, nocc=(52, 68), nunocc=500, omega=gl16,
                       ztype="c64", delta_min=1e-4, occ_range=(-0.8, 0.0),
                       unocc_range=(0.0, 3.0), metallic=True,
