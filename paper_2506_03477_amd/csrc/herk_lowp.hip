@@ -99,9 +99,14 @@ __device__ __forceinline__ uint32_t load_pairs(const HerkArgs& a, const ProbDesc
 }
 
 // LDS row = tile column (0..T-1), 16 dwords = 4 chunks of 4 pairs; chunk q of
-// row r lives at chunk q ^ ((r >> 2) & 3) (conflict-free 16-byte accesses).
+// row r lives at slot q ^ g(r), g(r) = (r1 ^ r3) + 2 r2 (r_i = bit i of r).
+// A 16-byte access of consecutive rows (same q) then hits distinct banks
+// within every 8 lanes for 32 banks (8 rows span 128 bytes) and within every
+// 16 lanes for 64 banks, so the fragment reads and the staging writes are
+// conflict-free with either bank count.
 __device__ __forceinline__ int swz(int row, int q) {
-  return row * 16 + 4 * (q ^ ((row >> 2) & 3));
+  const int g = (((row >> 1) ^ (row >> 3)) & 1) | (((row >> 2) & 1) << 1);
+  return row * 16 + 4 * (q ^ g);
 }
 
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
@@ -376,7 +381,7 @@ __global__ __launch_bounds__(kNT, OCC) void herk_bf16x3_kernel(HerkArgs a) {
 //      instructions, so the split / scale work overlaps the matrix cores;
 //   3. one barrier.
 // The stage loop is unrolled by two so every buffer index is a constant.
-template <bool LOLO>
+template <bool LOLO, bool HINT>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
   constexpr int T = 128, NB = 2, LG = 2, GPT = 2, NP = 8;
   constexpr bool ROT = true;
@@ -413,10 +418,12 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
     uint32_t mk0 = 0, mk1 = 0;
 
     auto interleave = [&]() {
+      if constexpr (HINT) {
 #pragma unroll
-      for (int k = 0; k < (LOLO ? 64 : 48); ++k) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // 1 MFMA
-        __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);   // 5 VALU
+        for (int k = 0; k < (LOLO ? 64 : 48); ++k) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // 1 MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);   // 5 VALU
+        }
       }
     };
 
@@ -662,7 +669,7 @@ __device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32
 //      (s + 1) % 2) in one block with interleaving hints;
 //   3. the P staging of stage s + 1 (its loads have had the MFMA phase to
 //      land), then one barrier.
-template <bool LOLO>
+template <bool LOLO, bool HINT>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
   constexpr int TP = 256, TQ = 128;
   __shared__ __attribute__((aligned(16))) Bf16TallLds L;
@@ -702,10 +709,12 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
     uint32_t mk0 = 0, mk1 = 0;
 
     auto interleave = [&]() {
+      if constexpr (HINT) {
 #pragma unroll
-      for (int k = 0; k < (LOLO ? 128 : 96); ++k) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // 1 MFMA
-        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // 2 VALU
+        for (int k = 0; k < (LOLO ? 128 : 96); ++k) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // 1 MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // 2 VALU
+        }
       }
     };
 
@@ -768,8 +777,10 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
 // holds the operands as complex64, rows = tile columns, 16 pairs per row
 // (8 chunks of 2 pairs, XOR-swizzled).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int swz32(int row, int q) {  // q: chunk of 2 pairs (16 B)
-  return row * 32 + 4 * (q ^ ((row >> 1) & 7));
+// q: chunk of 2 pairs (16 B); slot q ^ ((r & 7) ^ r3): 8 consecutive rows and
+// the 8 even (or odd) rows of 16 consecutive ones use distinct slots.
+__device__ __forceinline__ int swz32(int row, int q) {
+  return row * 32 + 4 * (q ^ ((row & 7) ^ ((row >> 3) & 1)));
 }
 
 template <int T>
@@ -888,6 +899,8 @@ static const TileConfig kBf16Tiles[] = {
     {128, kKC, 1024, kNT, 128},   // 3: pipelined, shorter FP32 runs
     {128, kKC, 4096, kNT, 128},   // 4: in sequence, two workgroups per CU
     {256, kKC, 4096, kNT, 128, 1},   // 5: pipelined, tall 256 x 128 tiles, P pre-split
+    {128, kKC, 4096, kNT, 128},      // 6: as 0, compiler scheduling (no interleave hints)
+    {256, kKC, 4096, kNT, 128, 1},   // 7: as 5, compiler scheduling
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -904,26 +917,29 @@ static void launch_bf16_seq(bool lolo, const HerkArgs& a, int nwg, hipStream_t s
     hipLaunchKernelGGL((herk_bf16x3_kernel<T, false, OCC>), dim3(nwg), dim3(kNT), 0, s, a);
 }
 
+#define CHI0_BF16_KERNEL_LAUNCH(kern, lolo, hint, nwg, s, a)                                   \
+  do {                                                                                         \
+    if (lolo) {                                                                                \
+      if (hint) hipLaunchKernelGGL((kern<true, true>), dim3(nwg), dim3(kNT), 0, s, a);         \
+      else hipLaunchKernelGGL((kern<true, false>), dim3(nwg), dim3(kNT), 0, s, a);             \
+    } else {                                                                                   \
+      if (hint) hipLaunchKernelGGL((kern<false, true>), dim3(nwg), dim3(kNT), 0, s, a);        \
+      else hipLaunchKernelGGL((kern<false, false>), dim3(nwg), dim3(kNT), 0, s, a);            \
+    }                                                                                          \
+  } while (0)
+
 hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
   if (idx < 0 || idx >= herk_bf16x3_tile_count()) return hipErrorInvalidValue;
   const bool lolo = (a.flags & 2) != 0;
   switch (idx) {
     case 0:
-    case 3:
-      if (lolo)
-        hipLaunchKernelGGL(herk_bf16x3_pipe_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
-      else
-        hipLaunchKernelGGL(herk_bf16x3_pipe_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
-      break;
+    case 3: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_pipe_kernel, lolo, true, nwg, s, a); break;
+    case 6: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_pipe_kernel, lolo, false, nwg, s, a); break;
     case 1: launch_bf16_seq<128, 1>(lolo, a, nwg, s); break;
     case 2: launch_bf16_seq<64, 1>(lolo, a, nwg, s); break;
     case 4: launch_bf16_seq<128, 2>(lolo, a, nwg, s); break;
-    default:
-      if (lolo)
-        hipLaunchKernelGGL(herk_bf16x3_tall_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
-      else
-        hipLaunchKernelGGL(herk_bf16x3_tall_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
-      break;
+    case 5: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, true, nwg, s, a); break;
+    default: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, false, nwg, s, a); break;
   }
   return hipGetLastError();
 }
@@ -933,7 +949,8 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
   switch (idx) {
     case 0:
     case 3:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_pipe_kernel<false>, kNT, 0);
+    case 6:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_pipe_kernel<false, true>, kNT, 0);
       break;
     case 1:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false, 1>, kNT, 0);
@@ -945,7 +962,7 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false, 2>, kNT, 0);
       break;
     default:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall_kernel<false>, kNT, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall_kernel<false, true>, kNT, 0);
       break;
   }
   return e == hipSuccess && n > 0 ? n : 1;
