@@ -577,17 +577,18 @@ __device__ __forceinline__ void tall_stage_q(Bf16TallLds& L, int buf, int lq, in
   }
 }
 
-// The 2 k-steps of one stage for a wave's 128 x 64 sub-tile.
-template <bool LOLO>
+// The 2 k-steps of one stage for a wave's (32 NBI) x 64 sub-tile at P rows
+// 32 NBI wr and Q columns 64 wc.
+template <bool LOLO, int NBI = 4>
 __device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr, int wc, int g8,
-                                          int l32, f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
+                                          int l32, f32x16 (&cr)[NBI][2], f32x16 (&ci)[NBI][2]) {
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
     const int q = 2 * ks + g8;
-    bf16x8 fah[4], fal[4], fbh[2], fbl[2], fih[2], fil[2];
+    bf16x8 fah[NBI], fal[NBI], fbh[2], fbl[2], fih[2], fil[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = wr * 128 + i * 32 + l32;
+    for (int i = 0; i < NBI; ++i) {
+      const int row = wr * (32 * NBI) + i * 32 + l32;
       fah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.ah[buf][swz(row, q)]));
       fal[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.al[buf][swz(row, q)]));
     }
@@ -600,21 +601,21 @@ __device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr,
       fil[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bil[buf][swz(row, q)]));
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NBI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbh[j], cr[i][j], 0, 0, 0);
         ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fih[j], ci[i][j], 0, 0, 0);
       }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NBI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbl[j], cr[i][j], 0, 0, 0);
         ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fil[j], ci[i][j], 0, 0, 0);
       }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NBI; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbh[j], cr[i][j], 0, 0, 0);
@@ -622,7 +623,7 @@ __device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr,
       }
     if (LOLO) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NBI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbl[j], cr[i][j], 0, 0, 0);
@@ -632,18 +633,20 @@ __device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr,
   }
 }
 
-// Add (or store, when first) a wave's 128 x 64 accumulators into the FP64
-// partial tile (256 x 128, row-major); 16 old values are loaded as a group.
-__device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32x16 (&cr)[4][2],
-                                           const f32x16 (&ci)[4][2], int wr, int wc, int lane,
+// Add (or store, when first) a wave's (32 NBI) x 64 accumulators into the
+// FP64 partial tile (256 x 128, row-major); 16 old values are loaded as a
+// group.
+template <int NBI = 4>
+__device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32x16 (&cr)[NBI][2],
+                                           const f32x16 (&ci)[NBI][2], int wr, int wc, int lane,
                                            bool first) {
   constexpr int TQ = 128;
   const int g = lane >> 5;
   const int cl = lane & 31;
-  int base = (wr * 128 + 4 * g) * TQ + wc * 64 + cl;
+  int base = (wr * (32 * NBI) + 4 * g) * TQ + wc * 64 + cl;
   asm volatile("" : "+v"(base));
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NBI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       double2* blk = part + base + i * 32 * TQ + j * 32;
@@ -769,6 +772,152 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
         }
     }
     if (first_flush) tall_flush(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
+  }
+}
+
+// Tall tiles with 8 waves (two per SIMD, so one wave's matrix-core work can
+// issue while the other waits on LDS or a barrier): waves of 64 x 64 (2 x 2
+// blocks, 128 accumulators, at most 256 registers per lane).  Thread t stages
+// P row t % 256 (chunks 2 (t / 256), + 1 of both planes) and Q column t % 128,
+// chunk t / 128 (wave-uniform); one register set, staged after the MFMAs.
+template <bool LOLO>
+__global__ __launch_bounds__(512, 1) void herk_bf16x3_tall8_kernel(HerkArgs a) {
+  constexpr int TP = 256, TQ = 128;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  typedef const u32x4 __attribute__((address_space(1)))* gu4ptr;
+  typedef const char __attribute__((address_space(1)))* gcptr;
+  __shared__ __attribute__((aligned(16))) Bf16TallLds L;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g8 = lane >> 5;
+  const int l32 = lane & 31;
+  const int lp = tid & (TP - 1);
+  const int pq0 = 2 * (tid >> 8);     // first P chunk (wave-uniform)
+  const int lq = tid & (TQ - 1);
+  const int lg = tid >> 7;            // Q chunk (wave-uniform)
+
+  // P: chunks pq0, pq0 + 1 of tile row lp from the pre-split planes
+  auto load_p = [&](const Cursor& c, int npb, uint32_t offP, uint4 (&ph)[2], uint4 (&pl)[2]) {
+    const int b = __builtin_amdgcn_readfirstlane(c.b);
+    const int p0 = __builtin_amdgcn_readfirstlane(c.p0);
+    const int q0 = __builtin_amdgcn_readfirstlane(pq0);
+    const BlockDesc* bp = a.blocks + b;
+    const size_t chunk_bytes = static_cast<size_t>(npb) * 16;
+    const gcptr hi = (gcptr)(ld_const(&bp->zs, 0)) +
+                     static_cast<size_t>((p0 >> 2) + q0) * chunk_bytes;
+    const gcptr lo = hi + ld_const(&bp->zs_plane, 0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t o = static_cast<uint32_t>(j) * static_cast<uint32_t>(chunk_bytes) + offP;
+      const u32x4 h = *(gu4ptr)(hi + o);
+      const u32x4 l = *(gu4ptr)(lo + o);
+      ph[j] = uint4{h.x, h.y, h.z, h.w};
+      pl[j] = uint4{l.x, l.y, l.z, l.w};
+    }
+  };
+  auto stage_p = [&](int buf, const uint4 (&ph)[2], const uint4 (&pl)[2]) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int o = swz(lp, pq0 + j);
+      *reinterpret_cast<uint4*>(&L.ah[buf][o]) = ph[j];
+      *reinterpret_cast<uint4*>(&L.al[buf][o]) = pl[j];
+    }
+  };
+  // Q: the 4 pairs of chunk lg, column offQ, with weights (wave-uniform rows)
+  auto load_q = [&](const ProbDesc& pd, int iw, const Cursor& c, int npb, uint32_t offQ,
+                    float2 (&rb)[4], float (&rw)[4]) -> uint32_t {
+    const int b = __builtin_amdgcn_readfirstlane(c.b);
+    const int p0 = __builtin_amdgcn_readfirstlane(c.p0);
+    const int last = __builtin_amdgcn_readfirstlane(c.pend) - 1 - p0;
+    const int g = __builtin_amdgcn_readfirstlane(lg);
+    const BlockDesc* bp = a.blocks + b;
+    const uint32_t row_bytes = static_cast<uint32_t>(npb) * 8u;
+    const gcptr z = (gcptr)(ld_const(&bp->z, 0)) + static_cast<size_t>(p0) * row_bytes;
+    const int64_t pbase = ld_const(&bp->pair_base, 0);
+    const float* w = static_cast<const float*>(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase + p0;
+    uint32_t mask = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int o = 4 * g + e;
+      const bool valid = o <= last;
+      const int oc = valid ? o : last;
+      mask |= valid ? (1u << e) : 0u;
+      rb[e] = ld_c64((gf2ptr)(z + static_cast<uint32_t>(oc) * row_bytes + offQ));
+      rw[e] = ld_const(w, oc);
+    }
+    return mask;
+  };
+  auto stage_q = [&](int buf, const float2 (&rb)[4], const float (&rw)[4], uint32_t mask) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float wq = ((mask >> e) & 1u) ? rw[e] : 0.f;
+      split2(rb[e].x * wq, rb[e].y * wq, h[e], l[e]);
+    }
+    const int o = swz(lq, lg);
+    const uint4 vh = uint4{h[0], h[1], h[2], h[3]};
+    const uint4 vl = uint4{l[0], l[1], l[2], l[3]};
+    *reinterpret_cast<uint4*>(&L.bh[buf][o]) = vh;
+    *reinterpret_cast<uint4*>(&L.bl[buf][o]) = vl;
+    *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(vh);
+    *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(vl);
+  };
+
+  const int beg = a.wg_offsets[blockIdx.x];
+  const int end = a.wg_offsets[blockIdx.x + 1];
+  for (int ui = beg; ui < end; ++ui) {
+    const Unit u = a.units[a.wg_units[ui]];
+    const ProbDesc pd = a.probs[u.prob];
+    const int npb = pd.npb;
+    const int flush_pairs = pd.flush > 2 * kKC ? pd.flush / (2 * kKC) : 1;
+    const uint32_t cQ = col_offset(u.tq * TQ + lq, npb);
+    const uint32_t cP = (u.tp * TP + lp < npb ? static_cast<uint32_t>(u.tp * TP + lp) : 0u) * 16u;
+    double2* part = a.partials + static_cast<size_t>(u.slot) * TP * TQ;
+
+    f32x16 cr[2][2], ci[2][2];
+    zero_acc<2>(cr, ci);
+    float2 rb[4];
+    float rw[4];
+    uint4 ph[2], pl[2];
+    uint32_t mk = 0;
+
+    // stage s: loads of stage s + 1 in flight during the MFMAs of stage s,
+    // then staged into the other buffer; the second wave of each SIMD covers
+    // the waits of the first.
+    Cursor cur;
+    bool have = cursor_first(u, a.blocks, cur);
+    __syncthreads();  // previous unit's last MFMAs are done with the LDS
+    if (have) {
+      load_p(cur, npb, cP, ph, pl);
+      mk = load_q(pd, u.iw, cur, npb, cQ, rb, rw);
+      stage_p(0, ph, pl);
+      stage_q(0, rb, rw, mk);
+    }
+    __syncthreads();
+    int buf = 0;
+    bool first_flush = true;
+    while (have) {
+      for (int ns = 0; ns < flush_pairs * 2 && have; ++ns) {
+        Cursor nxt = cur;
+        const bool more = cursor_next<kKC>(u, a.blocks, nxt);
+        load_p(nxt, npb, cP, ph, pl);                       // unused when !more
+        mk = load_q(pd, u.iw, nxt, npb, cQ, rb, rw);
+        tall_mfma<LOLO, 2>(L, buf, wr, wc, g8, l32, cr, ci);
+        stage_p(buf ^ 1, ph, pl);
+        stage_q(buf ^ 1, rb, rw, mk);
+        __syncthreads();
+        cur = nxt;
+        have = more;
+        buf ^= 1;
+      }
+      tall_flush<2>(part, cr, ci, wr, wc, lane, first_flush);
+      first_flush = false;
+      zero_acc<2>(cr, ci);
+    }
+    if (first_flush) tall_flush<2>(part, cr, ci, wr, wc, lane, true);  // empty unit: zeros
   }
 }
 
@@ -901,6 +1050,7 @@ static const TileConfig kBf16Tiles[] = {
     {256, kKC, 4096, kNT, 128, 1},   // 5: pipelined, tall 256 x 128 tiles, P pre-split
     {128, kKC, 4096, kNT, 128},      // 6: as 0, compiler scheduling (no interleave hints)
     {256, kKC, 4096, kNT, 128, 1},   // 7: as 5, compiler scheduling
+    {256, kKC, 4096, 512, 128, 1},   // 8: tall tiles, 8 waves (two per SIMD)
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -939,7 +1089,13 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
     case 2: launch_bf16_seq<64, 1>(lolo, a, nwg, s); break;
     case 4: launch_bf16_seq<128, 2>(lolo, a, nwg, s); break;
     case 5: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, true, nwg, s, a); break;
-    default: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, false, nwg, s, a); break;
+    case 7: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, false, nwg, s, a); break;
+    default:
+      if (lolo)
+        hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<true>, dim3(nwg), dim3(512), 0, s, a);
+      else
+        hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<false>, dim3(nwg), dim3(512), 0, s, a);
+      break;
   }
   return hipGetLastError();
 }
@@ -961,8 +1117,12 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
     case 4:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_kernel<128, false, 2>, kNT, 0);
       break;
-    default:
+    case 5:
+    case 7:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall_kernel<false, true>, kNT, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false>, 512, 0);
       break;
   }
   return e == hipSuccess && n > 0 ? n : 1;
