@@ -349,6 +349,20 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
     return n;
   };
   while (count_units(per_unit) * slot_bytes > max_partial_bytes) per_unit *= 1.5;
+  // one problem shape: pick the range count so that the units fill whole
+  // rounds of the persistent grid (round-robin dealing is then exact)
+  if (nprob == 1 && ps[0].K > 0) {
+    const double jobs = static_cast<double>(ps[0].nomega) * ps[0].ntl;
+    const int64_t s0 = std::max<int64_t>(1, std::llround(std::ceil(ps[0].K / per_unit)));
+    for (int64_t sr = s0; sr <= s0 + 16 && sr <= ps[0].K; ++sr) {
+      const double nu = jobs * sr;
+      if (std::fmod(nu, static_cast<double>(nwg)) == 0.0 &&
+          nu * slot_bytes <= max_partial_bytes) {
+        per_unit = static_cast<double>(ps[0].K) / sr * (1.0 + 1e-9);
+        break;
+      }
+    }
+  }
 
   struct Range { int b0, p0, b1, p1; int64_t n; };
   std::vector<std::vector<Range>> ranges(nprob);
@@ -425,19 +439,41 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
     if (ua.tq != ub.tq) return ua.tq < ub.tq;
     return ua.iw < ub.iw;
   });
-  // greedy list scheduling over logical workgroups
+  // Dealing.  When the units cost about the same (one problem shape: every
+  // tile has the same pairs), they are dealt round-robin in locality order,
+  // so that in every round the frequencies of a tile start together on
+  // neighbouring logical workgroups (one XCD) and stream the same rows of Z
+  // at the same time, sharing that XCD's L2.  Otherwise greedy list
+  // scheduling (each unit to the workgroup that becomes free first) keeps
+  // uneven problems balanced.
   std::vector<std::vector<int>> lists(nwg);
   std::vector<double> load(nwg, 0.0);
-  typedef std::pair<double, int> Slot;
-  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
-  for (int w = 0; w < nwg; ++w) heap.push(Slot(0.0, w));
-  for (int id : order) {
-    Slot sl = heap.top();
-    heap.pop();
-    lists[sl.second].push_back(id);
-    sl.first += hp.cost[id];
-    load[sl.second] = sl.first;
-    heap.push(sl);
+  double cmin = 0.0, cmax = 0.0;
+  for (size_t i = 0; i < hp.cost.size(); ++i) {
+    cmin = i ? std::min(cmin, hp.cost[i]) : hp.cost[i];
+    cmax = i ? std::max(cmax, hp.cost[i]) : hp.cost[i];
+  }
+  const size_t nu = order.size();
+  const bool uniform = nu > 0 && cmax <= 1.05 * cmin &&
+                       (nu % nwg == 0 || nu / nwg >= 16 || nu < static_cast<size_t>(nwg));
+  if (uniform) {
+    for (size_t i = 0; i < nu; ++i) {
+      const int w = static_cast<int>(i % nwg);
+      lists[w].push_back(order[i]);
+      load[w] += hp.cost[order[i]];
+    }
+  } else {
+    typedef std::pair<double, int> Slot;
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (int w = 0; w < nwg; ++w) heap.push(Slot(0.0, w));
+    for (int id : order) {
+      Slot sl = heap.top();
+      heap.pop();
+      lists[sl.second].push_back(id);
+      sl.first += hp.cost[id];
+      load[sl.second] = sl.first;
+      heap.push(sl);
+    }
   }
   // logical -> physical placement (XCD-major)
   const int nxcd = 8;
