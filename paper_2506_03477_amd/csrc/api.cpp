@@ -571,7 +571,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this build", prec);
   int tile_idx = tile_override >= 0 ? tile_override
                  : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
-                 : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind] : 0;
+                 : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind] : herk_default_tile(kind);
   if (tile_idx >= ntile) tile_idx = 0;
   int wg_per_cu = std::max(1, herk_max_wg_per_cu(kind, tile_idx));
   const int nwg = h->ncu * wg_per_cu;
@@ -1016,7 +1016,8 @@ int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile) {
   if (!h || !tile) return fail(CHI0_EINVAL, "NULL argument");
   const int k = kind_of(prec);
   if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
-  *tile = h->tile_sel[k] >= 0 ? h->tile_sel[k] : h->tile_tuned[k] >= 0 ? h->tile_tuned[k] : 0;
+  *tile = h->tile_sel[k] >= 0 ? h->tile_sel[k] : h->tile_tuned[k] >= 0 ? h->tile_tuned[k]
+                                                                         : herk_default_tile(k);
   return CHI0_OK;
 }
 
