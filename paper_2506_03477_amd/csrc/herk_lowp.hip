@@ -876,6 +876,11 @@ __global__ __launch_bounds__(512, 1) void herk_bf16x3_tall8_kernel(HerkArgs a) {
     const uint32_t cQ = col_offset(u.tq * TQ + lq, npb);
     const uint32_t cP = (u.tp * TP + lp < npb ? static_cast<uint32_t>(u.tp * TP + lp) : 0u) * 16u;
     double2* part = a.partials + static_cast<size_t>(u.slot) * TP * TQ;
+    // a wave whose 64 x 64 sub-tile lies entirely above the diagonal has no
+    // entry the reduction reads: it stages and synchronises but skips its
+    // MFMAs, leaving its SIMD to the other wave (tiles on the diagonal band)
+    const bool active =
+        __builtin_amdgcn_readfirstlane(u.tp * TP + wr * 64 + 63 >= u.tq * TQ + wc * 64) != 0;
 
     f32x16 cr[2][2], ci[2][2];
     zero_acc<2>(cr, ci);
@@ -905,7 +910,7 @@ __global__ __launch_bounds__(512, 1) void herk_bf16x3_tall8_kernel(HerkArgs a) {
         const bool more = cursor_next<kKC>(u, a.blocks, nxt);
         load_p(nxt, npb, cP, ph, pl);                       // unused when !more
         mk = load_q(pd, u.iw, nxt, npb, cQ, rb, rw);
-        tall_mfma<LOLO, 2>(L, buf, wr, wc, g8, l32, cr, ci);
+        if (active) tall_mfma<LOLO, 2>(L, buf, wr, wc, g8, l32, cr, ci);
         stage_p(buf ^ 1, ph, pl);
         stage_q(buf ^ 1, rb, rw, mk);
         __syncthreads();
