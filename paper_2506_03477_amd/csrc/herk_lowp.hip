@@ -780,12 +780,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
 // blocks, 128 accumulators, at most 256 registers per lane).  Thread t stages
 // P row t % 256 (chunks 2 (t / 256), + 1 of both planes) and Q column t % 128,
 // chunk t / 128 (wave-uniform); one register set, staged after the MFMAs.
-// ALT: the two waves of each SIMD (waves w and w + 4) run their phases in
-// opposite order -- one does MFMAs then staging, the other staging (of data
-// it loaded a stage earlier) then MFMAs -- so that one wave's staging overlaps
-// the other's matrix-core work instead of both idling the matrix core at the
-// same time before the barrier.
-template <bool LOLO, bool ALT>
+template <bool LOLO>
 __global__ __launch_bounds__(512, 1) void herk_bf16x3_tall8_kernel(HerkArgs a) {
   constexpr int TP = 256, TQ = 128;
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -886,7 +881,6 @@ __global__ __launch_bounds__(512, 1) void herk_bf16x3_tall8_kernel(HerkArgs a) {
     // MFMAs, leaving its SIMD to the other wave (tiles on the diagonal band)
     const bool active =
         __builtin_amdgcn_readfirstlane(u.tp * TP + wr * 64 + 63 >= u.tq * TQ + wc * 64) != 0;
-    const bool stage_first = ALT && __builtin_amdgcn_readfirstlane((wave >> 2) & 1) != 0;
 
     f32x16 cr[2][2], ci[2][2];
     zero_acc<2>(cr, ci);
@@ -906,12 +900,6 @@ __global__ __launch_bounds__(512, 1) void herk_bf16x3_tall8_kernel(HerkArgs a) {
       mk = load_q(pd, u.iw, cur, npb, cQ, rb, rw);
       stage_p(0, ph, pl);
       stage_q(0, rb, rw, mk);
-      if (stage_first) {   // registers hold the next stage's data from here on
-        Cursor nxt = cur;
-        cursor_next<kKC>(u, a.blocks, nxt);
-        load_p(nxt, npb, cP, ph, pl);
-        mk = load_q(pd, u.iw, nxt, npb, cQ, rb, rw);
-      }
     }
     __syncthreads();
     int buf = 0;
@@ -920,22 +908,11 @@ __global__ __launch_bounds__(512, 1) void herk_bf16x3_tall8_kernel(HerkArgs a) {
       for (int ns = 0; ns < flush_pairs * 2 && have; ++ns) {
         Cursor nxt = cur;
         const bool more = cursor_next<kKC>(u, a.blocks, nxt);
-        // stage-first waves stage the data of stage nxt (loaded one stage
-        // earlier) before loading the one after it; the others load nxt,
-        // run their MFMAs and stage afterwards
-        Cursor ld = nxt;
-        if (stage_first) {
-          stage_p(buf ^ 1, ph, pl);
-          stage_q(buf ^ 1, rb, rw, mk);
-          cursor_next<kKC>(u, a.blocks, ld);
-        }
-        load_p(ld, npb, cP, ph, pl);                        // unused when !more
-        mk = load_q(pd, u.iw, ld, npb, cQ, rb, rw);
+        load_p(nxt, npb, cP, ph, pl);                       // unused when !more
+        mk = load_q(pd, u.iw, nxt, npb, cQ, rb, rw);
         if (active) tall_mfma<LOLO, 2>(L, buf, wr, wc, g8, l32, cr, ci);
-        if (!stage_first) {
-          stage_p(buf ^ 1, ph, pl);
-          stage_q(buf ^ 1, rb, rw, mk);
-        }
+        stage_p(buf ^ 1, ph, pl);
+        stage_q(buf ^ 1, rb, rw, mk);
         __syncthreads();
         cur = nxt;
         have = more;
@@ -1079,7 +1056,6 @@ static const TileConfig kBf16Tiles[] = {
     {128, kKC, 4096, kNT, 128},      // 6: as 0, compiler scheduling (no interleave hints)
     {256, kKC, 4096, kNT, 128, 1},   // 7: as 5, compiler scheduling
     {256, kKC, 4096, 512, 128, 1},   // 8: tall tiles, 8 waves (two per SIMD)
-    {256, kKC, 4096, 512, 128, 1},   // 9: as 8, the two waves of a SIMD in opposite phase
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -1119,17 +1095,11 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
     case 4: launch_bf16_seq<128, 2>(lolo, a, nwg, s); break;
     case 5: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, true, nwg, s, a); break;
     case 7: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, false, nwg, s, a); break;
-    case 8:
-      if (lolo)
-        hipLaunchKernelGGL((herk_bf16x3_tall8_kernel<true, false>), dim3(nwg), dim3(512), 0, s, a);
-      else
-        hipLaunchKernelGGL((herk_bf16x3_tall8_kernel<false, false>), dim3(nwg), dim3(512), 0, s, a);
-      break;
     default:
       if (lolo)
-        hipLaunchKernelGGL((herk_bf16x3_tall8_kernel<true, true>), dim3(nwg), dim3(512), 0, s, a);
+        hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<true>, dim3(nwg), dim3(512), 0, s, a);
       else
-        hipLaunchKernelGGL((herk_bf16x3_tall8_kernel<false, true>), dim3(nwg), dim3(512), 0, s, a);
+        hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<false>, dim3(nwg), dim3(512), 0, s, a);
       break;
   }
   return hipGetLastError();
@@ -1157,7 +1127,7 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall_kernel<false, true>, kNT, 0);
       break;
     default:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false, true>, 512, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false>, 512, 0);
       break;
   }
   return e == hipSuccess && n > 0 ? n : 1;

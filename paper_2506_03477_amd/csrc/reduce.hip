@@ -58,14 +58,15 @@ hipError_t reduce_launch(const ReduceArgs& a, int njobs, hipStream_t s) {
 }
 
 // Built-in default configuration per path (fastest measured on the
-// npb = 2048 and spin-polarised workloads: the 8-wave tall BF16x3 kernel, the
-// 8-wave FP64 kernel, 64 x 64 FP32 tiles); the autotuner or chi0_set_tile
+// npb = 2048 and spin-polarised workloads: the 4-wave tall BF16x3 kernel
+// without scheduling hints, within run-to-run noise of the 8-wave one; the
+// 8-wave FP64 kernel; 64 x 64 FP32 tiles); the autotuner or chi0_set_tile
 // overrides it.
 int herk_default_tile(int kind) {
   switch (kind) {
     case HERK_FP64: return 3;
     case HERK_FP32: return 1;
-    case HERK_BF16X3: return 8;
+    case HERK_BF16X3: return 7;
   }
   return 0;
 }
