@@ -2,8 +2,8 @@
 the GPU path.  Input generation only: no polarization arithmetic lives here."""
 from .philox import philox4x32
 from .workloads import (Block, Workload, workload, z_scale_table, vsqrt_table,
-                        gauss_legendre_imag_axis, c3_word, KEY0, KEY1, TAG_Z)
+                        gauss_legendre_imag_axis, c3_word, KEY0, KEY1, TAG_Z, TAG_WC)
 
 __all__ = ["philox4x32", "Block", "Workload", "workload", "z_scale_table",
            "vsqrt_table", "gauss_legendre_imag_axis", "c3_word", "KEY0", "KEY1",
-           "TAG_Z"]
+           "TAG_Z", "TAG_WC"]

@@ -50,7 +50,51 @@ __global__ __launch_bounds__(256) void z_fill_kernel(void* out, int npb, uint64_
   }
 }
 
+// Synthetic W^c for the correlation workloads: element (i, mu, nu) of
+// [nomega][nmu][nmu] is -(C[i][mu] C[i][nu]) h[mu][nu] with h = 1 on the
+// diagonal and h = x F2[|mu - nu|] below it (x the centred Irwin-Hall draw of
+// element e = mu * nmu + nu), conjugated above it.  Products only, each
+// correctly rounded, in the order the CPU generator uses.
+__global__ __launch_bounds__(256) void wc_fill_kernel(double2* __restrict__ out, int nmu, int nomega,
+                                                      uint32_t bid, uint32_t c3,
+                                                      const double* __restrict__ F2,
+                                                      const double* __restrict__ C) {
+  const uint64_t plane = static_cast<uint64_t>(nmu) * nmu;
+  const uint64_t total = plane * nomega;
+  for (uint64_t t = blockIdx.x * 256ull + threadIdx.x; t < total; t += static_cast<uint64_t>(gridDim.x) * 256ull) {
+    const int i = static_cast<int>(t / plane);
+    const uint64_t rem = t - static_cast<uint64_t>(i) * plane;
+    const int mu = static_cast<int>(rem / nmu);
+    const int nu = static_cast<int>(rem - static_cast<uint64_t>(mu) * nmu);
+    double hr = 1.0, hi = 0.0;
+    if (mu != nu) {
+      const int a = mu > nu ? mu : nu, b = mu > nu ? nu : mu;
+      const uint64_t e = static_cast<uint64_t>(a) * nmu + b;
+      uint32_t c[4] = {static_cast<uint32_t>(e), static_cast<uint32_t>(e >> 32), bid, c3};
+      philox4x32_10(c, kKey0, kKey1);
+      const double f = F2[a - b];
+      hr = static_cast<double>(halves(c[0], c[1]) - 131070) * f;
+      hi = static_cast<double>(halves(c[2], c[3]) - 131070) * f;
+      if (mu < nu) hi = -hi;
+    }
+    const double cc = C[static_cast<size_t>(i) * nmu + mu] * C[static_cast<size_t>(i) * nmu + nu];
+    out[t] = double2{-(cc * hr), -(cc * hi)};
+  }
+}
+
 }  // namespace
+
+extern "C" int synth_wc_fill(void* out, int nmu, int nomega, uint32_t bid, uint32_t c3,
+                             const double* F2, const double* C, void* stream) {
+  if (!out || !F2 || !C || nmu < 1 || nomega < 1) return -1;
+  const uint64_t total = static_cast<uint64_t>(nmu) * nmu * nomega;
+  uint64_t nblk = (total + 255) / 256;
+  if (nblk > 1u << 20) nblk = 1u << 20;
+  hipLaunchKernelGGL(wc_fill_kernel, dim3(static_cast<unsigned>(nblk)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), static_cast<double2*>(out), nmu, nomega, bid, c3,
+                     F2, C);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
 
 extern "C" int synth_z_fill(void* out, int is_c64, int npb, int nocc, int nunocc, uint32_t bid,
                             uint32_t c3, const double* F, void* stream) {

@@ -13,7 +13,7 @@ from ctypes import c_int, c_uint32, c_void_p
 
 import numpy as np
 
-from .workloads import TAG_Z, Workload, c3_word, z_scale_table
+from .workloads import TAG_WC, TAG_Z, Workload, c3_word, z_scale_table
 
 _LIB = None
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynth_gen.so")
@@ -28,6 +28,9 @@ def _lib():
         lib.synth_z_fill.restype = c_int
         lib.synth_z_fill.argtypes = [c_void_p, c_int, c_int, c_int, c_int, c_uint32, c_uint32,
                                      c_void_p, c_void_p]
+        lib.synth_wc_fill.restype = c_int
+        lib.synth_wc_fill.argtypes = [c_void_p, c_int, c_int, c_uint32, c_uint32, c_void_p,
+                                      c_void_p, c_void_p]
         _LIB = lib
     return _LIB
 
@@ -65,3 +68,39 @@ def device_workload(wl: Workload, q: int = 0, device="cuda", ztype=None, blocks=
     omega = torch.tensor(wl.omega, dtype=torch.float64, device=device)
     vsqrt = torch.from_numpy(wl.vsqrt()).to(device)
     return out, omega, vsqrt
+
+
+def wc_block_device(wl: Workload, blk, device="cuda", tables=None):
+    """Synthetic W^c of one block as a [nomega, nmu, nmu] complex128 device
+    tensor (bit-identical to ``Workload.wc_block``)."""
+    import torch
+    nmu = blk.nunocc
+    if tables is None:
+        f2, c = wl.wc_tables(nmu)
+        tables = (torch.from_numpy(f2).to(device), torch.from_numpy(np.ascontiguousarray(c)).to(device))
+    w = torch.empty((wl.nomega, nmu, nmu), dtype=torch.complex128, device=device)
+    s = torch.cuda.current_stream(w.device)
+    rc = _lib().synth_wc_fill(c_void_p(w.data_ptr()), nmu, wl.nomega, blk.bid,
+                              c3_word(wl.cfg, TAG_WC, wl.seed), c_void_p(tables[0].data_ptr()),
+                              c_void_p(tables[1].data_ptr()), c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"synth_wc_fill failed ({rc})")
+    return w
+
+
+def device_sigc_workload(wl: Workload, q: int = 0, device="cuda", blocks=None):
+    """Inputs of one q-point of a correlation workload on the device:
+    (list of (z, wc, eps_mid (host numpy), wk, Block), eps_qp (host numpy))."""
+    import torch
+    tab = torch.from_numpy(z_scale_table(wl.npb)).to(device)
+    wtab = {}
+    out = []
+    for blk in (wl.blocks(q) if blocks is None else blocks):
+        if blk.nunocc not in wtab:
+            f2, c = wl.wc_tables(blk.nunocc)
+            wtab[blk.nunocc] = (torch.from_numpy(f2).to(device),
+                                torch.from_numpy(np.ascontiguousarray(c)).to(device))
+        z = z_block_device(wl, blk, device, tab, "c128")
+        wc = wc_block_device(wl, blk, device, wtab[blk.nunocc])
+        out.append((z, wc, wl.eps_mid(blk), blk.wk, blk))
+    return out, wl.eps_qp(q)

@@ -48,6 +48,8 @@ TAG_Z = 0
 TAG_EOCC = 1
 TAG_EUNOCC = 2
 TAG_SIZE = 3
+TAG_EQP = 4
+TAG_WC = 5
 
 IRWIN_HALL_CENTRE = 131070  # 4 * (65535 / 2)
 
@@ -117,6 +119,7 @@ class Workload:
     metallic: bool = False
     seed: int = 0
     paths: Tuple[str, ...] = ("fp64",)
+    nval: int = 0                  # correlation workloads: occupied states among n', n
 
     # ------------------------------------------------------------------ layout
     def replace(self, **kw) -> "Workload":
@@ -189,6 +192,75 @@ class Workload:
         |G|^2 growing as mu^(2/3)."""
         return (1.0 + np.arange(blk.nunocc, dtype=np.float64)) ** (-2.0 / 3.0)
 
+    # ---------------------------------------- correlation self-energy inputs
+    # For the correlation workloads the block fields read: npb = nqp (the
+    # quasiparticle states n, innermost index of Z), nocc = nall (all
+    # intermediate states n'), nunocc = number of product-basis functions mu.
+    def eps_qp(self, q: int = 0) -> np.ndarray:
+        """Quasiparticle energies eps_{q n}, n < npb: the lowest nval
+        occupied in occ_range, the rest unoccupied in unocc_range, sorted."""
+        nv = min(self.nval, self.npb)
+        bid = 0xFFFF0000 | (q & 0xFFFF)
+        u = self._uniform(self.npb, bid, TAG_EQP)
+        olo, ohi = self.occ_range
+        ulo, uhi = self.unocc_range
+        e = np.concatenate([olo + (ohi - olo) * u[:nv], ulo + (uhi - ulo) * u[nv:]])
+        return np.sort(e)
+
+    def eps_mid(self, blk: Block) -> np.ndarray:
+        """Intermediate-state energies eps_{q-k, n'}, n' < nocc (= nall):
+        nval occupied, the rest unoccupied, sorted."""
+        nv = min(self.nval, blk.nocc)
+        olo, ohi = self.occ_range
+        ulo, uhi = self.unocc_range
+        eo = olo + (ohi - olo) * self._uniform(nv, blk.bid, TAG_EOCC)
+        eu = ulo + (uhi - ulo) * self._uniform(blk.nocc - nv, blk.bid, TAG_EUNOCC)
+        return np.sort(np.concatenate([eo, eu]))
+
+    def wc_tables(self, nmu: int) -> Tuple[np.ndarray, np.ndarray]:
+        """Factor tables of the synthetic W^c (see ``wc_block``):
+        F2[d] = 0.02 sqrt(3)/65536 exp(-d/8) for d = |mu - nu|, and
+        C[i][mu] = s_mu / sqrt(1 + (w_i / Omega_mu)^2) with s_mu = 1/(1+mu),
+        Omega_mu = 0.3 + 3 mu / nmu (Hartree)."""
+        d = np.arange(nmu, dtype=np.float64)
+        f2 = (0.02 * math.sqrt(3.0) / 65536.0) * np.exp(-d / 8.0)
+        om = self.omega_array()[:, None]
+        big_omega = 0.3 + 3.0 * d / max(nmu, 1)
+        c = (1.0 / (1.0 + d))[None, :] / np.sqrt(1.0 + (om / big_omega[None, :]) ** 2)
+        return f2, c
+
+    def wc_block(self, blk: Block, tables=None) -> np.ndarray:
+        """Synthetic correlation interaction W^c_k(i w_i)[mu][nu], complex128
+        [nomega][nmu][nmu] with nmu = blk.nunocc: Hermitian and negative
+        definite at every w_i, decaying as 1/w^2.  W = -(C_i[mu] C_i[nu]) h,
+        with h[mu][mu] = 1 and, for mu > nu, h = x F2[mu - nu] where x is the
+        Irwin-Hall complex draw at element e = mu * nmu + nu of stream
+        TAG_WC; h[nu][mu] = conj(h[mu][nu]).  Every value is one or two
+        correctly rounded products of exact numbers, so the GPU generator
+        reproduces it bit for bit."""
+        nmu = blk.nunocc
+        f2, c = self.wc_tables(nmu) if tables is None else tables
+        mu = np.arange(nmu, dtype=np.uint64)
+        e = (mu[:, None] * np.uint64(nmu) + mu[None, :]).reshape(-1)
+        r0, r1, r2, r3 = philox4x32(e & np.uint64(0xFFFFFFFF), e >> np.uint64(32), blk.bid,
+                                    c3_word(self.cfg, TAG_WC, self.seed), KEY0, KEY1)
+        xr = (_halves_sum(r0, r1).astype(np.int64) - IRWIN_HALL_CENTRE).astype(np.float64)
+        xi = (_halves_sum(r2, r3).astype(np.int64) - IRWIN_HALL_CENTRE).astype(np.float64)
+        xr = xr.reshape(nmu, nmu)
+        xi = xi.reshape(nmu, nmu)
+        dd = np.abs(np.arange(nmu)[:, None] - np.arange(nmu)[None, :])
+        lower = np.tril(np.ones((nmu, nmu), bool), -1)
+        hr = np.where(lower, xr * f2[dd], 0.0)
+        hi = np.where(lower, xi * f2[dd], 0.0)
+        hr = hr + hr.T + np.eye(nmu)
+        hi = hi - hi.T
+        out = np.empty((self.nomega, nmu, nmu), np.complex128)
+        for i in range(self.nomega):
+            cc = c[i][:, None] * c[i][None, :]
+            out[i].real = -(cc * hr)
+            out[i].imag = -(cc * hi)
+        return out
+
     # ----------------------------------------------------------------------- Z
     def z_elements(self, blk: Block, pair_index: np.ndarray,
                    cols: np.ndarray) -> np.ndarray:
@@ -259,6 +331,17 @@ def workload(cfg: int, **overrides) -> Workload:
         wl = Workload(name="sigx_nqp287_nocc92_npb2097", cfg=5, npb=287, nq=1, nspin=1,
                       nk=16, nocc=92, nunocc=2097, omega=(0.0,), ztype="c128",
                       paths=("fp64", "fp32", "bf16x3"))
+    elif cfg == 6:
+        # Imaginary-axis correlation self-energy I^c (Eq.(sigci)) at the
+        # (InAs)2(GaSb)2 sizes of the paper's system-size table: nqp = 206
+        # quasiparticle states, nall = 361 intermediate states n' (92
+        # occupied), 1356 product-basis functions mu, 16 k-points; 11
+        # imaginary frequencies including w = 0 (0 and 10 Gauss-Legendre
+        # nodes mapped to [0, inf)).
+        mesh = (0.0,) + tuple(float(x) for x in gauss_legendre_imag_axis(10))
+        wl = Workload(name="sigc_nqp206_nall361_npb1356_nk16_11w", cfg=6, npb=206, nq=1,
+                      nspin=1, nk=16, nocc=361, nunocc=1356, omega=mesh, ztype="c128",
+                      nval=92, paths=("fp64", "bf16x3"))
     else:
         raise ValueError(f"unknown workload {cfg}")
     if overrides:

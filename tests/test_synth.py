@@ -100,3 +100,29 @@ def test_gauss_legendre_map():
     x = (w - 1) / (w + 1)
     xr, _ = np.polynomial.legendre.leggauss(12)
     assert np.allclose(np.sort(x), np.sort(xr), atol=1e-13)
+
+
+def test_correlation_workload_inputs():
+    """Workload 6 (imaginary-axis correlation self-energy): sizes, energies
+    and the synthetic W^c (Hermitian, negative definite, decaying in w)."""
+    wl = workload(6)
+    assert wl.omega[0] == 0.0 and np.all(np.diff(wl.omega) > 0) and wl.nomega == 11
+    blks = wl.blocks()
+    assert len(blks) == 16 and all(b.nocc == 361 and b.nunocc == 1356 for b in blks)
+    eq = wl.eps_qp()
+    assert eq.shape == (206,) and (eq < 0).sum() == 92 and np.all(np.diff(eq) >= 0)
+    em = wl.eps_mid(blks[3])
+    assert em.shape == (361,) and (em < 0).sum() == 92
+    small = wl.replace(npb=5, nocc=4, nunocc=24, nval=2)
+    b = small.blocks()[1]
+    w = small.wc_block(b)
+    assert w.shape == (11, 24, 24)
+    assert np.array_equal(w, np.conj(np.transpose(w, (0, 2, 1))))
+    ev = np.linalg.eigvalsh(w)
+    assert ev.max() < 0
+    norms = np.linalg.norm(w, axis=(1, 2))
+    assert np.all(np.diff(norms) < 0)
+    # large-w tail ~ 1/w^2 for the first product-basis function
+    assert abs(w[-1, 0, 0] / w[-2, 0, 0] - (1 + (wl.omega[-2] / 0.3) ** 2) /
+               (1 + (wl.omega[-1] / 0.3) ** 2)) < 1e-12
+    assert not np.array_equal(small.wc_block(small.blocks()[2]), w)
