@@ -283,6 +283,127 @@ def bench_sigx(args):
     ctx.close()
 
 
+def sigc_flops(nqp, nall, nmu, nomega):
+    """Algorithmic flops of one block of the imaginary-axis correlation
+    self-energy: the first contraction (rows (n', n), columns nu, contraction
+    (i, mu)) and the second (nqp x nqp, contraction (n', nu)), 8 flops per
+    complex multiply-add."""
+    first = 8.0 * nall * nqp * nmu * nomega * nmu
+    second = 8.0 * nqp * nqp * nall * nmu
+    return first, second
+
+
+def sigc_cpu_baseline(wl, target_s=15.0):
+    """The correlation oracle on a bounded sample: the first n' states of one
+    k-point at full nqp, product-basis size and mesh."""
+    from threadpoolctl import threadpool_info
+
+    from oracle.sigc_oracle import sigc_ref
+
+    blk = wl.blocks(0)[0]
+    wc = wl.wc_block(blk)
+    eps_mid = wl.eps_mid(blk)
+    eps_qp = wl.eps_qp()
+
+    def run(nall_s):
+        sub = blk.__class__(q=blk.q, spin=blk.spin, k=blk.k, nocc=nall_s, nunocc=blk.nunocc,
+                            wk=blk.wk, bid=blk.bid)
+        z = wl.z_block(sub)
+        t0 = time.perf_counter()
+        sigc_ref([(z, wc, eps_mid[:nall_s], blk.wk)], eps_qp, wl.omega)
+        return time.perf_counter() - t0
+
+    t1 = run(1)
+    nall_s = int(min(blk.nocc, max(1, round(target_s / max(t1, 1e-4)))))
+    t_meas = run(nall_s) if nall_s > 1 else t1
+    flops = sum(sigc_flops(wl.npb, nall_s, blk.nunocc, wl.nomega))
+    threads = 0
+    for info in threadpool_info():
+        if info.get("user_api") == "blas":
+            threads = max(threads, int(info.get("num_threads", 0)))
+    return {"value": flops / t_meas / 1e12, "unit": "TFLOP/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{nall_s} of {blk.nocc} intermediate states of one k-point, nqp={wl.npb}, "
+                      f"{blk.nunocc} product-basis functions, {wl.nomega} frequencies "
+                      f"({t_meas:.1f} s)"}
+
+
+def bench_sigc(args):
+    """Imaginary-axis correlation self-energy (Eq.(sigci)) of one q-point,
+    FP64 path: one JSON line."""
+    import torch
+
+    from paper_2506_03477_amd import Context, SigcBlock, SigcProblem
+    from synth import workload
+    from synth.gpu import device_sigc_workload
+
+    wl = workload(6)
+    prec = args.precision or "fp64"
+    if prec != "fp64":
+        raise SystemExit("the correlation self-energy runs on the FP64 path only")
+    torch.cuda.set_device(0)
+    ctx = Context(0)
+    if args.tile >= 0:
+        ctx.sigc_set_variant(args.tile)
+    log(f"generating {wl.name} inputs on the GPU")
+    blks, eps_qp = device_sigc_workload(wl)
+    out = torch.empty((wl.npb, wl.npb), dtype=torch.complex128, device="cuda")
+    prob = SigcProblem([SigcBlock(z, wc, em, wk) for z, wc, em, wk, _ in blks], eps_qp,
+                       wl.omega_array(), out)
+    first = second = 0.0
+    exe_first = 0.0
+    for b in wl.blocks(0):
+        f1, f2 = sigc_flops(wl.npb, b.nocc, b.nunocc, wl.nomega)
+        first += f1
+        second += f2
+        t = 128
+        rows = -(-b.nocc * wl.npb // t) * t
+        cols = -(-b.nunocc // t) * t
+        exe_first += 8.0 * rows * cols * wl.nomega * (-(-b.nunocc // 8) * 8)
+    for _ in range(args.warmup):
+        ctx.sigc_accumulate([prob])
+    ctx.sync()
+    ctx.profile_enable(True)
+    ctx.profile_read()
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for s in range(args.steps):
+        ctx.sigc_accumulate([prob])
+    b.record(stream)
+    b.synchronize()
+    ctx.sync()
+    ms = a.elapsed_time(b) / args.steps
+    kern_ms, n = ctx.profile_read()
+    roof = None
+    if n:
+        launches_per_step = n / args.steps
+        kern_avg = kern_ms / n
+        per_launch = first / launches_per_step
+        ach = per_launch / (kern_avg * 1e-3) / 1e12
+        exe = exe_first / launches_per_step / (kern_avg * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["fp64"],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS["fp64"], 4), "traffic": None,
+                "kernel": "sigc_gemm_kernel (first contraction)", "kernel_ms": round(kern_avg, 3),
+                "launches_per_step": launches_per_step,
+                "executed_mfma_tflops": round(exe, 3),
+                "executed_mfma_frac": round(exe / PEAK_TFLOPS["fp64"], 4)}
+    cpu = None if args.no_cpu_baseline else sigc_cpu_baseline(wl)
+    print(json.dumps({
+        "metric": "I^c TFLOP/s per q-point (imaginary-axis correlation self-energy, Eq. sigci)",
+        "value": round((first + second) / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "nqp": wl.npb, "nk": wl.nk, "nall": wl.nocc,
+                   "nmu": wl.nunocc, "nomega": wl.nomega, "path": prec,
+                   "variant": args.tile if args.tile >= 0 else 0},
+        "flops_first": first, "flops_second": second,
+        "roofline": roof, "cpu_baseline": cpu}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +428,8 @@ def main():
     ap.add_argument("--command", default="", help="profiled command (for the summaries)")
     ap.add_argument("--sigx", action="store_true",
                     help="time the exchange self-energy (Eq. sigx) instead of chi0")
+    ap.add_argument("--sigc", action="store_true",
+                    help="time the imaginary-axis correlation self-energy (Eq. sigci)")
     args = ap.parse_args()
 
     if args.summarize_counters:
@@ -324,6 +447,9 @@ def main():
 
     if args.sigx and args.gpus == 1:
         bench_sigx(args)
+        return
+    if args.sigc and args.gpus == 1:
+        bench_sigc(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "

@@ -182,6 +182,62 @@ int sigx_accumulate(chi0_handle h, const sigx_problem* probs, int32_t nprob,
                     chi0_ztype zt, chi0_precision prec, uint32_t flags,
                     void* hip_stream);
 
+/* Imaginary-axis part I^c of the correlation self-energy (Eq.(sigci),
+ * Section "Self-energy"; the QK-Omega^I block of the self-energy algorithm)
+ * of one q-point, one k-point block:
+ *   I^c[n][m] += -w_k sum_{n'} sum_i w_i(eps_qp[n] - eps_mid[n'])
+ *                sum_{mu,nu} conj(Z[n'][mu][n]) W^c_i[mu][nu] Z[n'][nu][m].
+ * n' runs over all intermediate states (occupied and unoccupied); the row n
+ * alone sets the energy difference, so I^c is not Hermitian in general.
+ * The integration weights w_i(dE) (the Aryasetiawan-Gunnarsson weights the
+ * paper cites but does not print) are the exact integrals of
+ * dE / (pi (dE^2 + w^2)) over [0, inf) against the interpolant of W^c on the
+ * mesh: constant below omega[0], linear between nodes, W^c(omega_last)
+ * (omega_last / w)^2 beyond the last node; at dE = 0 they are 0. */
+typedef struct {
+  int32_t nall;            /* intermediate states n', >= 0                    */
+  int32_t nmu;             /* product-basis functions mu, >= 1                */
+  const void* z;           /* DEVICE [nall][nmu][nqp] complex128, Z_k[n'][mu][n],
+                              16-byte aligned                                 */
+  const void* wc;          /* DEVICE [nomega][nmu][nmu] complex128,
+                              W^c_k(i omega_i)[mu][nu] (e.g. the CHI0_OUT_WC
+                              output of dielectric_invert), 16-byte aligned   */
+  const double* eps_mid;   /* HOST [nall]: eps_{q-k, n'}, finite              */
+  double wk;               /* >= 0, finite; Brillouin-zone / spin weight      */
+} sigc_block;
+
+typedef struct {
+  int32_t nqp;             /* quasiparticle states n, m, >= 1                 */
+  int32_t nblocks;         /* >= 0                                            */
+  const sigc_block* blocks;/* HOST [nblocks]                                  */
+  const double* eps_qp;    /* HOST [nqp]: eps_{q n}, finite                   */
+  int32_t nomega;          /* imaginary-axis mesh size, >= 1                  */
+  int32_t pad;
+  const double* omega;     /* HOST [nomega]: 0 <= omega[0] < omega[1] < ...   */
+  void* sigc;              /* DEVICE out [nqp][nqp] complex128, 16-byte aligned */
+} sigc_problem;
+
+/* I^c for `nprob` q-points.  FP64 path only (prec = CHI0_PREC_FP64, zt =
+ * CHI0_Z_C128; anything else returns CHI0_EUNSUPPORTED).  flags:
+ * CHI0_ACCUMULATE adds to sigc instead of overwriting it.  Work: a first
+ * FP64 matrix-core contraction ZW[n'][n][nu] = sum_{i,mu} t conj(Z) W^c_i
+ * (t = -w_k w_i) into a workspace the size of Z, blocks grouped so that it
+ * stays under the workspace cap, then sum_{n', nu} ZW Z in segments whose
+ * FP64 partial tiles are summed in a fixed order (deterministic).
+ * Asynchronous on hip_stream like chi0_accumulate; inputs must stay valid
+ * until the stream reaches the call's end. */
+int sigc_accumulate(chi0_handle h, const sigc_problem* probs, int32_t nprob,
+                    chi0_ztype zt, chi0_precision prec, uint32_t flags,
+                    void* hip_stream);
+
+/* Kernel variant of the first contraction (0: 4 waves of 64 x 64 per
+ * 128 x 128 tile, 1: 8 waves of 64 x 32); CHI0_EINVAL when out of range. */
+int sigc_set_variant(chi0_handle h, int32_t variant);
+
+/* Cap in bytes of the ZW workspace of one group of blocks (0: the default,
+ * 4 GiB; a block larger than the cap forms a group of its own). */
+int sigc_set_workspace_cap(chi0_handle h, int64_t bytes);
+
 /* Dielectric step for one q-point (Eq.(dielectricfunction), Eq.(wc);
  * Algorithm "hrcxq" builds eps, inverts it, forms W^c):
  *   eps[w] = 1 - diag(vsqrt) chi0[w] diag(vsqrt), eps_inv[w] = eps[w]^{-1}

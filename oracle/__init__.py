@@ -11,4 +11,5 @@ from .chi0_oracle import (chi0_ref, chi0_brute, chi0_exact, chi0_entries,
                           pair_delta, pair_included, rel_fro, workload_blocks)
 from .sigx_oracle import sigx_block, sigx_brute, sigx_exact, sigx_ref  # noqa: F401
 from .sigc_oracle import (ag_weights, ag_weight_table, sigc_block, sigc_brute,  # noqa: F401
-                          sigc_contract, sigc_contract_exact, sigc_ref, sigc_rows)
+                          sigc_contract, sigc_contract_exact, sigc_entries, sigc_ref,
+                          sigc_rows)

@@ -38,6 +38,7 @@ unpinned".
 """
 from __future__ import annotations
 
+import math
 from fractions import Fraction
 from typing import Iterable, Sequence, Tuple
 
@@ -66,8 +67,8 @@ def ag_weights(delta: float, mesh: Sequence[float]) -> np.ndarray:
     # precision
     scale = max(abs(mesh[-1]), 1e-300)
     lo = min(mesh[i + 1] - mesh[i] for i in range(n - 1)) if n > 1 else scale
-    extra = (2 * max(0.0, np.log10(scale / abs(delta)))
-             + 2 * max(0.0, np.log10(abs(delta) / lo)) + max(0.0, np.log10(scale / lo)))
+    ls, ld, ll = math.log10(scale), math.log10(abs(delta)), math.log10(lo)
+    extra = 2 * max(0.0, ls - ld) + 2 * max(0.0, ld - ll) + max(0.0, ls - ll)
     with mpmath.workdps(40 + int(extra) + 5):
         d = mpmath.mpf(delta)
         om = [mpmath.mpf(x) for x in mesh]
@@ -166,6 +167,30 @@ def sigc_rows(blocks: Iterable[SigcBlock], eps_qp: np.ndarray,
             for i in range(wc.shape[0]):
                 zw += (zr * wt[a, :, i][None, :]).conj().T @ wc[i]
             part += zw @ z[a]
+        acc.add(-float(wk) * part)
+    return acc.value()
+
+
+def sigc_entries(blocks, eps_qp: np.ndarray, mesh: Sequence[float],
+                 entries: Sequence[Tuple[int, int]]) -> np.ndarray:
+    """Selected entries I^c[n][m] of a large problem.  ``blocks`` yields
+    (zc, cols, W^c, eps_mid, w_k) with zc[n'][mu][j] = Z[n'][mu][cols[j]]
+    holding at least the columns n and m of every entry."""
+    eps_qp = np.asarray(eps_qp, np.float64)
+    rows = sorted({int(n) for n, _ in entries})
+    acc = _CompensatedSum((len(entries),))
+    for zc, cols, wc, eps_mid, wk in blocks:
+        zc = np.asarray(zc, np.complex128)                         # [n', mu, j]
+        wc = np.asarray(wc, np.complex128)
+        where = {int(c): j for j, c in enumerate(cols)}
+        wt = ag_weight_table(eps_qp[rows], eps_mid, mesh)          # [n', row, i]
+        wrow = {n: k for k, n in enumerate(rows)}
+        part = np.zeros(len(entries), np.complex128)
+        for i in range(wc.shape[0]):
+            t = np.matmul(wc[i][None, :, :], zc)                   # W_i Z[n'], [n', nu, j]
+            s = np.matmul(np.conj(np.transpose(zc, (0, 2, 1))), t)  # [n', j, k]
+            for e, (n, m) in enumerate(entries):
+                part[e] += np.sum(wt[:, wrow[n], i] * s[:, where[n], where[m]])
         acc.add(-float(wk) * part)
     return acc.value()
 

@@ -57,6 +57,17 @@ class sigx_problem(ctypes.Structure):
                 ("sigx", c_void_p)]
 
 
+class sigc_block(ctypes.Structure):
+    _fields_ = [("nall", c_int32), ("nmu", c_int32), ("z", c_void_p), ("wc", c_void_p),
+                ("eps_mid", c_void_p), ("wk", c_double)]
+
+
+class sigc_problem(ctypes.Structure):
+    _fields_ = [("nqp", c_int32), ("nblocks", c_int32), ("blocks", POINTER(sigc_block)),
+                ("eps_qp", c_void_p), ("nomega", c_int32), ("pad", c_int32),
+                ("omega", c_void_p), ("sigc", c_void_p)]
+
+
 class Chi0Error(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libchi0 error {code}: {msg}")
@@ -86,6 +97,9 @@ def load() -> ctypes.CDLL:
         "dielectric_invert": (c_int, [vp, c_int32, c_int32, vp, vp, vp, vp, vp, c_uint32, vp]),
         "chi0_sync": (c_int, [vp]),
         "sigx_accumulate": (c_int, [vp, POINTER(sigx_problem), c_int32, c_int, c_int, c_uint32, vp]),
+        "sigc_accumulate": (c_int, [vp, POINTER(sigc_problem), c_int32, c_int, c_int, c_uint32, vp]),
+        "sigc_set_variant": (c_int, [vp, c_int32]),
+        "sigc_set_workspace_cap": (c_int, [vp, c_int64]),
         "chi0_tile_count": (c_int, [c_int]),
         "chi0_tile_info": (c_int, [c_int, c_int32, POINTER(c_int32), POINTER(c_int32),
                                    POINTER(c_int32), POINTER(c_int32)]),
@@ -205,6 +219,76 @@ def _marshal_sigx(problems: Sequence[SigxProblem]):
     return arr, keep
 
 
+@dataclass
+class SigcBlock:
+    """One k-point of the imaginary-axis correlation self-energy: z
+    [nall, nmu, nqp] and wc [nomega, nmu, nmu] complex128 device tensors,
+    eps_mid [nall] host float64 array (energies of the intermediate states),
+    wk."""
+    z: object
+    wc: object
+    eps_mid: object
+    wk: float
+
+
+@dataclass
+class SigcProblem:
+    """One q-point: blocks, host eps_qp [nqp] and omega [nomega] (float64),
+    and the [nqp, nqp] complex128 device output."""
+    blocks: List[SigcBlock]
+    eps_qp: object
+    omega: object
+    sigc: object
+
+
+def _host_f64(x, n, what):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(x.cpu() if hasattr(x, "cpu") else x, dtype=np.float64))
+    if a.ndim != 1 or a.size != n:
+        raise ValueError(f"{what} must have {n} values, has shape {a.shape}")
+    return a
+
+
+def _marshal_sigc(problems: Sequence[SigcProblem]):
+    import torch
+    keep = []
+    arr = (sigc_problem * len(problems))()
+    for i, p in enumerate(problems):
+        nqp, nqp2 = p.sigc.shape
+        if nqp != nqp2:
+            raise ValueError("sigc must be [nqp, nqp]")
+        eq = _host_f64(p.eps_qp, nqp, "eps_qp")
+        om = _host_f64(p.omega, len(p.omega), "omega")
+        nomega = om.size
+        barr = (sigc_block * max(1, len(p.blocks)))()
+        for j, b in enumerate(p.blocks):
+            nomega_b, nmu, nmu2 = b.wc.shape
+            if nmu != nmu2 or nomega_b != nomega:
+                raise ValueError(f"block {j}: wc shape {tuple(b.wc.shape)} != {(nomega, nmu, nmu)}")
+            has_z = b.z is not None and b.z.numel() > 0
+            nall = int(b.z.shape[0]) if has_z else 0
+            if has_z and tuple(b.z.shape) != (nall, nmu, nqp):
+                raise ValueError(f"block {j}: z shape {tuple(b.z.shape)} != {(nall, nmu, nqp)}")
+            em = _host_f64(b.eps_mid, nall, "eps_mid")
+            keep.append(em)
+            barr[j].nall = nall
+            barr[j].nmu = nmu
+            barr[j].z = _dev_ptr(b.z, torch.complex128, "z") if has_z else None
+            barr[j].wc = _dev_ptr(b.wc, torch.complex128, "wc")
+            barr[j].eps_mid = em.ctypes.data if nall else None
+            barr[j].wk = float(b.wk)
+        keep += [barr, eq, om]
+        arr[i].nqp = nqp
+        arr[i].nblocks = len(p.blocks)
+        arr[i].blocks = ctypes.cast(barr, POINTER(sigc_block))
+        arr[i].eps_qp = eq.ctypes.data
+        arr[i].nomega = nomega
+        arr[i].pad = 0
+        arr[i].omega = om.ctypes.data
+        arr[i].sigc = _dev_ptr(p.sigc, torch.complex128, "sigc")
+    return arr, keep
+
+
 def _marshal(problems: Sequence[Problem]):
     import torch
     keep = []
@@ -289,6 +373,20 @@ class Context:
             (CHI0_USE_GRAPH if graph else 0)
         _check(self._lib.sigx_accumulate(self._h, arr, len(problems), zt, PREC[precision], flags,
                                          _stream_ptr(stream)))
+
+    # -- imaginary-axis correlation self-energy --------------------------------
+    def sigc_accumulate(self, problems: Sequence[SigcProblem], precision: str = "fp64",
+                        accumulate: bool = False, stream=None) -> None:
+        arr, keep = _marshal_sigc(problems)
+        flags = CHI0_ACCUMULATE if accumulate else 0
+        _check(self._lib.sigc_accumulate(self._h, arr, len(problems), ZTYPE["c128"],
+                                         PREC[precision], flags, _stream_ptr(stream)))
+
+    def sigc_set_variant(self, variant: int) -> None:
+        _check(self._lib.sigc_set_variant(self._h, int(variant)))
+
+    def sigc_set_workspace_cap(self, nbytes: int) -> None:
+        _check(self._lib.sigc_set_workspace_cap(self._h, int(nbytes)))
 
     # -- dielectric ----------------------------------------------------------
     def dielectric_invert(self, vsqrt, chi0, eps_inv, eps=None, wc=None, method: str = "gj",

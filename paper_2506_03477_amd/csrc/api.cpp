@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -104,6 +105,9 @@ struct chi0_ctx {
   DevBuf zsplit;        // pre-split P-side planes of the current call
   DevBuf gj_work, gj_wrow, gj_piv, gj_perm;
   DevBuf hpd_p, hpd_c, hpd_dinv;  // HPD inverse: kept panel, new panel, D^{-1}
+  DevBuf sigc_tab, sigc_wt, sigc_zw, sigc_part, sigc_acc;  // correlation self-energy
+  int sigc_variant = 0;
+  int64_t sigc_zw_cap = int64_t(4) << 30;
   uint64_t ws_gen = 1;
   int32_t* d_status = nullptr;
   void* staging = nullptr;  // pinned host staging for table uploads
@@ -770,6 +774,321 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   return CHI0_OK;
 }
 
+int validate_sigc(const sigc_problem* probs, int32_t nprob, chi0_ztype zt, chi0_precision prec,
+                  uint32_t flags) {
+  if (nprob < 0) return fail(CHI0_EINVAL, "nprob = %d < 0", nprob);
+  if (nprob > 0 && !probs) return fail(CHI0_EINVAL, "probs is NULL");
+  if (prec != CHI0_PREC_FP64 && prec != CHI0_PREC_FP32 && prec != CHI0_PREC_BF16X3)
+    return fail(CHI0_EINVAL, "unknown precision %d", static_cast<int>(prec));
+  if (zt != CHI0_Z_C128 && zt != CHI0_Z_C64)
+    return fail(CHI0_EINVAL, "unknown Z type %d", static_cast<int>(zt));
+  if (flags & ~static_cast<uint32_t>(CHI0_ACCUMULATE))
+    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  for (int p = 0; p < nprob; ++p) {
+    const sigc_problem& pr = probs[p];
+    if (pr.nqp < 1) return fail(CHI0_EINVAL, "problem %d: nqp = %d < 1", p, pr.nqp);
+    if (pr.nblocks < 0) return fail(CHI0_EINVAL, "problem %d: nblocks = %d < 0", p, pr.nblocks);
+    if (pr.nblocks > 0 && !pr.blocks) return fail(CHI0_EINVAL, "problem %d: blocks is NULL", p);
+    if (pr.nomega < 1) return fail(CHI0_EINVAL, "problem %d: nomega = %d < 1", p, pr.nomega);
+    if (!pr.omega || !pr.eps_qp) return fail(CHI0_EINVAL, "problem %d: omega or eps_qp is NULL", p);
+    for (int i = 0; i < pr.nomega; ++i) {
+      if (!std::isfinite(pr.omega[i]) || pr.omega[i] < 0.0)
+        return fail(CHI0_EINVAL, "problem %d: omega[%d] must be finite and >= 0", p, i);
+      if (i > 0 && !(pr.omega[i] > pr.omega[i - 1]))
+        return fail(CHI0_EINVAL, "problem %d: omega must be strictly increasing", p);
+    }
+    for (int n = 0; n < pr.nqp; ++n)
+      if (!std::isfinite(pr.eps_qp[n])) return fail(CHI0_EINVAL, "problem %d: eps_qp[%d] not finite", p, n);
+    if (!pr.sigc) return fail(CHI0_EINVAL, "problem %d: sigc is NULL", p);
+    if (!aligned(pr.sigc, 16)) return fail(CHI0_EINVAL, "problem %d: sigc not 16-byte aligned", p);
+    for (int b = 0; b < pr.nblocks; ++b) {
+      const sigc_block& bl = pr.blocks[b];
+      if (bl.nall < 0) return fail(CHI0_EINVAL, "problem %d block %d: nall = %d < 0", p, b, bl.nall);
+      if (bl.nmu < 1) return fail(CHI0_EINVAL, "problem %d block %d: nmu = %d < 1", p, b, bl.nmu);
+      if (static_cast<int64_t>(bl.nall) * bl.nmu > 0x7fffffffLL ||
+          static_cast<int64_t>(bl.nall) * pr.nqp > 0x7fffffffLL)
+        return fail(CHI0_EINVAL, "problem %d block %d: nall * nmu or nall * nqp above 2^31-1", p, b);
+      if (!std::isfinite(bl.wk) || bl.wk < 0.0)
+        return fail(CHI0_EINVAL, "problem %d block %d: wk must be finite and >= 0", p, b);
+      if (bl.nall > 0) {
+        if (!bl.z || !bl.wc || !bl.eps_mid)
+          return fail(CHI0_EINVAL, "problem %d block %d: z, wc or eps_mid is NULL", p, b);
+        if (!aligned(bl.z, 16) || !aligned(bl.wc, 16))
+          return fail(CHI0_EINVAL, "problem %d block %d: z or wc not 16-byte aligned", p, b);
+        for (int a = 0; a < bl.nall; ++a)
+          if (!std::isfinite(bl.eps_mid[a]))
+            return fail(CHI0_EINVAL, "problem %d block %d: eps_mid[%d] not finite", p, b, a);
+      }
+    }
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(pr.sigc);
+    const uintptr_t a1 = a0 + static_cast<uintptr_t>(pr.nqp) * pr.nqp * 16;
+    for (int q = 0; q < p; ++q) {
+      const uintptr_t b0 = reinterpret_cast<uintptr_t>(probs[q].sigc);
+      const uintptr_t b1 = b0 + static_cast<uintptr_t>(probs[q].nqp) * probs[q].nqp * 16;
+      if (a0 < b1 && b0 < a1) return fail(CHI0_EINVAL, "problems %d and %d: outputs overlap", q, p);
+    }
+  }
+  if (prec != CHI0_PREC_FP64)
+    return fail(CHI0_EUNSUPPORTED, "the correlation self-energy runs on the FP64 path only");
+  if (zt != CHI0_Z_C128) return fail(CHI0_EUNSUPPORTED, "the FP64 path needs Z type CHI0_Z_C128");
+  return CHI0_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, uint32_t flags, hipStream_t stream) {
+  const int T = sigc_tile();
+  // flat block list (blocks with nall = 0 contribute nothing and are dropped)
+  struct Ref {
+    int prob, blk;
+  };
+  std::vector<Ref> refs;
+  int max_nqp = 0;
+  for (int p = 0; p < nprob; ++p) {
+    max_nqp = std::max(max_nqp, probs[p].nqp);
+    for (int b = 0; b < probs[p].nblocks; ++b)
+      if (probs[p].blocks[b].nall > 0) refs.push_back({p, b});
+  }
+  const int nb = static_cast<int>(refs.size());
+
+  // chunks of consecutive blocks whose zw workspace stays under the cap
+  std::vector<int> chunk0{0};
+  int64_t zw_max = 0, cur = 0;
+  std::vector<int64_t> zw_off(nb, 0);
+  for (int i = 0; i < nb; ++i) {
+    const sigc_problem& pr = probs[refs[i].prob];
+    const sigc_block& bl = pr.blocks[refs[i].blk];
+    const int64_t bytes = static_cast<int64_t>(align256(static_cast<size_t>(bl.nall) * bl.nmu * pr.nqp * 16));
+    if (cur > 0 && cur + bytes > h->sigc_zw_cap) {
+      chunk0.push_back(i);
+      cur = 0;
+    }
+    zw_off[i] = cur;
+    cur += bytes;
+    zw_max = std::max(zw_max, cur);
+  }
+  chunk0.push_back(nb);
+  const int nchunks = static_cast<int>(chunk0.size()) - 1;
+
+  // host-side tables: energies and meshes, block descriptors, problems, and
+  // per chunk the units of both contractions and the reduction jobs
+  std::vector<double> dbl;
+  std::vector<size_t> qp_off(nprob), om_off(nprob), mid_off(nb);
+  for (int p = 0; p < nprob; ++p) {
+    qp_off[p] = dbl.size();
+    dbl.insert(dbl.end(), probs[p].eps_qp, probs[p].eps_qp + probs[p].nqp);
+    om_off[p] = dbl.size();
+    dbl.insert(dbl.end(), probs[p].omega, probs[p].omega + probs[p].nomega);
+  }
+  size_t wt_bytes = 0;
+  std::vector<size_t> wt_off(nb);
+  int64_t max_wt_elems = 0;
+  for (int i = 0; i < nb; ++i) {
+    const sigc_problem& pr = probs[refs[i].prob];
+    const sigc_block& bl = pr.blocks[refs[i].blk];
+    mid_off[i] = dbl.size();
+    dbl.insert(dbl.end(), bl.eps_mid, bl.eps_mid + bl.nall);
+    wt_off[i] = wt_bytes;
+    const int64_t elems = static_cast<int64_t>(bl.nall) * pr.nqp * pr.nomega;
+    max_wt_elems = std::max(max_wt_elems, elems);
+    wt_bytes += align256(static_cast<size_t>(elems) * 8);
+  }
+
+  struct ChunkTabs {
+    std::vector<SigcUnit> u1, u2;
+    std::vector<SigcJob> jobs;
+    std::vector<int32_t> slots;
+    int seg_len = 0;
+  };
+  std::vector<ChunkTabs> ct(nchunks);
+  size_t max_part_units = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    ChunkTabs& t = ct[c];
+    int64_t rows_tiles = 0;
+    for (int i = chunk0[c]; i < chunk0[c + 1]; ++i) {
+      const sigc_problem& pr = probs[refs[i].prob];
+      const sigc_block& bl = pr.blocks[refs[i].blk];
+      const int64_t M = static_cast<int64_t>(bl.nall) * pr.nqp;
+      const int tps = (bl.nmu + T - 1) / T;
+      const int64_t tcs = (M + T - 1) / T;
+      for (int64_t tc = 0; tc < tcs; ++tc)
+        for (int tp = 0; tp < tps; ++tp) t.u1.push_back({i, tp, static_cast<int32_t>(tc), 0});
+      const int tq = (pr.nqp + T - 1) / T;
+      rows_tiles += static_cast<int64_t>(bl.nall) * bl.nmu * tq * tq;
+    }
+    // segment length: about four second-contraction units per CU
+    const int64_t target = std::max<int64_t>(1, 4LL * h->ncu);
+    int64_t seg = (rows_tiles + target - 1) / target;
+    seg = std::max<int64_t>(64, (seg + 7) / 8 * 8);
+    seg = std::min<int64_t>(seg, 0x40000000LL);
+    t.seg_len = static_cast<int>(seg);
+    // units ordered (block, segment, tile) so the tiles of one segment are
+    // adjacent; jobs per (problem, tile) list their slots in unit order
+    std::vector<std::vector<int32_t>> tile_slots;
+    std::vector<std::array<int, 3>> tile_key;
+    std::unordered_map<int64_t, int> key_index;
+    for (int i = chunk0[c]; i < chunk0[c + 1]; ++i) {
+      const int p = refs[i].prob;
+      const sigc_problem& pr = probs[p];
+      const sigc_block& bl = pr.blocks[refs[i].blk];
+      const int64_t K = static_cast<int64_t>(bl.nall) * bl.nmu;
+      const int nseg = static_cast<int>((K + seg - 1) / seg);
+      const int tq = (pr.nqp + T - 1) / T;
+      for (int sg = 0; sg < nseg; ++sg)
+        for (int tp = 0; tp < tq; ++tp)
+          for (int tc = 0; tc < tq; ++tc) {
+            const int64_t key = (static_cast<int64_t>(p) * tq + tp) * tq + tc;
+            auto it = key_index.find(key);
+            int k;
+            if (it == key_index.end()) {
+              k = static_cast<int>(tile_slots.size());
+              key_index.emplace(key, k);
+              tile_slots.emplace_back();
+              tile_key.push_back({p, tp, tc});
+            } else {
+              k = it->second;
+            }
+            tile_slots[k].push_back(static_cast<int32_t>(t.u2.size()));
+            t.u2.push_back({i, tp, tc, sg});
+          }
+    }
+    for (size_t k = 0; k < tile_slots.size(); ++k) {
+      SigcJob j;
+      j.prob = tile_key[k][0];
+      j.tp = tile_key[k][1];
+      j.tc = tile_key[k][2];
+      j.slot0 = static_cast<int32_t>(t.slots.size());
+      j.nslot = static_cast<int32_t>(tile_slots[k].size());
+      j.pad = 0;
+      t.slots.insert(t.slots.end(), tile_slots[k].begin(), tile_slots[k].end());
+      t.jobs.push_back(j);
+    }
+    max_part_units = std::max(max_part_units, t.u2.size());
+  }
+
+  // workspace
+  int rc;
+  size_t acc_bytes = 0;
+  std::vector<size_t> acc_off(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    acc_off[p] = acc_bytes;
+    acc_bytes += align256(static_cast<size_t>(probs[p].nqp) * probs[p].nqp * 16);
+  }
+  if ((rc = h->sigc_acc.reserve(std::max<size_t>(acc_bytes, 256), &h->ws_gen))) return rc;
+  if ((rc = h->sigc_wt.reserve(std::max<size_t>(wt_bytes, 256), &h->ws_gen))) return rc;
+  if ((rc = h->sigc_zw.reserve(std::max<size_t>(static_cast<size_t>(zw_max), 256), &h->ws_gen))) return rc;
+  if ((rc = h->sigc_part.reserve(std::max<size_t>(max_part_units * T * T * 16, 256), &h->ws_gen)))
+    return rc;
+
+  // one device table: doubles | descs | probs | per chunk (u1 | u2 | jobs | slots)
+  size_t off = align256(dbl.size() * 8);
+  const size_t desc_off = off;
+  off += align256(static_cast<size_t>(nb) * sizeof(SigcDesc));
+  const size_t prob_off = off;
+  off += align256(static_cast<size_t>(nprob) * sizeof(SigcProb));
+  std::vector<std::array<size_t, 4>> coff(nchunks);
+  for (int c = 0; c < nchunks; ++c) {
+    coff[c][0] = off;
+    off += align256(ct[c].u1.size() * sizeof(SigcUnit));
+    coff[c][1] = off;
+    off += align256(ct[c].u2.size() * sizeof(SigcUnit));
+    coff[c][2] = off;
+    off += align256(ct[c].jobs.size() * sizeof(SigcJob));
+    coff[c][3] = off;
+    off += align256(ct[c].slots.size() * sizeof(int32_t));
+  }
+  const size_t tab_bytes = off;
+  if ((rc = h->sigc_tab.reserve(tab_bytes, &h->ws_gen))) return rc;
+  char* dtab = static_cast<char*>(h->sigc_tab.p);
+  const double* ddbl = reinterpret_cast<const double*>(dtab);
+
+  std::vector<SigcDesc> descs(nb);
+  for (int i = 0; i < nb; ++i) {
+    const int p = refs[i].prob;
+    const sigc_problem& pr = probs[p];
+    const sigc_block& bl = pr.blocks[refs[i].blk];
+    SigcDesc& d = descs[i];
+    d.z = static_cast<const double2*>(bl.z);
+    d.wc = static_cast<const double2*>(bl.wc);
+    d.zw = reinterpret_cast<double2*>(static_cast<char*>(h->sigc_zw.p) + zw_off[i]);
+    d.wt = reinterpret_cast<double*>(static_cast<char*>(h->sigc_wt.p) + wt_off[i]);
+    d.eps_mid = ddbl + mid_off[i];
+    d.eps_qp = ddbl + qp_off[p];
+    d.omega = ddbl + om_off[p];
+    d.wk = bl.wk;
+    d.nall = bl.nall;
+    d.nmu = bl.nmu;
+    d.nqp = pr.nqp;
+    d.nomega = pr.nomega;
+    d.prob = p;
+    d.pad = 0;
+  }
+  std::vector<SigcProb> ptab(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    ptab[p].acc = reinterpret_cast<double2*>(static_cast<char*>(h->sigc_acc.p) + acc_off[p]);
+    ptab[p].out = static_cast<double2*>(probs[p].sigc);
+    ptab[p].nqp = probs[p].nqp;
+    ptab[p].pad = 0;
+  }
+  if ((rc = staging_reserve(h, tab_bytes))) return rc;
+  char* st = static_cast<char*>(h->staging);
+  memcpy(st, dbl.data(), dbl.size() * 8);
+  if (nb) memcpy(st + desc_off, descs.data(), nb * sizeof(SigcDesc));
+  memcpy(st + prob_off, ptab.data(), nprob * sizeof(SigcProb));
+  for (int c = 0; c < nchunks; ++c) {
+    if (!ct[c].u1.empty()) memcpy(st + coff[c][0], ct[c].u1.data(), ct[c].u1.size() * sizeof(SigcUnit));
+    if (!ct[c].u2.empty()) memcpy(st + coff[c][1], ct[c].u2.data(), ct[c].u2.size() * sizeof(SigcUnit));
+    if (!ct[c].jobs.empty()) memcpy(st + coff[c][2], ct[c].jobs.data(), ct[c].jobs.size() * sizeof(SigcJob));
+    if (!ct[c].slots.empty())
+      memcpy(st + coff[c][3], ct[c].slots.data(), ct[c].slots.size() * sizeof(int32_t));
+  }
+  HIP_TRY(hipMemcpyAsync(dtab, st, tab_bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(h->staging_done, stream));
+  h->staging_pending = true;
+
+  const SigcDesc* d_desc = reinterpret_cast<const SigcDesc*>(dtab + desc_off);
+  const SigcProb* d_prob = reinterpret_cast<const SigcProb*>(dtab + prob_off);
+  hipError_t e = sigc_clear_launch(d_prob, nprob, max_nqp, stream);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "clear launch: %s", hipGetErrorString(e));
+  e = sigc_weights_launch(d_desc, nb, max_wt_elems, stream);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "weight launch: %s", hipGetErrorString(e));
+  for (int c = 0; c < nchunks; ++c) {
+    SigcArgs a1;
+    a1.units = reinterpret_cast<const SigcUnit*>(dtab + coff[c][0]);
+    a1.descs = d_desc;
+    a1.partials = nullptr;
+    a1.nunits = static_cast<int32_t>(ct[c].u1.size());
+    a1.seg_len = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->profiling) {
+      e0 = get_event(h);
+      e1 = get_event(h);
+      if (e0) HIP_TRY(hipEventRecord(e0, stream));
+    }
+    e = sigc_zw_launch(h->sigc_variant, a1, stream);
+    if (e != hipSuccess) return fail(CHI0_EDEVICE, "first contraction launch: %s", hipGetErrorString(e));
+    if (h->profiling && e0 && e1) {
+      HIP_TRY(hipEventRecord(e1, stream));
+      h->prof_pending.emplace_back(e0, e1);
+    }
+    SigcArgs a2;
+    a2.units = reinterpret_cast<const SigcUnit*>(dtab + coff[c][1]);
+    a2.descs = d_desc;
+    a2.partials = static_cast<double2*>(h->sigc_part.p);
+    a2.nunits = static_cast<int32_t>(ct[c].u2.size());
+    a2.seg_len = ct[c].seg_len;
+    e = sigc_zwz_launch(a2, stream);
+    if (e != hipSuccess) return fail(CHI0_EDEVICE, "second contraction launch: %s", hipGetErrorString(e));
+    e = sigc_reduce_launch(reinterpret_cast<const SigcJob*>(dtab + coff[c][2]),
+                           reinterpret_cast<const int32_t*>(dtab + coff[c][3]), a2.partials, d_prob,
+                           static_cast<int>(ct[c].jobs.size()), stream);
+    if (e != hipSuccess) return fail(CHI0_EDEVICE, "reduction launch: %s", hipGetErrorString(e));
+  }
+  e = sigc_store_launch(d_prob, nprob, max_nqp, (flags & CHI0_ACCUMULATE) != 0, stream);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "store launch: %s", hipGetErrorString(e));
+  return CHI0_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -830,6 +1149,11 @@ int chi0_destroy(chi0_handle h) {
   h->hpd_p.release();
   h->hpd_c.release();
   h->hpd_dinv.release();
+  h->sigc_tab.release();
+  h->sigc_wt.release();
+  h->sigc_zw.release();
+  h->sigc_part.release();
+  h->sigc_acc.release();
   if (h->d_status) hipFree(h->d_status);
   if (h->staging) hipHostFree(h->staging);
   if (h->staging_done) hipEventDestroy(h->staging_done);
@@ -874,6 +1198,31 @@ int sigx_accumulate(chi0_handle h, const sigx_problem* probs, int32_t nprob, chi
   }
   return run_accumulate(h, cp.data(), nprob, prec, 0.0, flags, static_cast<hipStream_t>(hip_stream),
                         -1, kWeightsCoulomb);
+}
+
+int sigc_accumulate(chi0_handle h, const sigc_problem* probs, int32_t nprob, chi0_ztype zt,
+                    chi0_precision prec, uint32_t flags, void* hip_stream) {
+  int rc = validate_sigc(probs, nprob, zt, prec, flags);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (nprob == 0) return CHI0_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  return run_sigc(h, probs, nprob, flags, static_cast<hipStream_t>(hip_stream));
+}
+
+int sigc_set_variant(chi0_handle h, int32_t variant) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (variant < 0 || variant >= sigc_zw_variants())
+    return fail(CHI0_EINVAL, "variant %d out of range [0, %d)", variant, sigc_zw_variants());
+  h->sigc_variant = variant;
+  return CHI0_OK;
+}
+
+int sigc_set_workspace_cap(chi0_handle h, int64_t bytes) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (bytes < 0) return fail(CHI0_EINVAL, "cap %lld < 0", static_cast<long long>(bytes));
+  h->sigc_zw_cap = bytes == 0 ? (int64_t(4) << 30) : bytes;
+  return CHI0_OK;
 }
 
 int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_ztype zt,

@@ -88,6 +88,58 @@ struct ReduceArgs {
   int32_t pad;
 };
 
+// Imaginary-axis correlation self-energy (Eq.(sigci)): one k-point block of
+// one q-point as the kernels see it.
+struct SigcDesc {
+  const double2* z;       // [nall][nmu][nqp] Z_k[n'][mu][n]
+  const double2* wc;      // [nomega][nmu][nmu] W^c_k(i w_i)[mu][nu]
+  double2* zw;            // [nall][nmu][nqp] workspace: conj(sum_i Z_w^H W^c_i), per n'
+  double* wt;             // [nomega][nall * nqp] integration weights times -w_k
+  const double* eps_mid;  // [nall]
+  const double* eps_qp;   // [nqp] (the problem's)
+  const double* omega;    // [nomega] (the problem's mesh)
+  double wk;
+  int32_t nall, nmu, nqp, nomega;
+  int32_t prob, pad;
+};
+
+// Work unit of the two contractions: block, tile row (P side), tile column
+// (Q side) and contraction segment (second contraction only).
+struct SigcUnit {
+  int32_t blk, tp, tc, seg;
+};
+
+// Reduction job: the partial slots slot_list[slot0 .. slot0 + nslot) of one
+// output tile of one problem are summed in order into its FP64 accumulator.
+struct SigcJob {
+  int32_t prob, tp, tc, slot0, nslot, pad;
+};
+
+struct SigcProb {
+  double2* acc;           // [nqp][nqp] FP64 accumulator (workspace)
+  double2* out;           // [nqp][nqp] caller's output
+  int32_t nqp, pad;
+};
+
+struct SigcArgs {
+  const SigcUnit* units;
+  const SigcDesc* descs;
+  double2* partials;      // second contraction: [unit][T][T]
+  int32_t nunits;
+  int32_t seg_len;        // second contraction: rows (n', nu) per segment
+};
+
+hipError_t sigc_weights_launch(const SigcDesc* descs, int nblocks, int64_t max_elems, hipStream_t s);
+hipError_t sigc_zw_launch(int variant, const SigcArgs& a, hipStream_t s);
+hipError_t sigc_zwz_launch(const SigcArgs& a, hipStream_t s);
+hipError_t sigc_reduce_launch(const SigcJob* jobs, const int32_t* slot_list, const double2* partials,
+                              const SigcProb* probs, int njobs, hipStream_t s);
+hipError_t sigc_clear_launch(const SigcProb* probs, int nprob, int max_nqp, hipStream_t s);
+hipError_t sigc_store_launch(const SigcProb* probs, int nprob, int max_nqp, bool accumulate,
+                             hipStream_t s);
+int sigc_zw_variants();
+int sigc_tile();
+
 // Kernel variants of the rank-K contraction.
 enum HerkKind { HERK_FP64 = 0, HERK_FP32 = 1, HERK_BF16X3 = 2 };
 

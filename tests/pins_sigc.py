@@ -196,6 +196,11 @@ def pin_contract_exact_and_brute(orc):
     if not _close(orc.sigc_rows(blocks, eps_qp, mesh, [2, 0]),
                   orc.sigc_ref(blocks, eps_qp, mesh)[[2, 0]], 1e-14):
         fails.append("row sampler != reference")
+    ent = [(0, 2), (1, 1), (2, 0)]
+    sel = [(z[:, :, [0, 1, 2]], [0, 1, 2], wc, em, wk) for z, wc, em, wk in blocks]
+    full = orc.sigc_ref(blocks, eps_qp, mesh)
+    if not _close(orc.sigc_entries(sel, eps_qp, mesh, ent), [full[n, m] for n, m in ent], 1e-14):
+        fails.append("entry sampler != reference")
     return fails
 
 

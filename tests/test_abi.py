@@ -135,3 +135,69 @@ def test_null_handle_calls():
     assert lib.chi0_set_tile(None, 0, 0) == L.CHI0_EINVAL
     assert lib.chi0_profile_enable(None, 1) == L.CHI0_EINVAL
     assert lib.chi0_create(None, 0) == L.CHI0_EINVAL
+
+
+def _sigc(nqp=3, nomega=2, omega=(0.0, 1.0), nall=2, nmu=4, z=FAKE, wc=FAKE, wk=0.5,
+          eps_qp=None, eps_mid=None, sigc=FAKE, nblocks=1):
+    import numpy as np
+    keep = []
+    eq = np.ascontiguousarray(np.linspace(-0.5, 0.5, nqp) if eps_qp is None else eps_qp, np.float64)
+    om = np.ascontiguousarray(omega, np.float64)
+    em = np.ascontiguousarray(np.zeros(max(nall, 1)) if eps_mid is None else eps_mid, np.float64)
+    keep += [eq, om, em]
+    blocks = (L.sigc_block * max(1, nblocks))()
+    for i in range(nblocks):
+        blocks[i].nall, blocks[i].nmu = nall, nmu
+        blocks[i].z, blocks[i].wc = z, wc
+        blocks[i].eps_mid = em.ctypes.data
+        blocks[i].wk = wk
+    p = (L.sigc_problem * 1)()
+    p[0].nqp, p[0].nblocks = nqp, nblocks
+    p[0].blocks = ctypes.cast(blocks, ctypes.POINTER(L.sigc_block))
+    p[0].eps_qp, p[0].nomega, p[0].omega, p[0].sigc = eq.ctypes.data, nomega, om.ctypes.data, sigc
+    keep.append(blocks)
+    return p, keep
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nqp=0), L.CHI0_EINVAL),
+    (dict(nomega=0), L.CHI0_EINVAL),
+    (dict(omega=(1.0, 0.5)), L.CHI0_EINVAL),
+    (dict(omega=(-0.1, 0.5)), L.CHI0_EINVAL),
+    (dict(omega=(0.0, float("inf"))), L.CHI0_EINVAL),
+    (dict(eps_qp=[0.0, float("nan"), 1.0]), L.CHI0_EINVAL),
+    (dict(eps_mid=[0.0, float("inf")]), L.CHI0_EINVAL),
+    (dict(nmu=0), L.CHI0_EINVAL),
+    (dict(nall=-1), L.CHI0_EINVAL),
+    (dict(wk=-1.0), L.CHI0_EINVAL),
+    (dict(wk=float("nan")), L.CHI0_EINVAL),
+    (dict(z=None), L.CHI0_EINVAL),
+    (dict(wc=None), L.CHI0_EINVAL),
+    (dict(z=FAKE + 8), L.CHI0_EINVAL),
+    (dict(sigc=None), L.CHI0_EINVAL),
+    (dict(sigc=FAKE + 4), L.CHI0_EINVAL),
+    (dict(nall=70000, nmu=40000), L.CHI0_EINVAL),
+])
+def test_sigc_validation_rejects(kw, code):
+    lib = pkg.load()
+    p, keep = _sigc(**kw)
+    assert lib.sigc_accumulate(None, p, 1, 0, 0, 0, None) == code
+
+
+def test_sigc_validation_flags_precision_and_handle():
+    lib = pkg.load()
+    p, keep = _sigc()
+    assert lib.sigc_accumulate(None, p, 1, 0, 0, 0x100, None) == L.CHI0_EINVAL
+    assert lib.sigc_accumulate(None, p, 1, 0, 9, 0, None) == L.CHI0_EINVAL
+    assert lib.sigc_accumulate(None, p, 1, 0, 1, 0, None) == L.CHI0_EUNSUPPORTED
+    assert lib.sigc_accumulate(None, p, 1, 1, 0, 0, None) == L.CHI0_EUNSUPPORTED
+    assert lib.sigc_accumulate(None, p, -1, 0, 0, 0, None) == L.CHI0_EINVAL
+    # valid arguments: only the NULL handle is left to reject
+    assert lib.sigc_accumulate(None, p, 1, 0, 0, L.CHI0_ACCUMULATE, None) == L.CHI0_EINVAL
+    assert "handle" in lib.chi0_last_error().decode()
+    # an empty block (nall = 0) needs no pointers
+    p2, keep2 = _sigc(nall=0, z=None, wc=None)
+    assert lib.sigc_accumulate(None, p2, 1, 0, 0, 0, None) == L.CHI0_EINVAL
+    assert "handle" in lib.chi0_last_error().decode()
+    assert lib.sigc_set_variant(None, 0) == L.CHI0_EINVAL
+    assert lib.sigc_set_workspace_cap(None, 0) == L.CHI0_EINVAL
