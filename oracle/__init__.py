@@ -13,3 +13,5 @@ from .sigx_oracle import sigx_block, sigx_brute, sigx_exact, sigx_ref  # noqa: F
 from .sigc_oracle import (ag_weights, ag_weight_table, sigc_block, sigc_brute,  # noqa: F401
                           sigc_contract, sigc_contract_exact, sigc_entries, sigc_ref,
                           sigc_rows)
+from .hist_oracle import (bin_fractions, hilbert_apply, hilbert_imag, hilbert_real,  # noqa: F401
+                          hist_brute, hist_exact, hist_ref, log_edges)
