@@ -10,7 +10,8 @@ library.
 Reading (the tetrahedron weights of Eq.(tetw) need a k-point mesh, which a
 synthetic workload does not have; a uniform spread stands in for them):
 
-* Bins j = [e_j, e_{j+1}) for edges 0 <= e_0 < e_1 < ... < e_nb.
+* Bins j = [e_j, e_{j+1}) for edges 0 < e_0 < e_1 < ... < e_nb (a first
+  edge at 0 would make the bin average of 2x / x^2 at w = 0 diverge).
 * A pair (n, n') of a block enters as for chi0: D = eps_unocc[n'] -
   eps_occ[n] > 0 and D >= delta_min.  Its weight w_k is spread uniformly
   over [D (1 - sigma), D (1 + sigma)] (0 <= sigma < 1; sigma = 0 puts all of
@@ -48,8 +49,8 @@ from .chi0_oracle import _CompensatedSum, pair_delta, pair_included
 
 def check_edges(edges: Sequence[float]) -> np.ndarray:
     e = np.asarray(edges, np.float64)
-    if e.ndim != 1 or e.size < 2 or e[0] < 0 or np.any(np.diff(e) <= 0):
-        raise ValueError("edges must be strictly increasing, >= 0, at least two")
+    if e.ndim != 1 or e.size < 2 or not e[0] > 0 or np.any(np.diff(e) <= 0):
+        raise ValueError("edges must be strictly increasing, > 0, at least two")
     return e
 
 
@@ -151,25 +152,35 @@ def hist_exact(blocks, npb: int, edges: Sequence[Fraction], delta_min=Fraction(0
 
 
 def hilbert_imag(edges, omega: Sequence[float]) -> np.ndarray:
-    """c_j(i w) of every (w, bin), float64 [nomega][nb]."""
+    """c_j(i w) of every (w, bin), float64 [nomega][nb].  The difference of
+    logarithms is evaluated as log1p((e_{j+1} - e_j)(e_{j+1} + e_j) /
+    (e_j^2 + w^2)), which keeps full relative accuracy when w is far above
+    the bin (the plain difference cancels there)."""
     e = check_edges(edges)
     w = np.asarray(omega, np.float64)[:, None]
     lo, hi = e[None, :-1], e[None, 1:]
-    return (np.log(hi * hi + w * w) - np.log(lo * lo + w * w)) / (hi - lo)
+    h = hi - lo
+    return np.log1p(h * (hi + lo) / (lo * lo + w * w)) / h
 
 
 def hilbert_real(edges, omega: Sequence[float]) -> np.ndarray:
     """c_j(w) of every real (w, bin), complex128 [nreal][nb]; w must not be an
-    edge."""
+    edge.  ln|e_{j+1} - w| - ln|e_j - w| is log1p(h / (e_j - w)) for w
+    outside the bin and the plain difference inside it; ln(e_{j+1} + w) -
+    ln(e_j + w) is log1p(h / (e_j + w))."""
     e = check_edges(edges)
-    w = np.asarray(omega, np.float64)[:, None]
-    if np.any(np.isin(np.asarray(omega, np.float64), e)):
+    om = np.asarray(omega, np.float64)
+    if np.any(np.isin(om, e)):
         raise ValueError("a real frequency lies on a bin edge")
+    w = om[:, None]
     lo, hi = e[None, :-1], e[None, 1:]
     h = hi - lo
-    re = (np.log(np.abs(hi - w)) - np.log(np.abs(lo - w)) + np.log(hi + w) - np.log(lo + w)) / h
     inside = (w > lo) & (w < hi)
-    return re + 1j * np.pi * inside / h
+    with np.errstate(divide="ignore", invalid="ignore"):
+        near = np.where(inside, np.log(np.abs(hi - w)) - np.log(np.abs(lo - w)),
+                        np.log1p(h / (lo - w)))
+        far = np.log1p(h / (lo + w))
+    return (near + far) / h + 1j * np.pi * inside / h
 
 
 def hilbert_apply(coeff: np.ndarray, hist: np.ndarray) -> np.ndarray:
