@@ -404,6 +404,110 @@ def bench_sigc(args):
     ctx.close()
 
 
+HIST_SIGMA = 0.015
+
+
+def hist_cpu_baseline(wl, edges, target_s=10.0):
+    """The histogram oracle on a bounded sample: the first occupied states of
+    one k-block at full npb, into a window of 32 bins around the median
+    transition energy (the oracle holds every bin as a dense npb x npb
+    matrix, so all bins of the mesh at npb = 2048 would not fit in host
+    memory)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle.hist_oracle as H
+
+    blk = wl.blocks(0)[0]
+    eo, eu = wl.energies(blk)
+    med = float(np.median(eu[None, :] - eo[:, None]))
+    j0 = max(0, int(np.searchsorted(edges, med)) - 16)
+    win = edges[j0:j0 + 33]
+
+    def run(nocc_s):
+        sub = blk.__class__(q=blk.q, spin=blk.spin, k=blk.k, nocc=nocc_s, nunocc=blk.nunocc,
+                            wk=blk.wk, bid=blk.bid)
+        z = wl.z_block(sub).astype(np.complex128)
+        t0 = time.perf_counter()
+        H.hist_ref([(z, eo[:nocc_s], eu, blk.wk)], wl.npb, win, HIST_SIGMA)
+        dt = time.perf_counter() - t0
+        bins, _ = H.pair_bins(eo[:nocc_s], eu, win, HIST_SIGMA, 0.0, blk.wk)
+        return dt, int((bins >= 0).sum())
+
+    t1, n1 = run(1)
+    nocc_s = int(min(blk.nocc, max(1, round(target_s / max(t1, 1e-4)))))
+    t_meas, nrec = run(nocc_s) if nocc_s > 1 else (t1, n1)
+    flops = zherk_flops(wl.npb, nrec, 1)
+    threads = 0
+    for info in threadpool_info():
+        if info.get("user_api") == "blas":
+            threads = max(threads, int(info.get("num_threads", 0)))
+    return {"value": flops / t_meas / 1e12, "unit": "TFLOP/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{nocc_s} occupied x {blk.nunocc} unoccupied states of one k-block, "
+                      f"32 bins around the median transition ({nrec} records), npb={wl.npb} "
+                      f"({t_meas:.1f} s)"}
+
+
+def bench_hist(args):
+    """chi0 at every imaginary frequency through the histogram route
+    (binning, per-bin rank-K updates, Hilbert transform): one JSON line."""
+    import torch
+
+    from paper_2506_03477_amd import Block, Context, HistSpec, Problem
+    from synth import hist_edges, workload
+    from synth.gpu import device_workload
+
+    wl = workload(args.workload)
+    prec = args.precision or wl.paths[0]
+    ztype = "c128" if prec == "fp64" else "c64"
+    emax = max(wl.unocc_range[1] - wl.occ_range[0], 1e-3) * 1.05
+    edges = hist_edges(emax)
+    torch.cuda.set_device(0)
+    ctx = Context(0)
+    log(f"generating {wl.name} inputs ({ztype}) on the GPU")
+    blks, omega, _ = device_workload(wl, 0, ztype=ztype)
+    out = torch.empty((wl.nomega, wl.npb, wl.npb), dtype=torch.complex128, device="cuda")
+    prob = Problem([Block(z, eo, eu, wk) for z, eo, eu, wk, _ in blks], omega, out)
+    spec = HistSpec(edges, HIST_SIGMA)
+    for _ in range(args.warmup):
+        ctx.chi0_hist_accumulate([prob], [spec], precision=prec, delta_min=wl.delta_min)
+    ctx.sync()
+    ctx.profile_enable(True)
+    ctx.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.chi0_hist_accumulate([prob], [spec], precision=prec, delta_min=wl.delta_min)
+    ctx.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kern_ms, n = ctx.profile_read()
+    records, bins_used = ctx.hist_stats()
+    flops = zherk_flops(wl.npb, records, 1)
+    direct = zherk_flops(wl.npb, wl.npairs(0), wl.nomega)
+    roof = None
+    if n:
+        kern_avg = kern_ms / n
+        ach = flops / (kern_avg * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4), "traffic": None,
+                "kernel": f"herk_{prec} (gathered rows)", "kernel_ms": round(kern_avg, 3)}
+    cpu = None if args.no_cpu_baseline else hist_cpu_baseline(wl, edges)
+    print(json.dumps({
+        "metric": "chi0 ms per q-point (all omega) through the histogram route (Eq. impolf + Eq. hilbert)",
+        "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": MFMA_DTYPE[prec] if prec != "bf16x3" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "npb": wl.npb, "nomega": wl.nomega, "path": prec,
+                   "bins": len(edges) - 1, "bins_used": bins_used, "sigma": HIST_SIGMA,
+                   "mesh": "5e-6 Ha * 1.03^j"},
+        "records": records, "records_per_pair": round(records / wl.npairs(0), 4),
+        "rank_k_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+        "direct_equivalent_tflops": round(direct / (ms * 1e-3) / 1e12, 3),
+        "roofline": roof, "cpu_baseline": cpu}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -430,6 +534,8 @@ def main():
                     help="time the exchange self-energy (Eq. sigx) instead of chi0")
     ap.add_argument("--sigc", action="store_true",
                     help="time the imaginary-axis correlation self-energy (Eq. sigci)")
+    ap.add_argument("--hist", action="store_true",
+                    help="time chi0 through the histogram route (Eq. impolf + Eq. hilbert)")
     args = ap.parse_args()
 
     if args.summarize_counters:
@@ -450,6 +556,9 @@ def main():
         return
     if args.sigc and args.gpus == 1:
         bench_sigc(args)
+        return
+    if args.hist and args.gpus == 1:
+        bench_hist(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "

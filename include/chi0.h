@@ -182,6 +182,53 @@ int sigx_accumulate(chi0_handle h, const sigx_problem* probs, int32_t nprob,
                     chi0_ztype zt, chi0_precision prec, uint32_t flags,
                     void* hip_stream);
 
+/* The paper's real-axis route for chi0 (Eq.(impolf), Eq.(tetw),
+ * Eq.(hilbert); the histogram steps of the polarization algorithm): the
+ * anti-Hermitian part is accumulated into histogram bins of the transition
+ * energy and chi0 at any frequency follows by a Hilbert transform, so the
+ * rank-K work does not grow with the number of frequencies.
+ *   Bins j = [edges[j], edges[j+1]).  A pair of a block enters as for
+ *   chi0_accumulate (D = eps_unocc[n'] - eps_occ[n] > 0, D >= delta_min); its
+ *   weight w_k is spread uniformly over [D (1 - sigma), D (1 + sigma)]
+ *   (sigma = 0: all at D) -- a stand-in for the tetrahedron weights of
+ *   Eq.(tetw), which need a k mesh -- and the fraction inside bin j is its
+ *   bin weight; weight outside [edges[0], edges[nbins]) is dropped.
+ *   hist_j = -sum_pairs weight_j conj(Z_pair) Z_pair^T.
+ *   Imaginary axis: chi0(i w) = sum_j hist_j
+ *     [ln(e_{j+1}^2 + w^2) - ln(e_j^2 + w^2)] / (e_{j+1} - e_j).
+ *   Real axis (w not on an edge): chi0(w) = sum_j hist_j
+ *     ([ln|e_{j+1} - w| - ln|e_j - w| + ln(e_{j+1} + w) - ln(e_j + w)]
+ *      + i pi [w in bin j]) / (e_{j+1} - e_j)
+ *   (uniform spectral density within each bin; principal value).
+ * Each problem's chi0 output receives chi0(i omega) at its nomega imaginary
+ * frequencies (omega on the device, as for chi0_accumulate). */
+typedef struct {
+  int32_t nbins;           /* >= 1; all problems together at most 16384      */
+  int32_t nreal;           /* real frequencies, >= 0                          */
+  const double* edges;     /* HOST [nbins + 1]: 0 < e_0 < e_1 < ..., finite   */
+  double sigma;            /* relative half-width of a pair's spread, [0, 1)  */
+  const double* omega_re;  /* HOST [nreal]: finite, >= 0, none on an edge     */
+  void* chi0_re;           /* DEVICE out [nreal][npb][npb] complex128, used iff
+                              nreal > 0, 16-byte aligned                      */
+  void* hist;              /* DEVICE out [nbins][npb][npb] complex128 (hist_j),
+                              or NULL; 16-byte aligned                         */
+} chi0_hist;
+
+/* Histogram route for `nprob` problems (hists[p] belongs to probs[p]).
+ * prec: CHI0_PREC_FP64 (zt CHI0_Z_C128) or CHI0_PREC_BF16X3 (zt
+ * CHI0_Z_C64); FP32 returns CHI0_EUNSUPPORTED.  flags: 0 or CHI0_BF16_LOLO
+ * (outputs are overwritten).  Binning and a stable counting sort run on the
+ * device; the call then waits for the bin counts (one device-to-host copy)
+ * to plan the per-bin rank-K updates, so it synchronises hip_stream and
+ * cannot be captured in a graph. */
+int chi0_hist_accumulate(chi0_handle h, const chi0_problem* probs, const chi0_hist* hists,
+                         int32_t nprob, chi0_ztype zt, chi0_precision prec,
+                         double delta_min, uint32_t flags, void* hip_stream);
+
+/* Records (pair, bin) kept and bins used (all problems together) by the
+ * handle's last chi0_hist_accumulate call; 0 before the first. */
+int chi0_hist_stats(chi0_handle h, int64_t* records, int32_t* bins_used);
+
 /* Imaginary-axis part I^c of the correlation self-energy (Eq.(sigci),
  * Section "Self-energy"; the QK-Omega^I block of the self-energy algorithm)
  * of one q-point, one k-point block:

@@ -14,4 +14,4 @@ from .sigc_oracle import (ag_weights, ag_weight_table, sigc_block, sigc_brute,  
                           sigc_contract, sigc_contract_exact, sigc_entries, sigc_ref,
                           sigc_rows)
 from .hist_oracle import (bin_fractions, hilbert_apply, hilbert_imag, hilbert_real,  # noqa: F401
-                          hist_brute, hist_exact, hist_ref, log_edges)
+                          hist_brute, hist_entries, hist_exact, hist_ref, log_edges)

@@ -86,6 +86,44 @@ def pair_bin_table(eps_occ, eps_unocc, edges, sigma, delta_min, wk) -> np.ndarra
     return out
 
 
+def pair_bins(eps_occ, eps_unocc, edges, sigma, delta_min, wk, nslots: int = 8):
+    """The bin weights of every pair in sparse form, vectorised for large
+    blocks: (bins [K, nslots] with -1 for unused slots, weights [K, nslots]),
+    slot t of a pair holding its t-th bin in increasing order.  The same
+    arithmetic as ``bin_fractions`` (pinned equal to ``pair_bin_table``)."""
+    e = check_edges(edges)
+    nb = e.size - 1
+    d = pair_delta(eps_occ, eps_unocc).reshape(-1)
+    inc = pair_included(d, delta_min)
+    bins = np.full((d.size, nslots), -1, np.int64)
+    w = np.zeros((d.size, nslots))
+    if sigma == 0.0:
+        ok = inc & (d >= e[0]) & (d < e[-1])
+        j = np.searchsorted(e, d, side="right") - 1
+        bins[ok, 0] = j[ok]
+        w[ok, 0] = wk * 1.0
+        return bins, w
+    lo, hi = d * (1.0 - sigma), d * (1.0 + sigma)
+    width = hi - lo
+    j0 = np.maximum(np.searchsorted(e, lo, side="right") - 1, 0)
+    t = np.zeros(d.size, np.int64)
+    for k in range(nslots + 1):
+        j = j0 + k
+        live = inc & (j < nb)
+        jj = np.minimum(j, nb - 1)
+        live &= e[jj] < hi
+        a = np.maximum(lo, e[jj])
+        b = np.minimum(hi, e[jj + 1])
+        take = live & (b > a)
+        if np.any(take & (t >= nslots)):
+            raise ValueError("more bins per pair than slots")
+        idx = np.nonzero(take)[0]
+        bins[idx, t[idx]] = jj[idx]
+        w[idx, t[idx]] = wk * ((b[idx] - a[idx]) / width[idx])
+        t[idx] += 1
+    return bins, w
+
+
 def hist_block(z: np.ndarray, eps_occ, eps_unocc, wk, edges, sigma, delta_min) -> np.ndarray:
     """hist_j = -S_j of one block, [nb][npb][npb]."""
     z = np.asarray(z, np.complex128)
@@ -149,6 +187,31 @@ def hist_exact(blocks, npb: int, edges: Sequence[Fraction], delta_min=Fraction(0
                             r0, i0 = out[j][i][k]
                             out[j][i][k] = (r0 - wk * re, i0 - wk * im)
     return out
+
+
+def hist_entries(block_columns, edges, sigma: float, entries: Sequence[Tuple[int, int]],
+                 col_index: dict, delta_min: float = 0.0) -> np.ndarray:
+    """hist_j[I][J] of the listed entries only, [nb][len(entries)].
+    ``block_columns`` yields (Zc[K, ncols], eps_occ, eps_unocc, w_k) with Zc
+    holding the columns of Z (pairs n-major) listed in ``col_index``."""
+    e = check_edges(edges)
+    nb = e.size - 1
+    ii = np.array([col_index[i] for i, _ in entries])
+    jj = np.array([col_index[j] for _, j in entries])
+    acc = _CompensatedSum((nb, len(entries)))
+    for zc, eo, eu, wk in block_columns:
+        zc = np.asarray(zc, np.complex128)
+        bins, w = pair_bins(eo, eu, e, sigma, delta_min, wk)
+        prod = zc[:, ii].conj() * zc[:, jj]                    # [K, entries]
+        used = bins >= 0
+        b = bins[used]
+        part = np.zeros((nb, len(entries)), np.complex128)
+        for k in range(len(entries)):
+            v = (w * prod[:, k][:, None])[used]
+            part[:, k] = -(np.bincount(b, weights=v.real, minlength=nb)
+                           + 1j * np.bincount(b, weights=v.imag, minlength=nb))
+        acc.add(part)
+    return acc.value()
 
 
 def hilbert_imag(edges, omega: Sequence[float]) -> np.ndarray:

@@ -68,6 +68,11 @@ class sigc_problem(ctypes.Structure):
                 ("omega", c_void_p), ("sigc", c_void_p)]
 
 
+class chi0_hist(ctypes.Structure):
+    _fields_ = [("nbins", c_int32), ("nreal", c_int32), ("edges", c_void_p), ("sigma", c_double),
+                ("omega_re", c_void_p), ("chi0_re", c_void_p), ("hist", c_void_p)]
+
+
 class Chi0Error(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libchi0 error {code}: {msg}")
@@ -98,7 +103,10 @@ def load() -> ctypes.CDLL:
         "chi0_sync": (c_int, [vp]),
         "sigx_accumulate": (c_int, [vp, POINTER(sigx_problem), c_int32, c_int, c_int, c_uint32, vp]),
         "sigc_accumulate": (c_int, [vp, POINTER(sigc_problem), c_int32, c_int, c_int, c_uint32, vp]),
+        "chi0_hist_accumulate": (c_int, [vp, POINTER(chi0_problem), POINTER(chi0_hist), c_int32, c_int,
+                                         c_int, c_double, c_uint32, vp]),
         "sigc_set_variant": (c_int, [vp, c_int32]),
+        "chi0_hist_stats": (c_int, [vp, POINTER(c_int64), POINTER(c_int32)]),
         "sigc_set_workspace_cap": (c_int, [vp, c_int64]),
         "chi0_tile_count": (c_int, [c_int]),
         "chi0_tile_info": (c_int, [c_int, c_int32, POINTER(c_int32), POINTER(c_int32),
@@ -217,6 +225,19 @@ def _marshal_sigx(problems: Sequence[SigxProblem]):
         arr[i].blocks = ctypes.cast(barr, POINTER(sigx_block))
         arr[i].sigx = _dev_ptr(p.sigx, torch.complex128, "sigx")
     return arr, keep
+
+
+@dataclass
+class HistSpec:
+    """Histogram route settings of one problem: bin edges (host, > 0,
+    increasing), spread sigma, optional real frequencies (host) with their
+    [nreal, npb, npb] complex128 device output, optional [nbins, npb, npb]
+    complex128 device output of the bin matrices."""
+    edges: object
+    sigma: float = 0.0
+    omega_re: object = None
+    chi0_re: object = None
+    hist: object = None
 
 
 @dataclass
@@ -373,6 +394,50 @@ class Context:
             (CHI0_USE_GRAPH if graph else 0)
         _check(self._lib.sigx_accumulate(self._h, arr, len(problems), zt, PREC[precision], flags,
                                          _stream_ptr(stream)))
+
+    # -- histogram route ---------------------------------------------------------
+    def chi0_hist_accumulate(self, problems: Sequence[Problem], hists: Sequence["HistSpec"],
+                             precision: str = "fp64", delta_min: float = 0.0, lolo: bool = False,
+                             stream=None) -> None:
+        import numpy as np
+        import torch
+        if len(hists) != len(problems):
+            raise ValueError("one HistSpec per problem")
+        arr, keep = _marshal(problems)
+        harr = (chi0_hist * max(1, len(hists)))()
+        for i, (p, hs) in enumerate(zip(problems, hists)):
+            npb = int(p.chi0.shape[-1])
+            e = np.ascontiguousarray(np.asarray(hs.edges, dtype=np.float64))
+            wr = np.ascontiguousarray(np.asarray(hs.omega_re if hs.omega_re is not None else [],
+                                                 dtype=np.float64))
+            keep += [e, wr]
+            harr[i].nbins = e.size - 1
+            harr[i].nreal = wr.size
+            harr[i].edges = e.ctypes.data
+            harr[i].sigma = float(hs.sigma)
+            harr[i].omega_re = wr.ctypes.data if wr.size else None
+            if wr.size:
+                if tuple(hs.chi0_re.shape) != (wr.size, npb, npb):
+                    raise ValueError("chi0_re must be [nreal, npb, npb]")
+                harr[i].chi0_re = _dev_ptr(hs.chi0_re, torch.complex128, "chi0_re")
+            else:
+                harr[i].chi0_re = None
+            if hs.hist is not None:
+                if tuple(hs.hist.shape) != (e.size - 1, npb, npb):
+                    raise ValueError("hist must be [nbins, npb, npb]")
+                harr[i].hist = _dev_ptr(hs.hist, torch.complex128, "hist")
+            else:
+                harr[i].hist = None
+        flags = CHI0_BF16_LOLO if lolo else 0
+        _check(self._lib.chi0_hist_accumulate(self._h, arr, harr, len(problems), _ztype_of(problems),
+                                              PREC[precision], float(delta_min), flags,
+                                              _stream_ptr(stream)))
+
+    def hist_stats(self):
+        """(records kept, bins used) of the last chi0_hist_accumulate call."""
+        r, b = c_int64(), c_int32()
+        _check(self._lib.chi0_hist_stats(self._h, byref(r), byref(b)))
+        return int(r.value), int(b.value)
 
     # -- imaginary-axis correlation self-energy --------------------------------
     def sigc_accumulate(self, problems: Sequence[SigcProblem], precision: str = "fp64",

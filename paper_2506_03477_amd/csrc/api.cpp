@@ -106,6 +106,13 @@ struct chi0_ctx {
   DevBuf gj_work, gj_wrow, gj_piv, gj_perm;
   DevBuf hpd_p, hpd_c, hpd_dinv;  // HPD inverse: kept panel, new panel, D^{-1}
   DevBuf sigc_tab, sigc_wt, sigc_zw, sigc_part, sigc_acc;  // correlation self-energy
+  DevBuf hist_tab, hist_rec, hist_sorted, hist_cnt, hist_mats, hist_coeff;  // histogram route
+  int64_t* hist_off_host = nullptr;  // pinned copy of the bin offsets
+  size_t hist_off_host_n = 0;
+  std::unique_ptr<Plan> gather_plan;  // plan of the last gathered (histogram) call
+  std::string gather_key;
+  int64_t hist_records = 0;           // records kept by the last histogram call
+  int32_t hist_bins_used = 0;         // non-empty bins of the last histogram call
   int sigc_variant = 0;
   int64_t sigc_zw_cap = int64_t(4) << 30;
   uint64_t ws_gen = 1;
@@ -567,9 +574,18 @@ hipError_t weights_launch(int mode, const BlockDesc* blocks, const ProbDesc* pro
                                  : pair_weights_launch(blocks, probs, nblocks, kmax, delta_min, f64, s);
 }
 
+// Gathered rows and given weights (the histogram path): problem p's single
+// block reads its rows at rows[off[p] ..] and its weights at wts[off[p] ..]
+// (double for FP64, float otherwise).
+struct GatherHook {
+  const uint64_t* rows;
+  const void* wts;
+  const int64_t* off;
+};
+
 int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_precision prec,
                    double delta_min, uint32_t flags, hipStream_t stream, int tile_override,
-                   int mode = kWeightsChi0) {
+                   int mode = kWeightsChi0, const GatherHook* hk = nullptr) {
   const int kind = kind_of(prec);
   const int ntile = herk_tile_count(kind);
   if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this build", prec);
@@ -577,19 +593,34 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
                  : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
                  : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind] : herk_default_tile(kind);
   if (tile_idx >= ntile) tile_idx = 0;
+  if (hk && !herk_tile_gathers(kind, tile_idx)) tile_idx = herk_default_tile(kind);
+  if (hk && !herk_tile_gathers(kind, tile_idx))
+    return fail(CHI0_EUNSUPPORTED, "precision %d has no gathering kernel", prec);
   int wg_per_cu = std::max(1, herk_max_wg_per_cu(kind, tile_idx));
   const int nwg = h->ncu * wg_per_cu;
   const std::string key = plan_key(kind, tile_idx, nwg, probs, nprob);
-  auto it = h->plans.find(key);
   Plan* pl;
-  if (it == h->plans.end()) {
-    std::unique_ptr<Plan> np(new Plan());
-    int rc = build_plan(h, *np, kind, tile_idx, probs, nprob);
-    if (rc) return rc;
-    pl = np.get();
-    h->plans.emplace(key, std::move(np));
+  if (hk) {
+    // histogram bins change with the data: one reusable slot, not the cache
+    if (!h->gather_plan || h->gather_key != key) {
+      std::unique_ptr<Plan> np(new Plan());
+      int rc = build_plan(h, *np, kind, tile_idx, probs, nprob);
+      if (rc) return rc;
+      h->gather_plan = std::move(np);
+      h->gather_key = key;
+    }
+    pl = h->gather_plan.get();
   } else {
-    pl = it->second.get();
+    auto it = h->plans.find(key);
+    if (it == h->plans.end()) {
+      std::unique_ptr<Plan> np(new Plan());
+      int rc = build_plan(h, *np, kind, tile_idx, probs, nprob);
+      if (rc) return rc;
+      pl = np.get();
+      h->plans.emplace(key, std::move(np));
+    } else {
+      pl = it->second.get();
+    }
   }
   if (pl->nunits == 0) return CHI0_OK;
   const int TP = pl->tc.tile, TQ = pl->tc.tile_q;
@@ -610,7 +641,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
     }
     wbytes += ((static_cast<size_t>(kt) * probs[p].nomega * wsize + 255) / 256) * 256;
   }
-  if ((rc = h->wts.reserve(std::max<size_t>(wbytes, 256), &h->ws_gen))) return rc;
+  if (!hk && (rc = h->wts.reserve(std::max<size_t>(wbytes, 256), &h->ws_gen))) return rc;
 
   // pre-split P-side planes (kernels that read them only)
   const bool presplit = pl->tc.presplit != 0;
@@ -638,7 +669,8 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   for (int p = 0; p < nprob; ++p) {
     ptab[p].chi0 = static_cast<double2*>(probs[p].chi0);
     ptab[p].omega = probs[p].omega;
-    ptab[p].wts = static_cast<char*>(h->wts.p) + woff;
+    ptab[p].wts = hk ? const_cast<char*>(static_cast<const char*>(hk->wts)) + hk->off[p] * wsize
+                     : static_cast<char*>(h->wts.p) + woff;
     ptab[p].npb = probs[p].npb;
     ptab[p].nomega = probs[p].nomega;
     ptab[p].flush = flush_length(h, pl->tc, probs[p]);
@@ -658,6 +690,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
       d.pad = 0;
       d.zs = nullptr;
       d.zs_plane = 0;
+      d.rows = hk ? hk->rows + hk->off[p] : nullptr;
       if (presplit) {
         const int64_t G = presplit_groups(static_cast<int64_t>(bl.nocc) * bl.nunocc);
         const size_t plane = ((static_cast<size_t>(G) * probs[p].npb * 16 + 255) / 256) * 256;
@@ -701,7 +734,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   ra.pad = 0;
   ra.accumulate = (flags & CHI0_ACCUMULATE) ? 1 : 0;
 
-  const bool use_graph = (flags & CHI0_USE_GRAPH) && !h->profiling;
+  const bool use_graph = (flags & CHI0_USE_GRAPH) && !h->profiling && !hk;
   if (use_graph) {
     // delta_min and the LO*LO flag are kernel arguments: the cached graph is
     // only reused with the same values, so they join the key
@@ -750,8 +783,9 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
     return CHI0_OK;
   }
 
-  hipError_t ew = weights_launch(mode, ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
-                                 kind == HERK_FP64, stream);
+  hipError_t ew = hk ? hipSuccess
+                     : weights_launch(mode, ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
+                                      kind == HERK_FP64, stream);
   if (ew != hipSuccess) return fail(CHI0_EDEVICE, "pair-weight launch: %s", hipGetErrorString(ew));
   if (presplit) {
     ew = presplit_launch(ha.blocks, ha.probs, nblocks_total, max_groups, max_npb, stream);
@@ -763,7 +797,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
     e1 = get_event(h);
     if (e0) HIP_TRY(hipEventRecord(e0, stream));
   }
-  hipError_t e = herk_launch(kind, pl->tile_idx, ha, pl->nwg, stream);
+  hipError_t e = herk_launch(kind, pl->tile_idx, ha, pl->nwg, stream, hk != nullptr);
   if (e != hipSuccess) return fail(CHI0_EDEVICE, "rank-K kernel launch: %s", hipGetErrorString(e));
   if (h->profiling && e0 && e1) {
     HIP_TRY(hipEventRecord(e1, stream));
@@ -771,6 +805,306 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   }
   e = reduce_launch(ra, pl->njobs, stream);
   if (e != hipSuccess) return fail(CHI0_EDEVICE, "reduction launch: %s", hipGetErrorString(e));
+  return CHI0_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int validate_hist(const chi0_problem* probs, const chi0_hist* hists, int32_t nprob, chi0_ztype zt,
+                  chi0_precision prec, double delta_min, uint32_t flags) {
+  if (flags & ~static_cast<uint32_t>(CHI0_BF16_LOLO))
+    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  int rc = validate_problems(probs, nprob, zt, prec, delta_min, 0);
+  if (rc) return rc;
+  if (nprob > 0 && !hists) return fail(CHI0_EINVAL, "hists is NULL");
+  int64_t nbt = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const chi0_hist& hs = hists[p];
+    if (hs.nbins < 1) return fail(CHI0_EINVAL, "problem %d: nbins = %d < 1", p, hs.nbins);
+    if (hs.nreal < 0) return fail(CHI0_EINVAL, "problem %d: nreal = %d < 0", p, hs.nreal);
+    if (!hs.edges) return fail(CHI0_EINVAL, "problem %d: edges is NULL", p);
+    nbt += hs.nbins;
+    for (int j = 0; j <= hs.nbins; ++j) {
+      if (!std::isfinite(hs.edges[j]) || !(hs.edges[j] > 0.0))
+        return fail(CHI0_EINVAL, "problem %d: edges[%d] must be finite and > 0", p, j);
+      if (j > 0 && !(hs.edges[j] > hs.edges[j - 1]))
+        return fail(CHI0_EINVAL, "problem %d: edges must be strictly increasing", p);
+    }
+    if (!std::isfinite(hs.sigma) || hs.sigma < 0.0 || hs.sigma >= 1.0)
+      return fail(CHI0_EINVAL, "problem %d: sigma must be in [0, 1)", p);
+    if (hs.nreal > 0) {
+      if (!hs.omega_re || !hs.chi0_re)
+        return fail(CHI0_EINVAL, "problem %d: omega_re or chi0_re is NULL", p);
+      if (!aligned(hs.chi0_re, 16)) return fail(CHI0_EINVAL, "problem %d: chi0_re not 16-byte aligned", p);
+      for (int i = 0; i < hs.nreal; ++i) {
+        const double w = hs.omega_re[i];
+        if (!std::isfinite(w) || w < 0.0)
+          return fail(CHI0_EINVAL, "problem %d: omega_re[%d] must be finite and >= 0", p, i);
+        if (std::binary_search(hs.edges, hs.edges + hs.nbins + 1, w))
+          return fail(CHI0_EINVAL, "problem %d: omega_re[%d] lies on a bin edge", p, i);
+      }
+    }
+    if (hs.hist && !aligned(hs.hist, 16)) return fail(CHI0_EINVAL, "problem %d: hist not 16-byte aligned", p);
+  }
+  if (nbt > 16384) return fail(CHI0_EINVAL, "%lld bins in all, more than 16384", static_cast<long long>(nbt));
+  if (prec == CHI0_PREC_FP32)
+    return fail(CHI0_EUNSUPPORTED, "the histogram route runs on the FP64 and BF16x3 paths");
+  return CHI0_OK;
+}
+
+// Records one pair can produce: 1 + the most edges inside one spread
+// [x (1 - s), x (1 + s)]; every edge inside such a spread lies in
+// [e_k, rho e_k) for the first edge e_k above its lower end, rho = (1+s)/(1-s).
+int hist_records_per_pair(const chi0_hist& hs) {
+  if (hs.sigma == 0.0) return 1;
+  const double rho = (1.0 + hs.sigma) / (1.0 - hs.sigma) * (1.0 + 1e-12);
+  int best = 0;
+  int m = 0;
+  for (int k = 0; k <= hs.nbins; ++k) {
+    if (m < k) m = k;
+    while (m <= hs.nbins && hs.edges[m] < rho * hs.edges[k]) ++m;
+    best = std::max(best, m - k);
+  }
+  return 1 + best;
+}
+
+int run_hist(chi0_ctx* h, const chi0_problem* probs, const chi0_hist* hists, int32_t nprob,
+             chi0_precision prec, double delta_min, uint32_t flags, hipStream_t stream) {
+  const bool f64 = prec == CHI0_PREC_FP64;
+  int R = 1;
+  for (int p = 0; p < nprob; ++p) R = std::max(R, hist_records_per_pair(hists[p]));
+  if (R > 64) return fail(CHI0_EINVAL, "a spread covers up to %d bins (more than 63)", R - 1);
+
+  // blocks, record slots and bins
+  std::vector<HistBlock> hb;
+  std::vector<HistProb> hp(nprob);
+  std::vector<double> dbl;          // edges of every problem
+  std::vector<size_t> edge_off(nprob);
+  int64_t nrs = 0, max_pairs = 0;
+  int nbt = 0;
+  for (int p = 0; p < nprob; ++p) {
+    edge_off[p] = dbl.size();
+    dbl.insert(dbl.end(), hists[p].edges, hists[p].edges + hists[p].nbins + 1);
+    hp[p].sigma = hists[p].sigma;
+    hp[p].nbins = hists[p].nbins;
+    hp[p].bin0 = nbt;
+    nbt += hists[p].nbins;
+    for (int b = 0; b < probs[p].nblocks; ++b) {
+      const chi0_block& bl = probs[p].blocks[b];
+      const int64_t K = static_cast<int64_t>(bl.nocc) * bl.nunocc;
+      if (K == 0) continue;
+      HistBlock d;
+      d.z = bl.z;
+      d.eps_occ = bl.eps_occ;
+      d.eps_unocc = bl.eps_unocc;
+      d.wk = bl.wk;
+      d.nocc = bl.nocc;
+      d.nunocc = bl.nunocc;
+      d.rec0 = nrs;
+      d.prob = p;
+      d.row_bytes = probs[p].npb * (f64 ? 16 : 8);
+      hb.push_back(d);
+      nrs += K * R;
+      max_pairs = std::max(max_pairs, K);
+    }
+  }
+  if (nrs > 0x7fffffffLL)
+    return fail(CHI0_EINVAL, "%lld record slots (pairs x %d), more than 2^31-1", static_cast<long long>(nrs), R);
+  const int nchunks = static_cast<int>((nrs + hist_chunk() - 1) / hist_chunk());
+  const size_t wsz = f64 ? 8 : 4;
+  int rc;
+  const size_t rec_bytes = align256(nrs * 4) + align256(nrs * 8) + align256(nrs * 8);
+  if ((rc = h->hist_rec.reserve(std::max<size_t>(rec_bytes, 256), &h->ws_gen))) return rc;
+  const size_t sorted_bytes = align256(nrs * 8) + align256(nrs * wsz);
+  if ((rc = h->hist_sorted.reserve(std::max<size_t>(sorted_bytes, 256), &h->ws_gen))) return rc;
+  const size_t cnt_bytes = align256(static_cast<size_t>(nbt) * std::max(nchunks, 1) * 4) +
+                           align256(static_cast<size_t>(nbt + 1) * 8);
+  if ((rc = h->hist_cnt.reserve(cnt_bytes, &h->ws_gen))) return rc;
+  char* rec = static_cast<char*>(h->hist_rec.p);
+  int32_t* rbin = reinterpret_cast<int32_t*>(rec);
+  double* rwt = reinterpret_cast<double*>(rec + align256(nrs * 4));
+  uint64_t* rrow = reinterpret_cast<uint64_t*>(rec + align256(nrs * 4) + align256(nrs * 8));
+  uint64_t* srow = static_cast<uint64_t*>(h->hist_sorted.p);
+  void* swt = static_cast<char*>(h->hist_sorted.p) + align256(nrs * 8);
+  int32_t* cnt = static_cast<int32_t*>(h->hist_cnt.p);
+  int64_t* doff = reinterpret_cast<int64_t*>(static_cast<char*>(h->hist_cnt.p) +
+                                             align256(static_cast<size_t>(nbt) * std::max(nchunks, 1) * 4));
+
+  // tables A (edges | HistProb | HistBlock) and, after the bin counts are
+  // known, tables B (Hilbert descriptors | slot and bin lists | real
+  // frequencies | zero list) in one buffer sized for the most bins up front
+  const size_t a_prob = align256(dbl.size() * 8);
+  const size_t a_blk = a_prob + align256(hp.size() * sizeof(HistProb));
+  const size_t a_bytes = a_blk + align256(std::max<size_t>(hb.size(), 1) * sizeof(HistBlock));
+  int64_t nreal_all = 0;
+  for (int p = 0; p < nprob; ++p) nreal_all += hists[p].nreal;
+  const size_t b_hp = 0;
+  const size_t b_int = align256(nprob * sizeof(HilbertProb));
+  const size_t b_ore = b_int + align256(static_cast<size_t>(2 * nbt) * 4);
+  const size_t b_zero = b_ore + align256(static_cast<size_t>(std::max<int64_t>(nreal_all, 1)) * 8);
+  const size_t b_bytes = b_zero + align256(static_cast<size_t>(nbt) * sizeof(void*));
+  if ((rc = h->hist_tab.reserve(a_bytes + b_bytes, &h->ws_gen))) return rc;
+  char* dtab = static_cast<char*>(h->hist_tab.p);
+  for (int p = 0; p < nprob; ++p) hp[p].edges = reinterpret_cast<const double*>(dtab) + edge_off[p];
+  if ((rc = staging_reserve(h, a_bytes))) return rc;
+  char* st = static_cast<char*>(h->staging);
+  memcpy(st, dbl.data(), dbl.size() * 8);
+  memcpy(st + a_prob, hp.data(), hp.size() * sizeof(HistProb));
+  if (!hb.empty()) memcpy(st + a_blk, hb.data(), hb.size() * sizeof(HistBlock));
+  HIP_TRY(hipMemcpyAsync(dtab, st, a_bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(h->staging_done, stream));
+  h->staging_pending = true;
+
+  hipError_t e = hist_records_launch(reinterpret_cast<const HistBlock*>(dtab + a_blk),
+                                     reinterpret_cast<const HistProb*>(dtab + a_prob),
+                                     static_cast<int>(hb.size()), max_pairs, R, delta_min, rbin, rwt, rrow,
+                                     stream);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "binning launch: %s", hipGetErrorString(e));
+  e = hist_sort_launch(rbin, rwt, rrow, nrs, nbt, cnt, doff, srow, swt, f64, stream);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "bin sort launch: %s", hipGetErrorString(e));
+  if (h->hist_off_host_n < static_cast<size_t>(nbt + 1)) {
+    if (h->hist_off_host) hipHostFree(h->hist_off_host);
+    h->hist_off_host = nullptr;
+    h->hist_off_host_n = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->hist_off_host), (nbt + 1) * 8, hipHostMallocDefault));
+    h->hist_off_host_n = nbt + 1;
+  }
+  HIP_TRY(hipMemcpyAsync(h->hist_off_host, doff, (nbt + 1) * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const int64_t* off = h->hist_off_host;
+
+  h->hist_records = off[nbt];
+  h->hist_bins_used = 0;
+  for (int b = 0; b < nbt; ++b) h->hist_bins_used += off[b + 1] > off[b] ? 1 : 0;
+
+  // one rank-K problem per non-empty bin
+  std::vector<chi0_problem> iprob;
+  std::vector<chi0_block> iblk;
+  std::vector<int64_t> ioff;
+  std::vector<std::vector<int32_t>> slots(nprob), bins(nprob);
+  std::vector<int> empty_prob, empty_bin;
+  size_t ws_mats = 0;
+  std::vector<size_t> mat_off(nprob, 0);
+  for (int p = 0; p < nprob; ++p) {
+    mat_off[p] = ws_mats;
+    const size_t n2 = static_cast<size_t>(probs[p].npb) * probs[p].npb;
+    int used = 0;
+    for (int j = 0; j < hists[p].nbins; ++j) {
+      const int64_t c = off[hp[p].bin0 + j + 1] - off[hp[p].bin0 + j];
+      if (c > 0x7fffffffLL) return fail(CHI0_EINVAL, "bin %d of problem %d holds more than 2^31-1 records", j, p);
+      if (c > 0) {
+        bins[p].push_back(j);
+        slots[p].push_back(hists[p].hist ? j : used);
+        ++used;
+      } else if (hists[p].hist) {
+        empty_prob.push_back(p);
+        empty_bin.push_back(j);
+      }
+    }
+    if (!hists[p].hist) ws_mats += static_cast<size_t>(used) * n2 * 16;
+  }
+  if ((rc = h->hist_mats.reserve(std::max<size_t>(ws_mats, 256), &h->ws_gen))) return rc;
+  for (int p = 0; p < nprob; ++p) {
+    const size_t n2 = static_cast<size_t>(probs[p].npb) * probs[p].npb;
+    double2* base = hists[p].hist ? static_cast<double2*>(hists[p].hist)
+                                  : reinterpret_cast<double2*>(static_cast<char*>(h->hist_mats.p) + mat_off[p]);
+    for (size_t k = 0; k < bins[p].size(); ++k) {
+      const int j = bins[p][k];
+      chi0_block b{};
+      b.nocc = static_cast<int32_t>(off[hp[p].bin0 + j + 1] - off[hp[p].bin0 + j]);
+      b.nunocc = 1;
+      iblk.push_back(b);
+      chi0_problem q{};
+      q.npb = probs[p].npb;
+      q.nblocks = 1;
+      q.nomega = 1;
+      q.omega = probs[p].omega;
+      q.chi0 = base + static_cast<size_t>(slots[p][k]) * n2;
+      iprob.push_back(q);
+      ioff.push_back(off[hp[p].bin0 + j]);
+    }
+  }
+  for (size_t q = 0; q < iprob.size(); ++q) iprob[q].blocks = &iblk[q];
+
+  // tables B: Hilbert descriptors, slot / bin lists, zero list; coefficients
+  size_t coeff_bytes = 0;
+  std::vector<size_t> coeff_off(nprob);
+  int max_out = 0, max_bins = 0;
+  int64_t max_n2 = 0;
+  for (int p = 0; p < nprob; ++p) {
+    coeff_off[p] = coeff_bytes;
+    const int nout = probs[p].nomega + hists[p].nreal;
+    coeff_bytes += align256(static_cast<size_t>(nout) * std::max<size_t>(bins[p].size(), 1) * 16);
+    max_out = std::max(max_out, nout);
+    max_bins = std::max(max_bins, static_cast<int>(bins[p].size()));
+    max_n2 = std::max<int64_t>(max_n2, static_cast<int64_t>(probs[p].npb) * probs[p].npb);
+  }
+  if ((rc = h->hist_coeff.reserve(std::max<size_t>(coeff_bytes, 256), &h->ws_gen))) return rc;
+  std::vector<int32_t> ints;
+  std::vector<size_t> slot_off(nprob), bin_off(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    slot_off[p] = ints.size();
+    ints.insert(ints.end(), slots[p].begin(), slots[p].end());
+    bin_off[p] = ints.size();
+    ints.insert(ints.end(), bins[p].begin(), bins[p].end());
+  }
+  std::vector<double> oreal;
+  std::vector<size_t> ore_off(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    ore_off[p] = oreal.size();
+    if (hists[p].nreal > 0) oreal.insert(oreal.end(), hists[p].omega_re, hists[p].omega_re + hists[p].nreal);
+  }
+  char* btab = dtab + a_bytes;
+  std::vector<HilbertProb> hb2(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    HilbertProb& x = hb2[p];
+    x.hist = hists[p].hist ? static_cast<const double2*>(hists[p].hist)
+                           : reinterpret_cast<const double2*>(static_cast<char*>(h->hist_mats.p) + mat_off[p]);
+    x.slots = reinterpret_cast<const int32_t*>(btab + b_int) + slot_off[p];
+    x.bins = reinterpret_cast<const int32_t*>(btab + b_int) + bin_off[p];
+    x.edges = reinterpret_cast<const double*>(dtab) + edge_off[p];
+    x.omega = probs[p].omega;
+    x.omega_re = reinterpret_cast<const double*>(btab + b_ore) + ore_off[p];
+    x.coeff = reinterpret_cast<double2*>(static_cast<char*>(h->hist_coeff.p) + coeff_off[p]);
+    x.out = static_cast<double2*>(probs[p].chi0);
+    x.out_re = static_cast<double2*>(hists[p].chi0_re);
+    x.npb = probs[p].npb;
+    x.nimag = probs[p].nomega;
+    x.nreal = hists[p].nreal;
+    x.nbins_used = static_cast<int32_t>(bins[p].size());
+  }
+  std::vector<double2*> zero_ptrs(empty_prob.size());
+  for (size_t i = 0; i < empty_prob.size(); ++i)
+    zero_ptrs[i] = static_cast<double2*>(hists[empty_prob[i]].hist) +
+                   static_cast<size_t>(empty_bin[i]) * probs[empty_prob[i]].npb * probs[empty_prob[i]].npb;
+  if ((rc = staging_reserve(h, b_bytes))) return rc;
+  st = static_cast<char*>(h->staging);
+  memcpy(st + b_hp, hb2.data(), nprob * sizeof(HilbertProb));
+  if (!ints.empty()) memcpy(st + b_int, ints.data(), ints.size() * 4);
+  if (!oreal.empty()) memcpy(st + b_ore, oreal.data(), oreal.size() * 8);
+  if (!zero_ptrs.empty()) memcpy(st + b_zero, zero_ptrs.data(), zero_ptrs.size() * sizeof(void*));
+  HIP_TRY(hipMemcpyAsync(btab, st, b_bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(h->staging_done, stream));
+  h->staging_pending = true;
+
+  if (!iprob.empty()) {
+    GatherHook hk{srow, swt, ioff.data()};
+    rc = run_accumulate(h, iprob.data(), static_cast<int32_t>(iprob.size()), prec, 0.0,
+                        flags & CHI0_BF16_LOLO, stream, -1, kWeightsChi0, &hk);
+    if (rc) return rc;
+  }
+  // zero lists are grouped by problem size: one launch per distinct npb
+  for (size_t i = 0; i < empty_prob.size();) {
+    size_t k = i;
+    const int npb = probs[empty_prob[i]].npb;
+    while (k < empty_prob.size() && probs[empty_prob[k]].npb == npb) ++k;
+    e = hist_zero_launch(reinterpret_cast<double2* const*>(btab + b_zero) + i, static_cast<int>(k - i),
+                         static_cast<int64_t>(npb) * npb, stream);
+    if (e != hipSuccess) return fail(CHI0_EDEVICE, "zero launch: %s", hipGetErrorString(e));
+    i = k;
+  }
+  e = hilbert_launch(reinterpret_cast<const HilbertProb*>(btab + b_hp), nprob, max_out, max_bins, max_n2, stream);
+  if (e != hipSuccess) return fail(CHI0_EDEVICE, "Hilbert launch: %s", hipGetErrorString(e));
   return CHI0_OK;
 }
 
@@ -833,8 +1167,6 @@ int validate_sigc(const sigc_problem* probs, int32_t nprob, chi0_ztype zt, chi0_
   if (zt != CHI0_Z_C128) return fail(CHI0_EUNSUPPORTED, "the FP64 path needs Z type CHI0_Z_C128");
   return CHI0_OK;
 }
-
-size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, uint32_t flags, hipStream_t stream) {
   const int T = sigc_tile();
@@ -1154,6 +1486,14 @@ int chi0_destroy(chi0_handle h) {
   h->sigc_zw.release();
   h->sigc_part.release();
   h->sigc_acc.release();
+  h->gather_plan.reset();
+  h->hist_tab.release();
+  h->hist_rec.release();
+  h->hist_sorted.release();
+  h->hist_cnt.release();
+  h->hist_mats.release();
+  h->hist_coeff.release();
+  if (h->hist_off_host) hipHostFree(h->hist_off_host);
   if (h->d_status) hipFree(h->d_status);
   if (h->staging) hipHostFree(h->staging);
   if (h->staging_done) hipEventDestroy(h->staging_done);
@@ -1208,6 +1548,24 @@ int sigc_accumulate(chi0_handle h, const sigc_problem* probs, int32_t nprob, chi
   if (nprob == 0) return CHI0_OK;
   HIP_TRY(hipSetDevice(h->device));
   return run_sigc(h, probs, nprob, flags, static_cast<hipStream_t>(hip_stream));
+}
+
+int chi0_hist_accumulate(chi0_handle h, const chi0_problem* probs, const chi0_hist* hists, int32_t nprob,
+                         chi0_ztype zt, chi0_precision prec, double delta_min, uint32_t flags,
+                         void* hip_stream) {
+  int rc = validate_hist(probs, hists, nprob, zt, prec, delta_min, flags);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (nprob == 0) return CHI0_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  return run_hist(h, probs, hists, nprob, prec, delta_min, flags, static_cast<hipStream_t>(hip_stream));
+}
+
+int chi0_hist_stats(chi0_handle h, int64_t* records, int32_t* bins_used) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (records) *records = h->hist_records;
+  if (bins_used) *bins_used = h->hist_bins_used;
+  return CHI0_OK;
 }
 
 int sigc_set_variant(chi0_handle h, int32_t variant) {

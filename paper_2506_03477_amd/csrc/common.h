@@ -22,6 +22,10 @@ struct BlockDesc {
   // padded with zero pairs to whole 16-pair stages; lo = hi + zs_plane bytes.
   void* zs;
   int64_t zs_plane;
+  // Gathered blocks (histogram bins): byte address of the Z row of each of
+  // the block's rows, which then need not be contiguous; NULL: row p is at
+  // z + p * npb elements.
+  const uint64_t* rows = nullptr;
 };
 
 // One q-point (device table entry).
@@ -140,6 +144,51 @@ hipError_t sigc_store_launch(const SigcProb* probs, int nprob, int max_nqp, bool
 int sigc_zw_variants();
 int sigc_tile();
 
+// Histogram route (Eq.(impolf), Eq.(hilbert)): one k-point block as the
+// binning kernel sees it.
+struct HistBlock {
+  const void* z;            // [nocc][nunocc][npb] complex
+  const double* eps_occ;    // [nocc]
+  const double* eps_unocc;  // [nunocc]
+  double wk;
+  int32_t nocc, nunocc;
+  int64_t rec0;             // first record slot (R slots per pair)
+  int32_t prob;
+  int32_t row_bytes;        // bytes of one Z row (npb complex values)
+};
+
+struct HistProb {
+  const double* edges;      // [nbins + 1]
+  double sigma;             // relative half-width of a transition's spread
+  int32_t nbins;
+  int32_t bin0;             // first bin of this problem in the global bin list
+};
+
+// Hilbert transform of one problem: outputs sum_k coeff[o][k] hist[slots[k]]
+// over the problem's non-empty bins.
+struct HilbertProb {
+  const double2* hist;      // base of the problem's bin matrices [.][npb][npb]
+  const int32_t* slots;     // [nbins_used] matrix index of each non-empty bin
+  const int32_t* bins;      // [nbins_used] its bin index j
+  const double* edges;      // [nbins + 1]
+  const double* omega;      // [nimag] imaginary frequencies
+  const double* omega_re;   // [nreal] real frequencies
+  double2* coeff;           // [nimag + nreal][nbins_used] (written by the kernels)
+  double2* out;             // [nimag][npb][npb]
+  double2* out_re;          // [nreal][npb][npb]
+  int32_t npb, nimag, nreal, nbins_used;
+};
+
+int hist_chunk();
+hipError_t hist_records_launch(const HistBlock* blocks, const HistProb* probs, int nblocks, int64_t max_pairs,
+                               int R, double delta_min, int32_t* rbin, double* rw, uint64_t* rrow,
+                               hipStream_t s);
+hipError_t hist_sort_launch(const int32_t* rbin, const double* rw, const uint64_t* rrow, int64_t nrec, int nbt,
+                            int32_t* cnt, int64_t* off, uint64_t* srow, void* sw, bool f64, hipStream_t s);
+hipError_t hilbert_launch(const HilbertProb* hp, int nprob, int max_out, int max_bins, int64_t max_n2,
+                          hipStream_t s);
+hipError_t hist_zero_launch(double2* const* mats, int nmats, int64_t n2, hipStream_t s);
+
 // Kernel variants of the rank-K contraction.
 enum HerkKind { HERK_FP64 = 0, HERK_FP32 = 1, HERK_BF16X3 = 2 };
 
@@ -167,7 +216,9 @@ int herk_default_tile(int kind);
 TileConfig herk_tile_config(int kind, int idx);
 int herk_max_wg_per_cu(int kind, int idx);
 hipError_t herk_launch(int kind, int idx, const HerkArgs& a, int nwg,
-                       hipStream_t s);
+                       hipStream_t s, bool gather = false);
+// Tile configurations whose kernels read gathered rows (BlockDesc::rows).
+bool herk_tile_gathers(int kind, int idx);
 hipError_t reduce_launch(const ReduceArgs& a, int njobs, hipStream_t s);
 
 hipError_t dielectric_build_launch(const double2* chi0, const double* vsqrt,

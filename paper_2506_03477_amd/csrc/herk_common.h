@@ -80,7 +80,7 @@ __device__ __forceinline__ bool cursor_next(const Unit& u, const BlockDesc* bloc
 // Host-side dispatch tables of the three precision paths.
 int herk_fp64_tile_count();
 TileConfig herk_fp64_tile(int idx);
-hipError_t herk_fp64_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s);
+hipError_t herk_fp64_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s, bool gather);
 int herk_fp64_max_wg_per_cu(int idx);
 
 int herk_fp32_tile_count();
@@ -90,7 +90,7 @@ int herk_fp32_max_wg_per_cu(int idx);
 
 int herk_bf16x3_tile_count();
 TileConfig herk_bf16x3_tile(int idx);
-hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s);
+hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s, bool gather);
 int herk_bf16x3_max_wg_per_cu(int idx);
 
 }  // namespace chi0

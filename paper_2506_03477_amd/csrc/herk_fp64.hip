@@ -142,7 +142,7 @@ typedef const double __attribute__((address_space(1)))* gdptr;
 // Loads are issued unconditionally with the row clamped into the block; bit
 // k of the returned mask says whether pair k exists (a missing pair gets
 // weight 0).
-template <int NP>
+template <int NP, bool GATHER>
 __device__ __forceinline__ uint32_t load_pairs64(const HerkArgs& a, const ProbDesc& pd, int iw,
                                                  const Cursor& c, const int (&poff)[NP], int npb,
                                                  uint32_t offP, uint32_t offQ, double2 (&ra)[NP],
@@ -154,6 +154,7 @@ __device__ __forceinline__ uint32_t load_pairs64(const HerkArgs& a, const ProbDe
   const BlockDesc* bp = a.blocks + b;
   const uint32_t row_bytes = static_cast<uint32_t>(npb) * 16u;
   const gcptr z = (gcptr)(ld_const(&bp->z, 0)) + static_cast<size_t>(p0) * row_bytes;
+  const uint64_t* rows = GATHER ? ld_const(&bp->rows, 0) + p0 : nullptr;
   const int64_t pbase = ld_const(&bp->pair_base, 0);
   const double* w = static_cast<const double*>(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase + p0;
   uint32_t mask = 0;
@@ -163,7 +164,7 @@ __device__ __forceinline__ uint32_t load_pairs64(const HerkArgs& a, const ProbDe
     const bool valid = o <= last;
     const int oc = valid ? o : last;
     mask |= valid ? (1u << k) : 0u;
-    const gcptr row = z + static_cast<uint32_t>(oc) * row_bytes;
+    const gcptr row = GATHER ? (gcptr)ld_const(rows, oc) : z + static_cast<uint32_t>(oc) * row_bytes;
     const dvec2 va = *(gd2ptr)(row + offP);
     const dvec2 vb = *(gd2ptr)(row + offQ);
     ra[k] = double2{va.x, va.y};
@@ -176,7 +177,7 @@ __device__ __forceinline__ uint32_t load_pairs64(const HerkArgs& a, const ProbDe
 // NW = 4: 2 x 2 waves of 64 x 64 (one wave per SIMD, 256 accumulator
 // registers); NW = 8: 2 x 4 waves of 64 x 32 (two waves per SIMD, so one
 // wave's MFMAs can issue while the other waits).
-template <int NW>
+template <int NW, bool GATHER>
 __global__ __launch_bounds__(64 * NW, 1) void herk_fp64_pipe_kernel(HerkArgs a) {
   constexpr int T = 128, KC = 8, NT = 64 * NW;
   constexpr int WC = NW / 2;          // wave columns
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(64 * NW, 1) void herk_fp64_pipe_kernel(HerkArgs a) 
     Cursor cur;
     bool have = cursor_first(u, a.blocks, cur);
     __syncthreads();
-    if (have) mk = load_pairs64<NP>(a, pd, u.iw, cur, poff, npb, cP, cQ, ra, rb, rw);
+    if (have) mk = load_pairs64<NP, GATHER>(a, pd, u.iw, cur, poff, npb, cP, cQ, ra, rb, rw);
     int buf = 0;
     while (have) {
 #pragma unroll
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(64 * NW, 1) void herk_fp64_pipe_kernel(HerkArgs a) 
       }
       Cursor nxt = cur;
       const bool more = cursor_next<KC>(u, a.blocks, nxt);
-      mk = load_pairs64<NP>(a, pd, u.iw, nxt, poff, npb, cP, cQ, ra, rb, rw);
+      mk = load_pairs64<NP, GATHER>(a, pd, u.iw, nxt, poff, npb, cP, cQ, ra, rb, rw);
       __syncthreads();
 #pragma unroll
       for (int st = 0; st < KC / 2; ++st) {
@@ -292,13 +293,19 @@ static const TileConfig kFp64Tiles[] = {
 int herk_fp64_tile_count() { return sizeof(kFp64Tiles) / sizeof(kFp64Tiles[0]); }
 TileConfig herk_fp64_tile(int idx) { return kFp64Tiles[idx]; }
 
-hipError_t herk_fp64_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
+hipError_t herk_fp64_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s, bool gather) {
   switch (idx) {
     case 0:
-      hipLaunchKernelGGL(herk_fp64_pipe_kernel<4>, dim3(nwg), dim3(256), 0, s, a);
+      if (gather)
+        hipLaunchKernelGGL((herk_fp64_pipe_kernel<4, true>), dim3(nwg), dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((herk_fp64_pipe_kernel<4, false>), dim3(nwg), dim3(256), 0, s, a);
       break;
     case 3:
-      hipLaunchKernelGGL(herk_fp64_pipe_kernel<8>, dim3(nwg), dim3(512), 0, s, a);
+      if (gather)
+        hipLaunchKernelGGL((herk_fp64_pipe_kernel<8, true>), dim3(nwg), dim3(512), 0, s, a);
+      else
+        hipLaunchKernelGGL((herk_fp64_pipe_kernel<8, false>), dim3(nwg), dim3(512), 0, s, a);
       break;
     case 1:
       hipLaunchKernelGGL((herk_fp64_kernel<64, 16>), dim3(nwg), dim3(256), 0, s, a);
@@ -316,9 +323,9 @@ int herk_fp64_max_wg_per_cu(int idx) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   if (idx == 0)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_pipe_kernel<4>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_pipe_kernel<4, false>, 256, 0);
   else if (idx == 3)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_pipe_kernel<8>, 512, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_pipe_kernel<8, false>, 512, 0);
   else if (idx == 1)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp64_kernel<64, 16>, 256, 0);
   else if (idx == 2)

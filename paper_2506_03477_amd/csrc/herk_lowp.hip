@@ -492,6 +492,7 @@ struct Bf16TallLds {
 
 // Q-side loads of one stage: column offQ of the 8 pairs 4 (lg + 2 gi) + e,
 // and their weights (wave-uniform rows, see load_pairs).
+template <bool GATHER>
 __device__ __forceinline__ uint32_t tall_load_q(const HerkArgs& a, const ProbDesc& pd, int iw,
                                                 const Cursor& c, int lg, int npb, uint32_t offQ,
                                                 float2 (&rb)[8], float (&rw)[8]) {
@@ -503,6 +504,7 @@ __device__ __forceinline__ uint32_t tall_load_q(const HerkArgs& a, const ProbDes
   const BlockDesc* bp = a.blocks + b;
   const uint32_t row_bytes = static_cast<uint32_t>(npb) * 8u;
   const gcptr z = (gcptr)(ld_const(&bp->z, 0)) + static_cast<size_t>(p0) * row_bytes;
+  const uint64_t* rows = GATHER ? ld_const(&bp->rows, 0) + p0 : nullptr;
   const int64_t pbase = ld_const(&bp->pair_base, 0);
   const float* w = static_cast<const float*>(pd.wts) + static_cast<size_t>(iw) * pd.ktot + pbase + p0;
   uint32_t mask = 0;
@@ -512,7 +514,8 @@ __device__ __forceinline__ uint32_t tall_load_q(const HerkArgs& a, const ProbDes
     const bool valid = o <= last;
     const int oc = valid ? o : last;
     mask |= valid ? (1u << k) : 0u;
-    rb[k] = ld_c64((gf2ptr)(z + static_cast<uint32_t>(oc) * row_bytes + offQ));
+    const gcptr row = GATHER ? (gcptr)ld_const(rows, oc) : z + static_cast<uint32_t>(oc) * row_bytes;
+    rb[k] = ld_c64((gf2ptr)(row + offQ));
     rw[k] = ld_const(w, oc);
   }
   return mask;
@@ -672,7 +675,7 @@ __device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32
 //      (s + 1) % 2) in one block with interleaving hints;
 //   3. the P staging of stage s + 1 (its loads have had the MFMA phase to
 //      land), then one barrier.
-template <bool LOLO, bool HINT>
+template <bool LOLO, bool HINT, bool GATHER = false>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
   constexpr int TP = 256, TQ = 128;
   __shared__ __attribute__((aligned(16))) Bf16TallLds L;
@@ -728,8 +731,8 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
     __syncthreads();  // previous unit's last MFMAs are done with the LDS
     if (h_s) {
       tall_load_p(a, c_s, npb, cP, ph, pl);
-      mk0 = tall_load_q(a, pd, u.iw, c_s, lg, npb, cQ, rb0, rw0);
-      mk1 = tall_load_q(a, pd, u.iw, c_1, lg, npb, cQ, rb1, rw1);
+      mk0 = tall_load_q<GATHER>(a, pd, u.iw, c_s, lg, npb, cQ, rb0, rw0);
+      mk1 = tall_load_q<GATHER>(a, pd, u.iw, c_1, lg, npb, cQ, rb1, rw1);
       tall_stage_p(L, 0, lp, ph, pl);
       tall_stage_q(L, 0, lq, lg, rb0, rw0, mk0);
     }
@@ -741,7 +744,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
         c_2 = c_1;
         bool h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
         tall_load_p(a, c_1, npb, cP, ph, pl);                     // unused when !h_1
-        mk0 = tall_load_q(a, pd, u.iw, c_2, lg, npb, cQ, rb0, rw0);
+        mk0 = tall_load_q<GATHER>(a, pd, u.iw, c_2, lg, npb, cQ, rb0, rw0);
         tall_mfma<LOLO>(L, 0, wr, wc, g8, l32, cr, ci);
         tall_stage_q(L, 1, lq, lg, rb1, rw1, mk1);
         interleave();
@@ -753,7 +756,7 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_tall_kernel(HerkArgs a) {
         c_2 = c_1;
         h_2 = h_1 && cursor_next<kKC>(u, a.blocks, c_2);
         tall_load_p(a, c_1, npb, cP, ph, pl);
-        mk1 = tall_load_q(a, pd, u.iw, c_2, lg, npb, cQ, rb1, rw1);
+        mk1 = tall_load_q<GATHER>(a, pd, u.iw, c_2, lg, npb, cQ, rb1, rw1);
         tall_mfma<LOLO>(L, 1, wr, wc, g8, l32, cr, ci);
         tall_stage_q(L, 0, lq, lg, rb0, rw0, mk0);
         interleave();
@@ -1083,7 +1086,22 @@ static void launch_bf16_seq(bool lolo, const HerkArgs& a, int nwg, hipStream_t s
     }                                                                                          \
   } while (0)
 
-hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
+#define CHI0_BF16_TALL_GATHER_LAUNCH(lolo, hint, nwg, s, a)                                      \
+  do {                                                                                           \
+    if (lolo) {                                                                                  \
+      if (hint) hipLaunchKernelGGL((herk_bf16x3_tall_kernel<true, true, true>), dim3(nwg),       \
+                                   dim3(kNT), 0, s, a);                                          \
+      else hipLaunchKernelGGL((herk_bf16x3_tall_kernel<true, false, true>), dim3(nwg),           \
+                              dim3(kNT), 0, s, a);                                               \
+    } else {                                                                                     \
+      if (hint) hipLaunchKernelGGL((herk_bf16x3_tall_kernel<false, true, true>), dim3(nwg),      \
+                                   dim3(kNT), 0, s, a);                                          \
+      else hipLaunchKernelGGL((herk_bf16x3_tall_kernel<false, false, true>), dim3(nwg),          \
+                              dim3(kNT), 0, s, a);                                               \
+    }                                                                                            \
+  } while (0)
+
+hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s, bool gather) {
   if (idx < 0 || idx >= herk_bf16x3_tile_count()) return hipErrorInvalidValue;
   const bool lolo = (a.flags & 2) != 0;
   switch (idx) {
@@ -1093,8 +1111,14 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
     case 1: launch_bf16_seq<128, 1>(lolo, a, nwg, s); break;
     case 2: launch_bf16_seq<64, 1>(lolo, a, nwg, s); break;
     case 4: launch_bf16_seq<128, 2>(lolo, a, nwg, s); break;
-    case 5: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, true, nwg, s, a); break;
-    case 7: CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, false, nwg, s, a); break;
+    case 5:
+      if (gather) CHI0_BF16_TALL_GATHER_LAUNCH(lolo, true, nwg, s, a);
+      else CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, true, nwg, s, a);
+      break;
+    case 7:
+      if (gather) CHI0_BF16_TALL_GATHER_LAUNCH(lolo, false, nwg, s, a);
+      else CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, false, nwg, s, a);
+      break;
     default:
       if (lolo)
         hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<true>, dim3(nwg), dim3(512), 0, s, a);

@@ -8,7 +8,8 @@
 // and stored as 16-byte chunks
 //   hi plane: zs + (g * npb + c) * 16,  lo plane: the same + zs_plane,
 // each 32-bit word holding (re, im) of one pair, re in the low half; pairs
-// beyond the block's end (padding to whole 16-pair stages) are zero.
+// beyond the block's end (padding to whole 16-pair stages) are zero.  A
+// gathered block (BlockDesc::rows) reads row p at the address rows[p].
 #include "common.h"
 #include "herk_common.h"
 
@@ -41,7 +42,9 @@ __global__ __launch_bounds__(256) void presplit_kernel(const BlockDesc* __restri
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t p = 4 * g + e;
-      const float2 x = p < K ? z[p * npb + c] : float2{0.f, 0.f};
+      const float2 x = p >= K   ? float2{0.f, 0.f}
+                       : bd.rows ? reinterpret_cast<const float2*>(bd.rows[p])[c]
+                                 : z[p * npb + c];
       h[e] = pack2(x.x, x.y);
       const float hr = __uint_as_float(h[e] << 16);
       const float hm = __uint_as_float(h[e] & 0xFFFF0000u);

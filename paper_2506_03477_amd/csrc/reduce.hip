@@ -98,13 +98,20 @@ int herk_max_wg_per_cu(int kind, int idx) {
   return 1;
 }
 
-hipError_t herk_launch(int kind, int idx, const HerkArgs& a, int nwg, hipStream_t s) {
+hipError_t herk_launch(int kind, int idx, const HerkArgs& a, int nwg, hipStream_t s, bool gather) {
+  if (gather && !herk_tile_gathers(kind, idx)) return hipErrorInvalidValue;
   switch (kind) {
-    case HERK_FP64: return herk_fp64_launch(idx, a, nwg, s);
+    case HERK_FP64: return herk_fp64_launch(idx, a, nwg, s, gather);
     case HERK_FP32: return herk_fp32_launch(idx, a, nwg, s);
-    case HERK_BF16X3: return herk_bf16x3_launch(idx, a, nwg, s);
+    case HERK_BF16X3: return herk_bf16x3_launch(idx, a, nwg, s, gather);
   }
   return hipErrorInvalidValue;
+}
+
+bool herk_tile_gathers(int kind, int idx) {
+  if (kind == HERK_FP64) return idx == 0 || idx == 3;
+  if (kind == HERK_BF16X3) return idx == 5 || idx == 7;
+  return false;
 }
 
 }  // namespace chi0

@@ -77,6 +77,13 @@ def gauss_legendre_imag_axis(n: int, omega_c: float = 1.0) -> np.ndarray:
     return np.sort(omega_c * (1.0 + x) / (1.0 - x))
 
 
+def hist_edges(emax: float, e0: float = 5e-6, ratio: float = 1.03) -> np.ndarray:
+    """Histogram bin edges of the paper's real-axis mesh, e0 * ratio^j Ha
+    (1e-5 * 1.03^j Ry), from e0 to the first edge above emax."""
+    n = int(math.ceil(math.log(emax / e0) / math.log(ratio))) + 1
+    return e0 * ratio ** np.arange(n + 1, dtype=np.float64)
+
+
 def vsqrt_table(npb: int) -> np.ndarray:
     """Square roots of the Coulomb eigenvalues, s_I = 1 / (1 + I)."""
     return 1.0 / (1.0 + np.arange(npb, dtype=np.float64))

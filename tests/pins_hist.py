@@ -74,6 +74,12 @@ def pin_exact_and_brute(orc):
         fails.append("loops != exact")
     if not _close(orc.hist_brute(blocks, npb, fe, 0.3, 0.0), orc.hist_ref(blocks, npb, fe, 0.3, 0.0), 1e-14):
         fails.append("loops != reference with spread")
+    ent = [(0, 2), (1, 1), (2, 0)]
+    cols = [(z.reshape(-1, npb), eo, eu, wk) for z, eo, eu, wk in blocks]
+    got = orc.hist_entries(cols, fe, 0.3, ent, {0: 0, 1: 1, 2: 2})
+    full = orc.hist_ref(blocks, npb, fe, 0.3, 0.0)
+    if not _close(got, np.array([[full[j, a, b] for a, b in ent] for j in range(full.shape[0])]), 1e-14):
+        fails.append("entry sampler != reference")
     return fails
 
 
@@ -230,7 +236,29 @@ def pin_delta_min_as_direct(orc):
     return fails
 
 
-PINS = [pin_fractions_hand, pin_exact_and_brute, pin_single_pair_imag, pin_single_pair_real,
+def pin_sparse_table(orc):
+    """The vectorised sparse bin table equals the per-pair definition
+    exactly (same arithmetic), with and without spread, for random energies
+    around random log meshes, ties at edges included."""
+    fails = []
+    rng = np.random.default_rng(17)
+    for sigma in (0.0, 0.015, 0.2):
+        edges = orc.log_edges(0.05, 1.03 if sigma < 0.1 else 1.2, 3.5)
+        eo = np.sort(rng.uniform(-0.8, 0, 7))
+        eu = np.concatenate([np.sort(rng.uniform(0.05, 3.0, 40)), edges[[5, 9]] + eo[0]])
+        dense = orc.pair_bin_table(eo, eu, edges, sigma, 0.1, 0.25)
+        bins, w = orc.pair_bins(eo, eu, edges, sigma, 0.1, 0.25)
+        rebuilt = np.zeros_like(dense)
+        for p in range(bins.shape[0]):
+            for t in range(bins.shape[1]):
+                if bins[p, t] >= 0:
+                    rebuilt[bins[p, t], p] += w[p, t]
+        if not np.array_equal(rebuilt, dense):
+            fails.append(f"sparse table != definition at sigma {sigma}")
+    return fails
+
+
+PINS = [pin_sparse_table, pin_fractions_hand, pin_exact_and_brute, pin_single_pair_imag, pin_single_pair_real,
         pin_converges_to_direct, pin_real_imag_consistency, pin_order_properties,
         pin_delta_min_as_direct]
 

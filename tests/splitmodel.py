@@ -100,3 +100,22 @@ def chi0_model(blocks, npb, omega, delta_min, path="bf16x3", lolo=False):
                 si = sum(x.T @ v - u.T @ y for x, u, y, v in terms)
             out[iw] -= sr + 1j * si
     return mirror_lower(out)
+
+
+def hist_model(blocks, npb, edges, sigma, delta_min=0.0, path="bf16x3", lolo=False):
+    """Histogram bins of the reduced-precision path: per bin, the weighted
+    rank-K model over the pairs with a non-zero bin weight (FP32 weight on
+    the Q side, bf16 split); blocks: (Z complex64 [nocc, nunocc, npb], eps_occ,
+    eps_unocc, wk)."""
+    from oracle.hist_oracle import pair_bin_table
+    nb = len(edges) - 1
+    out = np.zeros((nb, npb, npb), np.complex128)
+    for z, eo, eu, wk in blocks:
+        nocc, nunocc, _ = z.shape
+        a = np.asarray(z, np.complex64).reshape(nocc * nunocc, npb)
+        t = pair_bin_table(eo, eu, edges, sigma, delta_min, wk)
+        for j in range(nb):
+            rows = np.nonzero(t[j])[0]
+            if rows.size:
+                out[j] += weighted_model(a[rows], t[j, rows], path, lolo)
+    return mirror_lower(out)

@@ -201,3 +201,52 @@ def test_sigc_validation_flags_precision_and_handle():
     assert "handle" in lib.chi0_last_error().decode()
     assert lib.sigc_set_variant(None, 0) == L.CHI0_EINVAL
     assert lib.sigc_set_workspace_cap(None, 0) == L.CHI0_EINVAL
+
+
+def _hist(nbins=3, edges=(0.1, 0.5, 1.0, 2.0), sigma=0.0, nreal=0, omega_re=(), chi0_re=None,
+          hist=None):
+    import numpy as np
+    e = np.ascontiguousarray(edges, np.float64)
+    w = np.ascontiguousarray(omega_re if len(omega_re) else [0.0], np.float64)
+    h = (L.chi0_hist * 1)()
+    h[0].nbins, h[0].nreal, h[0].edges, h[0].sigma = nbins, nreal, e.ctypes.data, sigma
+    h[0].omega_re = w.ctypes.data
+    h[0].chi0_re = chi0_re
+    h[0].hist = hist
+    return h, (e, w)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nbins=0), L.CHI0_EINVAL),
+    (dict(edges=(0.0, 0.5, 1.0, 2.0)), L.CHI0_EINVAL),
+    (dict(edges=(0.1, 0.5, 0.5, 2.0)), L.CHI0_EINVAL),
+    (dict(edges=(0.1, 0.5, float("nan"), 2.0)), L.CHI0_EINVAL),
+    (dict(sigma=1.0), L.CHI0_EINVAL),
+    (dict(sigma=-0.1), L.CHI0_EINVAL),
+    (dict(nreal=1, omega_re=(0.5,), chi0_re=FAKE), L.CHI0_EINVAL),      # on an edge
+    (dict(nreal=1, omega_re=(-0.3,), chi0_re=FAKE), L.CHI0_EINVAL),
+    (dict(nreal=1, omega_re=(0.3,), chi0_re=None), L.CHI0_EINVAL),
+    (dict(nreal=1, omega_re=(0.3,), chi0_re=FAKE + 8), L.CHI0_EINVAL),
+    (dict(hist=FAKE + 4), L.CHI0_EINVAL),
+    (dict(nbins=20000, edges=tuple(0.001 * (1 + i) for i in range(20001))), L.CHI0_EINVAL),
+])
+def test_hist_validation_rejects(kw, code):
+    lib = pkg.load()
+    p, keep = _problem(npb=8, nomega=2)
+    h, keep2 = _hist(**kw)
+    assert lib.chi0_hist_accumulate(None, p, h, 1, 0, 0, 0.0, 0, None) == code
+
+
+def test_hist_validation_flags_precision_and_handle():
+    lib = pkg.load()
+    p, keep = _problem(npb=8, nomega=2)
+    h, keep2 = _hist(sigma=0.05, nreal=2, omega_re=(0.3, 1.5), chi0_re=FAKE, hist=FAKE)
+    assert lib.chi0_hist_accumulate(None, p, h, 1, 0, 0, 0.0, L.CHI0_ACCUMULATE, None) == L.CHI0_EINVAL
+    assert lib.chi0_hist_accumulate(None, p, None, 1, 0, 0, 0.0, 0, None) == L.CHI0_EINVAL
+    assert lib.chi0_hist_accumulate(None, p, h, 1, 1, 1, 0.0, 0, None) == L.CHI0_EUNSUPPORTED
+    assert lib.chi0_hist_accumulate(None, p, h, 1, 1, 0, 0.0, 0, None) == L.CHI0_EUNSUPPORTED
+    assert lib.chi0_hist_accumulate(None, p, h, 1, 0, 0, -1.0, 0, None) == L.CHI0_EINVAL
+    assert lib.chi0_hist_accumulate(None, p, h, 1, 0, 0, 0.0, 0, None) == L.CHI0_EINVAL
+    assert "handle" in lib.chi0_last_error().decode()
+    assert lib.chi0_hist_accumulate(None, p, h, 1, 1, 2, 0.0, L.CHI0_BF16_LOLO, None) == L.CHI0_EINVAL
+    assert "handle" in lib.chi0_last_error().decode()
