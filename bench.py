@@ -339,8 +339,8 @@ def bench_sigc(args):
 
     wl = workload(6)
     prec = args.precision or "fp64"
-    if prec != "fp64":
-        raise SystemExit("the correlation self-energy runs on the FP64 path only")
+    if prec not in ("fp64", "bf16x3"):
+        raise SystemExit("the correlation self-energy runs on the FP64 and BF16x3 paths")
     torch.cuda.set_device(0)
     ctx = Context(0)
     if args.tile >= 0:
@@ -352,16 +352,17 @@ def bench_sigc(args):
                        wl.omega_array(), out)
     first = second = 0.0
     exe_first = 0.0
+    tp, kq = (256, 16) if prec == "bf16x3" else (128, 8)
+    split = 3.0 if prec == "bf16x3" else 1.0
     for b in wl.blocks(0):
         f1, f2 = sigc_flops(wl.npb, b.nocc, b.nunocc, wl.nomega)
         first += f1
         second += f2
-        t = 128
-        rows = -(-b.nocc * wl.npb // t) * t
-        cols = -(-b.nunocc // t) * t
-        exe_first += 8.0 * rows * cols * wl.nomega * (-(-b.nunocc // 8) * 8)
+        rows = -(-b.nocc * wl.npb // 128) * 128
+        cols = -(-b.nunocc // tp) * tp
+        exe_first += split * 8.0 * rows * cols * wl.nomega * (-(-b.nunocc // kq) * kq)
     for _ in range(args.warmup):
-        ctx.sigc_accumulate([prob])
+        ctx.sigc_accumulate([prob], precision=prec)
     ctx.sync()
     ctx.profile_enable(True)
     ctx.profile_read()
@@ -370,7 +371,7 @@ def bench_sigc(args):
     b = torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for s in range(args.steps):
-        ctx.sigc_accumulate([prob])
+        ctx.sigc_accumulate([prob], precision=prec)
     b.record(stream)
     b.synchronize()
     ctx.sync()
@@ -383,19 +384,20 @@ def bench_sigc(args):
         per_launch = first / launches_per_step
         ach = per_launch / (kern_avg * 1e-3) / 1e12
         exe = exe_first / launches_per_step / (kern_avg * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["fp64"],
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS["fp64"], 4), "traffic": None,
-                "kernel": "sigc_gemm_kernel (first contraction)", "kernel_ms": round(kern_avg, 3),
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4), "traffic": None,
+                "kernel": ("sigc_bf16x3_kernel" if prec == "bf16x3" else "sigc_gemm_kernel")
+                          + " (first contraction)", "kernel_ms": round(kern_avg, 3),
                 "launches_per_step": launches_per_step,
                 "executed_mfma_tflops": round(exe, 3),
-                "executed_mfma_frac": round(exe / PEAK_TFLOPS["fp64"], 4)}
+                "executed_mfma_frac": round(exe / PEAK_TFLOPS[prec], 4)}
     cpu = None if args.no_cpu_baseline else sigc_cpu_baseline(wl)
     print(json.dumps({
         "metric": "I^c TFLOP/s per q-point (imaginary-axis correlation self-energy, Eq. sigci)",
         "value": round((first + second) / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if prec == "fp64" else "bf16x3", "data": "synthetic",
         "config": {"workload": wl.name, "nqp": wl.npb, "nk": wl.nk, "nall": wl.nocc,
                    "nmu": wl.nunocc, "nomega": wl.nomega, "path": prec,
                    "variant": args.tile if args.tile >= 0 else 0},

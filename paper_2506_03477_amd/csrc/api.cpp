@@ -105,7 +105,7 @@ struct chi0_ctx {
   DevBuf zsplit;        // pre-split P-side planes of the current call
   DevBuf gj_work, gj_wrow, gj_piv, gj_perm;
   DevBuf hpd_p, hpd_c, hpd_dinv;  // HPD inverse: kept panel, new panel, D^{-1}
-  DevBuf sigc_tab, sigc_wt, sigc_zw, sigc_part, sigc_acc;  // correlation self-energy
+  DevBuf sigc_tab, sigc_wt, sigc_zw, sigc_part, sigc_acc, sigc_split;  // correlation self-energy
   DevBuf hist_tab, hist_rec, hist_sorted, hist_cnt, hist_mats, hist_coeff;  // histogram route
   int64_t* hist_off_host = nullptr;  // pinned copy of the bin offsets
   size_t hist_off_host_n = 0;
@@ -1162,14 +1162,19 @@ int validate_sigc(const sigc_problem* probs, int32_t nprob, chi0_ztype zt, chi0_
       if (a0 < b1 && b0 < a1) return fail(CHI0_EINVAL, "problems %d and %d: outputs overlap", q, p);
     }
   }
-  if (prec != CHI0_PREC_FP64)
-    return fail(CHI0_EUNSUPPORTED, "the correlation self-energy runs on the FP64 path only");
-  if (zt != CHI0_Z_C128) return fail(CHI0_EUNSUPPORTED, "the FP64 path needs Z type CHI0_Z_C128");
+  if (prec == CHI0_PREC_FP32)
+    return fail(CHI0_EUNSUPPORTED, "the correlation self-energy runs on the FP64 and BF16x3 paths");
+  if (zt != CHI0_Z_C128)
+    return fail(CHI0_EUNSUPPORTED, "the correlation self-energy reads Z and W^c as CHI0_Z_C128");
   return CHI0_OK;
 }
 
-int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, uint32_t flags, hipStream_t stream) {
+int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precision prec, uint32_t flags,
+             hipStream_t stream) {
   const int T = sigc_tile();
+  const bool bf16 = prec == CHI0_PREC_BF16X3;
+  // first-contraction tiles: nu x r = 128 x 128 (FP64) or 256 x 128 (BF16x3)
+  const int T1P = bf16 ? 256 : T, T1Q = T;
   // flat block list (blocks with nall = 0 contribute nothing and are dropped)
   struct Ref {
     int prob, blk;
@@ -1186,18 +1191,28 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, uint32_t fla
   // chunks of consecutive blocks whose zw workspace stays under the cap
   std::vector<int> chunk0{0};
   int64_t zw_max = 0, cur = 0;
-  std::vector<int64_t> zw_off(nb, 0);
+  std::vector<int64_t> zw_off(nb, 0), sp_off(nb, 0);
+  int64_t sp_cur = 0, sp_max = 0;
   for (int i = 0; i < nb; ++i) {
     const sigc_problem& pr = probs[refs[i].prob];
     const sigc_block& bl = pr.blocks[refs[i].blk];
     const int64_t bytes = static_cast<int64_t>(align256(static_cast<size_t>(bl.nall) * bl.nmu * pr.nqp * 16));
+    const int64_t groups = presplit_groups(bl.nmu);
+    const int64_t sbytes =
+        bf16 ? 2 * static_cast<int64_t>(align256(static_cast<size_t>(pr.nomega) * groups * bl.nmu * 16)) +
+                   2 * static_cast<int64_t>(align256(static_cast<size_t>(groups) * bl.nall * pr.nqp * 16))
+             : 0;
     if (cur > 0 && cur + bytes > h->sigc_zw_cap) {
       chunk0.push_back(i);
       cur = 0;
+      sp_cur = 0;
     }
     zw_off[i] = cur;
+    sp_off[i] = sp_cur;
     cur += bytes;
+    sp_cur += sbytes;
     zw_max = std::max(zw_max, cur);
+    sp_max = std::max(sp_max, sp_cur);
   }
   chunk0.push_back(nb);
   const int nchunks = static_cast<int>(chunk0.size()) - 1;
@@ -1241,8 +1256,8 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, uint32_t fla
       const sigc_problem& pr = probs[refs[i].prob];
       const sigc_block& bl = pr.blocks[refs[i].blk];
       const int64_t M = static_cast<int64_t>(bl.nall) * pr.nqp;
-      const int tps = (bl.nmu + T - 1) / T;
-      const int64_t tcs = (M + T - 1) / T;
+      const int tps = (bl.nmu + T1P - 1) / T1P;
+      const int64_t tcs = (M + T1Q - 1) / T1Q;
       for (int64_t tc = 0; tc < tcs; ++tc)
         for (int tp = 0; tp < tps; ++tp) t.u1.push_back({i, tp, static_cast<int32_t>(tc), 0});
       const int tq = (pr.nqp + T - 1) / T;
@@ -1309,6 +1324,8 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, uint32_t fla
   if ((rc = h->sigc_acc.reserve(std::max<size_t>(acc_bytes, 256), &h->ws_gen))) return rc;
   if ((rc = h->sigc_wt.reserve(std::max<size_t>(wt_bytes, 256), &h->ws_gen))) return rc;
   if ((rc = h->sigc_zw.reserve(std::max<size_t>(static_cast<size_t>(zw_max), 256), &h->ws_gen))) return rc;
+  if (bf16 && (rc = h->sigc_split.reserve(std::max<size_t>(static_cast<size_t>(sp_max), 256), &h->ws_gen)))
+    return rc;
   if ((rc = h->sigc_part.reserve(std::max<size_t>(max_part_units * T * T * 16, 256), &h->ws_gen)))
     return rc;
 
@@ -1353,7 +1370,18 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, uint32_t fla
     d.nqp = pr.nqp;
     d.nomega = pr.nomega;
     d.prob = p;
-    d.pad = 0;
+    d.groups = static_cast<int32_t>(presplit_groups(bl.nmu));
+    d.wsp = nullptr;
+    d.wsp_plane = 0;
+    d.zsp = nullptr;
+    d.zsp_plane = 0;
+    if (bf16) {
+      char* base = static_cast<char*>(h->sigc_split.p) + sp_off[i];
+      d.wsp_plane = static_cast<int64_t>(align256(static_cast<size_t>(pr.nomega) * d.groups * bl.nmu * 16));
+      d.zsp_plane = static_cast<int64_t>(align256(static_cast<size_t>(d.groups) * bl.nall * pr.nqp * 16));
+      d.wsp = base;
+      d.zsp = base + 2 * d.wsp_plane;
+    }
   }
   std::vector<SigcProb> ptab(nprob);
   for (int p = 0; p < nprob; ++p) {
@@ -1395,9 +1423,22 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, uint32_t fla
     if (h->profiling) {
       e0 = get_event(h);
       e1 = get_event(h);
-      if (e0) HIP_TRY(hipEventRecord(e0, stream));
     }
-    e = sigc_zw_launch(h->sigc_variant, a1, stream);
+    if (bf16) {
+      int max_nmu = 0, max_gw = 0, max_gz = 0;
+      int64_t max_m = 0;
+      for (int i = chunk0[c]; i < chunk0[c + 1]; ++i) {
+        max_nmu = std::max(max_nmu, descs[i].nmu);
+        max_gw = std::max(max_gw, descs[i].nomega * descs[i].groups);
+        max_gz = std::max(max_gz, descs[i].groups);
+        max_m = std::max<int64_t>(max_m, static_cast<int64_t>(descs[i].nall) * descs[i].nqp);
+      }
+      e = sigc_presplit_launch(d_desc + chunk0[c], chunk0[c + 1] - chunk0[c], max_nmu, max_m, max_gw, max_gz,
+                               stream);
+      if (e != hipSuccess) return fail(CHI0_EDEVICE, "pre-split launch: %s", hipGetErrorString(e));
+    }
+    if (h->profiling && e0) HIP_TRY(hipEventRecord(e0, stream));
+    e = bf16 ? sigc_bf16x3_launch(a1, stream) : sigc_zw_launch(h->sigc_variant, a1, stream);
     if (e != hipSuccess) return fail(CHI0_EDEVICE, "first contraction launch: %s", hipGetErrorString(e));
     if (h->profiling && e0 && e1) {
       HIP_TRY(hipEventRecord(e1, stream));
@@ -1486,6 +1527,7 @@ int chi0_destroy(chi0_handle h) {
   h->sigc_zw.release();
   h->sigc_part.release();
   h->sigc_acc.release();
+  h->sigc_split.release();
   h->gather_plan.reset();
   h->hist_tab.release();
   h->hist_rec.release();
@@ -1547,7 +1589,7 @@ int sigc_accumulate(chi0_handle h, const sigc_problem* probs, int32_t nprob, chi
   if (!h) return fail(CHI0_EINVAL, "handle is NULL");
   if (nprob == 0) return CHI0_OK;
   HIP_TRY(hipSetDevice(h->device));
-  return run_sigc(h, probs, nprob, flags, static_cast<hipStream_t>(hip_stream));
+  return run_sigc(h, probs, nprob, prec, flags, static_cast<hipStream_t>(hip_stream));
 }
 
 int chi0_hist_accumulate(chi0_handle h, const chi0_problem* probs, const chi0_hist* hists, int32_t nprob,

@@ -104,7 +104,15 @@ struct SigcDesc {
   const double* omega;    // [nomega] (the problem's mesh)
   double wk;
   int32_t nall, nmu, nqp, nomega;
-  int32_t prob, pad;
+  int32_t prob, groups;   // groups: 4-row groups of mu, padded to 16-row stages
+  // BF16x3 first contraction: hi planes of W^c (per mesh point i: group g of
+  // 4 rows mu, column nu at ((i * groups + g) * nmu + nu) * 16 bytes) and of
+  // Z (group g, column r = n' * nqp + n at (g * nall * nqp + r) * 16 bytes);
+  // each lo plane follows its hi plane at + *_plane bytes.
+  void* wsp;
+  int64_t wsp_plane;
+  void* zsp;
+  int64_t zsp_plane;
 };
 
 // Work unit of the two contractions: block, tile row (P side), tile column
@@ -143,6 +151,9 @@ hipError_t sigc_store_launch(const SigcProb* probs, int nprob, int max_nqp, bool
                              hipStream_t s);
 int sigc_zw_variants();
 int sigc_tile();
+hipError_t sigc_presplit_launch(const SigcDesc* descs, int nblocks, int max_nmu, int64_t max_m,
+                                int max_groups_w, int max_groups_z, hipStream_t s);
+hipError_t sigc_bf16x3_launch(const SigcArgs& a, hipStream_t s);
 
 // Histogram route (Eq.(impolf), Eq.(hilbert)): one k-point block as the
 // binning kernel sees it.

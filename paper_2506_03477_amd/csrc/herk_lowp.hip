@@ -1045,6 +1045,156 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Correlation self-energy (Eq.(sigci)), first contraction on the BF16x3 path:
+//   D[nu][r] = sum_i t_i(r) sum_mu conj(W_i[mu][nu]) Z[n'][mu][n],
+// r = (n', n), t = -w_k w_i(eps_qn - eps_n').  Both operands arrive pre-split
+// (sigc_split_w_kernel, sigc_split_z_kernel), so staging is a copy (plus the
+// 16-bit rotation of the Z side for the imaginary part); tiles are 256 nu x
+// 128 r with the tall kernels' LDS layout and MFMA core.  The weight depends
+// on (i, r) only, so the FP32 accumulators of one mesh point are multiplied
+// by t_i(r) in FP64 when they are flushed into the FP64 output zw[n'][nu][n]
+// (at the end of every mesh point, and every 4096 rows mu at most).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
+  typedef const char __attribute__((address_space(1)))* gcptr;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  typedef const u32x4 __attribute__((address_space(1)))* gu4ptr;
+  constexpr int TP = 256, TQ = 128, FL = 256;   // FL: stages between flushes at most
+  __shared__ __attribute__((aligned(16))) Bf16TallLds L;
+
+  const int per = (args.nunits + 7) / 8;
+  const int lu = static_cast<int>(blockIdx.x % 8) * per + static_cast<int>(blockIdx.x / 8);
+  if (lu >= args.nunits) return;
+  const SigcUnit u = args.units[lu];
+  const SigcDesc bd = args.descs[u.blk];
+  const int nmu = bd.nmu, nqp = bd.nqp;
+  const int64_t M = static_cast<int64_t>(bd.nall) * nqp;
+  const int ns = bd.groups / 4;                  // 16-row stages per mesh point
+  const int total = bd.nomega * ns;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g8 = lane >> 5;
+  const int l32 = lane & 31;
+  const int lp = tid;
+  const int lq = tid & (TQ - 1);
+  const int lg = tid >> 7;
+
+  const int pcol = u.tp * TP + lp;
+  const int64_t qcol = static_cast<int64_t>(u.tc) * TQ + lq;
+  const uint64_t offP = static_cast<uint64_t>(pcol < nmu ? pcol : 0) * 16u;
+  const uint64_t offQ = static_cast<uint64_t>(qcol < M ? qcol : 0) * 16u;
+  const uint64_t chunkP = static_cast<uint64_t>(nmu) * 16u;   // one group of W rows
+  const uint64_t chunkQ = static_cast<uint64_t>(M) * 16u;     // one group of Z rows
+  const gcptr wh = (gcptr)bd.wsp;
+  const gcptr zh = (gcptr)bd.zsp;
+
+  f32x16 cr[4][2], ci[4][2];
+  auto zero = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = f32x16{0};
+        ci[i][j] = f32x16{0};
+      }
+  };
+  zero();
+  uint4 ph[4], pl[4], qh[2], ql[2];
+
+  auto load = [&](int st) {
+    const int i = st / ns;
+    const int g0 = 4 * (st - i * ns);
+    const gcptr wb = wh + (static_cast<uint64_t>(i) * bd.groups + g0) * chunkP + offP;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u32x4 h = *(gu4ptr)(wb + q * chunkP);
+      const u32x4 l = *(gu4ptr)(wb + bd.wsp_plane + q * chunkP);
+      ph[q] = uint4{h.x, h.y, h.z, h.w};
+      pl[q] = uint4{l.x, l.y, l.z, l.w};
+    }
+    const gcptr zb = zh + static_cast<uint64_t>(g0) * chunkQ + offQ;
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+      const uint64_t o = static_cast<uint64_t>(lg + 2 * gi) * chunkQ;
+      const u32x4 h = *(gu4ptr)(zb + o);
+      const u32x4 l = *(gu4ptr)(zb + bd.zsp_plane + o);
+      qh[gi] = uint4{h.x, h.y, h.z, h.w};
+      ql[gi] = uint4{l.x, l.y, l.z, l.w};
+    }
+  };
+  auto stage = [&](int buf) {
+    tall_stage_p(L, buf, lp, ph, pl);
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+      const int o = swz(lq, lg + 2 * gi);
+      *reinterpret_cast<uint4*>(&L.bh[buf][o]) = qh[gi];
+      *reinterpret_cast<uint4*>(&L.bl[buf][o]) = ql[gi];
+      *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(qh[gi]);
+      *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(ql[gi]);
+    }
+  };
+  // D rows nu and columns r of this lane's accumulators, into zw, times t_i(r)
+  auto flush = [&](int i, bool first) {
+    const int g = lane >> 5;
+    const int cl = lane & 31;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t col = static_cast<int64_t>(u.tc) * TQ + wc * 64 + j * 32 + cl;
+      if (col >= M) continue;
+      const double t = bd.wt[static_cast<int64_t>(i) * M + col];
+      const int64_t a2 = col / nqp;
+      double2* dst = bd.zw + a2 * nmu * nqp + (col - a2 * nqp);
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = u.tp * TP + wr * 128 + bi * 32 + 4 * g + 8 * (r >> 2) + (r & 3);
+          if (row >= nmu) continue;
+          double2* p = dst + static_cast<int64_t>(row) * nqp;
+          const double vr = t * static_cast<double>(cr[bi][j][r]);
+          const double vi = t * static_cast<double>(ci[bi][j][r]);
+          if (first) {
+            *p = double2{vr, vi};
+          } else {
+            const double2 o = *p;
+            *p = double2{o.x + vr, o.y + vi};
+          }
+        }
+        // one 32 x 32 block at a time: keeps the in-flight FP64 values few
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  };
+
+  load(0);
+  stage(0);
+  __syncthreads();
+  int buf = 0, st = 0;
+  bool first = true;
+  // runs of stages of one mesh point (at most FL stages); the stage loop
+  // itself carries no flush code
+  while (st < total) {
+    const int i = st / ns;
+    const int seg_end = (i + 1) * ns < st + FL ? (i + 1) * ns : st + FL;
+    for (; st < seg_end; ++st) {
+      const bool more = st + 1 < total;
+      if (more) load(st + 1);
+      tall_mfma<false, 4>(L, buf, wr, wc, g8, l32, cr, ci);
+      if (more) stage(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    flush(i, first);
+    first = false;
+    zero();
+  }
+}
+
 }  // namespace
 
 // Tile tables: {tile, pairs per stage, cap of the FP32 run length (pairs),
@@ -1064,6 +1214,13 @@ static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
     {64, kKC, 4096, kNT, 64},
 };
+
+hipError_t sigc_bf16x3_launch(const SigcArgs& a, hipStream_t s) {
+  if (a.nunits <= 0) return hipSuccess;
+  const unsigned grid = static_cast<unsigned>((a.nunits + 7) / 8 * 8);
+  hipLaunchKernelGGL(sigc_bf16x3_kernel, dim3(grid), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
 
 int herk_bf16x3_tile_count() { return sizeof(kBf16Tiles) / sizeof(kBf16Tiles[0]); }
 TileConfig herk_bf16x3_tile(int idx) { return kBf16Tiles[idx]; }

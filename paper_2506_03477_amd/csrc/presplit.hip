@@ -56,7 +56,91 @@ __global__ __launch_bounds__(256) void presplit_kernel(const BlockDesc* __restri
   }
 }
 
+__device__ __forceinline__ void split_chunk(const float2 (&x)[4], uint4& hi, uint4& lo) {
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = pack2(x[e].x, x[e].y);
+    const float hr = __uint_as_float(h[e] << 16);
+    const float hm = __uint_as_float(h[e] & 0xFFFF0000u);
+    l[e] = pack2(x[e].x - hr, x[e].y - hm);
+  }
+  hi = uint4{h[0], h[1], h[2], h[3]};
+  lo = uint4{l[0], l[1], l[2], l[3]};
+}
+
+// Correlation self-energy, BF16x3 first contraction: W^c of every mesh point
+// (rows mu, columns nu) and Z (rows mu, columns r = (n', n)) of one block
+// (blockIdx.z) rounded to FP32 and split into the planes SigcDesc describes;
+// rows beyond nmu are zero.
+__global__ __launch_bounds__(256) void sigc_split_w_kernel(const SigcDesc* __restrict__ descs, int blk0) {
+#pragma clang fp contract(off)
+  const SigcDesc bd = descs[blk0 + blockIdx.z];
+  const int nu = blockIdx.x * 256 + threadIdx.x;
+  if (nu >= bd.nmu) return;
+  const int64_t total = static_cast<int64_t>(bd.nomega) * bd.groups;
+  for (int64_t gi = blockIdx.y; gi < total; gi += gridDim.y) {
+    const int i = static_cast<int>(gi / bd.groups);
+    const int g = static_cast<int>(gi - static_cast<int64_t>(i) * bd.groups);
+    float2 x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int mu = 4 * g + e;
+      double2 v = {0.0, 0.0};
+      if (mu < bd.nmu) v = bd.wc[(static_cast<int64_t>(i) * bd.nmu + mu) * bd.nmu + nu];
+      x[e] = float2{static_cast<float>(v.x), static_cast<float>(v.y)};
+    }
+    uint4 hi, lo;
+    split_chunk(x, hi, lo);
+    const size_t off = (static_cast<size_t>(gi) * bd.nmu + nu) * 16;
+    *reinterpret_cast<uint4*>(static_cast<char*>(bd.wsp) + off) = hi;
+    *reinterpret_cast<uint4*>(static_cast<char*>(bd.wsp) + bd.wsp_plane + off) = lo;
+  }
+}
+
+__global__ __launch_bounds__(256) void sigc_split_z_kernel(const SigcDesc* __restrict__ descs, int blk0) {
+#pragma clang fp contract(off)
+  const SigcDesc bd = descs[blk0 + blockIdx.z];
+  const int64_t M = static_cast<int64_t>(bd.nall) * bd.nqp;
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  const int64_t a = r / bd.nqp;
+  const int64_t n = r - a * bd.nqp;
+  const double2* zr = bd.z + a * bd.nmu * bd.nqp + n;
+  for (int g = blockIdx.y; g < bd.groups; g += gridDim.y) {
+    float2 x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int mu = 4 * g + e;
+      double2 v = {0.0, 0.0};
+      if (mu < bd.nmu) v = zr[static_cast<int64_t>(mu) * bd.nqp];
+      x[e] = float2{static_cast<float>(v.x), static_cast<float>(v.y)};
+    }
+    uint4 hi, lo;
+    split_chunk(x, hi, lo);
+    const size_t off = (static_cast<size_t>(g) * M + r) * 16;
+    *reinterpret_cast<uint4*>(static_cast<char*>(bd.zsp) + off) = hi;
+    *reinterpret_cast<uint4*>(static_cast<char*>(bd.zsp) + bd.zsp_plane + off) = lo;
+  }
+}
+
 }  // namespace
+
+hipError_t sigc_presplit_launch(const SigcDesc* descs, int nblocks, int max_nmu, int64_t max_m,
+                                int max_groups_w, int max_groups_z, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  for (int b0 = 0; b0 < nblocks; b0 += 65535) {
+    const int nb = nblocks - b0 < 65535 ? nblocks - b0 : 65535;
+    const unsigned gyw = static_cast<unsigned>(max_groups_w < 4096 ? max_groups_w : 4096);
+    hipLaunchKernelGGL(sigc_split_w_kernel, dim3((max_nmu + 255) / 256, gyw, nb), dim3(256), 0, s, descs, b0);
+    const unsigned gyz = static_cast<unsigned>(max_groups_z < 64 ? max_groups_z : 64);
+    hipLaunchKernelGGL(sigc_split_z_kernel, dim3(static_cast<unsigned>((max_m + 255) / 256), gyz, nb),
+                       dim3(256), 0, s, descs, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 hipError_t presplit_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
                            int64_t max_groups, int max_npb, hipStream_t s) {

@@ -1,8 +1,9 @@
 """GPU parity of the imaginary-axis correlation self-energy (Eq.(sigci),
-sigc_accumulate, FP64 path) against the CPU oracle: the integration weights
-alone, ragged multi-tile sizes, several problems and blocks, workspace
-grouping, both kernel variants, accumulate mode, degenerate cases, and the
-full-size workload on sampled entries."""
+sigc_accumulate, FP64 and BF16x3 paths) against the CPU oracle: the
+integration weights alone, ragged multi-tile sizes, several problems and
+blocks, workspace grouping, both FP64 kernel variants, accumulate mode,
+degenerate cases, and the full-size workload on sampled entries; the BF16x3
+path also against the numpy split model."""
 import sys
 
 import numpy as np
@@ -11,6 +12,7 @@ import torch
 
 from oracle.sigc_oracle import ag_weights, sigc_entries, sigc_ref
 from gpu_common import need_gpu, rel_fro
+from splitmodel import sigc_model
 from paper_2506_03477_amd import Context, SigcBlock, SigcProblem
 from synth import workload
 from synth.gpu import device_sigc_workload, wc_block_device
@@ -41,7 +43,7 @@ def _rand_block(rng, nall, nmu, nqp, nom):
     return z, wc
 
 
-def _run(ctx, problems, accumulate=False):
+def _run(ctx, problems, accumulate=False, precision="fp64"):
     """problems: list of (blocks [(z, wc, eps_mid, wk)], eps_qp, mesh) in numpy;
     returns the GPU outputs as numpy."""
     dev = []
@@ -50,7 +52,7 @@ def _run(ctx, problems, accumulate=False):
               for z, wc, em, wk in blocks]
         out = torch.zeros((len(eps_qp), len(eps_qp)), dtype=torch.complex128, device="cuda")
         dev.append(SigcProblem(bl, np.asarray(eps_qp), np.asarray(mesh), out))
-    ctx.sigc_accumulate(dev, accumulate=accumulate)
+    ctx.sigc_accumulate(dev, accumulate=accumulate, precision=precision)
     torch.cuda.synchronize()
     return dev, [p.sigc.cpu().numpy() for p in dev]
 
@@ -235,3 +237,51 @@ def test_full_size_sampled(ctx):
     _say(f"  sampled rel error {e:.2e}; |I| max {np.abs(got_full).max():.3e}")
     assert e < TOL
     assert np.all(np.isfinite(got_full))
+
+
+# BF16x3 first contraction.  Every operand keeps 16 significant bits (hi + lo
+# of its FP32 value), so a product carries a random relative error of about
+# 4e-6; the entries of Z_w^H W^c and of I^c are sums of terms of both signs,
+# which keep that relative error instead of averaging it down (unlike the
+# positive diagonal of chi0).  Bound against the oracle: 8e-6 relative
+# Frobenius.  Against the split model (exact products, FP64 sums) only the
+# FP32 runs of at most 4096 rows mu differ: relative u sqrt(run) ~ 4e-6 at
+# most, bound 4e-6.
+BF16_TOL = 8e-6
+BF16_MODEL_TOL = 4e-6
+
+
+@pytest.mark.parametrize("case", CASES[:3] + [(96, [(4, 520)], 3, 0.0)])
+def test_bf16x3_parity(ctx, case):
+    nqp, shapes, nom, w0 = case
+    _say(f"sigc bf16x3 nqp={nqp} blocks={shapes} nomega={nom}")
+    rng = np.random.default_rng(nqp * 11 + nom)
+    mesh = np.cumsum(np.concatenate([[w0], rng.uniform(0.1, 1.5, nom - 1)]))
+    eps_qp = np.sort(rng.uniform(-0.8, 2.0, nqp))
+    blocks = []
+    for nall, nmu in shapes:
+        z, wc = _rand_block(rng, nall, nmu, nqp, nom)
+        blocks.append((z, wc, np.sort(rng.uniform(-0.8, 3.0, nall)), float(rng.uniform(0.1, 1.0))))
+    ref = sigc_ref(blocks, eps_qp, mesh)
+    model = sigc_model(blocks, eps_qp, mesh)
+    _, (out,) = _run(ctx, [(blocks, eps_qp, mesh)], precision="bf16x3")
+    e, em = rel_fro(out, ref), rel_fro(out, model)
+    _say(f"  vs oracle {e:.2e}, vs split model {em:.2e}, model vs oracle {rel_fro(model, ref):.2e}")
+    assert e < BF16_TOL and em < BF16_MODEL_TOL
+
+
+def test_bf16x3_reduced_workload(ctx):
+    wl = workload(6).replace(npb=150, nocc=24, nunocc=260, nk=3, nval=8)
+    blks, eps_qp = device_sigc_workload(wl)
+    out = torch.empty((wl.npb, wl.npb), dtype=torch.complex128, device="cuda")
+    prob = SigcProblem([SigcBlock(z, wc, em, wk) for z, wc, em, wk, _ in blks], eps_qp,
+                       wl.omega_array(), out)
+    ctx.sigc_accumulate([prob], precision="bf16x3")
+    torch.cuda.synchronize()
+    cpu = [(wl.z_block(b).astype(np.complex128), wl.wc_block(b), wl.eps_mid(b), b.wk) for b in wl.blocks()]
+    ref = sigc_ref(cpu, wl.eps_qp(), wl.omega)
+    model = sigc_model(cpu, wl.eps_qp(), wl.omega)
+    got = out.cpu().numpy()
+    e, em = rel_fro(got, ref), rel_fro(got, model)
+    _say(f"reduced workload bf16x3: vs oracle {e:.2e}, vs model {em:.2e}")
+    assert e < BF16_TOL and em < BF16_MODEL_TOL
