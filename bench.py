@@ -400,7 +400,7 @@ def bench_sigc(args):
         "dtype": "f64" if prec == "fp64" else "bf16x3", "data": "synthetic",
         "config": {"workload": wl.name, "nqp": wl.npb, "nk": wl.nk, "nall": wl.nocc,
                    "nmu": wl.nunocc, "nomega": wl.nomega, "path": prec,
-                   "variant": args.tile if args.tile >= 0 else 0},
+                   "variant": args.tile if args.tile >= 0 else 1},
         "flops_first": first, "flops_second": second,
         "roofline": roof, "cpu_baseline": cpu}), flush=True)
     ctx.close()

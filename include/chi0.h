@@ -277,8 +277,9 @@ int sigc_accumulate(chi0_handle h, const sigc_problem* probs, int32_t nprob,
                     chi0_ztype zt, chi0_precision prec, uint32_t flags,
                     void* hip_stream);
 
-/* Kernel variant of the first contraction (0: 4 waves of 64 x 64 per
- * 128 x 128 tile, 1: 8 waves of 64 x 32); CHI0_EINVAL when out of range. */
+/* Kernel variant of the FP64 first contraction (0: 4 waves of 64 x 64 per
+ * 128 x 128 tile, 1: 8 waves of 64 x 32, the default); CHI0_EINVAL when out
+ * of range. */
 int sigc_set_variant(chi0_handle h, int32_t variant);
 
 /* Cap in bytes of the ZW workspace of one group of blocks (0: the default,

@@ -113,7 +113,7 @@ struct chi0_ctx {
   std::string gather_key;
   int64_t hist_records = 0;           // records kept by the last histogram call
   int32_t hist_bins_used = 0;         // non-empty bins of the last histogram call
-  int sigc_variant = 0;
+  int sigc_variant = 1;
   int64_t sigc_zw_cap = int64_t(4) << 30;
   uint64_t ws_gen = 1;
   int32_t* d_status = nullptr;

@@ -1138,35 +1138,72 @@ __global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
       *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(ql[gi]);
     }
   };
-  // D rows nu and columns r of this lane's accumulators, into zw, times t_i(r)
-  auto flush = [&](int i, bool first) {
+  // Add t times the accumulators of column block j (columns r of this lane,
+  // all its rows nu) into zw; plain stores until the column was written.
+  bool written[2] = {false, false};
+  auto flush_col = [&](int j, double t, int64_t col) {
     const int g = lane >> 5;
-    const int cl = lane & 31;
+    const int64_t a2 = col / nqp;
+    double2* dst = bd.zw + a2 * nmu * nqp + (col - a2 * nqp);
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = u.tp * TP + wr * 128 + bi * 32 + 4 * g + 8 * (r >> 2) + (r & 3);
+        if (row >= nmu) continue;
+        double2* p = dst + static_cast<int64_t>(row) * nqp;
+        const double vr = t * static_cast<double>(cr[bi][j][r]);
+        const double vi = t * static_cast<double>(ci[bi][j][r]);
+        if (!written[j]) {
+          *p = double2{vr, vi};
+        } else {
+          const double2 o = *p;
+          *p = double2{o.x + vr, o.y + vi};
+        }
+      }
+      // one 32 x 32 block at a time: keeps the in-flight FP64 values few
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    written[j] = true;
+  };
+  auto zero_col = [&](int j) {
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      cr[bi][j] = f32x16{0};
+      ci[bi][j] = f32x16{0};
+    }
+  };
+  // The accumulators hold sum_{i' <= i} (t_i' / t_i) D_i' for the current
+  // FP32 run; at the end of a run they are multiplied by t_i and added.
+  auto flush = [&](int i) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int64_t col = static_cast<int64_t>(u.tc) * TQ + wc * 64 + j * 32 + cl;
+      const int64_t col = static_cast<int64_t>(u.tc) * TQ + wc * 64 + j * 32 + (lane & 31);
+      if (col < M) flush_col(j, bd.wt[static_cast<int64_t>(i) * M + col], col);
+    }
+    zero();
+  };
+  // Between mesh points i and i + 1 inside a run: multiply by t_i / t_(i+1)
+  // instead of flushing; a column whose ratio is not a moderate finite number
+  // (t_(i+1) = 0, or an extreme ratio) is flushed with t_i and restarted.
+  auto rescale = [&](int i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t col = static_cast<int64_t>(u.tc) * TQ + wc * 64 + j * 32 + (lane & 31);
       if (col >= M) continue;
-      const double t = bd.wt[static_cast<int64_t>(i) * M + col];
-      const int64_t a2 = col / nqp;
-      double2* dst = bd.zw + a2 * nmu * nqp + (col - a2 * nqp);
+      const double ti = bd.wt[static_cast<int64_t>(i) * M + col];
+      const double tn = bd.wt[static_cast<int64_t>(i + 1) * M + col];
+      const double ratio = ti / tn;
+      if (tn != 0.0 && fabs(ratio) < 1e30 && fabs(ratio) > 1e-30) {
+        const float f = static_cast<float>(ratio);
 #pragma unroll
-      for (int bi = 0; bi < 4; ++bi) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = u.tp * TP + wr * 128 + bi * 32 + 4 * g + 8 * (r >> 2) + (r & 3);
-          if (row >= nmu) continue;
-          double2* p = dst + static_cast<int64_t>(row) * nqp;
-          const double vr = t * static_cast<double>(cr[bi][j][r]);
-          const double vi = t * static_cast<double>(ci[bi][j][r]);
-          if (first) {
-            *p = double2{vr, vi};
-          } else {
-            const double2 o = *p;
-            *p = double2{o.x + vr, o.y + vi};
-          }
+        for (int bi = 0; bi < 4; ++bi) {
+          cr[bi][j] *= f;
+          ci[bi][j] *= f;
         }
-        // one 32 x 32 block at a time: keeps the in-flight FP64 values few
-        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        flush_col(j, ti, col);
+        zero_col(j);
       }
     }
   };
@@ -1175,23 +1212,27 @@ __global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
   stage(0);
   __syncthreads();
   int buf = 0, st = 0;
-  bool first = true;
-  // runs of stages of one mesh point (at most FL stages); the stage loop
-  // itself carries no flush code
+  // FP32 runs of at most FL stages (4096 rows mu); a run spans several mesh
+  // points, rescaled at their boundaries; the stage loop carries no flush or
+  // rescale code
   while (st < total) {
-    const int i = st / ns;
-    const int seg_end = (i + 1) * ns < st + FL ? (i + 1) * ns : st + FL;
-    for (; st < seg_end; ++st) {
-      const bool more = st + 1 < total;
-      if (more) load(st + 1);
-      tall_mfma<false, 4>(L, buf, wr, wc, g8, l32, cr, ci);
-      if (more) stage(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+    const int run_end = st + FL < total ? st + FL : total;
+    int i = st / ns;
+    while (true) {
+      const int seg_end = (i + 1) * ns < run_end ? (i + 1) * ns : run_end;
+      for (; st < seg_end; ++st) {
+        const bool more = st + 1 < total;
+        if (more) load(st + 1);
+        tall_mfma<false, 4>(L, buf, wr, wc, g8, l32, cr, ci);
+        if (more) stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
+      if (st == run_end) break;
+      rescale(i);
+      ++i;
     }
-    flush(i, first);
-    first = false;
-    zero();
+    flush(i);
   }
 }
 

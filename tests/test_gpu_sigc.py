@@ -117,7 +117,7 @@ def test_parity_random(ctx, case):
         _say(f"  variant {variant}: rel Frobenius error {e:.2e}")
         assert e < TOL
         assert np.max(np.abs(out - ref)) <= TOL * np.max(np.abs(ref))
-    ctx.sigc_set_variant(0)
+    ctx.sigc_set_variant(1)
 
 
 def test_several_problems_grouping_and_accumulate(ctx):
@@ -285,3 +285,29 @@ def test_bf16x3_reduced_workload(ctx):
     e, em = rel_fro(got, ref), rel_fro(got, model)
     _say(f"reduced workload bf16x3: vs oracle {e:.2e}, vs model {em:.2e}")
     assert e < BF16_TOL and em < BF16_MODEL_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_zero_and_tiny_energy_differences(ctx, precision):
+    """Energy differences exactly 0 (all weights 0) and 1e-300 (weights of
+    very different sizes) next to ordinary ones: the BF16x3 kernel carries
+    its FP32 runs across mesh points by rescaling with weight ratios and must
+    fall back to flushing where a ratio is 0, infinite or extreme."""
+    rng = np.random.default_rng(41)
+    nqp, nom = 70, 5
+    mesh = np.array([0.0, 0.2, 0.7, 2.0, 9.0])
+    z, wc = _rand_block(rng, 4, 180, nqp, nom)
+    eps_mid = np.array([0.0, 0.4, -0.3, 1.1])
+    eps_qp = np.sort(rng.uniform(-0.8, 2.0, nqp))
+    eps_qp[3] = 0.4                      # dE = 0 against n' = 1
+    eps_qp[5] = 1e-300                   # dE = 1e-300 against n' = 0
+    eps_qp[6] = -1e-300
+    blocks = [(z, wc, eps_mid, 0.5)]
+    ref = sigc_ref(blocks, eps_qp, mesh)
+    _, (out,) = _run(ctx, [(blocks, eps_qp, mesh)], precision=precision)
+    e = rel_fro(out, ref)
+    tol = TOL if precision == "fp64" else BF16_TOL
+    _say(f"zero / tiny dE, {precision}: {e:.2e}")
+    assert e < tol
+    if precision == "bf16x3":
+        assert rel_fro(out, sigc_model(blocks, eps_qp, mesh)) < BF16_MODEL_TOL
