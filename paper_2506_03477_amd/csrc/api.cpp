@@ -1200,9 +1200,11 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
     const int64_t groups = presplit_groups(bl.nmu);
     const int64_t sbytes =
         bf16 ? 2 * static_cast<int64_t>(align256(static_cast<size_t>(pr.nomega) * groups * bl.nmu * 16)) +
-                   2 * static_cast<int64_t>(align256(static_cast<size_t>(groups) * bl.nall * pr.nqp * 16))
+                   2 * static_cast<int64_t>(
+                           align256(static_cast<size_t>(pr.nomega) * groups * bl.nall * pr.nqp * 16))
              : 0;
-    if (cur > 0 && cur + bytes > h->sigc_zw_cap) {
+    // the split planes (weighted Z per mesh point) are held to four times the cap
+    if (cur > 0 && (cur + bytes > h->sigc_zw_cap || sp_cur + sbytes > 4 * h->sigc_zw_cap)) {
       chunk0.push_back(i);
       cur = 0;
       sp_cur = 0;
@@ -1378,7 +1380,8 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
     if (bf16) {
       char* base = static_cast<char*>(h->sigc_split.p) + sp_off[i];
       d.wsp_plane = static_cast<int64_t>(align256(static_cast<size_t>(pr.nomega) * d.groups * bl.nmu * 16));
-      d.zsp_plane = static_cast<int64_t>(align256(static_cast<size_t>(d.groups) * bl.nall * pr.nqp * 16));
+      d.zsp_plane = static_cast<int64_t>(
+          align256(static_cast<size_t>(pr.nomega) * d.groups * bl.nall * pr.nqp * 16));
       d.wsp = base;
       d.zsp = base + 2 * d.wsp_plane;
     }

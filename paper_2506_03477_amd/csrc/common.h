@@ -107,8 +107,9 @@ struct SigcDesc {
   int32_t prob, groups;   // groups: 4-row groups of mu, padded to 16-row stages
   // BF16x3 first contraction: hi planes of W^c (per mesh point i: group g of
   // 4 rows mu, column nu at ((i * groups + g) * nmu + nu) * 16 bytes) and of
-  // Z (group g, column r = n' * nqp + n at (g * nall * nqp + r) * 16 bytes);
-  // each lo plane follows its hi plane at + *_plane bytes.
+  // the weighted Z, t_i(r) Z[mu][r] (per mesh point i: group g, column
+  // r = n' * nqp + n at ((i * groups + g) * nall * nqp + r) * 16 bytes); each
+  // lo plane follows its hi plane at + *_plane bytes.
   void* wsp;
   int64_t wsp_plane;
   void* zsp;

@@ -1050,12 +1050,12 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
 // Correlation self-energy (Eq.(sigci)), first contraction on the BF16x3 path:
 //   D[nu][r] = sum_i t_i(r) sum_mu conj(W_i[mu][nu]) Z[n'][mu][n],
 // r = (n', n), t = -w_k w_i(eps_qn - eps_n').  Both operands arrive pre-split
-// (sigc_split_w_kernel, sigc_split_z_kernel), so staging is a copy (plus the
-// 16-bit rotation of the Z side for the imaginary part); tiles are 256 nu x
-// 128 r with the tall kernels' LDS layout and MFMA core.  The weight depends
-// on (i, r) only, so the FP32 accumulators of one mesh point are multiplied
-// by t_i(r) in FP64 when they are flushed into the FP64 output zw[n'][nu][n]
-// (at the end of every mesh point, and every 4096 rows mu at most).
+// (sigc_split_w_kernel, sigc_split_z_kernel), the Z side already multiplied by
+// t_i(r) for every mesh point, so staging is a copy (plus the 16-bit rotation
+// of the Z side for the imaginary part) and the rows (i, mu) form one
+// contraction; tiles are 256 nu x 128 r with the tall kernels' LDS layout and
+// MFMA core.  The FP32 accumulators are flushed into the FP64 output
+// zw[n'][nu][n] every 4096 rows at most.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
   typedef const char __attribute__((address_space(1)))* gcptr;
@@ -1094,7 +1094,7 @@ __global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
   const gcptr zh = (gcptr)bd.zsp;
 
   f32x16 cr[4][2], ci[4][2];
-  auto zero = [&]() {
+  auto zero = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -1106,10 +1106,11 @@ __global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
   zero();
   uint4 ph[4], pl[4], qh[2], ql[2];
 
-  auto load = [&](int st) {
+  auto load = [&](int st) __attribute__((always_inline)) {
     const int i = st / ns;
     const int g0 = 4 * (st - i * ns);
-    const gcptr wb = wh + (static_cast<uint64_t>(i) * bd.groups + g0) * chunkP + offP;
+    const uint64_t gi = static_cast<uint64_t>(i) * bd.groups + g0;
+    const gcptr wb = wh + gi * chunkP + offP;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const u32x4 h = *(gu4ptr)(wb + q * chunkP);
@@ -1117,17 +1118,17 @@ __global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
       ph[q] = uint4{h.x, h.y, h.z, h.w};
       pl[q] = uint4{l.x, l.y, l.z, l.w};
     }
-    const gcptr zb = zh + static_cast<uint64_t>(g0) * chunkQ + offQ;
+    const gcptr zb = zh + gi * chunkQ + offQ;
 #pragma unroll
-    for (int gi = 0; gi < 2; ++gi) {
-      const uint64_t o = static_cast<uint64_t>(lg + 2 * gi) * chunkQ;
+    for (int gi2 = 0; gi2 < 2; ++gi2) {
+      const uint64_t o = static_cast<uint64_t>(lg + 2 * gi2) * chunkQ;
       const u32x4 h = *(gu4ptr)(zb + o);
       const u32x4 l = *(gu4ptr)(zb + bd.zsp_plane + o);
-      qh[gi] = uint4{h.x, h.y, h.z, h.w};
-      ql[gi] = uint4{l.x, l.y, l.z, l.w};
+      qh[gi2] = uint4{h.x, h.y, h.z, h.w};
+      ql[gi2] = uint4{l.x, l.y, l.z, l.w};
     }
   };
-  auto stage = [&](int buf) {
+  auto stage = [&](int buf) __attribute__((always_inline)) {
     tall_stage_p(L, buf, lp, ph, pl);
 #pragma unroll
     for (int gi = 0; gi < 2; ++gi) {
@@ -1138,101 +1139,77 @@ __global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
       *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(ql[gi]);
     }
   };
-  // Add t times the accumulators of column block j (columns r of this lane,
-  // all its rows nu) into zw; plain stores until the column was written.
-  bool written[2] = {false, false};
-  auto flush_col = [&](int j, double t, int64_t col) {
+  // Add the accumulators (columns r of this lane, all its rows nu) into zw in
+  // FP64; plain stores for the unit's first flush.  A block of 32 rows that
+  // lies inside nmu (the rule) takes no per-row test, so its 16 reads are in
+  // flight together.
+  auto flush = [&](bool first) {
     const int g = lane >> 5;
-    const int64_t a2 = col / nqp;
-    double2* dst = bd.zw + a2 * nmu * nqp + (col - a2 * nqp);
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = u.tp * TP + wr * 128 + bi * 32 + 4 * g + 8 * (r >> 2) + (r & 3);
-        if (row >= nmu) continue;
-        double2* p = dst + static_cast<int64_t>(row) * nqp;
-        const double vr = t * static_cast<double>(cr[bi][j][r]);
-        const double vi = t * static_cast<double>(ci[bi][j][r]);
-        if (!written[j]) {
-          *p = double2{vr, vi};
-        } else {
-          const double2 o = *p;
-          *p = double2{o.x + vr, o.y + vi};
-        }
-      }
-      // one 32 x 32 block at a time: keeps the in-flight FP64 values few
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    written[j] = true;
-  };
-  auto zero_col = [&](int j) {
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-      cr[bi][j] = f32x16{0};
-      ci[bi][j] = f32x16{0};
-    }
-  };
-  // The accumulators hold sum_{i' <= i} (t_i' / t_i) D_i' for the current
-  // FP32 run; at the end of a run they are multiplied by t_i and added.
-  auto flush = [&](int i) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t col = static_cast<int64_t>(u.tc) * TQ + wc * 64 + j * 32 + (lane & 31);
-      if (col < M) flush_col(j, bd.wt[static_cast<int64_t>(i) * M + col], col);
-    }
-    zero();
-  };
-  // Between mesh points i and i + 1 inside a run: multiply by t_i / t_(i+1)
-  // instead of flushing; a column whose ratio is not a moderate finite number
-  // (t_(i+1) = 0, or an extreme ratio) is flushed with t_i and restarted.
-  auto rescale = [&](int i) {
+    const int64_t rstride = nqp;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t col = static_cast<int64_t>(u.tc) * TQ + wc * 64 + j * 32 + (lane & 31);
       if (col >= M) continue;
-      const double ti = bd.wt[static_cast<int64_t>(i) * M + col];
-      const double tn = bd.wt[static_cast<int64_t>(i + 1) * M + col];
-      const double ratio = ti / tn;
-      if (tn != 0.0 && fabs(ratio) < 1e30 && fabs(ratio) > 1e-30) {
-        const float f = static_cast<float>(ratio);
+      const int64_t a2 = col / nqp;
+      double2* dst = bd.zw + a2 * nmu * nqp + (col - a2 * nqp);
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi) {
-          cr[bi][j] *= f;
-          ci[bi][j] *= f;
+      for (int bi = 0; bi < 4; ++bi) {
+        const int rb = u.tp * TP + wr * 128 + bi * 32;   // wave-uniform
+        double2* p0 = dst + static_cast<int64_t>(rb + 4 * g) * rstride;
+        if (rb + 32 <= nmu) {
+          double2 o[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            o[r] = double2{0.0, 0.0};
+            if (!first) o[r] = p0[(8 * (r >> 2) + (r & 3)) * rstride];
+          }
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            p0[(8 * (r >> 2) + (r & 3)) * rstride] = double2{o[r].x + static_cast<double>(cr[bi][j][r]),
+                                                             o[r].y + static_cast<double>(ci[bi][j][r])};
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            if (rb + 4 * g + 8 * (r >> 2) + (r & 3) >= nmu) continue;
+            double2* p = p0 + (8 * (r >> 2) + (r & 3)) * rstride;
+            const double vr = static_cast<double>(cr[bi][j][r]);
+            const double vi = static_cast<double>(ci[bi][j][r]);
+            if (first) {
+              *p = double2{vr, vi};
+            } else {
+              const double2 o = *p;
+              *p = double2{o.x + vr, o.y + vi};
+            }
+          }
         }
-      } else {
-        flush_col(j, ti, col);
-        zero_col(j);
+        // one 32 x 32 block at a time: keeps the in-flight FP64 values few
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
+    zero();
   };
 
   load(0);
   stage(0);
   __syncthreads();
   int buf = 0, st = 0;
-  // FP32 runs of at most FL stages (4096 rows mu); a run spans several mesh
-  // points, rescaled at their boundaries; the stage loop carries no flush or
-  // rescale code
+  bool first = true;
+  // The weights are folded into Z, so the stages of all mesh points form one
+  // sum, taken in FP32 runs of at most FL stages (4096 rows mu) that are added
+  // into zw in FP64.
   while (st < total) {
-    const int run_end = st + FL < total ? st + FL : total;
-    int i = st / ns;
-    while (true) {
-      const int seg_end = (i + 1) * ns < run_end ? (i + 1) * ns : run_end;
-      for (; st < seg_end; ++st) {
-        const bool more = st + 1 < total;
-        if (more) load(st + 1);
-        tall_mfma<false, 4>(L, buf, wr, wc, g8, l32, cr, ci);
-        if (more) stage(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-      }
-      if (st == run_end) break;
-      rescale(i);
-      ++i;
+    st = __builtin_amdgcn_readfirstlane(st);
+    const int run_end = __builtin_amdgcn_readfirstlane(st + FL < total ? st + FL : total);
+    for (; st < run_end; ++st) {
+      const bool more = st + 1 < total;
+      if (more) load(st + 1);
+      tall_mfma<false, 4>(L, buf, wr, wc, g8, l32, cr, ci);
+      if (more) stage(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
     }
-    flush(i);
+    flush(first);
+    first = false;
   }
 }
 

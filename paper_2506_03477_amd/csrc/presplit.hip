@@ -70,9 +70,9 @@ __device__ __forceinline__ void split_chunk(const float2 (&x)[4], uint4& hi, uin
 }
 
 // Correlation self-energy, BF16x3 first contraction: W^c of every mesh point
-// (rows mu, columns nu) and Z (rows mu, columns r = (n', n)) of one block
-// (blockIdx.z) rounded to FP32 and split into the planes SigcDesc describes;
-// rows beyond nmu are zero.
+// (rows mu, columns nu) and the weighted Z of every mesh point (rows mu,
+// columns r = (n', n)) of one block (blockIdx.z) rounded to FP32 and split
+// into the planes SigcDesc describes; rows beyond nmu are zero.
 __global__ __launch_bounds__(256) void sigc_split_w_kernel(const SigcDesc* __restrict__ descs, int blk0) {
 #pragma clang fp contract(off)
   const SigcDesc bd = descs[blk0 + blockIdx.z];
@@ -98,6 +98,9 @@ __global__ __launch_bounds__(256) void sigc_split_w_kernel(const SigcDesc* __res
   }
 }
 
+// Z scaled by the weight of each mesh point: the plane of mesh point i holds
+// t_i(r) Z[mu][r] (product in FP64, rounded to FP32, split), so the first
+// contraction sums every mesh point into one FP32 accumulator.
 __global__ __launch_bounds__(256) void sigc_split_z_kernel(const SigcDesc* __restrict__ descs, int blk0) {
 #pragma clang fp contract(off)
   const SigcDesc bd = descs[blk0 + blockIdx.z];
@@ -108,19 +111,23 @@ __global__ __launch_bounds__(256) void sigc_split_z_kernel(const SigcDesc* __res
   const int64_t n = r - a * bd.nqp;
   const double2* zr = bd.z + a * bd.nmu * bd.nqp + n;
   for (int g = blockIdx.y; g < bd.groups; g += gridDim.y) {
-    float2 x[4];
+    double2 v[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int mu = 4 * g + e;
-      double2 v = {0.0, 0.0};
-      if (mu < bd.nmu) v = zr[static_cast<int64_t>(mu) * bd.nqp];
-      x[e] = float2{static_cast<float>(v.x), static_cast<float>(v.y)};
+      v[e] = mu < bd.nmu ? zr[static_cast<int64_t>(mu) * bd.nqp] : double2{0.0, 0.0};
     }
-    uint4 hi, lo;
-    split_chunk(x, hi, lo);
-    const size_t off = (static_cast<size_t>(g) * M + r) * 16;
-    *reinterpret_cast<uint4*>(static_cast<char*>(bd.zsp) + off) = hi;
-    *reinterpret_cast<uint4*>(static_cast<char*>(bd.zsp) + bd.zsp_plane + off) = lo;
+    for (int i = 0; i < bd.nomega; ++i) {
+      const double t = bd.wt[static_cast<int64_t>(i) * M + r];
+      float2 x[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = float2{static_cast<float>(t * v[e].x), static_cast<float>(t * v[e].y)};
+      uint4 hi, lo;
+      split_chunk(x, hi, lo);
+      const size_t off = ((static_cast<size_t>(i) * bd.groups + g) * M + r) * 16;
+      *reinterpret_cast<uint4*>(static_cast<char*>(bd.zsp) + off) = hi;
+      *reinterpret_cast<uint4*>(static_cast<char*>(bd.zsp) + bd.zsp_plane + off) = lo;
+    }
   }
 }
 
