@@ -122,29 +122,32 @@ def hist_model(blocks, npb, edges, sigma, delta_min=0.0, path="bf16x3", lolo=Fal
 
 
 def sigc_model(blocks, eps_qp, mesh):
-    """I^c with the BF16x3 first contraction as the GPU runs it: W^c and Z
-    rounded to FP32 and split into bf16 hi / lo, three split products per
-    real product summed exactly (FP64) over mu for each mesh point, the
-    integration weight applied afterwards in FP64, the second contraction in
-    FP64.  blocks: (Z [nall, nmu, nqp], W^c [nomega, nmu, nmu], eps_mid, wk)."""
+    """I^c with the BF16x3 first contraction as the GPU runs it: W^c rounded
+    to FP32 and split into bf16 hi / lo; Z multiplied by the integration
+    weight of its column and mesh point in FP64, rounded to FP32 and split;
+    three split products per real product summed exactly (FP64) over all
+    (mesh point, mu) rows; the second contraction in FP64.
+    blocks: (Z [nall, nmu, nqp], W^c [nomega, nmu, nmu], eps_mid, wk)."""
     from oracle.sigc_oracle import ag_weight_table
     nqp = len(eps_qp)
     out = np.zeros((nqp, nqp), np.complex128)
     for z, wc, eps_mid, wk in blocks:
         z = np.asarray(z, np.complex128)
         wc = np.asarray(wc, np.complex128)
-        t = -float(wk) * ag_weight_table(eps_qp, eps_mid, mesh)        # [n', n, i]
-        zr32, zi32 = z.real.astype(np.float32), z.imag.astype(np.float32)
-        (zrh, zrl), (zih, zil) = split(zr32), split(zi32)
+        t = -float(wk) * ag_weight_table(eps_qp, eps_mid, mesh)       # [n', n, i]
+        wsplit = []
+        for i in range(wc.shape[0]):
+            wr32, wi32 = wc[i].real.astype(np.float32), wc[i].imag.astype(np.float32)
+            wsplit.append((split(wr32), split(wi32)))
         for a in range(z.shape[0]):
             zw = np.zeros((wc.shape[1], nqp), np.complex128)           # D[nu][n]
             for i in range(wc.shape[0]):
-                wr32, wi32 = wc[i].real.astype(np.float32), wc[i].imag.astype(np.float32)
-                (wrh, wrl), (wih, wil) = split(wr32), split(wi32)
-                d = np.zeros_like(zw)
-                for (pr, pi), (qr, qi) in (((wrh, wih), (zrh[a], zih[a])), ((wrh, wih), (zrl[a], zil[a])),
-                                           ((wrl, wil), (zrh[a], zih[a]))):
-                    d += (pr.T @ qr + pi.T @ qi) + 1j * (pr.T @ qi - pi.T @ qr)
-                zw += d * t[a, :, i][None, :]
+                (wrh, wrl), (wih, wil) = wsplit[i]
+                ti = t[a, :, i][None, :]
+                (zrh, zrl) = split((z[a].real * ti).astype(np.float32))
+                (zih, zil) = split((z[a].imag * ti).astype(np.float32))
+                for (pr, pi), (qr, qi) in (((wrh, wih), (zrh, zih)), ((wrh, wih), (zrl, zil)),
+                                           ((wrl, wil), (zrh, zih))):
+                    zw += (pr.T @ qr + pi.T @ qi) + 1j * (pr.T @ qi - pi.T @ qr)
             out += np.conj(zw).T @ z[a]
     return out

@@ -244,9 +244,9 @@ def test_full_size_sampled(ctx):
 # 4e-6; the entries of Z_w^H W^c and of I^c are sums of terms of both signs,
 # which keep that relative error instead of averaging it down (unlike the
 # positive diagonal of chi0).  Bound against the oracle: 8e-6 relative
-# Frobenius.  Against the split model (exact products, FP64 sums) only the
-# FP32 runs of at most 4096 rows mu differ: relative u sqrt(run) ~ 4e-6 at
-# most, bound 4e-6.
+# Frobenius.  Against the split model (the kernel's roundings, exact products,
+# FP64 sums) only the FP32 runs of at most 4096 rows (mesh point, mu) differ:
+# relative u sqrt(run) ~ 4e-6 at most, bound 4e-6.
 BF16_TOL = 8e-6
 BF16_MODEL_TOL = 4e-6
 
@@ -290,9 +290,10 @@ def test_bf16x3_reduced_workload(ctx):
 @pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
 def test_zero_and_tiny_energy_differences(ctx, precision):
     """Energy differences exactly 0 (all weights 0) and 1e-300 (weights of
-    very different sizes) next to ordinary ones: the BF16x3 kernel carries
-    its FP32 runs across mesh points by rescaling with weight ratios and must
-    fall back to flushing where a ratio is 0, infinite or extreme."""
+    very different sizes) next to ordinary ones: the BF16x3 path multiplies
+    Z by the weights before rounding it to FP32, where products with a
+    weight of 1e-300 become 0 (terms far below the tolerance), and sums all
+    mesh points in one run."""
     rng = np.random.default_rng(41)
     nqp, nom = 70, 5
     mesh = np.array([0.0, 0.2, 0.7, 2.0, 9.0])
