@@ -22,9 +22,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
-KERNEL_SOURCE = {"fp64": "paper_2506_03477_amd/csrc/herk_fp64.hip",
-                 "fp32": "paper_2506_03477_amd/csrc/herk_lowp.hip",
-                 "bf16x3": "paper_2506_03477_amd/csrc/herk_lowp.hip"}
+# sources of each rank-K kernel (the traffic counters are valid while these are unchanged)
+_LOWP = ("paper_2506_03477_amd/csrc/herk_lowp.hip", "paper_2506_03477_amd/csrc/bf16_tall.h",
+         "paper_2506_03477_amd/csrc/herk_common.h")
+KERNEL_SOURCE = {"fp64": ("paper_2506_03477_amd/csrc/herk_fp64.hip", "paper_2506_03477_amd/csrc/herk_common.h"),
+                 "fp32": _LOWP, "bf16x3": _LOWP}
 KERNEL_NAME = {"fp64": "herk_fp64", "fp32": "herk_fp32", "bf16x3": "herk_bf16x3"}
 CALIB_BYTES = 1 << 30   # plain device copy used to calibrate the byte counters
 MFMA_DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}
@@ -102,8 +104,11 @@ def cpu_baseline(wl, target_s=15.0):
 
 def source_sha(prec):
     import hashlib
-    with open(os.path.join(ROOT, KERNEL_SOURCE[prec]), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCE[prec]:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_file(prec, workload_name):

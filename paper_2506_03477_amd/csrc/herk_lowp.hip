@@ -27,19 +27,12 @@
 // workgroup adds its FP32 accumulators into its FP64 partial tile in global
 // memory every `flush` pairs (per problem) and at the end of the unit, so no FP32 sum runs
 // over more than `flush` pairs.
+#include "bf16_tall.h"
 #include "common.h"
 #include "herk_common.h"
 
 namespace chi0 {
 namespace {
-
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-
-constexpr int kKC = 16;   // pairs per stage
-
-constexpr int kNT = 256;  // threads
 
 // Z is read through a global-address-space pointer (global_load rather than
 // flat_load); one complex64 = one 64-bit word.
@@ -96,47 +89,6 @@ __device__ __forceinline__ uint32_t load_pairs(const HerkArgs& a, const ProbDesc
     rw[k] = ld_const(w, oc);
   }
   return mask;
-}
-
-// LDS row = tile column (0..T-1), 16 dwords = 4 chunks of 4 pairs; chunk q of
-// row r lives at slot q ^ g(r), g(r) = (r1 ^ r3) + 2 r2 (r_i = bit i of r).
-// A 16-byte access of consecutive rows (same q) then hits distinct banks
-// within every 8 lanes for 32 banks (8 rows span 128 bytes) and within every
-// 16 lanes for 64 banks, so the fragment reads and the staging writes are
-// conflict-free with either bank count.
-__device__ __forceinline__ int swz(int row, int q) {
-  const int g = (((row >> 1) ^ (row >> 3)) & 1) | (((row >> 2) & 1) << 1);
-  return row * 16 + 4 * (q ^ g);
-}
-
-__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
-  bf16x2 v;
-  v[0] = static_cast<__bf16>(lo);
-  v[1] = static_cast<__bf16>(hi);
-  return __builtin_bit_cast(uint32_t, v);
-}
-
-__device__ __forceinline__ float bf16_lo_to_f32(uint32_t p) { return __uint_as_float(p << 16); }
-__device__ __forceinline__ float bf16_hi_to_f32(uint32_t p) { return __uint_as_float(p & 0xFFFF0000u); }
-
-// (x_re, x_im) -> packed hi and lo bf16x2 words (re in the low half).
-__device__ __forceinline__ void split2(float re, float im, uint32_t& hi, uint32_t& lo) {
-  // no contraction: re, im are the FP32-rounded operands (for the scaled
-  // side, the rounded product), and x - hi is exact in FP32
-#pragma clang fp contract(off)
-  hi = pack_bf16x2(re, im);
-  lo = pack_bf16x2(re - bf16_lo_to_f32(hi), im - bf16_hi_to_f32(hi));
-}
-
-// (br, bi) packed -> (bi, -br) packed.
-__device__ __forceinline__ uint32_t rot_neg(uint32_t x) {
-  return __builtin_amdgcn_alignbit(x, x, 16) ^ 0x80000000u;
-}
-
-__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
-
-__device__ __forceinline__ uint4 rot_neg4(uint4 v) {
-  return uint4{rot_neg(v.x), rot_neg(v.y), rot_neg(v.z), rot_neg(v.w)};
 }
 
 // Add (or store, when first) the (T/2) x (T/2) wave tile of FP32 accumulators
@@ -481,15 +433,6 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
 // 128 x 64 sub-tile (4 x 2 blocks, 256 FP32 accumulators per lane) does 48
 // MFMAs per 16 fragment reads.
 // ---------------------------------------------------------------------------
-struct Bf16TallLds {
-  uint32_t ah[2][256 * 16];
-  uint32_t al[2][256 * 16];
-  uint32_t bh[2][128 * 16];
-  uint32_t bl[2][128 * 16];
-  uint32_t bih[2][128 * 16];
-  uint32_t bil[2][128 * 16];
-};
-
 // Q-side loads of one stage: column offQ of the 8 pairs 4 (lg + 2 gi) + e,
 // and their weights (wave-uniform rows, see load_pairs).
 template <bool GATHER>
@@ -546,16 +489,6 @@ __device__ __forceinline__ void tall_load_p(const HerkArgs& a, const Cursor& c, 
   }
 }
 
-__device__ __forceinline__ void tall_stage_p(Bf16TallLds& L, int buf, int lp, const uint4 (&ph)[4],
-                                             const uint4 (&pl)[4]) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int o = swz(lp, q);
-    *reinterpret_cast<uint4*>(&L.ah[buf][o]) = ph[q];
-    *reinterpret_cast<uint4*>(&L.al[buf][o]) = pl[q];
-  }
-}
-
 // Q side of one stage into LDS buffer `buf`: column lq, pair chunks lg and
 // lg + 2, scaled (0 for a missing pair), split and rotated.
 __device__ __forceinline__ void tall_stage_q(Bf16TallLds& L, int buf, int lq, int lg,
@@ -577,62 +510,6 @@ __device__ __forceinline__ void tall_stage_q(Bf16TallLds& L, int buf, int lq, in
     *reinterpret_cast<uint4*>(&L.bl[buf][o]) = vl;
     *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(vh);
     *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(vl);
-  }
-}
-
-// The 2 k-steps of one stage for a wave's (32 NBI) x 64 sub-tile at P rows
-// 32 NBI wr and Q columns 64 wc.
-template <bool LOLO, int NBI = 4>
-__device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr, int wc, int g8,
-                                          int l32, f32x16 (&cr)[NBI][2], f32x16 (&ci)[NBI][2]) {
-#pragma unroll
-  for (int ks = 0; ks < 2; ++ks) {
-    const int q = 2 * ks + g8;
-    bf16x8 fah[NBI], fal[NBI], fbh[2], fbl[2], fih[2], fil[2];
-#pragma unroll
-    for (int i = 0; i < NBI; ++i) {
-      const int row = wr * (32 * NBI) + i * 32 + l32;
-      fah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.ah[buf][swz(row, q)]));
-      fal[i] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.al[buf][swz(row, q)]));
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int row = wc * 64 + j * 32 + l32;
-      fbh[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bh[buf][swz(row, q)]));
-      fbl[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bl[buf][swz(row, q)]));
-      fih[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bih[buf][swz(row, q)]));
-      fil[j] = as_bf16x8(*reinterpret_cast<const uint4*>(&L.bil[buf][swz(row, q)]));
-    }
-#pragma unroll
-    for (int i = 0; i < NBI; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbh[j], cr[i][j], 0, 0, 0);
-        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fih[j], ci[i][j], 0, 0, 0);
-      }
-#pragma unroll
-    for (int i = 0; i < NBI; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fbl[j], cr[i][j], 0, 0, 0);
-        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[i], fil[j], ci[i][j], 0, 0, 0);
-      }
-#pragma unroll
-    for (int i = 0; i < NBI; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbh[j], cr[i][j], 0, 0, 0);
-        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fih[j], ci[i][j], 0, 0, 0);
-      }
-    if (LOLO) {
-#pragma unroll
-      for (int i = 0; i < NBI; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fbl[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[i], fil[j], ci[i][j], 0, 0, 0);
-        }
-    }
   }
 }
 
@@ -1045,174 +922,6 @@ __global__ __launch_bounds__(kNT, 1) void herk_fp32_kernel(HerkArgs a) {
   }
 }
 
-
-// ---------------------------------------------------------------------------
-// Correlation self-energy (Eq.(sigci)), first contraction on the BF16x3 path:
-//   D[nu][r] = sum_i t_i(r) sum_mu conj(W_i[mu][nu]) Z[n'][mu][n],
-// r = (n', n), t = -w_k w_i(eps_qn - eps_n').  Both operands arrive pre-split
-// (sigc_split_w_kernel, sigc_split_z_kernel), the Z side already multiplied by
-// t_i(r) for every mesh point, so staging is a copy (plus the 16-bit rotation
-// of the Z side for the imaginary part) and the rows (i, mu) form one
-// contraction; tiles are 256 nu x 128 r with the tall kernels' LDS layout and
-// MFMA core.  The FP32 accumulators are flushed into the FP64 output
-// zw[n'][nu][n] every 4096 rows at most.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
-  typedef const char __attribute__((address_space(1)))* gcptr;
-  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  typedef const u32x4 __attribute__((address_space(1)))* gu4ptr;
-  constexpr int TP = 256, TQ = 128, FL = 256;   // FL: stages between flushes at most
-  __shared__ __attribute__((aligned(16))) Bf16TallLds L;
-
-  const int per = (args.nunits + 7) / 8;
-  const int lu = static_cast<int>(blockIdx.x % 8) * per + static_cast<int>(blockIdx.x / 8);
-  if (lu >= args.nunits) return;
-  const SigcUnit u = args.units[lu];
-  const SigcDesc bd = args.descs[u.blk];
-  const int nmu = bd.nmu, nqp = bd.nqp;
-  const int64_t M = static_cast<int64_t>(bd.nall) * nqp;
-  const int ns = bd.groups / 4;                  // 16-row stages per mesh point
-  const int total = bd.nomega * ns;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int g8 = lane >> 5;
-  const int l32 = lane & 31;
-  const int lp = tid;
-  const int lq = tid & (TQ - 1);
-  const int lg = tid >> 7;
-
-  const int pcol = u.tp * TP + lp;
-  const int64_t qcol = static_cast<int64_t>(u.tc) * TQ + lq;
-  const uint64_t offP = static_cast<uint64_t>(pcol < nmu ? pcol : 0) * 16u;
-  const uint64_t offQ = static_cast<uint64_t>(qcol < M ? qcol : 0) * 16u;
-  const uint64_t chunkP = static_cast<uint64_t>(nmu) * 16u;   // one group of W rows
-  const uint64_t chunkQ = static_cast<uint64_t>(M) * 16u;     // one group of Z rows
-  const gcptr wh = (gcptr)bd.wsp;
-  const gcptr zh = (gcptr)bd.zsp;
-
-  f32x16 cr[4][2], ci[4][2];
-  auto zero = [&]() __attribute__((always_inline)) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        cr[i][j] = f32x16{0};
-        ci[i][j] = f32x16{0};
-      }
-  };
-  zero();
-  uint4 ph[4], pl[4], qh[2], ql[2];
-
-  auto load = [&](int st) __attribute__((always_inline)) {
-    const int i = st / ns;
-    const int g0 = 4 * (st - i * ns);
-    const uint64_t gi = static_cast<uint64_t>(i) * bd.groups + g0;
-    const gcptr wb = wh + gi * chunkP + offP;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const u32x4 h = *(gu4ptr)(wb + q * chunkP);
-      const u32x4 l = *(gu4ptr)(wb + bd.wsp_plane + q * chunkP);
-      ph[q] = uint4{h.x, h.y, h.z, h.w};
-      pl[q] = uint4{l.x, l.y, l.z, l.w};
-    }
-    const gcptr zb = zh + gi * chunkQ + offQ;
-#pragma unroll
-    for (int gi2 = 0; gi2 < 2; ++gi2) {
-      const uint64_t o = static_cast<uint64_t>(lg + 2 * gi2) * chunkQ;
-      const u32x4 h = *(gu4ptr)(zb + o);
-      const u32x4 l = *(gu4ptr)(zb + bd.zsp_plane + o);
-      qh[gi2] = uint4{h.x, h.y, h.z, h.w};
-      ql[gi2] = uint4{l.x, l.y, l.z, l.w};
-    }
-  };
-  auto stage = [&](int buf) __attribute__((always_inline)) {
-    tall_stage_p(L, buf, lp, ph, pl);
-#pragma unroll
-    for (int gi = 0; gi < 2; ++gi) {
-      const int o = swz(lq, lg + 2 * gi);
-      *reinterpret_cast<uint4*>(&L.bh[buf][o]) = qh[gi];
-      *reinterpret_cast<uint4*>(&L.bl[buf][o]) = ql[gi];
-      *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(qh[gi]);
-      *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(ql[gi]);
-    }
-  };
-  // Add the accumulators (columns r of this lane, all its rows nu) into zw in
-  // FP64; plain stores for the unit's first flush.  A block of 32 rows that
-  // lies inside nmu (the rule) takes no per-row test, so its 16 reads are in
-  // flight together.
-  auto flush = [&](bool first) {
-    const int g = lane >> 5;
-    const int64_t rstride = nqp;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t col = static_cast<int64_t>(u.tc) * TQ + wc * 64 + j * 32 + (lane & 31);
-      if (col >= M) continue;
-      const int64_t a2 = col / nqp;
-      double2* dst = bd.zw + a2 * nmu * nqp + (col - a2 * nqp);
-#pragma unroll
-      for (int bi = 0; bi < 4; ++bi) {
-        const int rb = u.tp * TP + wr * 128 + bi * 32;   // wave-uniform
-        double2* p0 = dst + static_cast<int64_t>(rb + 4 * g) * rstride;
-        if (rb + 32 <= nmu) {
-          double2 o[16];
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            o[r] = double2{0.0, 0.0};
-            if (!first) o[r] = p0[(8 * (r >> 2) + (r & 3)) * rstride];
-          }
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            p0[(8 * (r >> 2) + (r & 3)) * rstride] = double2{o[r].x + static_cast<double>(cr[bi][j][r]),
-                                                             o[r].y + static_cast<double>(ci[bi][j][r])};
-        } else {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            if (rb + 4 * g + 8 * (r >> 2) + (r & 3) >= nmu) continue;
-            double2* p = p0 + (8 * (r >> 2) + (r & 3)) * rstride;
-            const double vr = static_cast<double>(cr[bi][j][r]);
-            const double vi = static_cast<double>(ci[bi][j][r]);
-            if (first) {
-              *p = double2{vr, vi};
-            } else {
-              const double2 o = *p;
-              *p = double2{o.x + vr, o.y + vi};
-            }
-          }
-        }
-        // one 32 x 32 block at a time: keeps the in-flight FP64 values few
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    zero();
-  };
-
-  load(0);
-  stage(0);
-  __syncthreads();
-  int buf = 0, st = 0;
-  bool first = true;
-  // The weights are folded into Z, so the stages of all mesh points form one
-  // sum, taken in FP32 runs of at most FL stages (4096 rows mu) that are added
-  // into zw in FP64.
-  while (st < total) {
-    st = __builtin_amdgcn_readfirstlane(st);
-    const int run_end = __builtin_amdgcn_readfirstlane(st + FL < total ? st + FL : total);
-    for (; st < run_end; ++st) {
-      const bool more = st + 1 < total;
-      if (more) load(st + 1);
-      tall_mfma<false, 4>(L, buf, wr, wc, g8, l32, cr, ci);
-      if (more) stage(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
-    }
-    flush(first);
-    first = false;
-  }
-}
-
 }  // namespace
 
 // Tile tables: {tile, pairs per stage, cap of the FP32 run length (pairs),
@@ -1232,13 +941,6 @@ static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
     {64, kKC, 4096, kNT, 64},
 };
-
-hipError_t sigc_bf16x3_launch(const SigcArgs& a, hipStream_t s) {
-  if (a.nunits <= 0) return hipSuccess;
-  const unsigned grid = static_cast<unsigned>((a.nunits + 7) / 8 * 8);
-  hipLaunchKernelGGL(sigc_bf16x3_kernel, dim3(grid), dim3(kNT), 0, s, a);
-  return hipGetLastError();
-}
 
 int herk_bf16x3_tile_count() { return sizeof(kBf16Tiles) / sizeof(kBf16Tiles[0]); }
 TileConfig herk_bf16x3_tile(int idx) { return kBf16Tiles[idx]; }
