@@ -103,11 +103,17 @@ def cpu_baseline(wl, target_s=15.0):
 
 
 def source_sha(prec):
+    """Hash of the kernel's sources with comments and blank space removed, so
+    the stored counters stay valid across comment-only edits."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for path in KERNEL_SOURCE[prec]:
-        with open(os.path.join(ROOT, path), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, path), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -427,9 +427,9 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_pipe_kernel(HerkArgs a) {
 // ---------------------------------------------------------------------------
 // Tall tiles: 256 (P) x 128 (Q), P side pre-split.  The Q side (scaled and
 // split per frequency) is shared by twice as many P rows as in a square
-// tile, and the P side arrives already split (presplit.hip) and goes from
-// memory straight into LDS (global_load_lds, no registers, no vector ALU),
-// so the only staging arithmetic left is the Q side's.  Each wave's
+// tile, and the P side arrives already split (presplit.hip): its 16-byte
+// chunks are copied to LDS through registers without arithmetic, so the only
+// staging arithmetic left is the Q side's.  Each wave's
 // 128 x 64 sub-tile (4 x 2 blocks, 256 FP32 accumulators per lane) does 48
 // MFMAs per 16 fragment reads.
 // ---------------------------------------------------------------------------
