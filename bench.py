@@ -269,7 +269,7 @@ def bench_sigx(args):
     kern_ms, n = ctx.profile_read()
     kern_avg = kern_ms / n if n else None
     flops = zherk_flops(wl.npb, rows, 1)
-    tinfo = ctx.tile_info(prec, ctx.get_tile(prec))
+    tinfo = ctx.tile_info(prec, ctx.last_tile(prec))
     roof = None
     if kern_avg:
         ach = flops / (kern_avg * 1e-3) / 1e12
@@ -653,7 +653,7 @@ def main():
     total_ms = ev[0].elapsed_time(ev[1])
     kern_ms, nlaunch = ctx.profile_read()
     ms_per_step = total_ms / args.steps
-    tinfo = ctx.tile_info(prec, ctx.get_tile(prec))
+    tinfo = ctx.tile_info(prec, ctx.last_tile(prec))
     tile = tinfo["tile_p"]
 
     flops = zherk_flops(wl.npb, npairs, wl.nomega)
@@ -696,7 +696,7 @@ def main():
              "ms_per_q_inverse_gj": inv_ms["gj"], "ms_per_q_inverse_hpd": inv_ms["hpd"],
              "ms_per_q_chi0_plus_inverse": round(ms_per_step / wl.nq, 3),
              "nq_per_step": wl.nq, "tile": [tinfo["tile_p"], tinfo["tile_q"]],
-             "tile_index": ctx.get_tile(prec), "npairs": npairs}
+             "tile_index": ctx.last_tile(prec), "npairs": npairs}
     if wl.paths and "fp64" in wl.paths and prec != "fp64" and not args.no_fp64_compare:
         log("FP64 comparison: generating complex128 inputs")
         del probs, blks

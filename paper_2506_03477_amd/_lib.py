@@ -114,6 +114,7 @@ def load() -> ctypes.CDLL:
         "chi0_set_tile": (c_int, [vp, c_int, c_int32]),
         "chi0_set_flush": (c_int, [vp, c_int32]),
         "chi0_get_tile": (c_int, [vp, c_int, POINTER(c_int32)]),
+        "chi0_last_tile": (c_int, [vp, c_int, POINTER(c_int32)]),
         "chi0_autotune": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
                                   c_int32, POINTER(c_int32), POINTER(c_double), vp]),
         "chi0_plan_inspect": (c_int, [POINTER(chi0_problem), c_int32, c_int, c_int32, c_int32,
@@ -486,6 +487,13 @@ class Context:
     def get_tile(self, precision: str) -> int:
         t = c_int32()
         _check(self._lib.chi0_get_tile(self._h, PREC[precision], byref(t)))
+        return t.value
+
+    def last_tile(self, precision: str) -> int:
+        """Configuration of this handle's last rank-K launch at `precision`
+        (-1 before the first)."""
+        t = c_int32(-1)
+        _check(self._lib.chi0_last_tile(self._h, PREC[precision], byref(t)))
         return t.value
 
     def autotune(self, problems: Sequence[Problem], precision: str, delta_min: float = 0.0,

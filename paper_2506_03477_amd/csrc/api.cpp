@@ -124,6 +124,7 @@ struct chi0_ctx {
   std::unordered_map<std::string, std::unique_ptr<Plan>> plans;
   int tile_sel[3] = {-1, -1, -1};
   int tile_tuned[3] = {-1, -1, -1};
+  int tile_last[3] = {-1, -1, -1};   // configuration of the last rank-K launch
   int flush_override = 0;
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
@@ -583,6 +584,49 @@ struct GatherHook {
   const int64_t* off;
 };
 
+// BF16x3 configuration for a call with no tile fixed or tuned.  Modeled time
+// of a candidate: rows x padded lower-triangle tile area x frequencies x a
+// per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
+// it.  Costs relative to the tall kernel, fitted to MI355X timings at npb 287
+// and 2048: tall 256 x 128 (7) 1.0, 128^2 with two workgroups per CU (4) 1.12,
+// 64^2 (2) 1.70; the pre-split pass 144 per row and column.  A smaller tile
+// replaces the tall default only when modeled at least 15% faster (small npb,
+// where tall tiles are mostly padding).
+int bf16_tile_for(const chi0_problem* probs, int nprob) {
+  struct Cand {
+    int idx;
+    double cost;
+  };
+  const Cand cands[] = {{7, 1.0}, {4, 1.12}, {2, 1.70}};
+  const int ndef = herk_default_tile(HERK_BF16X3);
+  double def_time = -1.0, best_time = -1.0;
+  int best = ndef;
+  for (const Cand& c : cands) {
+    if (c.idx >= herk_tile_count(HERK_BF16X3)) continue;
+    const TileConfig tc = herk_tile_config(HERK_BF16X3, c.idx);
+    const int TP = tc.tile, TQ = tc.tile_q;
+    double t = 0.0;
+    for (int p = 0; p < nprob; ++p) {
+      double rows = 0.0;
+      for (int b = 0; b < probs[p].nblocks; ++b)
+        rows += static_cast<double>(probs[p].blocks[b].nocc) * probs[p].blocks[b].nunocc;
+      const int npb = probs[p].npb;
+      const int ntp = (npb + TP - 1) / TP, ntq = (npb + TQ - 1) / TQ;
+      double area = 0.0;
+      for (int tp = 0; tp < ntp; ++tp)
+        area += static_cast<double>(std::min(ntq, (tp * TP + TP - 1) / TQ + 1)) * TP * TQ;
+      t += rows * area * std::max(1, probs[p].nomega) * c.cost;
+      if (tc.presplit) t += rows * npb * 144.0;
+    }
+    if (c.idx == ndef) def_time = t;
+    if (best_time < 0.0 || t < best_time) {
+      best_time = t;
+      best = c.idx;
+    }
+  }
+  return def_time >= 0.0 && best != ndef && best_time >= 0.85 * def_time ? ndef : best;
+}
+
 int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_precision prec,
                    double delta_min, uint32_t flags, hipStream_t stream, int tile_override,
                    int mode = kWeightsChi0, const GatherHook* hk = nullptr) {
@@ -591,11 +635,14 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this build", prec);
   int tile_idx = tile_override >= 0 ? tile_override
                  : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
-                 : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind] : herk_default_tile(kind);
+                 : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind]
+                 : kind == HERK_BF16X3 && !hk ? bf16_tile_for(probs, nprob)
+                                              : herk_default_tile(kind);
   if (tile_idx >= ntile) tile_idx = 0;
   if (hk && !herk_tile_gathers(kind, tile_idx)) tile_idx = herk_default_tile(kind);
   if (hk && !herk_tile_gathers(kind, tile_idx))
     return fail(CHI0_EUNSUPPORTED, "precision %d has no gathering kernel", prec);
+  h->tile_last[kind] = tile_idx;
   int wg_per_cu = std::max(1, herk_max_wg_per_cu(kind, tile_idx));
   const int nwg = h->ncu * wg_per_cu;
   const std::string key = plan_key(kind, tile_idx, nwg, probs, nprob);
@@ -1770,6 +1817,14 @@ int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile) {
   if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
   *tile = h->tile_sel[k] >= 0 ? h->tile_sel[k] : h->tile_tuned[k] >= 0 ? h->tile_tuned[k]
                                                                          : herk_default_tile(k);
+  return CHI0_OK;
+}
+
+int chi0_last_tile(chi0_handle h, chi0_precision prec, int32_t* tile) {
+  if (!h || !tile) return fail(CHI0_EINVAL, "NULL argument");
+  const int k = kind_of(prec);
+  if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
+  *tile = h->tile_last[k];
   return CHI0_OK;
 }
 

@@ -69,3 +69,31 @@ def test_batched_graph_and_autotune(batch):
     ref = oracle_chi0(wl, q=3)
     assert np.all(rel_fro(probs[3].chi0.cpu().numpy(), ref) <= 1e-6)
     ctx.close()
+
+
+def test_bf16_default_tile_follows_size(batch):
+    """With no tile fixed or tuned, BF16x3 picks its configuration per call
+    from the padded tile area: at npb 384 the 256 x 128 tall tiles would be
+    mostly padding, so a square tile of at most 128 is chosen; a fixed tile
+    still wins, and both give the oracle's chi0."""
+    wl, probs = batch
+    _say("bf16x3 default tile at npb 384")
+    ctx = Context(0)
+    assert ctx.last_tile("bf16x3") == -1
+    sub = probs[:4]
+    ctx.chi0_accumulate(sub, precision="bf16x3", delta_min=wl.delta_min)
+    ctx.sync()
+    auto = ctx.last_tile("bf16x3")
+    info = ctx.tile_info("bf16x3", auto)
+    _say(f"  chosen tile {auto}: {info}")
+    assert info["tile_p"] <= 128 and info["tile_q"] <= 128
+    got_auto = sub[0].chi0.cpu().numpy()
+    ctx.set_tile("bf16x3", 7)
+    ctx.chi0_accumulate(sub, precision="bf16x3", delta_min=wl.delta_min)
+    ctx.sync()
+    assert ctx.last_tile("bf16x3") == 7
+    ref = oracle_chi0(wl, q=0)
+    e_auto, e_tall = rel_fro(got_auto, ref).max(), rel_fro(sub[0].chi0.cpu().numpy(), ref).max()
+    _say(f"  rel err: chosen {e_auto:.3e}, tall {e_tall:.3e}")
+    assert e_auto <= 2e-6 and e_tall <= 2e-6
+    ctx.close()
