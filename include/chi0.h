@@ -325,11 +325,12 @@ const char* chi0_last_error(void);
  * length before an FP64 flush; 0 for FP64).  chi0_set_tile() fixes the
  * configuration used for a precision (-1 = the autotuned or built-in
  * default).  chi0_get_tile() reports the fixed, else the autotuned, else the
- * built-in default configuration.  With none fixed or tuned, BF16X3 calls
- * that do not gather rows choose per call by a cost model of the padded tile
- * area (the 256 x 128 tall tiles for large npb, smaller square tiles when
- * npb is a few hundred); chi0_last_tile() reports the configuration of the
- * handle's last rank-K launch for a precision (-1 before the first). */
+ * built-in default configuration.  With none fixed or tuned, BF16X3 and FP64
+ * calls that do not gather rows choose per call by a cost model of the
+ * padded tile area (the large default tiles for large npb, smaller square
+ * tiles when npb is a few hundred); chi0_last_tile() reports the
+ * configuration of the handle's last rank-K launch for a precision (-1
+ * before the first). */
 int chi0_tile_count(chi0_precision prec);
 int chi0_tile_info(chi0_precision prec, int32_t tile, int32_t* tile_p,
                    int32_t* tile_q, int32_t* kchunk, int32_t* flush_len);

@@ -584,26 +584,31 @@ struct GatherHook {
   const int64_t* off;
 };
 
-// BF16x3 configuration for a call with no tile fixed or tuned.  Modeled time
-// of a candidate: rows x padded lower-triangle tile area x frequencies x a
+// Configuration for a call with no tile fixed or tuned.  Modeled time of a
+// candidate: rows x padded lower-triangle tile area x frequencies x a
 // per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
-// it.  Costs relative to the tall kernel, fitted to MI355X timings at npb 287
-// and 2048: tall 256 x 128 (7) 1.0, 128^2 with two workgroups per CU (4) 1.12,
-// 64^2 (2) 1.70; the pre-split pass 144 per row and column.  A smaller tile
-// replaces the tall default only when modeled at least 15% faster (small npb,
-// where tall tiles are mostly padding).
-int bf16_tile_for(const chi0_problem* probs, int nprob) {
+// it.  Costs relative to the built-in default, fitted to MI355X timings at
+// npb 287 and 2048: BF16x3 tall 256 x 128 (7) 1.0, 128^2 with two workgroups
+// per CU (4) 1.12, 64^2 (2) 1.70, the pre-split pass 144 per row and column;
+// FP64 128^2 with 8 waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42.  A smaller
+// tile replaces the default only when modeled at least 15% faster (npb of a
+// few hundred, where the large tiles are mostly padding).
+int tile_for(int kind, const chi0_problem* probs, int nprob) {
   struct Cand {
     int idx;
     double cost;
   };
-  const Cand cands[] = {{7, 1.0}, {4, 1.12}, {2, 1.70}};
-  const int ndef = herk_default_tile(HERK_BF16X3);
+  static const Cand bf16[] = {{7, 1.0}, {4, 1.12}, {2, 1.70}};
+  static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
+  const int ndef = herk_default_tile(kind);
+  const Cand* cands = kind == HERK_BF16X3 ? bf16 : kind == HERK_FP64 ? fp64 : nullptr;
+  if (!cands) return ndef;
   double def_time = -1.0, best_time = -1.0;
   int best = ndef;
-  for (const Cand& c : cands) {
-    if (c.idx >= herk_tile_count(HERK_BF16X3)) continue;
-    const TileConfig tc = herk_tile_config(HERK_BF16X3, c.idx);
+  for (int ci = 0; ci < 3; ++ci) {
+    const Cand& c = cands[ci];
+    if (c.idx >= herk_tile_count(kind)) continue;
+    const TileConfig tc = herk_tile_config(kind, c.idx);
     const int TP = tc.tile, TQ = tc.tile_q;
     double t = 0.0;
     for (int p = 0; p < nprob; ++p) {
@@ -636,8 +641,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   int tile_idx = tile_override >= 0 ? tile_override
                  : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
                  : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind]
-                 : kind == HERK_BF16X3 && !hk ? bf16_tile_for(probs, nprob)
-                                              : herk_default_tile(kind);
+                 : !hk ? tile_for(kind, probs, nprob) : herk_default_tile(kind);
   if (tile_idx >= ntile) tile_idx = 0;
   if (hk && !herk_tile_gathers(kind, tile_idx)) tile_idx = herk_default_tile(kind);
   if (hk && !herk_tile_gathers(kind, tile_idx))
