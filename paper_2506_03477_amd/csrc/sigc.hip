@@ -359,7 +359,7 @@ hipError_t sigc_zw_launch(int variant, const SigcArgs& a, hipStream_t s) {
 hipError_t sigc_zwz_launch(const SigcArgs& a, hipStream_t s) {
   if (a.nunits <= 0) return hipSuccess;
   const unsigned grid = static_cast<unsigned>((a.nunits + 7) / 8 * 8);
-  hipLaunchKernelGGL((sigc_gemm_kernel<false, 4>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((sigc_gemm_kernel<false, 8>), dim3(grid), dim3(512), 0, s, a);
   return hipGetLastError();
 }
 
