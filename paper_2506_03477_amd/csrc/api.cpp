@@ -1252,7 +1252,10 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
     const int64_t sbytes =
         bf16 ? 2 * static_cast<int64_t>(align256(static_cast<size_t>(pr.nomega) * groups * bl.nmu * 16)) +
                    2 * static_cast<int64_t>(
-                           align256(static_cast<size_t>(pr.nomega) * groups * bl.nall * pr.nqp * 16))
+                           align256(static_cast<size_t>(pr.nomega) * groups * bl.nall * pr.nqp * 16)) +
+                   4 * static_cast<int64_t>(align256(
+                           static_cast<size_t>(presplit_groups(static_cast<int64_t>(bl.nall) * bl.nmu)) *
+                           pr.nqp * 16))
              : 0;
     // the split planes (weighted Z per mesh point) are held to four times the cap
     if (cur > 0 && (cur + bytes > h->sigc_zw_cap || sp_cur + sbytes > 4 * h->sigc_zw_cap)) {
@@ -1316,11 +1319,25 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
       const int tq = (pr.nqp + T - 1) / T;
       rows_tiles += static_cast<int64_t>(bl.nall) * bl.nmu * tq * tq;
     }
-    // segment length: about four second-contraction units per CU
+    // segment length: about four second-contraction units per CU; BF16x3
+    // units are 256 x 128 tiles and one FP32 run each (a multiple of 16 rows,
+    // at most 4096)
     const int64_t target = std::max<int64_t>(1, 4LL * h->ncu);
-    int64_t seg = (rows_tiles + target - 1) / target;
-    seg = std::max<int64_t>(64, (seg + 7) / 8 * 8);
-    seg = std::min<int64_t>(seg, 0x40000000LL);
+    int64_t seg;
+    if (bf16) {
+      int64_t rt = 0;
+      for (int i = chunk0[c]; i < chunk0[c + 1]; ++i) {
+        const sigc_problem& pr = probs[refs[i].prob];
+        const sigc_block& bl = pr.blocks[refs[i].blk];
+        rt += static_cast<int64_t>(bl.nall) * bl.nmu * ((pr.nqp + 255) / 256) * ((pr.nqp + T - 1) / T);
+      }
+      seg = (rt + target - 1) / target;
+      seg = std::min<int64_t>(4096, std::max<int64_t>(256, (seg + 15) / 16 * 16));
+    } else {
+      seg = (rows_tiles + target - 1) / target;
+      seg = std::max<int64_t>(64, (seg + 7) / 8 * 8);
+      seg = std::min<int64_t>(seg, 0x40000000LL);
+    }
     t.seg_len = static_cast<int>(seg);
     // units ordered (block, segment, tile) so the tiles of one segment are
     // adjacent; jobs per (problem, tile) list their slots in unit order
@@ -1334,23 +1351,40 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
       const int64_t K = static_cast<int64_t>(bl.nall) * bl.nmu;
       const int nseg = static_cast<int>((K + seg - 1) / seg);
       const int tq = (pr.nqp + T - 1) / T;
-      for (int sg = 0; sg < nseg; ++sg)
-        for (int tp = 0; tp < tq; ++tp)
-          for (int tc = 0; tc < tq; ++tc) {
-            const int64_t key = (static_cast<int64_t>(p) * tq + tp) * tq + tc;
-            auto it = key_index.find(key);
-            int k;
-            if (it == key_index.end()) {
-              k = static_cast<int>(tile_slots.size());
-              key_index.emplace(key, k);
-              tile_slots.emplace_back();
-              tile_key.push_back({p, tp, tc});
-            } else {
-              k = it->second;
+      auto add_slot = [&](int tp, int tc, int32_t slot) {
+        const int64_t key = (static_cast<int64_t>(p) * tq + tp) * tq + tc;
+        auto it = key_index.find(key);
+        int k;
+        if (it == key_index.end()) {
+          k = static_cast<int>(tile_slots.size());
+          key_index.emplace(key, k);
+          tile_slots.emplace_back();
+          tile_key.push_back({p, tp, tc});
+        } else {
+          k = it->second;
+        }
+        tile_slots[k].push_back(slot);
+      };
+      if (bf16) {
+        // unit (block, 256-row tile tp2, column tile tc, segment): partial
+        // tiles 2 unit (rows 256 tp2 ..) and 2 unit + 1 (rows 256 tp2 + 128 ..)
+        const int tp2n = (pr.nqp + 255) / 256;
+        for (int sg = 0; sg < nseg; ++sg)
+          for (int tp2 = 0; tp2 < tp2n; ++tp2)
+            for (int tc = 0; tc < tq; ++tc) {
+              const int32_t un = static_cast<int32_t>(t.u2.size());
+              for (int h2 = 0; h2 < 2; ++h2)
+                if (2 * tp2 + h2 < tq) add_slot(2 * tp2 + h2, tc, 2 * un + h2);
+              t.u2.push_back({i, tp2, tc, sg});
             }
-            tile_slots[k].push_back(static_cast<int32_t>(t.u2.size()));
-            t.u2.push_back({i, tp, tc, sg});
-          }
+      } else {
+        for (int sg = 0; sg < nseg; ++sg)
+          for (int tp = 0; tp < tq; ++tp)
+            for (int tc = 0; tc < tq; ++tc) {
+              add_slot(tp, tc, static_cast<int32_t>(t.u2.size()));
+              t.u2.push_back({i, tp, tc, sg});
+            }
+      }
     }
     for (size_t k = 0; k < tile_slots.size(); ++k) {
       SigcJob j;
@@ -1363,7 +1397,7 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
       t.slots.insert(t.slots.end(), tile_slots[k].begin(), tile_slots[k].end());
       t.jobs.push_back(j);
     }
-    max_part_units = std::max(max_part_units, t.u2.size());
+    max_part_units = std::max(max_part_units, (bf16 ? 2 : 1) * t.u2.size());
   }
 
   // workspace
@@ -1428,6 +1462,11 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
     d.wsp_plane = 0;
     d.zsp = nullptr;
     d.zsp_plane = 0;
+    d.zwsp = nullptr;
+    d.zksp = nullptr;
+    d.k_plane = 0;
+    d.kgroups = static_cast<int32_t>(presplit_groups(static_cast<int64_t>(bl.nall) * bl.nmu));
+    d.pad2 = 0;
     if (bf16) {
       char* base = static_cast<char*>(h->sigc_split.p) + sp_off[i];
       d.wsp_plane = static_cast<int64_t>(align256(static_cast<size_t>(pr.nomega) * d.groups * bl.nmu * 16));
@@ -1435,6 +1474,9 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
           align256(static_cast<size_t>(pr.nomega) * d.groups * bl.nall * pr.nqp * 16));
       d.wsp = base;
       d.zsp = base + 2 * d.wsp_plane;
+      d.k_plane = static_cast<int64_t>(align256(static_cast<size_t>(d.kgroups) * pr.nqp * 16));
+      d.zwsp = static_cast<char*>(d.zsp) + 2 * d.zsp_plane;
+      d.zksp = static_cast<char*>(d.zwsp) + 2 * d.k_plane;
     }
   }
   std::vector<SigcProb> ptab(nprob);
@@ -1478,17 +1520,22 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
       e0 = get_event(h);
       e1 = get_event(h);
     }
+    int max_kg = 0;
     if (bf16) {
       int max_nmu = 0, max_gw = 0, max_gz = 0;
       int64_t max_m = 0;
+      max_kg = 0;
       for (int i = chunk0[c]; i < chunk0[c + 1]; ++i) {
         max_nmu = std::max(max_nmu, descs[i].nmu);
         max_gw = std::max(max_gw, descs[i].nomega * descs[i].groups);
         max_gz = std::max(max_gz, descs[i].groups);
+        max_kg = std::max(max_kg, descs[i].kgroups);
         max_m = std::max<int64_t>(max_m, static_cast<int64_t>(descs[i].nall) * descs[i].nqp);
       }
       e = sigc_presplit_launch(d_desc + chunk0[c], chunk0[c + 1] - chunk0[c], max_nmu, max_m, max_gw, max_gz,
                                stream);
+      if (e == hipSuccess) e = sigc_split_rows_launch(d_desc + chunk0[c], chunk0[c + 1] - chunk0[c], 1, max_nqp,
+                                                      max_kg, stream);
       if (e != hipSuccess) return fail(CHI0_EDEVICE, "pre-split launch: %s", hipGetErrorString(e));
     }
     if (h->profiling && e0) HIP_TRY(hipEventRecord(e0, stream));
@@ -1504,7 +1551,12 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
     a2.partials = static_cast<double2*>(h->sigc_part.p);
     a2.nunits = static_cast<int32_t>(ct[c].u2.size());
     a2.seg_len = ct[c].seg_len;
-    e = sigc_zwz_launch(a2, stream);
+    if (bf16) {
+      e = sigc_split_rows_launch(d_desc + chunk0[c], chunk0[c + 1] - chunk0[c], 0, max_nqp, max_kg, stream);
+      if (e == hipSuccess) e = sigc_bf16x3_zwz_launch(a2, stream);
+    } else {
+      e = sigc_zwz_launch(a2, stream);
+    }
     if (e != hipSuccess) return fail(CHI0_EDEVICE, "second contraction launch: %s", hipGetErrorString(e));
     e = sigc_reduce_launch(reinterpret_cast<const SigcJob*>(dtab + coff[c][2]),
                            reinterpret_cast<const int32_t*>(dtab + coff[c][3]), a2.partials, d_prob,

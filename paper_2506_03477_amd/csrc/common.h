@@ -114,6 +114,14 @@ struct SigcDesc {
   int64_t wsp_plane;
   void* zsp;
   int64_t zsp_plane;
+  // BF16x3 second contraction: hi planes of zw and of Z as [kappa][n]
+  // matrices (kappa = n' * nmu + nu; group g of 4 rows kappa, column n at
+  // (g * nqp + n) * 16 bytes), each lo plane at + k_plane bytes; kgroups
+  // groups (whole 16-row stages, rows beyond nall * nmu are zero).
+  void* zwsp;
+  void* zksp;
+  int64_t k_plane;
+  int32_t kgroups, pad2;
 };
 
 // Work unit of the two contractions: block, tile row (P side), tile column
@@ -137,7 +145,7 @@ struct SigcProb {
 struct SigcArgs {
   const SigcUnit* units;
   const SigcDesc* descs;
-  double2* partials;      // second contraction: [unit][T][T]
+  double2* partials;      // second contraction: [unit][T][T] (BF16x3: [unit][2][T][T])
   int32_t nunits;
   int32_t seg_len;        // second contraction: rows (n', nu) per segment
 };
@@ -155,6 +163,14 @@ int sigc_tile();
 hipError_t sigc_presplit_launch(const SigcDesc* descs, int nblocks, int max_nmu, int64_t max_m,
                                 int max_groups_w, int max_groups_z, hipStream_t s);
 hipError_t sigc_bf16x3_launch(const SigcArgs& a, hipStream_t s);
+// BF16x3 second contraction: units (block, 256-row P tile, 128-column Q
+// tile, segment of seg_len rows kappa, a multiple of 16, at most 4096), each
+// storing its 256 x 128 FP64 partial as partial tiles 2 unit and 2 unit + 1.
+hipError_t sigc_bf16x3_zwz_launch(const SigcArgs& a, hipStream_t s);
+// Split the [nall * nmu][nqp] complex128 matrix zw (which = 0) or Z
+// (which = 1) of each block into the second contraction's planes.
+hipError_t sigc_split_rows_launch(const SigcDesc* descs, int nblocks, int which, int max_nqp,
+                                  int max_kgroups, hipStream_t s);
 
 // Histogram route (Eq.(impolf), Eq.(hilbert)): one k-point block as the
 // binning kernel sees it.

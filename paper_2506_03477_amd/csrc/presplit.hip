@@ -131,7 +131,49 @@ __global__ __launch_bounds__(256) void sigc_split_z_kernel(const SigcDesc* __res
   }
 }
 
+// Second contraction of the correlation self-energy on the BF16x3 path: the
+// [nall * nmu][nqp] matrix zw (which = 0) or Z (which = 1) of one block
+// (blockIdx.z) rounded to FP32 and split: group g of 4 rows kappa, column n
+// at (g * nqp + n) * 16 bytes; rows beyond nall * nmu are zero.
+__global__ __launch_bounds__(256) void sigc_split_rows_kernel(const SigcDesc* __restrict__ descs, int blk0,
+                                                              int which) {
+  const SigcDesc bd = descs[blk0 + blockIdx.z];
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= bd.nqp) return;
+  const int64_t K = static_cast<int64_t>(bd.nall) * bd.nmu;
+  const double2* src = which ? bd.z : bd.zw;
+  char* dst = static_cast<char*>(which ? bd.zksp : bd.zwsp);
+  for (int64_t g = blockIdx.y; g < bd.kgroups; g += gridDim.y) {
+    float2 x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t kap = 4 * g + e;
+      const double2 v = kap < K ? src[kap * bd.nqp + n] : double2{0.0, 0.0};
+      x[e] = float2{static_cast<float>(v.x), static_cast<float>(v.y)};
+    }
+    uint4 hi, lo;
+    split_chunk(x, hi, lo);
+    const size_t off = (static_cast<size_t>(g) * bd.nqp + n) * 16;
+    *reinterpret_cast<uint4*>(dst + off) = hi;
+    *reinterpret_cast<uint4*>(dst + bd.k_plane + off) = lo;
+  }
+}
+
 }  // namespace
+
+hipError_t sigc_split_rows_launch(const SigcDesc* descs, int nblocks, int which, int max_nqp,
+                                  int max_kgroups, hipStream_t s) {
+  if (nblocks <= 0 || max_nqp <= 0) return hipSuccess;
+  const unsigned gy = static_cast<unsigned>(max_kgroups < 8192 ? (max_kgroups > 0 ? max_kgroups : 1) : 8192);
+  for (int b0 = 0; b0 < nblocks; b0 += 65535) {
+    const int nb = nblocks - b0 < 65535 ? nblocks - b0 : 65535;
+    hipLaunchKernelGGL(sigc_split_rows_kernel, dim3((max_nqp + 255) / 256, gy, nb), dim3(256), 0, s, descs,
+                       b0, which);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 hipError_t sigc_presplit_launch(const SigcDesc* descs, int nblocks, int max_nmu, int64_t max_m,
                                 int max_groups_w, int max_groups_z, hipStream_t s) {

@@ -173,7 +173,136 @@ __global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_kernel(SigcArgs args) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Second contraction on the BF16x3 path:
+//   I[n][m] = sum_kappa conj(zw[kappa][n]) Z[kappa][m],  kappa = (n', nu),
+// both operands pre-split as [kappa][n] matrices (sigc_split_rows_kernel).
+// A unit is one 256 (n) x 128 (m) tile over one segment of at most 4096 rows
+// kappa: a single FP32 run, stored as an FP64 partial (rows 0-127 and
+// 128-255 as two 128 x 128 partial tiles) and summed in a fixed order by the
+// FP64 reduction.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNT, 1) void sigc_bf16x3_zwz_kernel(SigcArgs args) {
+  typedef const char __attribute__((address_space(1)))* gcptr;
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  typedef const u32x4 __attribute__((address_space(1)))* gu4ptr;
+  constexpr int TP = 256, TQ = 128, T = 128;
+  __shared__ __attribute__((aligned(16))) Bf16TallLds L;
+
+  const int per = (args.nunits + 7) / 8;
+  const int lu = static_cast<int>(blockIdx.x % 8) * per + static_cast<int>(blockIdx.x / 8);
+  if (lu >= args.nunits) return;
+  const SigcUnit u = args.units[lu];
+  const SigcDesc bd = args.descs[u.blk];
+  const int nqp = bd.nqp;
+  const int total = bd.kgroups / 4;                 // 16-row stages
+  const int sps = args.seg_len / 16;                // stages per segment
+  const int s0 = u.seg * sps;
+  const int s1 = s0 + sps < total ? s0 + sps : total;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g8 = lane >> 5;
+  const int l32 = lane & 31;
+  const int lp = tid;
+  const int lq = tid & (TQ - 1);
+  const int lg = tid >> 7;
+
+  const int pcol = u.tp * TP + lp;
+  const int qcol = u.tc * TQ + lq;
+  const uint64_t offP = static_cast<uint64_t>(pcol < nqp ? pcol : 0) * 16u;
+  const uint64_t offQ = static_cast<uint64_t>(qcol < nqp ? qcol : 0) * 16u;
+  const uint64_t chunk = static_cast<uint64_t>(nqp) * 16u;   // one group of 4 rows
+  const gcptr ah = (gcptr)bd.zwsp;
+  const gcptr bh = (gcptr)bd.zksp;
+  const int64_t plane = bd.k_plane;
+
+  f32x16 cr[4][2], ci[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = f32x16{0};
+      ci[i][j] = f32x16{0};
+    }
+  uint4 ph[4], pl[4], qh[2], ql[2];
+
+  auto load = [&](int st) __attribute__((always_inline)) {
+    const uint64_t g0 = 4 * static_cast<uint64_t>(st);
+    const gcptr wb = ah + g0 * chunk + offP;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u32x4 h = *(gu4ptr)(wb + q * chunk);
+      const u32x4 l = *(gu4ptr)(wb + plane + q * chunk);
+      ph[q] = uint4{h.x, h.y, h.z, h.w};
+      pl[q] = uint4{l.x, l.y, l.z, l.w};
+    }
+    const gcptr zb = bh + g0 * chunk + offQ;
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+      const uint64_t o = static_cast<uint64_t>(lg + 2 * gi) * chunk;
+      const u32x4 h = *(gu4ptr)(zb + o);
+      const u32x4 l = *(gu4ptr)(zb + plane + o);
+      qh[gi] = uint4{h.x, h.y, h.z, h.w};
+      ql[gi] = uint4{l.x, l.y, l.z, l.w};
+    }
+  };
+  auto stage = [&](int buf) __attribute__((always_inline)) {
+    tall_stage_p(L, buf, lp, ph, pl);
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+      const int o = swz(lq, lg + 2 * gi);
+      *reinterpret_cast<uint4*>(&L.bh[buf][o]) = qh[gi];
+      *reinterpret_cast<uint4*>(&L.bl[buf][o]) = ql[gi];
+      *reinterpret_cast<uint4*>(&L.bih[buf][o]) = rot_neg4(qh[gi]);
+      *reinterpret_cast<uint4*>(&L.bil[buf][o]) = rot_neg4(ql[gi]);
+    }
+  };
+
+  if (s0 < s1) {
+    load(s0);
+    stage(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int st = s0; st < s1; ++st) {
+    const bool more = st + 1 < s1;
+    if (more) load(st + 1);
+    tall_mfma<false, 4>(L, buf, wr, wc, g8, l32, cr, ci);
+    if (more) stage(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // 256 x 128 partial, row-major: rows 0-127 are partial tile 2 lu, rows
+  // 128-255 partial tile 2 lu + 1 (tile rows beyond nqp are never read)
+  double2* out = args.partials + static_cast<size_t>(lu) * 2 * T * T;
+  const int g = lane >> 5;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col = wc * 64 + j * 32 + (lane & 31);
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr * 128 + bi * 32 + 4 * g + 8 * (r >> 2) + (r & 3);
+        out[row * T + col] = double2{static_cast<double>(cr[bi][j][r]), static_cast<double>(ci[bi][j][r])};
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t sigc_bf16x3_zwz_launch(const SigcArgs& a, hipStream_t s) {
+  if (a.nunits <= 0) return hipSuccess;
+  const unsigned grid = static_cast<unsigned>((a.nunits + 7) / 8 * 8);
+  hipLaunchKernelGGL(sigc_bf16x3_zwz_kernel, dim3(grid), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t sigc_bf16x3_launch(const SigcArgs& a, hipStream_t s) {
   if (a.nunits <= 0) return hipSuccess;

@@ -122,11 +122,12 @@ def hist_model(blocks, npb, edges, sigma, delta_min=0.0, path="bf16x3", lolo=Fal
 
 
 def sigc_model(blocks, eps_qp, mesh):
-    """I^c with the BF16x3 first contraction as the GPU runs it: W^c rounded
-    to FP32 and split into bf16 hi / lo; Z multiplied by the integration
-    weight of its column and mesh point in FP64, rounded to FP32 and split;
-    three split products per real product summed exactly (FP64) over all
-    (mesh point, mu) rows; the second contraction in FP64.
+    """I^c with both contractions on BF16x3 as the GPU runs them: W^c
+    rounded to FP32 and split into bf16 hi / lo; Z multiplied by the
+    integration weight of its column and mesh point in FP64, rounded to FP32
+    and split; three split products per real product summed exactly (FP64)
+    over all (mesh point, mu) rows; the second contraction the same way on
+    zw and Z rounded to FP32 and split.
     blocks: (Z [nall, nmu, nqp], W^c [nomega, nmu, nmu], eps_mid, wk)."""
     from oracle.sigc_oracle import ag_weight_table
     nqp = len(eps_qp)
@@ -149,5 +150,10 @@ def sigc_model(blocks, eps_qp, mesh):
                 for (pr, pi), (qr, qi) in (((wrh, wih), (zrh, zih)), ((wrh, wih), (zrl, zil)),
                                            ((wrl, wil), (zrh, zih))):
                     zw += (pr.T @ qr + pi.T @ qi) + 1j * (pr.T @ qi - pi.T @ qr)
-            out += np.conj(zw).T @ z[a]
+            (awrh, awrl), (awih, awil) = split(zw.real.astype(np.float32)), split(zw.imag.astype(np.float32))
+            (bzrh, bzrl), (bzih, bzil) = (split(z[a].real.astype(np.float32)),
+                                          split(z[a].imag.astype(np.float32)))
+            for (pr, pi), (qr, qi) in (((awrh, awih), (bzrh, bzih)), ((awrh, awih), (bzrl, bzil)),
+                                       ((awrl, awil), (bzrh, bzih))):
+                out += (pr.T @ qr + pi.T @ qi) + 1j * (pr.T @ qi - pi.T @ qr)
     return out

@@ -239,13 +239,14 @@ def test_full_size_sampled(ctx):
     assert np.all(np.isfinite(got_full))
 
 
-# BF16x3 first contraction.  Every operand keeps 16 significant bits (hi + lo
-# of its FP32 value), so a product carries a random relative error of about
+# BF16x3 contractions.  Every operand keeps 16 significant bits (hi + lo of
+# its FP32 value), so a product carries a random relative error of about
 # 4e-6; the entries of Z_w^H W^c and of I^c are sums of terms of both signs,
 # which keep that relative error instead of averaging it down (unlike the
-# positive diagonal of chi0).  Bound against the oracle: 8e-6 relative
-# Frobenius.  Against the split model (the kernel's roundings, exact products,
-# FP64 sums) only the FP32 runs of at most 4096 rows (mesh point, mu) differ:
+# positive diagonal of chi0), and the two contractions' errors add in
+# quadrature (about 5.7e-6 at most).  Bound against the oracle: 8e-6 relative
+# Frobenius.  Against the split model (the kernels' roundings, exact
+# products, FP64 sums) only the FP32 runs of at most 4096 rows differ:
 # relative u sqrt(run) ~ 4e-6 at most, bound 4e-6.
 BF16_TOL = 8e-6
 BF16_MODEL_TOL = 4e-6
