@@ -252,7 +252,7 @@ BF16_TOL = 8e-6
 BF16_MODEL_TOL = 4e-6
 
 
-@pytest.mark.parametrize("case", CASES[:3] + [(96, [(4, 520)], 3, 0.0)])
+@pytest.mark.parametrize("case", CASES + [(96, [(4, 520)], 3, 0.0)])
 def test_bf16x3_parity(ctx, case):
     nqp, shapes, nom, w0 = case
     _say(f"sigc bf16x3 nqp={nqp} blocks={shapes} nomega={nom}")
