@@ -264,13 +264,19 @@ typedef struct {
   void* sigc;              /* DEVICE out [nqp][nqp] complex128, 16-byte aligned */
 } sigc_problem;
 
-/* I^c for `nprob` q-points.  FP64 path only (prec = CHI0_PREC_FP64, zt =
- * CHI0_Z_C128; anything else returns CHI0_EUNSUPPORTED).  flags:
+/* I^c for `nprob` q-points.  zt = CHI0_Z_C128; prec = CHI0_PREC_FP64 or
+ * CHI0_PREC_BF16X3 (anything else returns CHI0_EUNSUPPORTED).  flags:
  * CHI0_ACCUMULATE adds to sigc instead of overwriting it.  Work: a first
- * FP64 matrix-core contraction ZW[n'][n][nu] = sum_{i,mu} t conj(Z) W^c_i
+ * matrix-core contraction ZW[n'][n][nu] = sum_{i,mu} t conj(Z) W^c_i
  * (t = -w_k w_i) into a workspace the size of Z, blocks grouped so that it
  * stays under the workspace cap, then sum_{n', nu} ZW Z in segments whose
- * FP64 partial tiles are summed in a fixed order (deterministic).
+ * FP64 partial tiles are summed in a fixed order (deterministic).  FP64: both
+ * contractions in FP64.  BF16X3: both contractions as three bf16 split
+ * products per real product with FP32 runs of at most 4096 rows added in
+ * FP64 (relative Frobenius error a few 1e-6: the entries are sums of terms
+ * of both signs); it needs, per block, the split operands besides ZW (W^c,
+ * and Z weighted for every mesh point: about nomega times the size of Z at
+ * half its precision), groups being capped at four times the workspace cap.
  * Asynchronous on hip_stream like chi0_accumulate; inputs must stay valid
  * until the stream reaches the call's end. */
 int sigc_accumulate(chi0_handle h, const sigc_problem* probs, int32_t nprob,
