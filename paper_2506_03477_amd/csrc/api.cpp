@@ -1811,11 +1811,24 @@ int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* 
   double2* wrow = static_cast<double2*>(h->gj_wrow.p);
   int32_t* piv = static_cast<int32_t*>(h->gj_piv.p);
   int32_t* perm = static_cast<int32_t*>(h->gj_perm.p);
+  // Each panel of nb columns is eliminated as sub-panels: a sub-panel is
+  // factored by one workgroup per frequency, then applied to the panel's
+  // other columns by the interchange / pivot-row and update kernels
+  // restricted to the panel (all CUs); the whole panel is then applied to
+  // every other column.
+  const int sb = gj_subpanel_width();
   for (int k0 = 0; k0 < npb; k0 += nb) {
     const int nbk = std::min(nb, npb - k0);
-    e = gj_panel_launch(work, npb, nomega, k0, nbk, piv, h->d_status, s);
-    if (e == hipSuccess) e = gj_swap_extract_launch(work, wrow, npb, nomega, k0, nbk, piv, s);
-    if (e == hipSuccess) e = gj_update_launch(work, wrow, npb, nomega, k0, nbk, s);
+    for (int j0 = 0; j0 < nbk && e == hipSuccess; j0 += sb) {
+      const int sw = std::min(sb, nbk - j0);
+      e = gj_panel_launch(work, npb, nomega, k0 + j0, sw, piv, h->d_status, s);
+      if (e == hipSuccess && sw < nbk)
+        e = gj_swap_extract_launch(work, wrow, npb, nomega, k0 + j0, sw, piv, k0, k0 + nbk, s);
+      if (e == hipSuccess && sw < nbk)
+        e = gj_update_launch(work, wrow, npb, nomega, k0 + j0, sw, k0, k0 + nbk, s);
+    }
+    if (e == hipSuccess) e = gj_swap_extract_launch(work, wrow, npb, nomega, k0, nbk, piv, 0, npb, s);
+    if (e == hipSuccess) e = gj_update_launch(work, wrow, npb, nomega, k0, nbk, 0, npb, s);
     if (e != hipSuccess) return fail(CHI0_EDEVICE, "Gauss-Jordan launch: %s", hipGetErrorString(e));
   }
   e = gj_finish_launch(work, static_cast<double2*>(eps_inv), wc_out, vsqrt, piv, perm, npb, nomega,

@@ -254,16 +254,20 @@ hipError_t dielectric_build_launch(const double2* chi0, const double* vsqrt,
                                    int nomega, hipStream_t s);
 hipError_t gj_panel_launch(double2* work, int n, int nomega, int k0, int nb,
                            int32_t* piv, int32_t* status, hipStream_t s);
+// Both restricted to the columns [jlo, jhi) outside the panel [k0, k0 + nb).
 hipError_t gj_swap_extract_launch(double2* work, double2* wrow, int n,
                                   int nomega, int k0, int nb,
-                                  const int32_t* piv, hipStream_t s);
+                                  const int32_t* piv, int jlo, int jhi,
+                                  hipStream_t s);
 hipError_t gj_update_launch(double2* work, const double2* wrow, int n,
-                            int nomega, int k0, int nb, hipStream_t s);
+                            int nomega, int k0, int nb, int jlo, int jhi,
+                            hipStream_t s);
 hipError_t gj_finish_launch(const double2* work, double2* eps_inv,
                             double2* wc, const double* vsqrt,
                             const int32_t* piv, int32_t* perm, int n,
                             int nomega, hipStream_t s);
 int gj_panel_width();
+int gj_subpanel_width();
 
 // Hermitian positive definite inverse (symmetric Gauss-Jordan sweeps).
 int hpd_block_width();

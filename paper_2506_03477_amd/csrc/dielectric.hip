@@ -348,12 +348,14 @@ __global__ __launch_bounds__(kPanelThreads) void gj_panel_reg_kernel(
   }
 }
 
+// Columns j in [jlo, jhi) outside the panel [k0, k0 + nb): the panel's row
+// interchanges, in order, then its pivot rows copied to wrow.
 __global__ __launch_bounds__(256) void gj_swap_extract_kernel(
     double2* __restrict__ work, double2* __restrict__ wrow, int n, int k0, int nb,
-    const int32_t* __restrict__ piv) {
+    const int32_t* __restrict__ piv, int jlo, int jhi) {
   const int mat = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n || (j >= k0 && j < k0 + nb)) return;
+  const int j = jlo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= jhi || (j >= k0 && j < k0 + nb)) return;
   double2* S = work + static_cast<size_t>(mat) * n * n;
   const int32_t* pv = piv + static_cast<size_t>(mat) * n;
   double2* W = wrow + static_cast<size_t>(mat) * kPanel * n;
@@ -371,22 +373,44 @@ __global__ __launch_bounds__(256) void gj_swap_extract_kernel(
   for (int b = 0; b < nb; ++b) W[static_cast<size_t>(b) * n + j] = S[static_cast<size_t>(k0 + b) * n + j];
 }
 
-// X[i][j] = (i in panel rows ? 0 : X[i][j]) + sum_b C[i][b] W[b][j], j outside
-// the panel.  64 x 64 complex output tile per workgroup, 4 waves of 32 x 32,
-// FP64 16x16x4 MFMA with (re, im) stacked along the contraction index:
+// X[i][j] = (i in panel rows ? 0 : X[i][j]) + sum_b C[i][b] W[b][j], j in
+// [jlo, jhi) outside the panel.  64 x 64 complex output tile per workgroup
+// (tile columns from the one holding jlo), 4 waves of 32 x 32, FP64 16x16x4
+// MFMA with (re, im) stacked along the contraction index:
 //   Re += [Cr, Ci] . [Wr, -Wi],  Im += [Cr, Ci] . [Wi, Wr].
 __global__ __launch_bounds__(256) void gj_update_kernel(
-    double2* __restrict__ work, const double2* __restrict__ wrow, int n, int k0, int nb) {
+    double2* __restrict__ work, const double2* __restrict__ wrow, int n, int k0, int nb, int jlo,
+    int jhi) {
   constexpr int T = 64;
   __shared__ double2 sC[kPanel][T];
   __shared__ double2 sW[kPanel][T];
   const int mat = blockIdx.z;
   const int i0 = blockIdx.y * T;
-  const int j0 = blockIdx.x * T;
+  const int j0 = (jlo / T) * T + blockIdx.x * T;
   if (j0 + T > k0 && j0 < k0 + nb && j0 >= k0 && j0 + T <= k0 + nb) return;  // inside panel
   double2* S = work + static_cast<size_t>(mat) * n * n;
   const double2* W = wrow + static_cast<size_t>(mat) * kPanel * n;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int m = lane & 15;
+  const int kk = lane >> 4;
+  // the 16 old values of this thread's outputs, read before the tile is
+  // staged so that their latency overlaps the staging and the MFMAs
+  double2 xo[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + kk + 4 * r;
+        const int j = j0 + wc * 32 + c * 16 + m;
+        const bool keep = i < n && j >= jlo && j < jhi && !(j >= k0 && j < k0 + nb) &&
+                          !(i >= k0 && i < k0 + nb);
+        xo[a][c][r] = keep ? S[static_cast<size_t>(i) * n + j] : double2{0.0, 0.0};
+      }
   for (int e = tid; e < kPanel * T; e += 256) {
     const int b = e % kPanel;
     const int i = e / kPanel;
@@ -400,11 +424,6 @@ __global__ __launch_bounds__(256) void gj_update_kernel(
     sW[bj][jj] = w;
   }
   __syncthreads();
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int m = lane & 15;
-  const int kk = lane >> 4;
   const int prr = kk >> 1;
   const bool isim = (kk & 1) != 0;
   f64x4 accR[2][2], accI[2][2];
@@ -445,12 +464,9 @@ __global__ __launch_bounds__(256) void gj_update_kernel(
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + wr * 32 + a * 16 + kk + 4 * r;  // f64 16x16x4 result rows
         const int j = j0 + wc * 32 + c * 16 + m;
-        if (i >= n || j >= n || (j >= k0 && j < k0 + nb)) continue;
+        if (i >= n || j < jlo || j >= jhi || (j >= k0 && j < k0 + nb)) continue;
         const size_t ad = static_cast<size_t>(i) * n + j;
-        double2 x = (i >= k0 && i < k0 + nb) ? double2{0.0, 0.0} : S[ad];
-        x.x += accR[a][c][r];
-        x.y += accI[a][c][r];
-        S[ad] = x;
+        S[ad] = double2{xo[a][c][r].x + accR[a][c][r], xo[a][c][r].y + accI[a][c][r]};
       }
 }
 
@@ -517,18 +533,23 @@ hipError_t gj_panel_launch(double2* work, int n, int nomega, int k0, int nb, int
   return hipGetLastError();
 }
 
+int gj_subpanel_width() { return 8; }
+
 hipError_t gj_swap_extract_launch(double2* work, double2* wrow, int n, int nomega, int k0, int nb,
-                                  const int32_t* piv, hipStream_t s) {
-  hipLaunchKernelGGL(gj_swap_extract_kernel, dim3((n + 255) / 256, nomega), dim3(256), 0, s, work,
-                     wrow, n, k0, nb, piv);
+                                  const int32_t* piv, int jlo, int jhi, hipStream_t s) {
+  if (jhi <= jlo) return hipSuccess;
+  hipLaunchKernelGGL(gj_swap_extract_kernel, dim3((jhi - jlo + 255) / 256, nomega), dim3(256), 0, s,
+                     work, wrow, n, k0, nb, piv, jlo, jhi);
   return hipGetLastError();
 }
 
 hipError_t gj_update_launch(double2* work, const double2* wrow, int n, int nomega, int k0, int nb,
-                            hipStream_t s) {
+                            int jlo, int jhi, hipStream_t s) {
+  if (jhi <= jlo) return hipSuccess;
   const int nt = (n + 63) / 64;
-  hipLaunchKernelGGL(gj_update_kernel, dim3(nt, nt, nomega), dim3(256), 0, s, work, wrow, n, k0,
-                     nb);
+  const int ntj = (jhi - 1) / 64 - jlo / 64 + 1;
+  hipLaunchKernelGGL(gj_update_kernel, dim3(ntj, nt, nomega), dim3(256), 0, s, work, wrow, n, k0,
+                     nb, jlo, jhi);
   return hipGetLastError();
 }
 
