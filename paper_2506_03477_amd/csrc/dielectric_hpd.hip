@@ -167,6 +167,26 @@ __global__ __launch_bounds__(256) void hpd_update_kernel(double2* __restrict__ w
   const int tid = threadIdx.x;
   const double2* Cm = cbuf + static_cast<size_t>(mat) * n * kNb;
   const double2* Pm = pbuf + static_cast<size_t>(mat) * n * kNb;
+  double2* X = work + static_cast<size_t>(mat) * n * n;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int m = lane & 15;
+  const int kk = lane >> 4;
+  // the 16 old values of this thread's outputs, read before the tile is
+  // staged so that their latency overlaps the staging and the MFMAs
+  double2 xo[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + kk + 4 * r;
+        const int j = j0 + wc * 32 + c * 16 + m;
+        const bool keep = i < n && j <= i && !(i >= k0 && i < k0 + nb) && !(j >= k0 && j < k0 + nb);
+        xo[a][c][r] = keep ? X[static_cast<size_t>(i) * n + j] : double2{0.0, 0.0};
+      }
   for (int e = tid; e < kNb * T; e += 256) {
     const int b = e % kNb;
     const int rr = e / kNb;
@@ -177,11 +197,6 @@ __global__ __launch_bounds__(256) void hpd_update_kernel(double2* __restrict__ w
     sP[b][rr] = okj ? Pm[static_cast<size_t>(rj) * kNb + b] : double2{0.0, 0.0};
   }
   __syncthreads();
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int m = lane & 15;
-  const int kk = lane >> 4;
   const int prr = kk >> 1;
   const bool isim = (kk & 1) != 0;
   f64x4 accR[2][2], accI[2][2];
@@ -215,7 +230,6 @@ __global__ __launch_bounds__(256) void hpd_update_kernel(double2* __restrict__ w
         accI[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bi[c], accI[a][c], 0, 0, 0);
       }
   }
-  double2* X = work + static_cast<size_t>(mat) * n * n;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -226,10 +240,7 @@ __global__ __launch_bounds__(256) void hpd_update_kernel(double2* __restrict__ w
         const int j = j0 + wc * 32 + c * 16 + m;
         if (i >= n || j > i || (i >= k0 && i < k0 + nb) || (j >= k0 && j < k0 + nb)) continue;
         const size_t ad = static_cast<size_t>(i) * n + j;
-        double2 x = X[ad];
-        x.x -= accR[a][c][r];
-        x.y -= accI[a][c][r];
-        X[ad] = x;
+        X[ad] = double2{xo[a][c][r].x - accR[a][c][r], xo[a][c][r].y - accI[a][c][r]};
       }
 }
 
