@@ -331,18 +331,22 @@ const char* chi0_last_error(void);
  * length before an FP64 flush; 0 for FP64).  chi0_set_tile() fixes the
  * configuration used for a precision (-1 = the autotuned or built-in
  * default).  chi0_get_tile() reports the fixed, else the autotuned, else the
- * built-in default configuration.  With none fixed or tuned, BF16X3 and FP64
- * calls that do not gather rows choose per call by a cost model of the
- * padded tile area (the large default tiles for large npb, smaller square
- * tiles when npb is a few hundred); chi0_last_tile() reports the
- * configuration of the handle's last rank-K launch for a precision (-1
- * before the first). */
+ * built-in default configuration.  With none fixed or tuned, calls that do
+ * not gather rows choose per call by a cost model of the padded tile area
+ * (rows x padded lower-triangle area x frequencies x a per-configuration
+ * cost; BF16X3 and FP64 take their large default tiles for large npb and
+ * smaller square tiles when npb is a few hundred, FP32 128^2 tiles for large
+ * npb and 64^2 otherwise); chi0_tile_choice() returns that model's choice for
+ * a set of problems (host data only: nocc, nunocc, npb, nomega; no handle,
+ * no device), and chi0_last_tile() reports the configuration of the handle's
+ * last rank-K launch for a precision (-1 before the first). */
 int chi0_tile_count(chi0_precision prec);
 int chi0_tile_info(chi0_precision prec, int32_t tile, int32_t* tile_p,
                    int32_t* tile_q, int32_t* kchunk, int32_t* flush_len);
 int chi0_set_tile(chi0_handle h, chi0_precision prec, int32_t tile);
 int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile);
 int chi0_last_tile(chi0_handle h, chi0_precision prec, int32_t* tile);
+int chi0_tile_choice(chi0_precision prec, const chi0_problem* probs, int32_t nprob, int32_t* tile);
 
 /* FP32 run length of the reduced-precision paths: the number of pairs summed
  * in FP32 before the partial sum is added into FP64.  By default it is

@@ -6,10 +6,10 @@ self-energy on the same matrix-core machinery.
 The computation lives in libchi0.so (hand-written HIP kernels behind the C ABI
 of include/chi0.h); this package is its ctypes binding.
 """
-from ._lib import (Block, Problem, SigxBlock, SigxProblem, SigcBlock, SigcProblem, HistSpec, Context, Chi0Error, load, header_functions, PREC, ZTYPE,
+from ._lib import (Block, Problem, SigxBlock, SigxProblem, SigcBlock, SigcProblem, HistSpec, Context, Chi0Error, load, header_functions, tile_choice, PREC, ZTYPE,
                    CHI0_OK, CHI0_EINVAL, CHI0_ENOMEM, CHI0_EDEVICE, CHI0_ENOTHPD,
                    CHI0_ESINGULAR, CHI0_EUNSUPPORTED)
 
-__all__ = ["Block", "Problem", "SigxBlock", "SigxProblem", "SigcBlock", "SigcProblem", "HistSpec", "Context", "Chi0Error", "load", "header_functions", "PREC",
+__all__ = ["Block", "Problem", "SigxBlock", "SigxProblem", "SigcBlock", "SigcProblem", "HistSpec", "Context", "Chi0Error", "load", "header_functions", "tile_choice", "PREC",
            "ZTYPE", "CHI0_OK", "CHI0_EINVAL", "CHI0_ENOMEM", "CHI0_EDEVICE",
            "CHI0_ENOTHPD", "CHI0_ESINGULAR", "CHI0_EUNSUPPORTED"]

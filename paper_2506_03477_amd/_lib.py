@@ -115,6 +115,7 @@ def load() -> ctypes.CDLL:
         "chi0_set_flush": (c_int, [vp, c_int32]),
         "chi0_get_tile": (c_int, [vp, c_int, POINTER(c_int32)]),
         "chi0_last_tile": (c_int, [vp, c_int, POINTER(c_int32)]),
+        "chi0_tile_choice": (c_int, [c_int, POINTER(chi0_problem), c_int32, POINTER(c_int32)]),
         "chi0_autotune": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
                                   c_int32, POINTER(c_int32), POINTER(c_double), vp]),
         "chi0_plan_inspect": (c_int, [POINTER(chi0_problem), c_int32, c_int, c_int32, c_int32,
@@ -339,6 +340,32 @@ def _marshal(problems: Sequence[Problem]):
         arr[i].omega = _dev_ptr(p.omega, torch.float64, "omega")
         arr[i].chi0 = _dev_ptr(p.chi0, torch.complex128, "chi0")
     return arr, keep
+
+
+def tile_choice(precision: str, shapes) -> int:
+    """The tile configuration the library's cost model picks for problems of
+    the given shapes when no tile is fixed or tuned (host computation, no
+    device).  shapes: [(npb, nomega, [(nocc, nunocc), ...]), ...]."""
+    lib = load()
+    keep = []
+    arr = (chi0_problem * max(1, len(shapes)))()
+    for i, (npb, nomega, blocks) in enumerate(shapes):
+        barr = (chi0_block * max(1, len(blocks)))()
+        for j, (nocc, nunocc) in enumerate(blocks):
+            barr[j].nocc = int(nocc)
+            barr[j].nunocc = int(nunocc)
+            barr[j].z = barr[j].eps_occ = barr[j].eps_unocc = None
+            barr[j].wk = 1.0
+        keep.append(barr)
+        arr[i].npb = int(npb)
+        arr[i].nblocks = len(blocks)
+        arr[i].blocks = ctypes.cast(barr, POINTER(chi0_block))
+        arr[i].nomega = int(nomega)
+        arr[i].omega = None
+        arr[i].chi0 = None
+    t = c_int32(-1)
+    _check(lib.chi0_tile_choice(PREC[precision], arr, len(shapes), byref(t)))
+    return t.value
 
 
 def _ztype_of(problems: Sequence[Problem]) -> int:

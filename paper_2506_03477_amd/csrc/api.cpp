@@ -588,11 +588,11 @@ struct GatherHook {
 // candidate: rows x padded lower-triangle tile area x frequencies x a
 // per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
 // it.  Costs relative to the built-in default, fitted to MI355X timings at
-// npb 287 and 2048: BF16x3 tall 256 x 128 (7) 1.0, 128^2 with two workgroups
-// per CU (4) 1.12, 64^2 (2) 1.70, the pre-split pass 144 per row and column;
-// FP64 128^2 with 8 waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42.  A smaller
-// tile replaces the default only when modeled at least 15% faster (npb of a
-// few hundred, where the large tiles are mostly padding).
+// npb 287, 384 and 2048: BF16x3 tall 256 x 128 (7) 1.0, 128^2 with two
+// workgroups per CU (4) 1.12, 64^2 (2) 1.70, the pre-split pass 144 per row
+// and column; FP64 128^2 with 8 waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42;
+// FP32 64^2 (1) 1.0, 128^2 (0) 0.914.  Another tile replaces the default
+// only when modeled at least 5% faster.
 int tile_for(int kind, const chi0_problem* probs, int nprob) {
   struct Cand {
     int idx;
@@ -600,12 +600,13 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
   };
   static const Cand bf16[] = {{7, 1.0}, {4, 1.12}, {2, 1.70}};
   static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
+  static const Cand fp32[] = {{1, 1.0}, {0, 0.914}};
   const int ndef = herk_default_tile(kind);
-  const Cand* cands = kind == HERK_BF16X3 ? bf16 : kind == HERK_FP64 ? fp64 : nullptr;
-  if (!cands) return ndef;
+  const Cand* cands = kind == HERK_BF16X3 ? bf16 : kind == HERK_FP64 ? fp64 : fp32;
+  const int ncand = kind == HERK_FP32 ? 2 : 3;
   double def_time = -1.0, best_time = -1.0;
   int best = ndef;
-  for (int ci = 0; ci < 3; ++ci) {
+  for (int ci = 0; ci < ncand; ++ci) {
     const Cand& c = cands[ci];
     if (c.idx >= herk_tile_count(kind)) continue;
     const TileConfig tc = herk_tile_config(kind, c.idx);
@@ -629,7 +630,7 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
       best = c.idx;
     }
   }
-  return def_time >= 0.0 && best != ndef && best_time >= 0.85 * def_time ? ndef : best;
+  return def_time >= 0.0 && best != ndef && best_time >= 0.95 * def_time ? ndef : best;
 }
 
 int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_precision prec,
@@ -1886,6 +1887,23 @@ int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile) {
   if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
   *tile = h->tile_sel[k] >= 0 ? h->tile_sel[k] : h->tile_tuned[k] >= 0 ? h->tile_tuned[k]
                                                                          : herk_default_tile(k);
+  return CHI0_OK;
+}
+
+int chi0_tile_choice(chi0_precision prec, const chi0_problem* probs, int32_t nprob, int32_t* tile) {
+  if (!tile) return fail(CHI0_EINVAL, "tile is NULL");
+  const int k = kind_of(prec);
+  if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
+  if (nprob < 0 || (nprob > 0 && !probs)) return fail(CHI0_EINVAL, "bad problem list");
+  for (int p = 0; p < nprob; ++p) {
+    if (probs[p].npb < 1) return fail(CHI0_EINVAL, "problem %d: npb = %d < 1", p, probs[p].npb);
+    if (probs[p].nblocks < 0 || (probs[p].nblocks > 0 && !probs[p].blocks))
+      return fail(CHI0_EINVAL, "problem %d: bad block list", p);
+    for (int b = 0; b < probs[p].nblocks; ++b)
+      if (probs[p].blocks[b].nocc < 0 || probs[p].blocks[b].nunocc < 0)
+        return fail(CHI0_EINVAL, "problem %d block %d: negative count", p, b);
+  }
+  *tile = tile_for(k, probs, nprob);
   return CHI0_OK;
 }
 
