@@ -222,6 +222,37 @@ def _check_hpd_inverse(eps, inv, eps_o, tag):
         assert np.all(np.diag(inv[iw]).imag == 0)
 
 
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 31, 32, 33, 40, 100, 130])
+def test_dielectric_gj_sizes_pivoting(ctx, n):
+    """Pivoted Gauss-Jordan inverse of a general (non-Hermitian) eps whose
+    off-diagonal entries are as large as its diagonal, so rows are
+    interchanged, at sizes that end a panel (32 columns) or a sub-panel (8
+    columns) early, exactly, or one column late; against the oracle's
+    textbook Gauss-Jordan."""
+    _say(f"dielectric gj n={n}")
+    rng = np.random.default_rng(1000 + n)
+    chi_h = (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))) * (2.0 / np.sqrt(n))
+    s_h = np.ones(n)
+    chi = torch.from_numpy(chi_h).cuda()
+    s = torch.from_numpy(s_h).cuda()
+    eps = torch.empty_like(chi)
+    inv = torch.empty_like(chi)
+    ctx.dielectric_invert(s, chi, inv, eps=eps, method="gj")
+    ctx.sync()
+    eps_o = oracle.dielectric(chi_h, s_h)
+    assert np.array_equal(eps.cpu().numpy(), eps_o)
+    inv_ref = oracle.inverse(eps_o, "gauss_jordan")
+    got = inv.cpu().numpy()
+    u = np.finfo(float).eps / 2
+    for iw in range(2):
+        kappa = np.linalg.cond(eps_o[iw])
+        e = rel_fro(got[iw], inv_ref[iw])
+        res = np.linalg.norm(eps_o[iw] @ got[iw] - np.eye(n)) / np.sqrt(n)
+        _say(f"  iw={iw} kappa={kappa:.3g} inv rel={e:.3g} residual={res:.3g}")
+        assert e <= max(TOL_FP64, 64 * kappa * u)
+        assert res <= 64 * n * kappa * u
+
+
 @pytest.mark.parametrize("n", [1, 31, 32, 33, 100, 130])
 def test_dielectric_hpd_sizes(ctx, n):
     """Hermitian positive definite inverse (symmetric sweeps) at block-
