@@ -19,14 +19,15 @@
 // FP32: v_mfma_f32_32x32x2f32 with the (re, im) of one pair as the two
 // contraction slots.
 //
-// All kernels: T x T complex tiles (T = 128 or 64), 4 waves of T/2 x T/2,
-// operands staged once per workgroup into double-buffered, XOR-swizzled LDS
-// (the split / the scaling happens while staging), one barrier per 16-pair
-// stage, later stages' global loads (Z and the precomputed pair weights)
-// issued before the current stage's MFMAs.  Each
-// workgroup adds its FP32 accumulators into its FP64 partial tile in global
-// memory every `flush` pairs (per problem) and at the end of the unit, so no FP32 sum runs
-// over more than `flush` pairs.
+// Kernels: T x T complex tiles (T = 128 or 64, 4 waves of T/2 x T/2) and
+// tall 256 x 128 tiles (4 waves of 128 x 64, or 8 waves), operands staged once
+// per workgroup into double-buffered, XOR-swizzled LDS (the split / the
+// scaling happens while staging; the tall kernels read the P side
+// pre-split), one barrier per 16-pair stage, later stages' global loads (Z
+// and the precomputed pair weights) issued before the current stage's MFMAs.
+// Each workgroup adds its FP32 accumulators into its FP64 partial tile in
+// global memory every `flush` pairs (per problem) and at the end of the unit,
+// so no FP32 sum runs over more than `flush` pairs.
 #include "bf16_tall.h"
 #include "common.h"
 #include "herk_common.h"

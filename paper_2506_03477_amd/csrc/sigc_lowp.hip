@@ -1,4 +1,4 @@
-// Correlation self-energy on the BF16x3 path: the first contraction of
+// Correlation self-energy on the BF16x3 path: both contractions of
 // Eq.(sigci) on the tall-tile MFMA core (bf16_tall.h).
 #include "bf16_tall.h"
 #include "common.h"
