@@ -368,13 +368,22 @@ def tile_choice(precision: str, shapes) -> int:
     return t.value
 
 
-def _ztype_of(problems: Sequence[Problem]) -> int:
+def _ztype_of(problems: Sequence[Problem], precision: str) -> int:
+    """The Z type of the call: that of the blocks' Z data; without any (every
+    block empty), the dtype of an empty Z tensor, else the precision's own
+    (complex128 for FP64, complex64 otherwise)."""
     import torch
+    hint = None
     for p in problems:
         for b in p.blocks:
-            if b.z is not None and b.z.numel():
-                return ZTYPE["c128"] if b.z.dtype == torch.complex128 else ZTYPE["c64"]
-    return ZTYPE["c128"]
+            if b.z is not None:
+                zt = ZTYPE["c128"] if b.z.dtype == torch.complex128 else ZTYPE["c64"]
+                if b.z.numel():
+                    return zt
+                hint = zt if hint is None else hint
+    if hint is not None:
+        return hint
+    return ZTYPE["c128"] if precision == "fp64" else ZTYPE["c64"]
 
 
 class Context:
@@ -403,7 +412,7 @@ class Context:
         arr, keep = _marshal(problems)
         flags = (CHI0_ACCUMULATE if accumulate else 0) | (CHI0_BF16_LOLO if lolo else 0) | \
             (CHI0_USE_GRAPH if graph else 0)
-        _check(self._lib.chi0_accumulate(self._h, arr, len(problems), _ztype_of(problems),
+        _check(self._lib.chi0_accumulate(self._h, arr, len(problems), _ztype_of(problems, precision),
                                          PREC[precision], float(delta_min), flags,
                                          _stream_ptr(stream)))
 
@@ -411,13 +420,8 @@ class Context:
     def sigx_accumulate(self, problems: Sequence[SigxProblem], precision: str = "fp64",
                         accumulate: bool = False, lolo: bool = False, graph: bool = False,
                         stream=None) -> None:
-        import torch
         arr, keep = _marshal_sigx(problems)
-        zt = ZTYPE["c128"]
-        for p in problems:
-            for b in p.blocks:
-                if b.z is not None and b.z.numel():
-                    zt = ZTYPE["c128"] if b.z.dtype == torch.complex128 else ZTYPE["c64"]
+        zt = _ztype_of(problems, precision)
         flags = (CHI0_ACCUMULATE if accumulate else 0) | (CHI0_BF16_LOLO if lolo else 0) | \
             (CHI0_USE_GRAPH if graph else 0)
         _check(self._lib.sigx_accumulate(self._h, arr, len(problems), zt, PREC[precision], flags,
@@ -457,7 +461,7 @@ class Context:
             else:
                 harr[i].hist = None
         flags = CHI0_BF16_LOLO if lolo else 0
-        _check(self._lib.chi0_hist_accumulate(self._h, arr, harr, len(problems), _ztype_of(problems),
+        _check(self._lib.chi0_hist_accumulate(self._h, arr, harr, len(problems), _ztype_of(problems, precision),
                                               PREC[precision], float(delta_min), flags,
                                               _stream_ptr(stream)))
 
@@ -529,7 +533,7 @@ class Context:
         n = self.tile_count(precision)
         ms = (c_double * max(1, n))()
         best = c_int32()
-        _check(self._lib.chi0_autotune(self._h, arr, len(problems), _ztype_of(problems),
+        _check(self._lib.chi0_autotune(self._h, arr, len(problems), _ztype_of(problems, precision),
                                        PREC[precision], float(delta_min), reps, byref(best), ms,
                                        _stream_ptr(stream)))
         return best.value, [ms[i] for i in range(n)]

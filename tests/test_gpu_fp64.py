@@ -95,6 +95,13 @@ def test_fp64_accumulate_deterministic_and_graph(ctx):
     ctx.sync()
     assert np.all(rel_fro(p2.chi0.cpu().numpy(), first.cpu().numpy()) <= 1e-14)
     assert_hermitian_exact(p2.chi0)
+    # streaming one k-block per call (accumulate mode) == one call (to rounding)
+    ps = Problem(prob.blocks[:1], prob.omega, torch.zeros_like(prob.chi0))
+    ctx.chi0_accumulate([ps])
+    for b in prob.blocks[1:]:
+        ctx.chi0_accumulate([Problem([b], prob.omega, ps.chi0)], accumulate=True)
+    ctx.sync()
+    assert np.all(rel_fro(ps.chi0.cpu().numpy(), first.cpu().numpy()) <= 1e-14)
     # graph replays (with eager work in between) reproduce the direct result
     for rep in range(3):
         prob.chi0.fill_(7.0)

@@ -1,0 +1,105 @@
+"""chi0 for hypothesis-drawn shapes on the GPU: npb from 1 to 140 (ragged
+against every tile), blocks with no occupied or no unoccupied states, single
+pairs, one to three frequencies with or without omega = 0, and dyadic
+energies so that pairs below the intraband cut, with D <= 0, or exactly at
+the cut (included) all occur.  FP64 against the oracle; BF16x3 against the
+split model (the kernels' roundings), which the oracle pins separately.
+Examples are derandomized, so every run draws the same shapes."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+from hypothesis import HealthCheck, given, settings, strategies as st
+
+import oracle
+from gpu_common import assert_hermitian_exact, need_gpu
+from paper_2506_03477_amd import Block, Context, Problem
+from splitmodel import chi0_model
+
+pytestmark = pytest.mark.gpu
+
+DMIN = 2.0 ** -6          # dyadic intraband cut: a pair exactly at it is included
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    need_gpu()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@st.composite
+def shapes(draw):
+    npb = draw(st.integers(1, 140))
+    blocks = draw(st.lists(st.tuples(st.integers(0, 5), st.integers(0, 30)), min_size=1, max_size=3))
+    nomega = draw(st.integers(1, 3))
+    zero = draw(st.booleans())
+    tie = draw(st.booleans())
+    seed = draw(st.integers(0, 2 ** 31 - 1))
+    return npb, blocks, nomega, zero, tie, seed
+
+
+def _inputs(npb, blocks, nomega, zero, tie, seed):
+    """Host blocks (Z complex128, eps_occ, eps_unocc, wk) with energies on a
+    1/256 Ha grid, and the frequency mesh."""
+    rng = np.random.default_rng(seed)
+    decay = np.exp(-np.arange(npb) / 32.0)
+    out = []
+    for nocc, nunocc in blocks:
+        z = (rng.standard_normal((nocc, nunocc, npb)) + 1j * rng.standard_normal((nocc, nunocc, npb))) * decay
+        eo = -rng.integers(1, 200, nocc).astype(np.float64) / 256.0
+        eu = rng.integers(-40, 400, nunocc).astype(np.float64) / 256.0
+        if tie and nocc and nunocc:
+            eu[0] = eo[0] + DMIN                      # D exactly at the cut (exact in binary)
+        out.append((z, eo, eu, float(rng.uniform(0.1, 1.0))))
+    omega = np.sort(rng.uniform(0.05, 3.0, nomega))
+    if zero:
+        omega[0] = 0.0
+    return out, omega
+
+
+def _per_omega_rel(got, ref):
+    errs = []
+    for g, r in zip(got, ref):
+        den = np.linalg.norm(r)
+        if den == 0.0:
+            assert np.all(g == 0)                     # no pair survives: exact zeros
+            errs.append(0.0)
+        else:
+            errs.append(np.linalg.norm(g - r) / den)
+    return np.array(errs)
+
+
+@settings(max_examples=25, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+@given(shapes())
+def test_random_shapes(ctx, shape):
+    npb, blocks, nomega, zero, tie, seed = shape
+    host, omega = _inputs(*shape)
+    _say(f"random shape npb={npb} blocks={blocks} nomega={nomega} omega0={zero} tie={tie}")
+    for path, ztype in (("fp64", np.complex128), ("bf16x3", np.complex64)):
+        hb = [(z.astype(ztype), eo, eu, wk) for z, eo, eu, wk in host]
+        dev = [Block(torch.from_numpy(np.ascontiguousarray(z)).cuda(), torch.from_numpy(eo).cuda(),
+                     torch.from_numpy(eu).cuda(), wk) for z, eo, eu, wk in hb]
+        out = torch.full((nomega, npb, npb), 5.0 + 1j, dtype=torch.complex128, device="cuda")
+        ctx.chi0_accumulate([Problem(dev, torch.from_numpy(omega).cuda(), out)], precision=path,
+                            delta_min=DMIN)
+        ctx.sync()
+        assert_hermitian_exact(out)
+        got = out.cpu().numpy()
+        if path == "fp64":
+            ref = oracle.chi0_ref([(z.astype(np.complex128), eo, eu, wk) for z, eo, eu, wk in hb],
+                                  npb, omega, DMIN)
+            e = _per_omega_rel(got, ref)
+            assert np.all(e <= 1e-12), e
+        else:
+            ref = chi0_model(hb, npb, omega, DMIN, "bf16x3")
+            e = _per_omega_rel(got, ref)
+            assert np.all(e <= 3e-7), e
