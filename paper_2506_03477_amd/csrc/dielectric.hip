@@ -151,9 +151,13 @@ __global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(
 // The panel's nb columns are processed as sub-panels of 8: a sub-panel lives
 // in registers (thread t owns rows t + 1024 r) through its 8 elimination
 // steps (pivot search by wave shuffles, row interchange and pivot-row
-// broadcast through LDS); it is then stored and its combined transformation
-// is applied to the other columns of the panel as a rank-8 update:
+// broadcast through LDS); it is then stored and, for nb > 8, its combined
+// transformation is applied to the other columns of the panel as a rank-8
+// update:
 //   y = (interchanges) x;   x <- y (rows outside the sub-panel) + C y[sub-panel rows].
+// The inverse launches it one sub-panel at a time (nb <= 8) and applies each
+// sub-panel with the interchange and update kernels restricted to the panel,
+// which use every CU.
 template <int R>
 __global__ __launch_bounds__(kPanelThreads) void gj_panel_reg_kernel(
     double2* __restrict__ work, int n, int k0, int nb, int32_t* __restrict__ piv,
