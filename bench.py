@@ -2,7 +2,11 @@
 dielectric inverse, on one MI355X.
 
 A step = chi0_accumulate (every frequency of the q-point) + dielectric_invert,
-on synthetic inputs already resident in HBM.  Prints one JSON line.
+on synthetic inputs already resident in HBM.  Prints one JSON line.  The
+step's inverse is the Hermitian positive definite sweep by default (eps =
+1 - v^1/2 chi0 v^1/2 with chi0 negative semidefinite), redone with the
+pivoted Gauss-Jordan inverse if a pivot is not positive; --inverse gj times
+the pivoted inverse alone.
 
 Default workload: npb = 2048, nk = 16, nocc = 200, nunocc = 1200, 12
 Gauss-Legendre imaginary frequencies, complex64 Z (62.9 GB), BF16x3 split
@@ -27,6 +31,8 @@ _LOWP = ("paper_2506_03477_amd/csrc/herk_lowp.hip", "paper_2506_03477_amd/csrc/b
          "paper_2506_03477_amd/csrc/herk_common.h")
 KERNEL_SOURCE = {"fp64": ("paper_2506_03477_amd/csrc/herk_fp64.hip", "paper_2506_03477_amd/csrc/herk_common.h"),
                  "fp32": _LOWP, "bf16x3": _LOWP}
+STEP_INVERSE = {"hpd_fallback_gj": "HPD sweeps, pivoted Gauss-Jordan if a pivot is not positive",
+                "gj": "pivoted Gauss-Jordan", "hpd": "HPD sweeps"}
 KERNEL_NAME = {"fp64": "herk_fp64", "fp32": "herk_fp32", "bf16x3": "herk_bf16x3"}
 CALIB_BYTES = 1 << 30   # plain device copy used to calibrate the byte counters
 MFMA_DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}
@@ -532,6 +538,8 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay chi0 from a hipGraph")
+    ap.add_argument("--inverse", default="hpd_fallback_gj", choices=("hpd_fallback_gj", "gj", "hpd"),
+                    help="the step's FP64 inverse of eps")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile configuration index (default: the library's default)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -619,7 +627,7 @@ def main():
 
     def invert_all():
         for chi, inv in zip(chis, invs):
-            ctx.dielectric_invert(vsqrt, chi, inv)
+            ctx.dielectric_invert(vsqrt, chi, inv, method=args.inverse)
 
     def step():
         ctx.chi0_accumulate(probs, precision=prec, delta_min=wl.delta_min, graph=args.graph)
@@ -680,7 +688,7 @@ def main():
                 "executed_mfma_frac": round(exe / PEAK_TFLOPS[prec], 4)}
 
     inv_ms = {}
-    for method in ("gj", "hpd"):
+    for method in ("gj", "hpd", "hpd_fallback_gj"):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -694,6 +702,7 @@ def main():
 
     extra = {"ms_per_q_chi0": round(chi_ms / args.steps / wl.nq, 3),
              "ms_per_q_inverse_gj": inv_ms["gj"], "ms_per_q_inverse_hpd": inv_ms["hpd"],
+             "ms_per_q_inverse_hpd_fallback_gj": inv_ms["hpd_fallback_gj"],
              "ms_per_q_chi0_plus_inverse": round(ms_per_step / wl.nq, 3),
              "nq_per_step": wl.nq, "tile": [tinfo["tile_p"], tinfo["tile_q"]],
              "tile_index": ctx.last_tile(prec), "npairs": npairs}
@@ -745,7 +754,8 @@ def main():
         "config": {"workload": wl.name, "npb": wl.npb, "nq": wl.nq, "nk": wl.nk, "nspin": wl.nspin,
                    "nocc": wl.nocc, "nunocc": wl.nunocc, "nomega": wl.nomega,
                    "ztype": ztype, "path": prec,
-                   "step": "chi0 (all omega) + FP64 Gauss-Jordan inverse of eps"},
+                   "step": "chi0 (all omega) + FP64 inverse of eps",
+                   "inverse": STEP_INVERSE[args.inverse]},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

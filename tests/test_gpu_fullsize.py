@@ -95,22 +95,25 @@ def test_fullsize_sampled_entries(ref, path, tol):
     _say(f"  max normalized entry error {errs.max():.3e} (tol {tol})")
     assert errs.max() <= tol, errs
     if path == "bf16x3":
-        # dielectric step at full size: eps exactly from chi0, inverse residual
+        # dielectric step at full size: eps exactly from chi0, inverse residual,
+        # for the step's default inverse (HPD sweeps with the pivoted fall-back)
+        # and for the pivoted Gauss-Jordan inverse
         inv = torch.empty_like(chi)
         eps = torch.empty_like(chi)
-        ctx.dielectric_invert(vsqrt, chi, inv, eps=eps)
-        ctx.sync()
-        for iw in (0, wl.nomega // 2, wl.nomega - 1):
-            e_ref = oracle.dielectric(chi[iw:iw + 1].cpu().numpy(), wl.vsqrt())[0]
-            e_gpu = eps[iw].cpu().numpy()
-            assert np.array_equal(e_gpu, e_ref)
-            x = inv[iw].cpu().numpy()
-            res = np.linalg.norm(e_gpu @ x - np.eye(wl.npb)) / np.sqrt(wl.npb)
-            kappa_bound = np.linalg.norm(e_gpu)             # lambda_min(eps) >= 1, ||.||_2 <= ||.||_F
-            _say(f"  iw={iw} residual {res:.3e} kappa<={kappa_bound:.3e}")
-            assert res <= 64 * wl.npb * kappa_bound * np.finfo(float).eps
-            asym = np.linalg.norm(x - x.conj().T) / np.linalg.norm(x)
-            assert asym <= 64 * wl.npb * kappa_bound * np.finfo(float).eps, asym
+        for method in ("hpd_fallback_gj", "gj"):
+            ctx.dielectric_invert(vsqrt, chi, inv, eps=eps, method=method)
+            ctx.sync()
+            for iw in (0, wl.nomega // 2, wl.nomega - 1):
+                e_ref = oracle.dielectric(chi[iw:iw + 1].cpu().numpy(), wl.vsqrt())[0]
+                e_gpu = eps[iw].cpu().numpy()
+                assert np.array_equal(e_gpu, e_ref)
+                x = inv[iw].cpu().numpy()
+                res = np.linalg.norm(e_gpu @ x - np.eye(wl.npb)) / np.sqrt(wl.npb)
+                kappa_bound = np.linalg.norm(e_gpu)         # lambda_min(eps) >= 1, ||.||_2 <= ||.||_F
+                _say(f"  {method} iw={iw} residual {res:.3e} kappa<={kappa_bound:.3e}")
+                assert res <= 64 * wl.npb * kappa_bound * np.finfo(float).eps
+                asym = np.linalg.norm(x - x.conj().T) / np.linalg.norm(x)
+                assert asym <= 64 * wl.npb * kappa_bound * np.finfo(float).eps, asym
     del prob
     ctx.close()
     torch.cuda.empty_cache()
