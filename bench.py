@@ -582,8 +582,8 @@ def main():
         bench_hist(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (sharding "
+                                   "q-points and k-blocks over GPUs is designed, not built)"}))
         sys.exit(2)
 
     import numpy as np
@@ -599,7 +599,7 @@ def main():
     torch.cuda.set_device(0)
     ctx = Context(0)
     if ctx.tile_count(prec) <= 0:
-        raise SystemExit(f"precision {prec} has no kernel in this build")
+        raise SystemExit(f"precision {prec} has no kernel in this library")
     if args.tile >= 0:
         ctx.set_tile(prec, args.tile)
     ztype = "c128" if prec == "fp64" else "c64"

@@ -638,7 +638,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
                    int mode = kWeightsChi0, const GatherHook* hk = nullptr) {
   const int kind = kind_of(prec);
   const int ntile = herk_tile_count(kind);
-  if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this build", prec);
+  if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this library", prec);
   int tile_idx = tile_override >= 0 ? tile_override
                  : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
                  : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind]
@@ -1933,7 +1933,7 @@ int chi0_autotune(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_
   HIP_TRY(hipSetDevice(h->device));
   const int k = kind_of(prec);
   const int n = herk_tile_count(k);
-  if (n <= 0) return fail(CHI0_EUNSUPPORTED, "precision has no kernel in this build");
+  if (n <= 0) return fail(CHI0_EUNSUPPORTED, "precision has no kernel in this library");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipEvent_t a = nullptr, b = nullptr;
   HIP_TRY(hipEventCreate(&a));
