@@ -1,0 +1,72 @@
+"""Host-side logic of bench.py (CPU): the one-GPU contract, the flop counts
+against explicit counts on small sizes, the tile count against brute force,
+the step's inverse choices against the binding, and the stored traffic
+counters against the current kernel sources."""
+import glob
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+from paper_2506_03477_amd import _lib  # noqa: E402
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_exits(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+@pytest.mark.parametrize("npb,npairs,nomega", [(1, 1, 1), (3, 5, 2), (7, 2, 3)])
+def test_zherk_flops_explicit(npb, npairs, nomega):
+    # one complex multiply-add (8 real flops) per pair, per lower-triangle
+    # entry (diagonal included), per frequency
+    macs = sum(1 for _ in range(nomega) for _ in range(npairs)
+               for p in range(npb) for q in range(npb) if p >= q)
+    assert bench.zherk_flops(npb, npairs, nomega) == 8 * macs
+
+
+@pytest.mark.parametrize("npb", [1, 5, 64, 100, 128, 257, 300])
+@pytest.mark.parametrize("tp,tq", [(128, 128), (256, 128), (64, 64), (32, 16)])
+def test_lower_tile_count_brute(npb, tp, tq):
+    brute = 0
+    for r in range(-(-npb // tp)):
+        for c in range(-(-npb // tq)):
+            rows = range(r * tp, min((r + 1) * tp, npb))
+            cols = range(c * tq, min((c + 1) * tq, npb))
+            if any(i >= j for i in rows for j in cols):
+                brute += 1
+    assert bench.lower_tile_count(npb, tp, tq) == brute
+
+
+def test_step_inverse_choices_match_binding():
+    assert set(bench.STEP_INVERSE) == set(_lib.INV_METHOD)
+
+
+def test_source_sha_ignores_comments(tmp_path, monkeypatch):
+    a = tmp_path / "a.hip"
+    a.write_text("int f() { return 1; }  // note\n/* block\n comment */\n")
+    monkeypatch.setitem(bench.KERNEL_SOURCE, "probe", (str(a),))
+    s0 = bench.source_sha("probe")
+    a.write_text("// other note\nint  f()  {\n return 1; }\n")
+    assert bench.source_sha("probe") == s0
+    a.write_text("int f() { return 2; }\n")
+    assert bench.source_sha("probe") != s0
+
+
+def test_stored_traffic_matches_kernel_sources():
+    files = glob.glob(os.path.join(ROOT, "profiles", "traffic_herk_bf16x3_*.json"))
+    assert files
+    for f in files:
+        with open(f) as fh:
+            t = json.load(fh)
+        assert t["kernel_source_sha"] == bench.source_sha("bf16x3"), f
+        assert t["traffic_bytes_per_launch"] > 0
