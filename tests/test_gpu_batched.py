@@ -97,3 +97,44 @@ def test_bf16_default_tile_follows_size(batch):
     _say(f"  rel err: chosen {e_auto:.3e}, tall {e_tall:.3e}")
     assert e_auto <= 2e-6 and e_tall <= 2e-6
     ctx.close()
+
+
+@pytest.mark.parametrize("tile", [None, 7])
+def test_bf16_graph_replay(batch, tile):
+    """BF16x3 chi0 replayed from a hipGraph (pair weights, the pre-split pass
+    when the tall tile runs, the rank-K kernel, the reduction): each replay,
+    with eager work and synchronizations between them, equals the eager call
+    bit for bit, in overwrite and in accumulate mode."""
+    wl, probs = batch
+    sub = probs[:6]
+    _say(f"bf16x3 graph replay, tile {tile}")
+    ctx = Context(0)
+    if tile is not None:
+        ctx.set_tile("bf16x3", tile)
+    ctx.chi0_accumulate(sub, precision="bf16x3", delta_min=wl.delta_min)
+    ctx.sync()
+    direct = [p.chi0.clone() for p in sub]
+    for rep in range(3):
+        for p in sub:
+            p.chi0.fill_(7.0)
+        ctx.chi0_accumulate(sub, precision="bf16x3", delta_min=wl.delta_min, graph=True)
+        ctx.sync()
+        _ = torch.randn(4096, device="cuda").sum()
+        torch.cuda.synchronize()
+        for p, d in zip(sub, direct):
+            assert torch.equal(p.chi0, d), rep
+    for rep in range(2):
+        for p, d in zip(sub, direct):
+            p.chi0.copy_(d)
+        ctx.chi0_accumulate(sub, precision="bf16x3", delta_min=wl.delta_min, accumulate=True,
+                            graph=True)
+        ctx.sync()
+        _ = torch.randn(4096, device="cuda").sum()
+        torch.cuda.synchronize()
+        for p, d in zip(sub, direct):
+            assert torch.equal(p.chi0, 2 * d), rep
+    if tile is not None:
+        assert ctx.last_tile("bf16x3") == tile
+    ref = oracle_chi0(wl, q=0)
+    assert rel_fro(direct[0].cpu().numpy(), ref).max() <= 2e-6
+    ctx.close()
