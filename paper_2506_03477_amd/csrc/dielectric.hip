@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(
     const int i = e / kPanel;
     double2 v = {0.0, 0.0};
     if (b < nb && i0 + i < n) v = S[static_cast<size_t>(i0 + i) * n + k0 + b];
-    sC[b][i] = v;
+    sC[b][i ^ (b & 15)] = v;   // rows XOR-swizzled by b: the 32 b of one row spread over the banks
     const int bj = e / T;
     const int jj = e % T;
     double2 w = {0.0, 0.0};
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(
     double av[2], wr_[2], wi_[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const double2 x = sC[b][wr * 32 + a * 16 + m];
+      const double2 x = sC[b][wr * 32 + a * 16 + (m ^ (b & 15))];
       av[a] = isim ? x.y : x.x;
     }
 #pragma unroll

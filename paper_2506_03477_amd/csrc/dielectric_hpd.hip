@@ -193,8 +193,9 @@ __global__ __launch_bounds__(256) void hpd_update_kernel(double2* __restrict__ w
     const int ri = i0 + rr, rj = j0 + rr;
     const bool oki = ri < n && !(ri >= k0 && ri < k0 + nb) && b < nb;
     const bool okj = rj < n && !(rj >= k0 && rj < k0 + nb) && b < nb;
-    sC[b][rr] = oki ? Cm[static_cast<size_t>(ri) * kNb + b] : double2{0.0, 0.0};
-    sP[b][rr] = okj ? Pm[static_cast<size_t>(rj) * kNb + b] : double2{0.0, 0.0};
+    // rows XOR-swizzled by b: the 32 b of one row spread over the LDS banks
+    sC[b][rr ^ (b & 15)] = oki ? Cm[static_cast<size_t>(ri) * kNb + b] : double2{0.0, 0.0};
+    sP[b][rr ^ (b & 15)] = okj ? Pm[static_cast<size_t>(rj) * kNb + b] : double2{0.0, 0.0};
   }
   __syncthreads();
   const int prr = kk >> 1;
@@ -213,12 +214,12 @@ __global__ __launch_bounds__(256) void hpd_update_kernel(double2* __restrict__ w
     double av[2], br[2], bi[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const double2 x = sC[b][wr * 32 + a * 16 + m];
+      const double2 x = sC[b][wr * 32 + a * 16 + (m ^ (b & 15))];
       av[a] = isim ? x.y : x.x;
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const double2 y = sP[b][wc * 32 + c * 16 + m];
+      const double2 y = sP[b][wc * 32 + c * 16 + (m ^ (b & 15))];
       br[c] = isim ? y.y : y.x;
       bi[c] = isim ? y.x : -y.y;
     }
