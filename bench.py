@@ -127,6 +127,19 @@ def traffic_file(prec, workload_name):
     return os.path.join(ROOT, "profiles", f"traffic_{KERNEL_NAME[prec]}_{workload_name}.json")
 
 
+def stored_traffic(prec, workload_name):
+    """HBM bytes per launch from the stored counter runs, or None when there
+    are none or the kernel's code has changed since they were taken."""
+    tf = traffic_file(prec, workload_name)
+    if not os.path.exists(tf):
+        return None
+    with open(tf) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != source_sha(prec):
+        return None
+    return round(t["traffic_bytes_per_launch"])
+
+
 def _dispatch_counters(db, counter):
     """{kernel_name: [value per dispatch]} for one counter of a rocprofv3 --pmc run."""
     import sqlite3
@@ -672,13 +685,7 @@ def main():
         ach = flops / (kern_avg_ms * 1e-3) / 1e12
         exe = executed_mfma_flops(wl.npb, npairs, wl.nomega, tinfo["tile_p"], tinfo["tile_q"],
                                   prec) / (kern_avg_ms * 1e-3) / 1e12
-        traffic = None
-        tf = traffic_file(prec, wl.name)
-        if os.path.exists(tf):
-            with open(tf) as f:
-                t = json.load(f)
-            if t.get("kernel_source_sha") == source_sha(prec):
-                traffic = round(t["traffic_bytes_per_launch"])
+        traffic = stored_traffic(prec, wl.name)
         roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec],
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4), "traffic": traffic,
                 "algorithmic_bytes": int(npairs * wl.npb * (16 if prec == "fp64" else 8)

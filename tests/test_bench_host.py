@@ -1,7 +1,7 @@
 """Host-side logic of bench.py (CPU): the one-GPU contract, the flop counts
 against explicit counts on small sizes, the tile count against brute force,
-the step's inverse choices against the binding, and the stored traffic
-counters against the current kernel sources."""
+the step's inverse choices against the binding, and the rule that stored
+traffic counters count only for the kernel code they were taken on."""
 import glob
 import json
 import os
@@ -62,11 +62,26 @@ def test_source_sha_ignores_comments(tmp_path, monkeypatch):
     assert bench.source_sha("probe") != s0
 
 
-def test_stored_traffic_matches_kernel_sources():
-    files = glob.glob(os.path.join(ROOT, "profiles", "traffic_herk_bf16x3_*.json"))
+def test_stored_traffic_only_for_current_kernel(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_text("__global__ void k() {}\n")
+    monkeypatch.setitem(bench.KERNEL_SOURCE, "probe", (str(src),))
+    tf = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "traffic_file", lambda prec, name: str(tf))
+    assert bench.stored_traffic("probe", "w") is None                   # no counters stored
+    tf.write_text(json.dumps({"kernel_source_sha": bench.source_sha("probe"),
+                              "traffic_bytes_per_launch": 1234.4}))
+    assert bench.stored_traffic("probe", "w") == 1234
+    src.write_text("// a comment only\n__global__ void k() {}\n")
+    assert bench.stored_traffic("probe", "w") == 1234                   # comment edits keep them
+    src.write_text("__global__ void k() { int x = 0; }\n")
+    assert bench.stored_traffic("probe", "w") is None                   # code edits void them
+
+
+def test_committed_traffic_files_well_formed():
+    files = glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))
     assert files
     for f in files:
         with open(f) as fh:
             t = json.load(fh)
-        assert t["kernel_source_sha"] == bench.source_sha("bf16x3"), f
-        assert t["traffic_bytes_per_launch"] > 0
+        assert len(t["kernel_source_sha"]) == 16 and t["traffic_bytes_per_launch"] > 0, f
