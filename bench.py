@@ -72,6 +72,25 @@ def executed_mfma_flops(npb, npairs, nomega, tile_p, tile_q, prec):
             * SPLIT_FACTOR[prec])
 
 
+def size_sample(run, nmax, target_s):
+    """Size an oracle sample to about target_s seconds: one warm-up call
+    (thread pools, caches), a one-state probe, the sized run, and one resize
+    if that run took under two thirds of the target.  run(n) returns the seconds (or
+    a tuple whose first item is).  Returns (n, the last run's result)."""
+    def secs(r):
+        return r[0] if isinstance(r, tuple) else r
+
+    run(1)
+    r = run(1)
+    n = int(min(nmax, max(1, round(target_s / max(secs(r), 1e-4)))))
+    if n > 1:
+        r = run(n)
+    if secs(r) < (2.0 / 3.0) * target_s and n < nmax:
+        n = int(min(nmax, max(n + 1, round(n * target_s / max(secs(r), 1e-4)))))
+        r = run(n)
+    return n, r
+
+
 def cpu_baseline(wl, target_s=15.0):
     """Time the oracle on a bounded sample of the workload (first occupied
     states of the first block, all product-basis functions, all frequencies)
@@ -92,9 +111,7 @@ def cpu_baseline(wl, target_s=15.0):
         oracle.chi0_ref([(z, eo[:nocc_s], eu, blk.wk)], wl.npb, wl.omega, wl.delta_min)
         return time.perf_counter() - t0
 
-    t1 = run(1)                        # probe, then one timed run of ~target_s
-    nocc_s = int(min(blk.nocc, max(1, round(target_s / max(t1, 1e-4)))))
-    t_meas = run(nocc_s) if nocc_s > 1 else t1
+    nocc_s, t_meas = size_sample(run, blk.nocc, target_s)
     flops = zherk_flops(wl.npb, nocc_s * blk.nunocc, wl.nomega)
     threads = 0
     for info in threadpool_info():
@@ -233,9 +250,7 @@ def sigx_cpu_baseline(wl, target_s=10.0):
         sigx_ref([(z, v, blk.wk)], wl.npb)
         return time.perf_counter() - t0
 
-    t1 = run(1)
-    nocc_s = int(min(blk.nocc, max(1, round(target_s / max(t1, 1e-4)))))
-    t_meas = run(nocc_s) if nocc_s > 1 else t1
+    nocc_s, t_meas = size_sample(run, blk.nocc, target_s)
     flops = zherk_flops(wl.npb, nocc_s * blk.nunocc, 1)
     threads = 0
     for info in threadpool_info():
@@ -343,9 +358,7 @@ def sigc_cpu_baseline(wl, target_s=15.0):
         sigc_ref([(z, wc, eps_mid[:nall_s], blk.wk)], eps_qp, wl.omega)
         return time.perf_counter() - t0
 
-    t1 = run(1)
-    nall_s = int(min(blk.nocc, max(1, round(target_s / max(t1, 1e-4)))))
-    t_meas = run(nall_s) if nall_s > 1 else t1
+    nall_s, t_meas = size_sample(run, blk.nocc, target_s)
     flops = sum(sigc_flops(wl.npb, nall_s, blk.nunocc, wl.nomega))
     threads = 0
     for info in threadpool_info():
@@ -466,9 +479,7 @@ def hist_cpu_baseline(wl, edges, target_s=10.0):
         bins, _ = H.pair_bins(eo[:nocc_s], eu, win, HIST_SIGMA, 0.0, blk.wk)
         return dt, int((bins >= 0).sum())
 
-    t1, n1 = run(1)
-    nocc_s = int(min(blk.nocc, max(1, round(target_s / max(t1, 1e-4)))))
-    t_meas, nrec = run(nocc_s) if nocc_s > 1 else (t1, n1)
+    nocc_s, (t_meas, nrec) = size_sample(run, blk.nocc, target_s)
     flops = zherk_flops(wl.npb, nrec, 1)
     threads = 0
     for info in threadpool_info():

@@ -85,3 +85,27 @@ def test_committed_traffic_files_well_formed():
         with open(f) as fh:
             t = json.load(fh)
         assert len(t["kernel_source_sha"]) == 16 and t["traffic_bytes_per_launch"] > 0, f
+
+
+@pytest.mark.parametrize("per_state,warm,nmax,tuple_out", [
+    (0.5, 3.0, 1000, False),      # a slow first call must not shrink the sample
+    (0.5, 0.0, 1000, True),
+    (0.5, 0.0, 10, False),        # capped by the states there are
+    (100.0, 0.0, 1000, False),    # one state already exceeds the target
+])
+def test_size_sample(per_state, warm, nmax, tuple_out):
+    calls = []
+
+    def run(n):
+        t = (warm if not calls else 0.0) + per_state * n
+        calls.append(n)
+        return (t, 7 * n) if tuple_out else t
+
+    n, r = bench.size_sample(run, nmax, target_s=15.0)
+    t = r[0] if tuple_out else r
+    assert 1 <= n <= nmax and calls[-1] == n
+    if tuple_out:
+        assert r[1] == 7 * n
+    if per_state * nmax >= 10.0 and per_state <= 15.0:
+        assert 10.0 <= t <= 30.0, (n, t)
+    assert sum(per_state * c for c in calls) <= 3 * 15.0 + per_state * 2
