@@ -75,18 +75,27 @@ def executed_mfma_flops(npb, npairs, nomega, tile_p, tile_q, prec):
 def size_sample(run, nmax, target_s):
     """Size an oracle sample to about target_s seconds: one warm-up call
     (thread pools, caches), a one-state probe, the sized run, and one resize
-    if that run took under two thirds of the target.  run(n) returns the seconds (or
+    (from the line through the probe and that run, so a fixed cost per call
+    counts) if that run took under two thirds of the target.  run(n) returns the seconds (or
     a tuple whose first item is).  Returns (n, the last run's result)."""
     def secs(r):
         return r[0] if isinstance(r, tuple) else r
 
     run(1)
     r = run(1)
-    n = int(min(nmax, max(1, round(target_s / max(secs(r), 1e-4)))))
+    t1 = secs(r)
+    n = int(min(nmax, max(1, round(target_s / max(t1, 1e-4)))))
     if n > 1:
         r = run(n)
-    if secs(r) < (2.0 / 3.0) * target_s and n < nmax:
-        n = int(min(nmax, max(n + 1, round(n * target_s / max(secs(r), 1e-4)))))
+    t = secs(r)
+    if t < (2.0 / 3.0) * target_s and n < nmax:
+        if n > 1 and t > t1:           # seconds = a + b n through the probe and the sized run
+            b = (t - t1) / (n - 1)
+            a = max(0.0, t1 - b)
+            n2 = round((target_s - a) / b)
+        else:
+            n2 = round(n * target_s / max(t, 1e-4))
+        n = int(min(nmax, max(n + 1, n2)))
         r = run(n)
     return n, r
 

@@ -87,17 +87,19 @@ def test_committed_traffic_files_well_formed():
         assert len(t["kernel_source_sha"]) == 16 and t["traffic_bytes_per_launch"] > 0, f
 
 
-@pytest.mark.parametrize("per_state,warm,nmax,tuple_out", [
-    (0.5, 3.0, 1000, False),      # a slow first call must not shrink the sample
-    (0.5, 0.0, 1000, True),
-    (0.5, 0.0, 10, False),        # capped by the states there are
-    (100.0, 0.0, 1000, False),    # one state already exceeds the target
+@pytest.mark.parametrize("per_state,warm,nmax,tuple_out,fixed", [
+    (0.5, 3.0, 1000, False, 0.0),      # a slow first call must not shrink the sample
+    (0.5, 0.0, 1000, True, 0.0),
+    (0.5, 0.0, 10, False, 0.0),        # capped by the states there are
+    (100.0, 0.0, 1000, False, 0.0),    # one state already exceeds the target
+    (0.04, 0.0, 200, True, 2.5),       # a fixed cost per call dominates small samples
+    (0.7, 0.0, 1000, False, 6.0),
 ])
-def test_size_sample(per_state, warm, nmax, tuple_out):
+def test_size_sample(per_state, warm, nmax, tuple_out, fixed):
     calls = []
 
     def run(n):
-        t = (warm if not calls else 0.0) + per_state * n
+        t = (warm if not calls else 0.0) + fixed + per_state * n
         calls.append(n)
         return (t, 7 * n) if tuple_out else t
 
@@ -106,6 +108,6 @@ def test_size_sample(per_state, warm, nmax, tuple_out):
     assert 1 <= n <= nmax and calls[-1] == n
     if tuple_out:
         assert r[1] == 7 * n
-    if per_state * nmax >= 10.0 and per_state <= 15.0:
+    if fixed + per_state * nmax >= 10.0 and fixed + per_state <= 15.0:
         assert 10.0 <= t <= 30.0, (n, t)
-    assert sum(per_state * c for c in calls) <= 3 * 15.0 + per_state * 2
+    assert sum(fixed + per_state * c for c in calls) <= 4 * 15.0 + per_state * 2
