@@ -20,7 +20,10 @@ What it computes (all complex128 / float64):
   conjugation on the first basis index, as in the GEMM Z_pair^dagger x W_Zpair
   of Algorithm "hrcxq" (the printed Eq.(polfx) conjugates the second index;
   the two conventions are transposes of each other since chi0 is Hermitian).
-  A pair is included iff D > 0 and D >= delta_min.
+  A pair is included iff D > 0 and D >= delta_min.  A pair with D <= 0 (an
+  "unoccupied" state at or below an occupied one) is not a transition of
+  Eq.(polfx); such input is rejected (``InvalidPairs``) unless the caller
+  asks for it to be skipped (``strict=False``).
 * eps[I, J] = delta_IJ - s_I chi0[I, J] s_J with s_I = sqrt(v_I),
   Eq.(dielectricfunction).
 * eps^{-1}: Gauss-Jordan elimination with partial pivoting on [eps | 1]
@@ -30,8 +33,9 @@ What it computes (all complex128 / float64):
   primitive for large matrices.
 * W^c[I, J] = s_I (eps^{-1} - 1)[I, J] s_J, Eq.(wc).
 
-Parity pins for every function live in ``tests/test_oracle_pins.py``; none of
-the functions here is "parity unpinned".
+Parity pins for every function live in ``tests/pins.py`` (run by
+``tests/test_oracle_pins.py``); none of the functions here is "parity
+unpinned".
 """
 from __future__ import annotations
 
@@ -54,6 +58,23 @@ def pair_included(delta: np.ndarray, delta_min: float) -> np.ndarray:
     """Pairs that enter the sum: positive excitation energy at or above the
     intraband cut delta_min."""
     return (delta > 0.0) & (delta >= delta_min)
+
+
+class InvalidPairs(ValueError):
+    """Some pair has D = eps_unocc - eps_occ <= 0."""
+
+
+def nonpositive_pairs(eps_occ: np.ndarray, eps_unocc: np.ndarray) -> int:
+    """Number of pairs with D <= 0 (input the polarization sum does not
+    define: every transition of Eq.(polfx) has a positive energy)."""
+    return int(np.count_nonzero(~(pair_delta(eps_occ, eps_unocc) > 0.0)))
+
+
+def _check_pairs(eps_occ, eps_unocc, strict: bool) -> None:
+    if strict:
+        bad = nonpositive_pairs(eps_occ, eps_unocc)
+        if bad:
+            raise InvalidPairs(f"{bad} pair(s) with D <= 0")
 
 
 def transition_weight(delta: np.ndarray, omega: float, wk: float) -> np.ndarray:
@@ -100,8 +121,10 @@ BlockInput = Tuple[np.ndarray, np.ndarray, np.ndarray, float]
 
 
 def chi0_block(z: np.ndarray, eps_occ: np.ndarray, eps_unocc: np.ndarray,
-               wk: float, omega: Sequence[float], delta_min: float) -> np.ndarray:
+               wk: float, omega: Sequence[float], delta_min: float,
+               strict: bool = True) -> np.ndarray:
     """Contribution of one block: [nomega, npb, npb] complex128."""
+    _check_pairs(eps_occ, eps_unocc, strict)
     z = np.asarray(z)
     nocc, nunocc, npb = z.shape
     a = z.reshape(nocc * nunocc, npb).astype(np.complex128)
@@ -117,18 +140,19 @@ def chi0_block(z: np.ndarray, eps_occ: np.ndarray, eps_unocc: np.ndarray,
 
 
 def chi0_ref(blocks: Iterable[BlockInput], npb: int, omega: Sequence[float],
-             delta_min: float = 0.0) -> np.ndarray:
+             delta_min: float = 0.0, strict: bool = True) -> np.ndarray:
     """chi0[nomega, npb, npb] for one q-point, streaming over blocks."""
     acc = _CompensatedSum((len(omega), npb, npb))
     for z, eo, eu, wk in blocks:
-        acc.add(chi0_block(z, eo, eu, wk, omega, delta_min))
+        acc.add(chi0_block(z, eo, eu, wk, omega, delta_min, strict))
     return acc.value()
 
 
 def chi0_ref_per_block(blocks: Iterable[BlockInput], npb: int,
-                       omega: Sequence[float], delta_min: float = 0.0) -> List[np.ndarray]:
+                       omega: Sequence[float], delta_min: float = 0.0,
+                       strict: bool = True) -> List[np.ndarray]:
     """Per-block contributions (for additivity / per-spin diagnostics)."""
-    return [chi0_block(z, eo, eu, wk, omega, delta_min) for z, eo, eu, wk in blocks]
+    return [chi0_block(z, eo, eu, wk, omega, delta_min, strict) for z, eo, eu, wk in blocks]
 
 
 # ---------------------------------------------------------------------------
@@ -137,9 +161,10 @@ def chi0_ref_per_block(blocks: Iterable[BlockInput], npb: int,
 
 
 def chi0_brute(blocks: Iterable[BlockInput], npb: int, omega: Sequence[float],
-               delta_min: float = 0.0) -> np.ndarray:
+               delta_min: float = 0.0, strict: bool = True) -> np.ndarray:
     out = np.zeros((len(omega), npb, npb), np.complex128)
     for z, eo, eu, wk in blocks:
+        _check_pairs(eo, eu, strict)
         nocc, nunocc, _ = np.shape(z)
         for iw, w in enumerate(omega):
             for n in range(nocc):
@@ -161,13 +186,15 @@ def chi0_brute(blocks: Iterable[BlockInput], npb: int, omega: Sequence[float],
 
 
 def chi0_exact(blocks, npb: int, omega: Sequence[Fraction],
-               delta_min: Fraction = Fraction(0)):
+               delta_min: Fraction = Fraction(0), strict: bool = True):
     """Exact chi0 with Fractions.  Z entries are (re, im) pairs of Fractions;
     energies, w_k and omega are Fractions.  Returns nested lists
     [iw][I][J] of (re, im) Fraction pairs."""
     res = [[[(Fraction(0), Fraction(0)) for _ in range(npb)] for _ in range(npb)]
            for _ in omega]
     for z, eo, eu, wk in blocks:
+        if strict and any(not (u - o > 0) for o in eo for u in eu):
+            raise InvalidPairs("pair(s) with D <= 0")
         for iw, w in enumerate(omega):
             for n in range(len(eo)):
                 for m in range(len(eu)):
@@ -194,7 +221,8 @@ def chi0_exact(blocks, npb: int, omega: Sequence[Fraction],
 
 def chi0_entries(block_columns: Iterable[Tuple[np.ndarray, np.ndarray, np.ndarray, float]],
                  entries: Sequence[Tuple[int, int]], col_index: dict,
-                 omega: Sequence[float], delta_min: float = 0.0) -> np.ndarray:
+                 omega: Sequence[float], delta_min: float = 0.0,
+                 strict: bool = True) -> np.ndarray:
     """chi0[iw, I, J] for the listed (I, J) entries only.
 
     ``block_columns`` yields (Zc[K, ncols], eps_occ, eps_unocc, w_k) where Zc
@@ -204,6 +232,7 @@ def chi0_entries(block_columns: Iterable[Tuple[np.ndarray, np.ndarray, np.ndarra
     ii = np.array([col_index[i] for i, _ in entries])
     jj = np.array([col_index[j] for _, j in entries])
     for zc, eo, eu, wk in block_columns:
+        _check_pairs(eo, eu, strict)
         delta = pair_delta(eo, eu).reshape(-1)
         keep = pair_included(delta, delta_min)
         zc = np.asarray(zc, np.complex128)[keep]

@@ -44,7 +44,7 @@ from typing import Iterable, List, Sequence, Tuple
 
 import numpy as np
 
-from .chi0_oracle import _CompensatedSum, pair_delta, pair_included
+from .chi0_oracle import InvalidPairs, _CompensatedSum, _check_pairs, pair_delta, pair_included
 
 
 def check_edges(edges: Sequence[float]) -> np.ndarray:
@@ -139,20 +139,25 @@ def hist_block(z: np.ndarray, eps_occ, eps_unocc, wk, edges, sigma, delta_min) -
     return out
 
 
-def hist_ref(blocks: Iterable, npb: int, edges, sigma: float, delta_min: float = 0.0) -> np.ndarray:
-    """hist_j summed over blocks (compensated), [nb][npb][npb]."""
+def hist_ref(blocks: Iterable, npb: int, edges, sigma: float, delta_min: float = 0.0,
+             strict: bool = True) -> np.ndarray:
+    """hist_j summed over blocks (compensated), [nb][npb][npb].  Pairs with
+    D <= 0 are rejected (InvalidPairs) unless strict=False skips them."""
     e = check_edges(edges)
     acc = _CompensatedSum((e.size - 1, npb, npb))
     for z, eo, eu, wk in blocks:
+        _check_pairs(eo, eu, strict)
         acc.add(hist_block(z, eo, eu, wk, e, sigma, delta_min))
     return acc.value()
 
 
-def hist_brute(blocks: Iterable, npb: int, edges, sigma: float, delta_min: float = 0.0) -> np.ndarray:
+def hist_brute(blocks: Iterable, npb: int, edges, sigma: float, delta_min: float = 0.0,
+               strict: bool = True) -> np.ndarray:
     """Explicit loops over pairs, bins and (I, J) (tiny inputs only)."""
     e = check_edges(edges)
     out = np.zeros((e.size - 1, npb, npb), np.complex128)
     for z, eo, eu, wk in blocks:
+        _check_pairs(eo, eu, strict)
         for n in range(len(eo)):
             for m in range(len(eu)):
                 d = float(eu[m] - eo[n])
@@ -165,12 +170,15 @@ def hist_brute(blocks: Iterable, npb: int, edges, sigma: float, delta_min: float
     return out
 
 
-def hist_exact(blocks, npb: int, edges: Sequence[Fraction], delta_min=Fraction(0)):
+def hist_exact(blocks, npb: int, edges: Sequence[Fraction], delta_min=Fraction(0),
+               strict: bool = True):
     """Exact histogram for sigma = 0 with rational energies, weights and
     (re, im) Fraction Z entries: [nb][npb][npb] of (re, im)."""
     nb = len(edges) - 1
     out = [[[(Fraction(0), Fraction(0)) for _ in range(npb)] for _ in range(npb)] for _ in range(nb)]
     for z, eo, eu, wk in blocks:
+        if strict and any(not (u - o > 0) for o in eo for u in eu):
+            raise InvalidPairs("pair(s) with D <= 0")
         for n in range(len(eo)):
             for m in range(len(eu)):
                 d = eu[m] - eo[n]
@@ -190,7 +198,7 @@ def hist_exact(blocks, npb: int, edges: Sequence[Fraction], delta_min=Fraction(0
 
 
 def hist_entries(block_columns, edges, sigma: float, entries: Sequence[Tuple[int, int]],
-                 col_index: dict, delta_min: float = 0.0) -> np.ndarray:
+                 col_index: dict, delta_min: float = 0.0, strict: bool = True) -> np.ndarray:
     """hist_j[I][J] of the listed entries only, [nb][len(entries)].
     ``block_columns`` yields (Zc[K, ncols], eps_occ, eps_unocc, w_k) with Zc
     holding the columns of Z (pairs n-major) listed in ``col_index``."""
@@ -200,6 +208,7 @@ def hist_entries(block_columns, edges, sigma: float, entries: Sequence[Tuple[int
     jj = np.array([col_index[j] for _, j in entries])
     acc = _CompensatedSum((nb, len(entries)))
     for zc, eo, eu, wk in block_columns:
+        _check_pairs(eo, eu, strict)
         zc = np.asarray(zc, np.complex128)
         bins, w = pair_bins(eo, eu, e, sigma, delta_min, wk)
         prod = zc[:, ii].conj() * zc[:, jj]                    # [K, entries]

@@ -337,9 +337,73 @@ def pin_inverse(orc):
     return fails
 
 
+def pin_entries(orc):
+    """Sampled entries (the full-size checks' oracle) against the hand-derived
+    golden example, exact rational brute force and the loop tier.  The
+    columns are handed over in a permuted order through the column map, the
+    blocks have unequal w_k, a delta_min cut drops pairs, and (I, J) entries
+    are asymmetric (I != J both ways), so the conjugation side, the column
+    map, the cut and w_k all show."""
+    fails = []
+    # golden example: Z columns reversed, all four entries
+    g, z, eo, eu, wk, s = _load_golden()
+    ents = [(0, 0), (0, 1), (1, 0), (1, 1)]
+    zc = z.reshape(-1, 2)[:, ::-1]
+    for case in g["cases"]:
+        w = float(Fraction(case["omega"]))
+        dmin = float(Fraction(case["delta_min"]))
+        got = orc.chi0_entries([(zc, eo, eu, wk)], ents, {0: 1, 1: 0}, [w], dmin)[0]
+        ref = _frac_mat(case["chi0"])
+        if not _close(got, np.array([ref[i, j] for i, j in ents]), 1e-15):
+            fails.append(f"entries golden omega={w} dmin={dmin}: {got}")
+    # exact rationals: small integer Z, dyadic energies, w_k 1/2, 1/4, 1/8
+    rng = np.random.default_rng(17)
+    bf, bq = _small_int_problem(rng, nblocks=3, nocc=2, nunocc=3, npb=4)
+    wks = [Fraction(1, 2), Fraction(1, 4), Fraction(1, 8)]
+    bf = [(zz, o, u, float(w)) for (zz, o, u, _), w in zip(bf, wks)]
+    bq = [(zz, o, u, w) for (zz, o, u, _), w in zip(bq, wks)]
+    cols = [3, 1, 2]
+    col_index = {c: k for k, c in enumerate(cols)}
+    ents = [(3, 1), (1, 3), (2, 2), (3, 3), (1, 2), (2, 1)]
+    omega_f, omega_q = [0.0, 0.5, 2.0], [Fraction(0), Fraction(1, 2), Fraction(2)]
+    for dmin_f, dmin_q in ((0.0, Fraction(0)), (0.5, Fraction(1, 2))):
+        ex = orc.chi0_exact(bq, 4, omega_q, dmin_q)
+        want = np.array([[complex(float(ex[iw][i][j][0]), float(ex[iw][i][j][1])) for i, j in ents]
+                         for iw in range(len(omega_q))])
+        bc = [(zz.reshape(-1, 4)[:, cols], o, u, w) for zz, o, u, w in bf]
+        got = orc.chi0_entries(bc, ents, col_index, omega_f, dmin_f)
+        err = np.max(np.abs(got - want)) / max(np.max(np.abs(want)), 1e-300)
+        if not err <= 1e-15:
+            fails.append(f"entries vs exact, dmin={dmin_f}: {err}")
+    # loop tier on a random problem with a cut that removes some pairs
+    rng = np.random.default_rng(23)
+    npb = 7
+    blocks = _random_problem(rng, npb=npb, nblocks=3, dmin_gap=0.02)
+    blocks = [(zz, o, u, w * (1 + b)) for b, (zz, o, u, w) in enumerate(blocks)]
+    omega = [0.0, 0.3, 2.5]
+    dmin = 0.4
+    brute = orc.chi0_brute(blocks, npb, omega, dmin)
+    ents = [(6, 0), (0, 6), (3, 4), (4, 3), (5, 5), (2, 6)]
+    cols = [6, 0, 4, 3, 5, 2]
+    col_index = {c: k for k, c in enumerate(cols)}
+    bc = [(zz.reshape(-1, npb)[:, cols], o, u, w) for zz, o, u, w in blocks]
+    got = orc.chi0_entries(bc, ents, col_index, omega, dmin)
+    want = np.stack([brute[:, i, j] for i, j in ents], axis=1)
+    if np.max(np.abs(got - want)) > 1e-14 * np.max(np.abs(brute)):
+        fails.append("entries vs loops")
+    # a D <= 0 pair is rejected
+    try:
+        orc.chi0_entries([(np.ones((2, 1)), np.array([0.1, -0.5]), np.array([0.1]), 1.0)],
+                         [(0, 0)], {0: 0}, [1.0])
+        fails.append("entries accepted a pair with D = 0")
+    except orc.InvalidPairs:
+        pass
+    return fails
+
+
 ALL_PINS = [pin_golden, pin_weight_is_polfx_on_imaginary_axis, pin_exact_bruteforce,
             pin_conjugation_side, pin_single_transition, pin_invariants,
-            pin_large_omega_tail, pin_structure, pin_inverse]
+            pin_large_omega_tail, pin_structure, pin_inverse, pin_entries]
 
 
 def run_all(orc):

@@ -223,16 +223,22 @@ def pin_order_properties(orc):
 
 
 def pin_delta_min_as_direct(orc):
-    """The pair filter is the chi0 one: a pair below delta_min, or with
-    D <= 0, contributes nothing; a tie is included."""
+    """The pair filter is the chi0 one: a pair below delta_min contributes
+    nothing, a tie is included, and a pair with D <= 0 is rejected (or,
+    when asked for, skipped)."""
     fails = []
     z = np.ones((1, 3, 2), complex)
     eo = np.array([0.0])
     eu = np.array([-0.1, 0.25, 0.5])                # D = -0.1, 0.25, 0.5
     edges = [0.01, 1.0]
-    h = orc.hist_ref([(z, eo, eu, 1.0)], 2, edges, 0.0, 0.25)
+    h = orc.hist_ref([(z, eo, eu, 1.0)], 2, edges, 0.0, 0.25, strict=False)
     if not _close(h[0], -2 * np.ones((2, 2)), 1e-15):
         fails.append("delta_min filter")
+    try:
+        orc.hist_ref([(z, eo, eu, 1.0)], 2, edges, 0.0, 0.25)
+        fails.append("a pair with D <= 0 was accepted")
+    except ValueError:
+        pass
     return fails
 
 

@@ -35,7 +35,7 @@ def _included_strict(delta, delta_min):
     return (delta > 0.0) & (delta > delta_min)
 
 
-def _block_conj_second(z, eps_occ, eps_unocc, wk, omega, delta_min):
+def _block_conj_second(z, eps_occ, eps_unocc, wk, omega, delta_min, strict=True):
     z = np.asarray(z)
     nocc, nunocc, npb = z.shape
     a = z.reshape(nocc * nunocc, npb).astype(np.complex128)
@@ -50,6 +50,27 @@ def _block_conj_second(z, eps_occ, eps_unocc, wk, omega, delta_min):
 
 
 
+def _entries_variant(conj_second=False, no_mask=False, no_wk=False, ignore_map=False):
+    """chi0_entries with one planted mistake."""
+    def fn(block_columns, entries, col_index, omega, delta_min=0.0, strict=True):
+        acc = orc._CompensatedSum((len(omega), len(entries)))
+        cmap = (lambda i: i) if ignore_map else (lambda i: col_index[i])
+        ii = np.array([cmap(i) for i, _ in entries])
+        jj = np.array([cmap(j) for _, j in entries])
+        for zc, eo, eu, wk in block_columns:
+            orc._check_pairs(eo, eu, strict)
+            delta = orc.pair_delta(eo, eu).reshape(-1)
+            keep = np.ones_like(delta, bool) if no_mask else orc.pair_included(delta, delta_min)
+            zc = np.asarray(zc, np.complex128)[keep]
+            delta = delta[keep]
+            part = np.empty((len(omega), len(entries)), np.complex128)
+            for iw, w in enumerate(omega):
+                c = orc.transition_weight(delta, float(w), 1.0 if no_wk else wk)
+                a, b = zc[:, ii], zc[:, jj]
+                part[iw] = np.sum(c[:, None] * (a * b.conj() if conj_second else a.conj() * b), axis=0)
+            acc.add(part)
+        return acc.value()
+    return fn
 
 
 def _dielectric_plus(chi0, vsqrt):
@@ -99,11 +120,11 @@ def _wc_no_minus_one(eps_inv, vsqrt):
     return s[..., :, None] * d * s[..., None, :]
 
 
-def _ref_drop_last_block(blocks, npb, omega, delta_min=0.0):
+def _ref_drop_last_block(blocks, npb, omega, delta_min=0.0, strict=True):
     blocks = list(blocks)
     acc = orc._CompensatedSum((len(omega), npb, npb))
     for z, eo, eu, wk in blocks[:-1] if len(blocks) > 1 else blocks:
-        acc.add(orc.chi0_block(z, eo, eu, wk, omega, delta_min))
+        acc.add(orc.chi0_block(z, eo, eu, wk, omega, delta_min, strict))
     return acc.value()
 
 
@@ -122,6 +143,10 @@ MUTATIONS = {
     "chol_upper_read": ("cholesky_lower", _chol_upper_read),
     "wc_no_minus_one": ("screened_wc", _wc_no_minus_one),
     "drop_last_block": ("chi0_ref", _ref_drop_last_block),
+    "entries_conj_second": ("chi0_entries", _entries_variant(conj_second=True)),
+    "entries_no_mask": ("chi0_entries", _entries_variant(no_mask=True)),
+    "entries_no_wk": ("chi0_entries", _entries_variant(no_wk=True)),
+    "entries_ignore_col_map": ("chi0_entries", _entries_variant(ignore_map=True)),
 }
 
 
