@@ -27,8 +27,14 @@
  *   - Calls are asynchronous on the given HIP stream (hipStream_t passed as
  *     void*; NULL is the default stream).  Argument errors are returned
  *     synchronously and nothing is enqueued.  Device-side failures (launch
- *     errors, a zero pivot during inversion) are reported by chi0_sync().
- *   - A handle may be used from one host thread at a time.
+ *     errors, a zero pivot during inversion, pairs with D <= 0) are reported
+ *     by chi0_sync().
+ *   - A handle may be used from one host thread at a time.  Its calls share
+ *     the handle's device workspace, so they are ordered: a call made on a
+ *     different stream from the previous call first makes its stream wait
+ *     for the previous call's work (an event recorded at the end of every
+ *     call).  A stream being captured into a graph is not made to wait; the
+ *     caller orders captured work.
  *   - Return values are chi0_status codes; chi0_last_error() gives a message
  *     for the calling thread's most recent failure.
  */
@@ -141,9 +147,17 @@ int chi0_destroy(chi0_handle h);
  * nocc / nunocc are balanced across the GPU by the planner.
  *
  * zt must match prec (C128 for FP64, C64 otherwise), else CHI0_EUNSUPPORTED.
- * delta_min >= 0 is the intraband cut; pairs with D < delta_min or D <= 0
- * contribute nothing.  Problems may have different npb and nomega.  Output
- * buffers of different problems must not overlap. */
+ * delta_min >= 0 is the intraband cut; pairs with 0 < D < delta_min
+ * contribute nothing.  A pair with D <= 0 is not a transition of
+ * Eq.(polfx): it contributes nothing either, and since the energies live on
+ * the device such pairs are counted there and chi0_sync() returns
+ * CHI0_EINVAL with their number.  Problems may have different npb and
+ * nomega.  Output buffers of different problems must not overlap.  The
+ * FP64 partial tiles of one launch are bounded by the handle's cap
+ * (chi0_set_partial_cap); a call whose (problem, frequency, tile) jobs
+ * exceed it runs as several launches over consecutive problems and
+ * frequency ranges, and a single frequency of a problem that alone exceeds
+ * it returns CHI0_ENOMEM. */
 int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob,
                     chi0_ztype zt, chi0_precision prec, double delta_min,
                     uint32_t flags, void* hip_stream);
@@ -188,7 +202,8 @@ int sigx_accumulate(chi0_handle h, const sigx_problem* probs, int32_t nprob,
  * energy and chi0 at any frequency follows by a Hilbert transform, so the
  * rank-K work does not grow with the number of frequencies.
  *   Bins j = [edges[j], edges[j+1]).  A pair of a block enters as for
- *   chi0_accumulate (D = eps_unocc[n'] - eps_occ[n] > 0, D >= delta_min); its
+ *   chi0_accumulate (D = eps_unocc[n'] - eps_occ[n] > 0, D >= delta_min; pairs
+ *   with D <= 0 are counted for chi0_sync() as there); its
  *   weight w_k is spread uniformly over [D (1 - sigma), D (1 + sigma)]
  *   (sigma = 0: all at D) -- a stand-in for the tetrahedron weights of
  *   Eq.(tetw), which need a k mesh -- and the fraction inside bin j is its
@@ -292,6 +307,13 @@ int sigc_set_variant(chi0_handle h, int32_t variant);
  * 4 GiB; a block larger than the cap forms a group of its own). */
 int sigc_set_workspace_cap(chi0_handle h, int64_t bytes);
 
+/* Cap in bytes of the FP64 partial tiles of one rank-K launch of
+ * chi0_accumulate, sigx_accumulate and chi0_hist_accumulate (0: the
+ * default, 6e9).  Work above the cap is split into sequential launches on
+ * the call's stream; a cap below one frequency's tiles of a problem makes
+ * the call return CHI0_ENOMEM.  CHI0_EINVAL for a negative value. */
+int chi0_set_partial_cap(chi0_handle h, int64_t bytes);
+
 /* Dielectric step for one q-point (Eq.(dielectricfunction), Eq.(wc);
  * Algorithm "hrcxq" builds eps, inverts it, forms W^c):
  *   eps[w] = 1 - diag(vsqrt) chi0[w] diag(vsqrt), eps_inv[w] = eps[w]^{-1}
@@ -313,10 +335,12 @@ int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega,
                       void* eps_inv, void* wc, uint32_t flags,
                       void* hip_stream);
 
-/* Wait for all work the handle enqueued, then report deferred failures:
- * CHI0_EDEVICE for a runtime error, CHI0_ESINGULAR for a zero pivot and
- * CHI0_ENOTHPD for a non-positive CHI0_INV_HPD pivot since the previous
- * chi0_sync(). */
+/* Wait for all work the handle enqueued, then report deferred failures since
+ * the previous chi0_sync(), in this order: CHI0_EDEVICE for a runtime error,
+ * CHI0_EINVAL for pairs with D <= 0 met by chi0_accumulate or
+ * chi0_hist_accumulate (the message gives their number), CHI0_ESINGULAR for
+ * a zero pivot, CHI0_ENOTHPD for a non-positive CHI0_INV_HPD pivot.  The
+ * deferred flags are cleared when reported. */
 int chi0_sync(chi0_handle h);
 
 /* Static description of a status code. */

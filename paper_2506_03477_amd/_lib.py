@@ -108,6 +108,7 @@ def load() -> ctypes.CDLL:
         "sigc_set_variant": (c_int, [vp, c_int32]),
         "chi0_hist_stats": (c_int, [vp, POINTER(c_int64), POINTER(c_int32)]),
         "sigc_set_workspace_cap": (c_int, [vp, c_int64]),
+        "chi0_set_partial_cap": (c_int, [vp, c_int64]),
         "chi0_tile_count": (c_int, [c_int]),
         "chi0_tile_info": (c_int, [c_int, c_int32, POINTER(c_int32), POINTER(c_int32),
                                    POINTER(c_int32), POINTER(c_int32)]),
@@ -484,6 +485,10 @@ class Context:
 
     def sigc_set_workspace_cap(self, nbytes: int) -> None:
         _check(self._lib.sigc_set_workspace_cap(self._h, int(nbytes)))
+
+    def set_partial_cap(self, nbytes: int) -> None:
+        """Bytes of FP64 partial tiles one rank-K launch may use (0: default)."""
+        _check(self._lib.chi0_set_partial_cap(self._h, int(nbytes)))
 
     # -- dielectric ----------------------------------------------------------
     def dielectric_invert(self, vsqrt, chi0, eps_inv, eps=None, wc=None, method: str = "gj",

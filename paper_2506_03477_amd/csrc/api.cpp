@@ -115,6 +115,7 @@ struct chi0_ctx {
   int32_t hist_bins_used = 0;         // non-empty bins of the last histogram call
   int sigc_variant = 1;
   int64_t sigc_zw_cap = int64_t(4) << 30;
+  double partial_cap = 6.0e9;  // FP64 partial tiles per rank-K launch (bytes)
   uint64_t ws_gen = 1;
   int32_t* d_status = nullptr;
   void* staging = nullptr;  // pinned host staging for table uploads
@@ -132,6 +133,10 @@ struct chi0_ctx {
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
   bool sticky_error = false;
+  // end of the previous call's work, on the stream it was enqueued on
+  hipEvent_t last_done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool last_valid = false;
 };
 
 namespace {
@@ -146,6 +151,37 @@ int kind_of(chi0_precision p) {
 }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Calls share the handle's workspace (partial tiles, weights, split planes,
+// plan tables, inverse buffers), so they are ordered across streams: a call
+// on another stream than the previous call's first waits for the event that
+// call recorded at its end.  A stream under capture is left alone (the
+// caller orders what it captures).
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
+int call_begin(chi0_ctx* h, hipStream_t s) {
+  if (h->last_valid && s != h->last_stream && !capturing(s))
+    HIP_TRY(hipStreamWaitEvent(s, h->last_done, 0));
+  return CHI0_OK;
+}
+
+int call_end(chi0_ctx* h, hipStream_t s, int rc) {
+  if (capturing(s)) return rc;
+  if (hipEventRecord(h->last_done, s) != hipSuccess) {
+    hipGetLastError();
+    return rc ? rc : fail(CHI0_EDEVICE, "event record on the call's stream failed");
+  }
+  h->last_stream = s;
+  h->last_valid = true;
+  return rc;
+}
 
 hipEvent_t get_event(chi0_ctx* h) {
   if (!h->event_pool.empty()) {
@@ -308,6 +344,9 @@ struct HostPlan {
   int nblocks_total = 0;
 };
 
+// Default upper bound on the FP64 partial tiles of one rank-K launch (bytes).
+constexpr double kMaxPartialBytes = 6.0e9;
+
 // Lower-triangle tiles of a TP x TQ tiling of an npb x npb matrix: tile
 // (tp, tq) is needed iff it holds an entry on or below the diagonal.
 void lower_tiles(int npb, int TP, int TQ, std::vector<std::pair<int, int>>& out) {
@@ -319,7 +358,8 @@ void lower_tiles(int npb, int TP, int TQ, std::vector<std::pair<int, int>>& out)
   }
 }
 
-void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int nprob, HostPlan& hp) {
+void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int nprob, HostPlan& hp,
+               double max_partial_bytes = kMaxPartialBytes) {
   const int TP = tc.tile, TQ = tc.tile_q;
   struct P {
     int npb, nomega, ntl, b0, nb;
@@ -353,14 +393,18 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
   const double min_pairs = 1024.0;
   double per_unit = std::max(min_pairs, work / (8.0 * nwg));
   const double slot_bytes = static_cast<double>(TP) * TQ * 16.0;
-  const double max_partial_bytes = 6.0e9;
   auto count_units = [&](double pu) {
     double n = 0;
     for (auto& q : ps)
       n += static_cast<double>(q.nomega) * q.ntl * std::max<int64_t>(1, std::llround(std::ceil(q.K / pu)));
     return n;
   };
-  while (count_units(per_unit) * slot_bytes > max_partial_bytes) per_unit *= 1.5;
+  // Once a unit may hold a whole problem every job has one unit and larger
+  // units change nothing; callers split work whose jobs alone exceed the cap
+  // (run_accumulate), so the loop ends with the storage bounded.
+  double kmax_all = 0.0;
+  for (auto& q : ps) kmax_all = std::max(kmax_all, static_cast<double>(q.K));
+  while (count_units(per_unit) * slot_bytes > max_partial_bytes && per_unit < kmax_all) per_unit *= 1.5;
   // one problem shape: pick the range count so that the units fill whole
   // rounds of the persistent grid (round-robin dealing is then exact)
   if (nprob == 1 && ps[0].K > 0) {
@@ -523,7 +567,7 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
   pl.nwg = nwg;
   pl.nprob = nprob;
   HostPlan hp;
-  plan_host(tc, nwg, probs, nprob, hp);
+  plan_host(tc, nwg, probs, nprob, hp, h->partial_cap);
   pl.nblocks_total = hp.nblocks_total;
   pl.nunits = static_cast<int>(hp.units.size());
   pl.njobs = static_cast<int>(hp.jobs.size());
@@ -569,10 +613,16 @@ int staging_reserve(chi0_ctx* h, size_t bytes) {
 // or, for the exchange self-energy, w_k v_mu (Eq.(sigx)).
 enum WeightMode { kWeightsChi0 = 0, kWeightsCoulomb = 1 };
 
+// Status words of a handle (int32, device): zero pivot of the pivoted
+// inverse, non-positive HPD pivot of the current call and since the last
+// sync, pairs with D <= 0 since the last sync.
+enum { kStZeroPivot = 0, kStHpdCall = 1, kStHpdSeen = 2, kStNonpositive = 3, kStWords = 4 };
+
 hipError_t weights_launch(int mode, const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
-                          int kmax, double delta_min, bool f64, hipStream_t s) {
-  return mode == kWeightsCoulomb ? coulomb_weights_launch(blocks, probs, nblocks, kmax, f64, s)
-                                 : pair_weights_launch(blocks, probs, nblocks, kmax, delta_min, f64, s);
+                          int kmax, double delta_min, bool f64, int32_t* status, hipStream_t s) {
+  return mode == kWeightsCoulomb
+             ? coulomb_weights_launch(blocks, probs, nblocks, kmax, f64, s)
+             : pair_weights_launch(blocks, probs, nblocks, kmax, delta_min, f64, status + kStNonpositive, s);
 }
 
 // Gathered rows and given weights (the histogram path): problem p's single
@@ -633,24 +683,20 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
   return def_time >= 0.0 && best != ndef && best_time >= 0.95 * def_time ? ndef : best;
 }
 
-int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_precision prec,
-                   double delta_min, uint32_t flags, hipStream_t stream, int tile_override,
-                   int mode = kWeightsChi0, const GatherHook* hk = nullptr) {
+// One rank-K launch (weights, pre-split, rank-K kernel, reduction) over a set
+// of problems whose minimal partial storage fits the handle's cap.
+int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_precision prec,
+                         double delta_min, uint32_t flags, hipStream_t stream, int tile_idx,
+                         int mode, const GatherHook* hk) {
   const int kind = kind_of(prec);
-  const int ntile = herk_tile_count(kind);
-  if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this library", prec);
-  int tile_idx = tile_override >= 0 ? tile_override
-                 : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
-                 : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind]
-                 : !hk ? tile_for(kind, probs, nprob) : herk_default_tile(kind);
-  if (tile_idx >= ntile) tile_idx = 0;
-  if (hk && !herk_tile_gathers(kind, tile_idx)) tile_idx = herk_default_tile(kind);
-  if (hk && !herk_tile_gathers(kind, tile_idx))
-    return fail(CHI0_EUNSUPPORTED, "precision %d has no gathering kernel", prec);
-  h->tile_last[kind] = tile_idx;
   int wg_per_cu = std::max(1, herk_max_wg_per_cu(kind, tile_idx));
   const int nwg = h->ncu * wg_per_cu;
-  const std::string key = plan_key(kind, tile_idx, nwg, probs, nprob);
+  std::string key = plan_key(kind, tile_idx, nwg, probs, nprob);
+  if (h->partial_cap != kMaxPartialBytes) {
+    char cb[40];
+    snprintf(cb, sizeof(cb), "#cap%a", h->partial_cap);
+    key += cb;
+  }
   Plan* pl;
   if (hk) {
     // histogram bins change with the data: one reusable slot, not the cache
@@ -812,7 +858,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
       hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess)
         e = weights_launch(mode, ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
-                           kind == HERK_FP64, cs);
+                           kind == HERK_FP64, h->d_status, cs);
       if (e == hipSuccess && presplit)
         e = presplit_launch(ha.blocks, ha.probs, nblocks_total, max_groups, max_npb, cs);
       if (e == hipSuccess) e = herk_launch(kind, pl->tile_idx, ha, pl->nwg, cs);
@@ -837,7 +883,7 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
 
   hipError_t ew = hk ? hipSuccess
                      : weights_launch(mode, ha.blocks, ha.probs, nblocks_total, kmax, delta_min,
-                                      kind == HERK_FP64, stream);
+                                      kind == HERK_FP64, h->d_status, stream);
   if (ew != hipSuccess) return fail(CHI0_EDEVICE, "pair-weight launch: %s", hipGetErrorString(ew));
   if (presplit) {
     ew = presplit_launch(ha.blocks, ha.probs, nblocks_total, max_groups, max_npb, stream);
@@ -857,6 +903,79 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   }
   e = reduce_launch(ra, pl->njobs, stream);
   if (e != hipSuccess) return fail(CHI0_EDEVICE, "reduction launch: %s", hipGetErrorString(e));
+  return CHI0_OK;
+}
+
+// Partial-tile bytes of one frequency of a problem (one unit per tile).
+double job_bytes(const TileConfig& tc, int npb) {
+  std::vector<std::pair<int, int>> t;
+  lower_tiles(npb, tc.tile, tc.tile_q, t);
+  return static_cast<double>(t.size()) * tc.tile * tc.tile_q * 16.0;
+}
+
+// A call's rank-K work: the tile configuration is resolved once, then the
+// problems run as one launch, or, when their (problem, frequency, tile) jobs
+// alone would need more than the handle's cap of partial tiles, as a
+// sequence of launches on the same stream over consecutive problems, a
+// problem split into frequency ranges if one does not fit (frequencies are
+// independent outputs).
+int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_precision prec,
+                   double delta_min, uint32_t flags, hipStream_t stream, int tile_override,
+                   int mode = kWeightsChi0, const GatherHook* hk = nullptr) {
+  const int kind = kind_of(prec);
+  const int ntile = herk_tile_count(kind);
+  if (ntile <= 0) return fail(CHI0_EUNSUPPORTED, "precision %d has no kernel in this library", prec);
+  int tile_idx = tile_override >= 0 ? tile_override
+                 : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
+                 : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind]
+                 : !hk ? tile_for(kind, probs, nprob) : herk_default_tile(kind);
+  if (tile_idx >= ntile) tile_idx = 0;
+  if (hk && !herk_tile_gathers(kind, tile_idx)) tile_idx = herk_default_tile(kind);
+  if (hk && !herk_tile_gathers(kind, tile_idx))
+    return fail(CHI0_EUNSUPPORTED, "precision %d has no gathering kernel", prec);
+  h->tile_last[kind] = tile_idx;
+  const TileConfig tc = herk_tile_config(kind, tile_idx);
+  const double cap = h->partial_cap;
+  double total = 0.0;
+  for (int p = 0; p < nprob; ++p) total += job_bytes(tc, probs[p].npb) * probs[p].nomega;
+  if (total <= cap)
+    return run_accumulate_group(h, probs, nprob, prec, delta_min, flags, stream, tile_idx, mode, hk);
+  // sub-problems: frequency ranges of each problem that fit the cap
+  std::vector<chi0_problem> sub;
+  std::vector<int> orig;
+  std::vector<double> bytes;
+  for (int p = 0; p < nprob; ++p) {
+    const double per_w = job_bytes(tc, probs[p].npb);
+    if (per_w > cap)
+      return fail(CHI0_ENOMEM, "problem %d: one frequency needs %.3g bytes of partial tiles (limit %.3g)",
+                  p, per_w, cap);
+    const int wmax = static_cast<int>(std::min<double>(probs[p].nomega, std::floor(cap / per_w)));
+    if (hk && wmax < probs[p].nomega)
+      return fail(CHI0_ENOMEM, "gathered problem %d needs %.3g bytes of partial tiles (limit %.3g)", p,
+                  per_w * probs[p].nomega, cap);
+    const size_t n2 = static_cast<size_t>(probs[p].npb) * probs[p].npb;
+    for (int w0 = 0; w0 < probs[p].nomega; w0 += wmax) {
+      chi0_problem q = probs[p];
+      q.nomega = std::min(wmax, probs[p].nomega - w0);
+      q.omega = probs[p].omega ? probs[p].omega + w0 : nullptr;
+      q.chi0 = static_cast<double2*>(probs[p].chi0) + static_cast<size_t>(w0) * n2;
+      sub.push_back(q);
+      orig.push_back(p);
+      bytes.push_back(per_w * q.nomega);
+    }
+  }
+  // consecutive sub-problems per launch while they fit
+  for (size_t g0 = 0; g0 < sub.size();) {
+    size_t g1 = g0;
+    double acc = 0.0;
+    while (g1 < sub.size() && (g1 == g0 || acc + bytes[g1] <= cap)) acc += bytes[g1++];
+    GatherHook sh{};
+    if (hk) sh = GatherHook{hk->rows, hk->wts, hk->off + orig[g0]};
+    const int rc = run_accumulate_group(h, sub.data() + g0, static_cast<int32_t>(g1 - g0), prec,
+                                        delta_min, flags, stream, tile_idx, mode, hk ? &sh : nullptr);
+    if (rc) return rc;
+    g0 = g1;
+  }
   return CHI0_OK;
 }
 
@@ -1010,7 +1129,7 @@ int run_hist(chi0_ctx* h, const chi0_problem* probs, const chi0_hist* hists, int
   hipError_t e = hist_records_launch(reinterpret_cast<const HistBlock*>(dtab + a_blk),
                                      reinterpret_cast<const HistProb*>(dtab + a_prob),
                                      static_cast<int>(hb.size()), max_pairs, R, delta_min, rbin, rwt, rrow,
-                                     stream);
+                                     h->d_status + kStNonpositive, stream);
   if (e != hipSuccess) return fail(CHI0_EDEVICE, "binning launch: %s", hipGetErrorString(e));
   e = hist_sort_launch(rbin, rwt, rrow, nrs, nbt, cnt, doff, srow, swt, f64, stream);
   if (e != hipSuccess) return fail(CHI0_EDEVICE, "bin sort launch: %s", hipGetErrorString(e));
@@ -1569,206 +1688,10 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
   return CHI0_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int chi0_version(void) { return 10000; }
-
-const char* chi0_status_string(int s) {
-  switch (s) {
-    case CHI0_OK: return "ok";
-    case CHI0_EINVAL: return "invalid argument";
-    case CHI0_ENOMEM: return "device allocation failed";
-    case CHI0_EDEVICE: return "HIP device or launch failure";
-    case CHI0_ENOTHPD: return "eps is not Hermitian positive definite";
-    case CHI0_ESINGULAR: return "zero pivot while inverting eps";
-    case CHI0_EUNSUPPORTED: return "unsupported combination";
-  }
-  return "unknown status";
-}
-
-const char* chi0_last_error(void) { return g_err.c_str(); }
-
-int chi0_create(chi0_handle* out, int device) {
-  if (!out) return fail(CHI0_EINVAL, "handle pointer is NULL");
-  *out = nullptr;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
-    hipGetLastError();
-    return fail(CHI0_EDEVICE, "no HIP device visible");
-  }
-  if (device < 0 || device >= ndev) return fail(CHI0_EINVAL, "device %d out of range [0, %d)", device, ndev);
-  HIP_TRY(hipSetDevice(device));
-  hipDeviceProp_t prop;
-  HIP_TRY(hipGetDeviceProperties(&prop, device));
-  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(CHI0_EDEVICE, "device %d is %s; libchi0 is built for gfx950 only", device, prop.gcnArchName);
-  std::unique_ptr<chi0_ctx> h(new chi0_ctx());
-  h->device = device;
-  h->ncu = prop.multiProcessorCount;
-  HIP_TRY(hipMalloc(&h->d_status, 64));
-  HIP_TRY(hipMemset(h->d_status, 0, 64));
-  HIP_TRY(hipEventCreateWithFlags(&h->staging_done, hipEventDisableTiming));
-  *out = h.release();
-  return CHI0_OK;
-}
-
-int chi0_destroy(chi0_handle h) {
-  if (!h) return CHI0_OK;
-  hipSetDevice(h->device);
-  hipDeviceSynchronize();
-  h->plans.clear();
-  h->partials.release();
-  h->wts.release();
-  h->zsplit.release();
-  h->gj_work.release();
-  h->gj_wrow.release();
-  h->gj_piv.release();
-  h->gj_perm.release();
-  h->hpd_p.release();
-  h->hpd_c.release();
-  h->hpd_dinv.release();
-  h->sigc_tab.release();
-  h->sigc_wt.release();
-  h->sigc_zw.release();
-  h->sigc_part.release();
-  h->sigc_acc.release();
-  h->sigc_split.release();
-  h->gather_plan.reset();
-  h->hist_tab.release();
-  h->hist_rec.release();
-  h->hist_sorted.release();
-  h->hist_cnt.release();
-  h->hist_mats.release();
-  h->hist_coeff.release();
-  if (h->hist_off_host) hipHostFree(h->hist_off_host);
-  if (h->d_status) hipFree(h->d_status);
-  if (h->staging) hipHostFree(h->staging);
-  if (h->staging_done) hipEventDestroy(h->staging_done);
-  for (auto& pr : h->prof_pending) {
-    hipEventDestroy(pr.first);
-    hipEventDestroy(pr.second);
-  }
-  for (auto e : h->event_pool) hipEventDestroy(e);
-  delete h;
-  return CHI0_OK;
-}
-
-int sigx_accumulate(chi0_handle h, const sigx_problem* probs, int32_t nprob, chi0_ztype zt,
-                    chi0_precision prec, uint32_t flags, void* hip_stream) {
-  int rc = validate_sigx(probs, nprob, zt, prec, flags);
-  if (rc) return rc;
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
-  if (nprob == 0) return CHI0_OK;
-  HIP_TRY(hipSetDevice(h->device));
-  // the exchange sum is the same weighted Hermitian rank-K update: rows
-  // (n', mu) of nqp values, weight w_k v_mu, one "frequency", output -S
-  std::vector<chi0_problem> cp(nprob);
-  std::vector<std::vector<chi0_block>> cb(nprob);
-  for (int p = 0; p < nprob; ++p) {
-    cb[p].resize(std::max(1, probs[p].nblocks));
-    for (int b = 0; b < probs[p].nblocks; ++b) {
-      const sigx_block& s = probs[p].blocks[b];
-      chi0_block& d = cb[p][b];
-      d.nocc = s.nocc;
-      d.nunocc = s.nmu;
-      d.z = s.z;
-      d.eps_occ = nullptr;
-      d.eps_unocc = s.v;
-      d.wk = s.wk;
-    }
-    cp[p].npb = probs[p].nqp;
-    cp[p].nblocks = probs[p].nblocks;
-    cp[p].blocks = cb[p].data();
-    cp[p].nomega = 1;
-    cp[p].omega = nullptr;
-    cp[p].chi0 = probs[p].sigx;
-  }
-  return run_accumulate(h, cp.data(), nprob, prec, 0.0, flags, static_cast<hipStream_t>(hip_stream),
-                        -1, kWeightsCoulomb);
-}
-
-int sigc_accumulate(chi0_handle h, const sigc_problem* probs, int32_t nprob, chi0_ztype zt,
-                    chi0_precision prec, uint32_t flags, void* hip_stream) {
-  int rc = validate_sigc(probs, nprob, zt, prec, flags);
-  if (rc) return rc;
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
-  if (nprob == 0) return CHI0_OK;
-  HIP_TRY(hipSetDevice(h->device));
-  return run_sigc(h, probs, nprob, prec, flags, static_cast<hipStream_t>(hip_stream));
-}
-
-int chi0_hist_accumulate(chi0_handle h, const chi0_problem* probs, const chi0_hist* hists, int32_t nprob,
-                         chi0_ztype zt, chi0_precision prec, double delta_min, uint32_t flags,
-                         void* hip_stream) {
-  int rc = validate_hist(probs, hists, nprob, zt, prec, delta_min, flags);
-  if (rc) return rc;
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
-  if (nprob == 0) return CHI0_OK;
-  HIP_TRY(hipSetDevice(h->device));
-  return run_hist(h, probs, hists, nprob, prec, delta_min, flags, static_cast<hipStream_t>(hip_stream));
-}
-
-int chi0_hist_stats(chi0_handle h, int64_t* records, int32_t* bins_used) {
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
-  if (records) *records = h->hist_records;
-  if (bins_used) *bins_used = h->hist_bins_used;
-  return CHI0_OK;
-}
-
-int sigc_set_variant(chi0_handle h, int32_t variant) {
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
-  if (variant < 0 || variant >= sigc_zw_variants())
-    return fail(CHI0_EINVAL, "variant %d out of range [0, %d)", variant, sigc_zw_variants());
-  h->sigc_variant = variant;
-  return CHI0_OK;
-}
-
-int sigc_set_workspace_cap(chi0_handle h, int64_t bytes) {
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
-  if (bytes < 0) return fail(CHI0_EINVAL, "cap %lld < 0", static_cast<long long>(bytes));
-  h->sigc_zw_cap = bytes == 0 ? (int64_t(4) << 30) : bytes;
-  return CHI0_OK;
-}
-
-int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_ztype zt,
-                    chi0_precision prec, double delta_min, uint32_t flags, void* hip_stream) {
-  int rc = validate_problems(probs, nprob, zt, prec, delta_min, flags);
-  if (rc) return rc;
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
-  if (nprob == 0) return CHI0_OK;
-  HIP_TRY(hipSetDevice(h->device));
-  return run_accumulate(h, probs, nprob, prec, delta_min, flags,
-                        static_cast<hipStream_t>(hip_stream), -1);
-}
-
-int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* vsqrt,
-                      const void* chi0, void* eps, void* eps_inv, void* wc, uint32_t flags,
-                      void* hip_stream) {
-  if (npb < 1) return fail(CHI0_EINVAL, "npb = %d < 1", npb);
-  if (nomega < 1) return fail(CHI0_EINVAL, "nomega = %d < 1", nomega);
-  if (flags & ~static_cast<uint32_t>(CHI0_OUT_WC | CHI0_INV_METHOD_MASK))
-    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
-  const uint32_t method = flags & CHI0_INV_METHOD_MASK;
-  if (method != CHI0_INV_GJ && method != CHI0_INV_HPD && method != CHI0_INV_HPD_FALLBACK_GJ)
-    return fail(CHI0_EINVAL, "unknown inversion method %u", method);
-  if (!vsqrt || !chi0 || !eps_inv) return fail(CHI0_EINVAL, "vsqrt, chi0 and eps_inv must be non-NULL");
-  if ((flags & CHI0_OUT_WC) && !wc) return fail(CHI0_EINVAL, "CHI0_OUT_WC set but wc is NULL");
-  if (!aligned(chi0, 16) || !aligned(eps_inv, 16) || (eps && !aligned(eps, 16)) ||
-      ((flags & CHI0_OUT_WC) && !aligned(wc, 16)) || !aligned(vsqrt, 8))
-    return fail(CHI0_EINVAL, "buffers must be 16-byte aligned (vsqrt 8-byte)");
+int run_invert(chi0_ctx* h, int32_t npb, int32_t nomega, const double* vsqrt, const void* chi0,
+               void* eps, void* eps_inv, void* wc, uint32_t flags, hipStream_t s) {
   const size_t bytes = static_cast<size_t>(nomega) * npb * npb * 16;
-  auto overlap = [bytes](const void* a, const void* b) {
-    if (!a || !b) return false;
-    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-    return x < y + bytes && y < x + bytes;
-  };
-  if (overlap(eps_inv, chi0) || overlap(eps_inv, eps) || ((flags & CHI0_OUT_WC) && (overlap(wc, eps_inv) || overlap(wc, chi0))))
-    return fail(CHI0_EINVAL, "eps_inv / wc must not overlap chi0, eps or each other");
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
-  HIP_TRY(hipSetDevice(h->device));
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const uint32_t method = flags & CHI0_INV_METHOD_MASK;
   double2* wc_out = (flags & CHI0_OUT_WC) ? static_cast<double2*>(wc) : nullptr;
   int rc;
   if ((rc = h->gj_work.reserve(bytes, &h->ws_gen))) return rc;
@@ -1838,17 +1761,239 @@ int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* 
   return CHI0_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int chi0_version(void) { return 10000; }
+
+const char* chi0_status_string(int s) {
+  switch (s) {
+    case CHI0_OK: return "ok";
+    case CHI0_EINVAL: return "invalid argument";
+    case CHI0_ENOMEM: return "device allocation failed";
+    case CHI0_EDEVICE: return "HIP device or launch failure";
+    case CHI0_ENOTHPD: return "eps is not Hermitian positive definite";
+    case CHI0_ESINGULAR: return "zero pivot while inverting eps";
+    case CHI0_EUNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+const char* chi0_last_error(void) { return g_err.c_str(); }
+
+int chi0_create(chi0_handle* out, int device) {
+  if (!out) return fail(CHI0_EINVAL, "handle pointer is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    hipGetLastError();
+    return fail(CHI0_EDEVICE, "no HIP device visible");
+  }
+  if (device < 0 || device >= ndev) return fail(CHI0_EINVAL, "device %d out of range [0, %d)", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(CHI0_EDEVICE, "device %d is %s; libchi0 is built for gfx950 only", device, prop.gcnArchName);
+  std::unique_ptr<chi0_ctx> h(new chi0_ctx());
+  h->device = device;
+  h->ncu = prop.multiProcessorCount;
+  HIP_TRY(hipMalloc(&h->d_status, 64));
+  HIP_TRY(hipMemset(h->d_status, 0, 64));
+  HIP_TRY(hipEventCreateWithFlags(&h->staging_done, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&h->last_done, hipEventDisableTiming));
+  *out = h.release();
+  return CHI0_OK;
+}
+
+int chi0_destroy(chi0_handle h) {
+  if (!h) return CHI0_OK;
+  hipSetDevice(h->device);
+  hipDeviceSynchronize();
+  h->plans.clear();
+  h->partials.release();
+  h->wts.release();
+  h->zsplit.release();
+  h->gj_work.release();
+  h->gj_wrow.release();
+  h->gj_piv.release();
+  h->gj_perm.release();
+  h->hpd_p.release();
+  h->hpd_c.release();
+  h->hpd_dinv.release();
+  h->sigc_tab.release();
+  h->sigc_wt.release();
+  h->sigc_zw.release();
+  h->sigc_part.release();
+  h->sigc_acc.release();
+  h->sigc_split.release();
+  h->gather_plan.reset();
+  h->hist_tab.release();
+  h->hist_rec.release();
+  h->hist_sorted.release();
+  h->hist_cnt.release();
+  h->hist_mats.release();
+  h->hist_coeff.release();
+  if (h->hist_off_host) hipHostFree(h->hist_off_host);
+  if (h->d_status) hipFree(h->d_status);
+  if (h->staging) hipHostFree(h->staging);
+  if (h->staging_done) hipEventDestroy(h->staging_done);
+  if (h->last_done) hipEventDestroy(h->last_done);
+  for (auto& pr : h->prof_pending) {
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  for (auto e : h->event_pool) hipEventDestroy(e);
+  delete h;
+  return CHI0_OK;
+}
+
+int sigx_accumulate(chi0_handle h, const sigx_problem* probs, int32_t nprob, chi0_ztype zt,
+                    chi0_precision prec, uint32_t flags, void* hip_stream) {
+  int rc = validate_sigx(probs, nprob, zt, prec, flags);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (nprob == 0) return CHI0_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  // the exchange sum is the same weighted Hermitian rank-K update: rows
+  // (n', mu) of nqp values, weight w_k v_mu, one "frequency", output -S
+  std::vector<chi0_problem> cp(nprob);
+  std::vector<std::vector<chi0_block>> cb(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    cb[p].resize(std::max(1, probs[p].nblocks));
+    for (int b = 0; b < probs[p].nblocks; ++b) {
+      const sigx_block& s = probs[p].blocks[b];
+      chi0_block& d = cb[p][b];
+      d.nocc = s.nocc;
+      d.nunocc = s.nmu;
+      d.z = s.z;
+      d.eps_occ = nullptr;
+      d.eps_unocc = s.v;
+      d.wk = s.wk;
+    }
+    cp[p].npb = probs[p].nqp;
+    cp[p].nblocks = probs[p].nblocks;
+    cp[p].blocks = cb[p].data();
+    cp[p].nomega = 1;
+    cp[p].omega = nullptr;
+    cp[p].chi0 = probs[p].sigx;
+  }
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((rc = call_begin(h, s))) return rc;
+  return call_end(h, s, run_accumulate(h, cp.data(), nprob, prec, 0.0, flags, s, -1, kWeightsCoulomb));
+}
+
+int sigc_accumulate(chi0_handle h, const sigc_problem* probs, int32_t nprob, chi0_ztype zt,
+                    chi0_precision prec, uint32_t flags, void* hip_stream) {
+  int rc = validate_sigc(probs, nprob, zt, prec, flags);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (nprob == 0) return CHI0_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((rc = call_begin(h, s))) return rc;
+  return call_end(h, s, run_sigc(h, probs, nprob, prec, flags, s));
+}
+
+int chi0_hist_accumulate(chi0_handle h, const chi0_problem* probs, const chi0_hist* hists, int32_t nprob,
+                         chi0_ztype zt, chi0_precision prec, double delta_min, uint32_t flags,
+                         void* hip_stream) {
+  int rc = validate_hist(probs, hists, nprob, zt, prec, delta_min, flags);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (nprob == 0) return CHI0_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((rc = call_begin(h, s))) return rc;
+  return call_end(h, s, run_hist(h, probs, hists, nprob, prec, delta_min, flags, s));
+}
+
+int chi0_hist_stats(chi0_handle h, int64_t* records, int32_t* bins_used) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (records) *records = h->hist_records;
+  if (bins_used) *bins_used = h->hist_bins_used;
+  return CHI0_OK;
+}
+
+int sigc_set_variant(chi0_handle h, int32_t variant) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (variant < 0 || variant >= sigc_zw_variants())
+    return fail(CHI0_EINVAL, "variant %d out of range [0, %d)", variant, sigc_zw_variants());
+  h->sigc_variant = variant;
+  return CHI0_OK;
+}
+
+int chi0_set_partial_cap(chi0_handle h, int64_t bytes) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (bytes < 0) return fail(CHI0_EINVAL, "cap %lld < 0", static_cast<long long>(bytes));
+  h->partial_cap = bytes == 0 ? kMaxPartialBytes : static_cast<double>(bytes);
+  return CHI0_OK;
+}
+
+int sigc_set_workspace_cap(chi0_handle h, int64_t bytes) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (bytes < 0) return fail(CHI0_EINVAL, "cap %lld < 0", static_cast<long long>(bytes));
+  h->sigc_zw_cap = bytes == 0 ? (int64_t(4) << 30) : bytes;
+  return CHI0_OK;
+}
+
+int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_ztype zt,
+                    chi0_precision prec, double delta_min, uint32_t flags, void* hip_stream) {
+  int rc = validate_problems(probs, nprob, zt, prec, delta_min, flags);
+  if (rc) return rc;
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (nprob == 0) return CHI0_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((rc = call_begin(h, s))) return rc;
+  return call_end(h, s, run_accumulate(h, probs, nprob, prec, delta_min, flags, s, -1));
+}
+
+int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* vsqrt,
+                      const void* chi0, void* eps, void* eps_inv, void* wc, uint32_t flags,
+                      void* hip_stream) {
+  if (npb < 1) return fail(CHI0_EINVAL, "npb = %d < 1", npb);
+  if (nomega < 1) return fail(CHI0_EINVAL, "nomega = %d < 1", nomega);
+  if (flags & ~static_cast<uint32_t>(CHI0_OUT_WC | CHI0_INV_METHOD_MASK))
+    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  const uint32_t method = flags & CHI0_INV_METHOD_MASK;
+  if (method != CHI0_INV_GJ && method != CHI0_INV_HPD && method != CHI0_INV_HPD_FALLBACK_GJ)
+    return fail(CHI0_EINVAL, "unknown inversion method %u", method);
+  if (!vsqrt || !chi0 || !eps_inv) return fail(CHI0_EINVAL, "vsqrt, chi0 and eps_inv must be non-NULL");
+  if ((flags & CHI0_OUT_WC) && !wc) return fail(CHI0_EINVAL, "CHI0_OUT_WC set but wc is NULL");
+  if (!aligned(chi0, 16) || !aligned(eps_inv, 16) || (eps && !aligned(eps, 16)) ||
+      ((flags & CHI0_OUT_WC) && !aligned(wc, 16)) || !aligned(vsqrt, 8))
+    return fail(CHI0_EINVAL, "buffers must be 16-byte aligned (vsqrt 8-byte)");
+  const size_t bytes = static_cast<size_t>(nomega) * npb * npb * 16;
+  auto overlap = [bytes](const void* a, const void* b) {
+    if (!a || !b) return false;
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+  };
+  if (overlap(eps_inv, chi0) || overlap(eps_inv, eps) || ((flags & CHI0_OUT_WC) && (overlap(wc, eps_inv) || overlap(wc, chi0))))
+    return fail(CHI0_EINVAL, "eps_inv / wc must not overlap chi0, eps or each other");
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  HIP_TRY(hipSetDevice(h->device));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int rc;
+  if ((rc = call_begin(h, s))) return rc;
+  return call_end(h, s, run_invert(h, npb, nomega, vsqrt, chi0, eps, eps_inv, wc, flags, s));
+}
+
 int chi0_sync(chi0_handle h) {
   if (!h) return fail(CHI0_EINVAL, "handle is NULL");
   HIP_TRY(hipSetDevice(h->device));
   HIP_TRY(hipDeviceSynchronize());
-  // status words: [0] zero pivot (Gauss-Jordan), [1] this call's HPD sweeps
-  // met a non-positive pivot, [2] the same, reported here
-  int32_t st[3] = {0, 0, 0};
+  int32_t st[kStWords] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpy(st, h->d_status, sizeof(st), hipMemcpyDeviceToHost));
-  if (st[0] || st[2]) {
+  if (st[kStZeroPivot] || st[kStHpdSeen] || st[kStNonpositive]) {
     HIP_TRY(hipMemset(h->d_status, 0, sizeof(st)));
-    if (st[0]) return fail(CHI0_ESINGULAR, "a zero pivot was met while inverting eps");
+    if (st[kStNonpositive])
+      return fail(CHI0_EINVAL, "%d pair(s) with D = eps_unocc - eps_occ <= 0 since the last sync "
+                  "(they contributed nothing)%s", st[kStNonpositive],
+                  st[kStZeroPivot] || st[kStHpdSeen] ? "; an inversion also failed" : "");
+    if (st[kStZeroPivot]) return fail(CHI0_ESINGULAR, "a zero pivot was met while inverting eps");
     return fail(CHI0_ENOTHPD, "a non-positive pivot was met: eps is not Hermitian positive definite");
   }
   return CHI0_OK;
@@ -1935,9 +2080,13 @@ int chi0_autotune(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_
   const int n = herk_tile_count(k);
   if (n <= 0) return fail(CHI0_EUNSUPPORTED, "precision has no kernel in this library");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((rc = call_begin(h, s))) return rc;
   hipEvent_t a = nullptr, b = nullptr;
   HIP_TRY(hipEventCreate(&a));
-  HIP_TRY(hipEventCreate(&b));
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return fail(CHI0_EDEVICE, "event creation failed");
+  }
   int bi = 0;
   double bms = 1e300;
   const bool prof = h->profiling;
@@ -1962,6 +2111,7 @@ int chi0_autotune(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi0_
   h->profiling = prof;
   hipEventDestroy(a);
   hipEventDestroy(b);
+  rc = call_end(h, s, rc);
   if (rc) return rc;
   h->tile_tuned[k] = bi;
   if (best) *best = bi;

@@ -210,7 +210,7 @@ struct HilbertProb {
 int hist_chunk();
 hipError_t hist_records_launch(const HistBlock* blocks, const HistProb* probs, int nblocks, int64_t max_pairs,
                                int R, double delta_min, int32_t* rbin, double* rw, uint64_t* rrow,
-                               hipStream_t s);
+                               int32_t* nonpositive, hipStream_t s);
 hipError_t hist_sort_launch(const int32_t* rbin, const double* rw, const uint64_t* rrow, int64_t nrec, int nbt,
                             int32_t* cnt, int64_t* off, uint64_t* srow, void* sw, bool f64, hipStream_t s);
 hipError_t hilbert_launch(const HilbertProb* hp, int nprob, int max_out, int max_bins, int64_t max_n2,
@@ -238,7 +238,8 @@ hipError_t coulomb_weights_launch(const BlockDesc* blocks, const ProbDesc* probs
 hipError_t presplit_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
                            int64_t max_groups, int max_npb, hipStream_t s);
 hipError_t pair_weights_launch(const BlockDesc* blocks, const ProbDesc* probs, int nblocks,
-                               int kmax, double delta_min, bool f64, hipStream_t s);
+                               int kmax, double delta_min, bool f64, int32_t* nonpositive,
+                               hipStream_t s);
 int herk_tile_count(int kind);
 int herk_default_tile(int kind);
 TileConfig herk_tile_config(int kind, int idx);

@@ -21,6 +21,16 @@ __device__ __forceinline__ double pair_weight(const BlockDesc& bd, int p, int K,
   return bd.wk * 2.0 * d / (d * d + w2);
 }
 
+// Adds the number of lanes with `bad` set to *count: one vector-memory
+// atomic per wave, from the lowest such lane.  Used to report pairs with
+// D <= 0, which the polarization sum does not define.
+__device__ __forceinline__ void count_lanes(int32_t* count, bool bad) {
+  const unsigned long long m = __ballot(bad);
+  if (m == 0ull) return;
+  if (static_cast<int>(__lane_id()) == __ffsll(static_cast<long long>(m)) - 1)
+    atomicAdd(count, static_cast<int32_t>(__popcll(m)));
+}
+
 // Read-only tables are read through the constant address space: they do not
 // change during a launch, so uniform reads become scalar loads that do not
 // wait behind the vector memory traffic.

@@ -11,6 +11,7 @@
 // each bin's records contiguous in pair order, so the rank-K sums run in a
 // fixed order.
 #include "common.h"
+#include "herk_common.h"
 
 namespace chi0 {
 namespace {
@@ -23,7 +24,8 @@ __global__ __launch_bounds__(256) void hist_records_kernel(const HistBlock* __re
                                                            const HistProb* __restrict__ probs, int R,
                                                            double delta_min, int32_t* __restrict__ rbin,
                                                            double* __restrict__ rw,
-                                                           uint64_t* __restrict__ rrow) {
+                                                           uint64_t* __restrict__ rrow,
+                                                           int32_t* nonpositive) {
 #pragma clang fp contract(off)
   const HistBlock bd = blocks[blockIdx.y];
   const HistProb pr = probs[bd.prob];
@@ -37,6 +39,7 @@ __global__ __launch_bounds__(256) void hist_records_kernel(const HistBlock* __re
     const uint64_t row = reinterpret_cast<uint64_t>(bd.z) + static_cast<uint64_t>(p) * bd.row_bytes;
     int t = 0;
     const double d = bd.eps_unocc[m] - bd.eps_occ[n];
+    count_lanes(nonpositive, !(d > 0.0));
     if (d > 0.0 && d >= delta_min) {
       if (pr.sigma == 0.0) {
         if (d >= e[0] && d < e[nb]) {
@@ -249,14 +252,14 @@ int hist_chunk() { return kChunk; }
 
 hipError_t hist_records_launch(const HistBlock* blocks, const HistProb* probs, int nblocks, int64_t max_pairs,
                                int R, double delta_min, int32_t* rbin, double* rw, uint64_t* rrow,
-                               hipStream_t s) {
+                               int32_t* nonpositive, hipStream_t s) {
   if (nblocks <= 0 || max_pairs <= 0) return hipSuccess;
   int64_t gx = (max_pairs + 255) / 256;
   if (gx > 4096) gx = 4096;
   for (int b0 = 0; b0 < nblocks; b0 += 65535) {
     const int nb = nblocks - b0 < 65535 ? nblocks - b0 : 65535;
     hipLaunchKernelGGL(hist_records_kernel, dim3(static_cast<unsigned>(gx), nb), dim3(256), 0, s, blocks + b0,
-                       probs, R, delta_min, rbin, rw, rrow);
+                       probs, R, delta_min, rbin, rw, rrow, nonpositive);
   }
   return hipGetLastError();
 }

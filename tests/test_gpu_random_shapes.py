@@ -4,6 +4,8 @@ pairs, one to three frequencies with or without omega = 0, and dyadic
 energies so that pairs below the intraband cut, with D <= 0, or exactly at
 the cut (included) all occur.  FP64 against the oracle; BF16x3 against the
 split model (the kernels' roundings), which the oracle pins separately.
+Pairs with D <= 0 contribute nothing and make the sync report CHI0_EINVAL
+with their number.
 Examples are derandomized, so every run draws the same shapes."""
 import sys
 
@@ -15,6 +17,7 @@ from hypothesis import HealthCheck, given, settings, strategies as st
 import oracle
 from gpu_common import assert_hermitian_exact, need_gpu
 from paper_2506_03477_amd import Block, Context, Problem
+from paper_2506_03477_amd._lib import CHI0_EINVAL, Chi0Error
 from splitmodel import chi0_model
 
 pytestmark = pytest.mark.gpu
@@ -91,12 +94,17 @@ def test_random_shapes(ctx, shape):
         out = torch.full((nomega, npb, npb), 5.0 + 1j, dtype=torch.complex128, device="cuda")
         ctx.chi0_accumulate([Problem(dev, torch.from_numpy(omega).cuda(), out)], precision=path,
                             delta_min=DMIN)
-        ctx.sync()
+        bad = sum(oracle.nonpositive_pairs(eo, eu) for _, eo, eu, _ in hb)
+        try:
+            ctx.sync()
+            assert bad == 0
+        except Chi0Error as e:
+            assert e.code == CHI0_EINVAL and f"{bad} pair(s)" in str(e), (bad, str(e))
         assert_hermitian_exact(out)
         got = out.cpu().numpy()
         if path == "fp64":
             ref = oracle.chi0_ref([(z.astype(np.complex128), eo, eu, wk) for z, eo, eu, wk in hb],
-                                  npb, omega, DMIN)
+                                  npb, omega, DMIN, strict=False)
             e = _per_omega_rel(got, ref)
             assert np.all(e <= 1e-12), e
         else:

@@ -148,3 +148,26 @@ def test_inspect_rejects_bad_input():
     buf = (c_int32 * 10)()
     if nu.value > 1:
         assert lib.chi0_plan_inspect(arr, 1, 0, 0, 4, None, None, buf, 1, None, None) == L.CHI0_EINVAL
+
+
+def test_many_large_problems_plan_returns():
+    """14 q-points at npb 2048 with 12 frequencies on the tall BF16x3 tiles
+    need more partial-tile storage than one launch may hold even at one unit
+    per (problem, frequency, tile) job: the planner must still return (one
+    unit per job), and the library splits such calls into several launches."""
+    lib = pkg.load()
+    tall = next(t for t in range(lib.chi0_tile_count(2))
+                if _tile(lib, 2, t)[:2] == (256, 128))
+    shapes = [(2048, 12, [(200, 1200)] * 16)] * 14
+    units, njobs, lmax, lmean = _inspect(shapes, 2, tall, 256)
+    assert njobs == 14 * 12 * 72
+    assert len(units) == njobs          # one unit per job: the bound forces it
+    # a single problem with 200 frequencies alone exceeds the default cap too
+    units, njobs, _, _ = _inspect([(2048, 200, [(200, 1200)] * 16)], 2, tall, 256)
+    assert len(units) == njobs == 200 * 72
+
+
+def _tile(lib, prec, t):
+    TP, TQ, KC = c_int32(), c_int32(), c_int32()
+    assert lib.chi0_tile_info(prec, t, byref(TP), byref(TQ), byref(KC), None) == 0
+    return TP.value, TQ.value, KC.value
