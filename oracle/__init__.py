@@ -5,7 +5,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 GPU library; its inputs come from the seeded generator in ``synth/``.
 """
 from .chi0_oracle import *  # noqa: F401,F403
-from .chi0_oracle import (chi0_ref, chi0_brute, chi0_exact, chi0_entries,
+from .chi0_oracle import (chi0_ref, chi0_brute, chi0_exact, chi0_entries, chi0_rows,
                           chi0_block, chi0_workload, dielectric, inverse,
                           inverse_gauss_jordan, screened_wc, transition_weight,
                           pair_delta, pair_included, rel_fro, workload_blocks)

@@ -215,6 +215,36 @@ def chi0_exact(blocks, npb: int, omega: Sequence[Fraction],
 
 
 # ---------------------------------------------------------------------------
+# chi0 rows (full-size checks of whole rows)
+# ---------------------------------------------------------------------------
+
+
+def chi0_rows(blocks: Iterable[BlockInput], rows: Sequence[int], npb: int,
+              omega: Sequence[float], delta_min: float = 0.0,
+              strict: bool = True) -> np.ndarray:
+    """chi0[iw, I, :] for the listed rows I only, [nomega, len(rows), npb]:
+    sum over pairs of f conj(Z(I)) Z(J) for every J, blocks combined with
+    compensated sums (the reference tier restricted to some rows)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    acc = _CompensatedSum((len(omega), len(rows), npb))
+    for z, eo, eu, wk in blocks:
+        _check_pairs(eo, eu, strict)
+        z = np.asarray(z)
+        nocc, nunocc, _ = z.shape
+        a = z.reshape(nocc * nunocc, npb).astype(np.complex128)
+        delta = pair_delta(eo, eu).reshape(-1)
+        keep = pair_included(delta, delta_min)
+        a = a[keep]
+        delta = delta[keep]
+        part = np.empty((len(omega), len(rows), npb), np.complex128)
+        for iw, w in enumerate(omega):
+            c = transition_weight(delta, float(w), wk)
+            part[iw] = (a[:, rows].conj() * c[:, None]).T @ a
+        acc.add(part)
+    return acc.value()
+
+
+# ---------------------------------------------------------------------------
 # chi0 entries one by one (full-size spot checks)
 # ---------------------------------------------------------------------------
 

@@ -401,9 +401,35 @@ def pin_entries(orc):
     return fails
 
 
+def pin_rows(orc):
+    """Whole rows (the full-size row checks' oracle) against the golden
+    example and the loop tier: rows given out of order, a delta_min cut,
+    unequal w_k; row I of the result is chi0[I, :] (conjugation on I)."""
+    fails = []
+    g, z, eo, eu, wk, s = _load_golden()
+    for case in g["cases"]:
+        w = float(Fraction(case["omega"]))
+        dmin = float(Fraction(case["delta_min"]))
+        got = orc.chi0_rows([(z, eo, eu, wk)], [1, 0], 2, [w], dmin)[0]
+        ref = _frac_mat(case["chi0"])
+        if not _close(got, ref[[1, 0]], 1e-15):
+            fails.append(f"rows golden omega={w} dmin={dmin}: {got}")
+    rng = np.random.default_rng(29)
+    npb = 8
+    blocks = _random_problem(rng, npb=npb, nblocks=3)
+    blocks = [(zz, o, u, w * (2.0 - 0.5 * b)) for b, (zz, o, u, w) in enumerate(blocks)]
+    omega = [0.0, 0.7, 3.0]
+    brute = orc.chi0_brute(blocks, npb, omega, 0.3)
+    rows = [5, 0, 7, 2]
+    got = orc.chi0_rows(blocks, rows, npb, omega, 0.3)
+    if np.max(np.abs(got - brute[:, rows, :])) > 1e-14 * np.max(np.abs(brute)):
+        fails.append("rows vs loops")
+    return fails
+
+
 ALL_PINS = [pin_golden, pin_weight_is_polfx_on_imaginary_axis, pin_exact_bruteforce,
             pin_conjugation_side, pin_single_transition, pin_invariants,
-            pin_large_omega_tail, pin_structure, pin_inverse, pin_entries]
+            pin_large_omega_tail, pin_structure, pin_inverse, pin_entries, pin_rows]
 
 
 def run_all(orc):

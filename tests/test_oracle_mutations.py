@@ -73,6 +73,32 @@ def _entries_variant(conj_second=False, no_mask=False, no_wk=False, ignore_map=F
     return fn
 
 
+def _rows_variant(conj_cols=False, rows_as_cols=False, no_wk=False):
+    """chi0_rows with one planted mistake."""
+    def fn(blocks, rows, npb, omega, delta_min=0.0, strict=True):
+        rows = np.asarray(rows)
+        acc = orc._CompensatedSum((len(omega), len(rows), npb))
+        for z, eo, eu, wk in blocks:
+            orc._check_pairs(eo, eu, strict)
+            z = np.asarray(z)
+            a = z.reshape(-1, npb).astype(np.complex128)
+            delta = orc.pair_delta(eo, eu).reshape(-1)
+            keep = orc.pair_included(delta, delta_min)
+            a, delta = a[keep], delta[keep]
+            part = np.empty((len(omega), len(rows), npb), np.complex128)
+            for iw, w in enumerate(omega):
+                c = orc.transition_weight(delta, float(w), 1.0 if no_wk else wk)
+                if conj_cols:
+                    part[iw] = a[:, rows].T @ (c[:, None] * a.conj())
+                elif rows_as_cols:
+                    part[iw] = (a.conj().T @ (c[:, None] * a[:, rows])).T
+                else:
+                    part[iw] = a[:, rows].conj().T @ (c[:, None] * a)
+            acc.add(part)
+        return acc.value()
+    return fn
+
+
 def _dielectric_plus(chi0, vsqrt):
     s = np.asarray(vsqrt)
     return np.eye(s.shape[0])[None] + s[None, :, None] * chi0 * s[None, None, :]
@@ -147,6 +173,9 @@ MUTATIONS = {
     "entries_no_mask": ("chi0_entries", _entries_variant(no_mask=True)),
     "entries_no_wk": ("chi0_entries", _entries_variant(no_wk=True)),
     "entries_ignore_col_map": ("chi0_entries", _entries_variant(ignore_map=True)),
+    "rows_conj_columns": ("chi0_rows", _rows_variant(conj_cols=True)),
+    "rows_are_columns": ("chi0_rows", _rows_variant(rows_as_cols=True)),
+    "rows_no_wk": ("chi0_rows", _rows_variant(no_wk=True)),
 }
 
 
