@@ -35,3 +35,18 @@ def assert_hermitian_exact(chi):
     assert torch.equal(c, c.conj().transpose(-1, -2))
     d = torch.diagonal(c, dim1=-2, dim2=-1)
     assert torch.all(d.imag == 0)
+
+
+def host_blocks(blks, nocc_chunk, say=None, tag=""):
+    """Oracle inputs streamed from device blocks (z, eps_occ, eps_unocc, wk,
+    ...): chunks of `nocc_chunk` occupied states, Z copied to the host and
+    upcast exactly to complex128.  The device Z comes from the synthetic
+    generator, bit-identical to the CPU one."""
+    for k, b in enumerate(blks):
+        z, eo, eu, wk = b[0], b[1].cpu().numpy(), b[2].cpu().numpy(), b[3]
+        if say is not None:
+            say(f"{tag} block {k + 1}/{len(blks)}")
+        for n0 in range(0, z.shape[0], nocc_chunk):
+            n1 = min(z.shape[0], n0 + nocc_chunk)
+            zc = z[n0:n1].cpu().numpy().astype(np.complex128)
+            yield zc, eo[n0:n1], eu, wk
