@@ -137,5 +137,37 @@ __device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr,
   }
 }
 
+// Add (or store, when first) a wave's (32 NBI) x 64 accumulators into the
+// FP64 partial tile (256 x 128, row-major); 16 old values are loaded as a
+// group.
+template <int NBI = 4>
+__device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32x16 (&cr)[NBI][2],
+                                           const f32x16 (&ci)[NBI][2], int wr, int wc, int lane,
+                                           bool first) {
+  constexpr int TQ = 128;
+  const int g = lane >> 5;
+  const int cl = lane & 31;
+  int base = (wr * (32 * NBI) + 4 * g) * TQ + wc * 64 + cl;
+  asm volatile("" : "+v"(base));
+#pragma unroll
+  for (int i = 0; i < NBI; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      double2* blk = part + base + i * 32 * TQ + j * 32;
+      double2 o[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[r] = double2{0.0, 0.0};
+      if (!first) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[r] = blk[(8 * (r >> 2) + (r & 3)) * TQ];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        blk[(8 * (r >> 2) + (r & 3)) * TQ] =
+            double2{static_cast<double>(cr[i][j][r]) + o[r].x,
+                    static_cast<double>(ci[i][j][r]) + o[r].y};
+    }
+}
+
 }  // namespace
 }  // namespace chi0

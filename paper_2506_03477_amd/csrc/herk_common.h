@@ -102,5 +102,9 @@ int herk_bf16x3_tile_count();
 TileConfig herk_bf16x3_tile(int idx);
 hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s, bool gather);
 int herk_bf16x3_max_wg_per_cu(int idx);
+// Register-direct BF16x3 kernel (256 x 128 tall-tile units, P side pre-split).
+hipError_t herk_bf16x3_direct_launch(bool lolo, bool hint, const HerkArgs& a, int nwg,
+                                     hipStream_t s);
+int herk_bf16x3_direct_max_wg_per_cu();
 
 }  // namespace chi0

@@ -514,38 +514,6 @@ __device__ __forceinline__ void tall_stage_q(Bf16TallLds& L, int buf, int lq, in
   }
 }
 
-// Add (or store, when first) a wave's (32 NBI) x 64 accumulators into the
-// FP64 partial tile (256 x 128, row-major); 16 old values are loaded as a
-// group.
-template <int NBI = 4>
-__device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32x16 (&cr)[NBI][2],
-                                           const f32x16 (&ci)[NBI][2], int wr, int wc, int lane,
-                                           bool first) {
-  constexpr int TQ = 128;
-  const int g = lane >> 5;
-  const int cl = lane & 31;
-  int base = (wr * (32 * NBI) + 4 * g) * TQ + wc * 64 + cl;
-  asm volatile("" : "+v"(base));
-#pragma unroll
-  for (int i = 0; i < NBI; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      double2* blk = part + base + i * 32 * TQ + j * 32;
-      double2 o[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) o[r] = double2{0.0, 0.0};
-      if (!first) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) o[r] = blk[(8 * (r >> 2) + (r & 3)) * TQ];
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        blk[(8 * (r >> 2) + (r & 3)) * TQ] =
-            double2{static_cast<double>(cr[i][j][r]) + o[r].x,
-                    static_cast<double>(ci[i][j][r]) + o[r].y};
-    }
-}
-
 // Software-pipelined tall-tile kernel.  Stage s (buffer s % 2):
 //   1. the P loads of stage s + 1 (one register set) and the Q loads of stage
 //      s + 2 (register set s % 2);
@@ -937,6 +905,8 @@ static const TileConfig kBf16Tiles[] = {
     {128, kKC, 4096, kNT, 128},      // 6: as 0, compiler scheduling (no interleave hints)
     {256, kKC, 4096, kNT, 128, 1},   // 7: as 5, compiler scheduling
     {256, kKC, 4096, 512, 128, 1},   // 8: tall tiles, 8 waves (two per SIMD)
+    {256, kKC, 4096, kNT, 128, 1},   // 9: tall tiles, operands straight to registers
+    {256, kKC, 4096, kNT, 128, 1},   // 10: as 9, with issue-order hints
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -997,6 +967,9 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
       if (gather) CHI0_BF16_TALL_GATHER_LAUNCH(lolo, false, nwg, s, a);
       else CHI0_BF16_KERNEL_LAUNCH(herk_bf16x3_tall_kernel, lolo, false, nwg, s, a);
       break;
+    case 9:
+    case 10:
+      return herk_bf16x3_direct_launch(lolo, idx == 10, a, nwg, s);
     default:
       if (lolo)
         hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<true>, dim3(nwg), dim3(512), 0, s, a);
@@ -1028,6 +1001,9 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
     case 7:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall_kernel<false, true>, kNT, 0);
       break;
+    case 9:
+    case 10:
+      return herk_bf16x3_direct_max_wg_per_cu();
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false>, 512, 0);
       break;
