@@ -335,6 +335,30 @@ int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega,
                       void* eps_inv, void* wc, uint32_t flags,
                       void* hip_stream);
 
+/* Bytes of the fixed device array behind dielectric_invert_noalloc (one per
+ * GPU, held until the process ends). */
+#define CHI0_NOALLOC_SCRATCH_BYTES (256u << 20)
+
+/* dielectric_invert without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid it).  Same arguments, methods, results and error
+ * reports as dielectric_invert; its workspace (the eps matrices being
+ * inverted, the panel buffers and the pivots: about
+ * nomega * npb * (16 npb + 1544) bytes) is carved from a fixed device array
+ * of CHI0_NOALLOC_SCRATCH_BYTES instead of the handle's buffers.  A call that
+ * needs more returns CHI0_EINVAL and enqueues nothing (npb = 2048: at most 3
+ * frequencies per call; npb = 1024: 14; npb = 512: 53).  It calls no
+ * allocation routine.
+ * Every call on one GPU, from any handle, uses that GPU's one array, which
+ * keeps the last call's contents: calls that overlap on one GPU race, so the
+ * caller orders them (one stream, or events).  CHI0_INV_HPD_FALLBACK_GJ waits
+ * for the stream before it returns, as for dielectric_invert, so it cannot
+ * be captured into a graph. */
+int dielectric_invert_noalloc(chi0_handle h, int32_t npb, int32_t nomega,
+                              const double* vsqrt, const void* chi0, void* eps,
+                              void* eps_inv, void* wc, uint32_t flags,
+                              void* hip_stream);
+
 /* Wait for all work the handle enqueued, then report deferred failures since
  * the previous chi0_sync(), in this order: CHI0_EDEVICE for a runtime error,
  * CHI0_EINVAL for pairs with D <= 0 met by chi0_accumulate or

@@ -35,6 +35,7 @@ CHI0_INV_HPD = 1
 CHI0_INV_HPD_FALLBACK_GJ = 2
 INV_METHOD = {"gj": CHI0_INV_GJ, "hpd": CHI0_INV_HPD, "hpd_fallback_gj": CHI0_INV_HPD_FALLBACK_GJ}
 CHI0_OUT_WC = 8
+CHI0_NOALLOC_SCRATCH_BYTES = 256 << 20  # include/chi0.h
 
 
 class chi0_block(ctypes.Structure):
@@ -100,6 +101,7 @@ def load() -> ctypes.CDLL:
         "chi0_accumulate": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
                                     c_uint32, vp]),
         "dielectric_invert": (c_int, [vp, c_int32, c_int32, vp, vp, vp, vp, vp, c_uint32, vp]),
+        "dielectric_invert_noalloc": (c_int, [vp, c_int32, c_int32, vp, vp, vp, vp, vp, c_uint32, vp]),
         "chi0_sync": (c_int, [vp]),
         "sigx_accumulate": (c_int, [vp, POINTER(sigx_problem), c_int32, c_int, c_int, c_uint32, vp]),
         "sigc_accumulate": (c_int, [vp, POINTER(sigc_problem), c_int32, c_int, c_int, c_uint32, vp]),
@@ -497,6 +499,19 @@ class Context:
         nomega, npb, _ = chi0.shape
         flags = (CHI0_OUT_WC if wc is not None else 0) | INV_METHOD[method]
         _check(self._lib.dielectric_invert(
+            self._h, npb, nomega, _dev_ptr(vsqrt, torch.float64, "vsqrt"),
+            _dev_ptr(chi0, torch.complex128, "chi0"), _dev_ptr(eps, torch.complex128, "eps"),
+            _dev_ptr(eps_inv, torch.complex128, "eps_inv"), _dev_ptr(wc, torch.complex128, "wc"),
+            flags, _stream_ptr(stream)))
+
+    def dielectric_invert_noalloc(self, vsqrt, chi0, eps_inv, eps=None, wc=None,
+                                  method: str = "gj", stream=None) -> None:
+        """dielectric_invert with its workspace in the library's fixed
+        device array (no allocation); see CHI0_NOALLOC_SCRATCH_BYTES."""
+        import torch
+        nomega, npb, _ = chi0.shape
+        flags = (CHI0_OUT_WC if wc is not None else 0) | INV_METHOD[method]
+        _check(self._lib.dielectric_invert_noalloc(
             self._h, npb, nomega, _dev_ptr(vsqrt, torch.float64, "vsqrt"),
             _dev_ptr(chi0, torch.complex128, "chi0"), _dev_ptr(eps, torch.complex128, "eps"),
             _dev_ptr(eps_inv, torch.complex128, "eps_inv"), _dev_ptr(wc, torch.complex128, "wc"),

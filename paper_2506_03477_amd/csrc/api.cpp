@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <unordered_map>
@@ -1688,26 +1689,122 @@ int run_sigc(chi0_ctx* h, const sigc_problem* probs, int32_t nprob, chi0_precisi
   return CHI0_OK;
 }
 
+// Fixed workspace of the no-allocation inverse (dielectric_invert_noalloc):
+// a device array of CHI0_NOALLOC_SCRATCH_BYTES that every GPU the library
+// runs on holds until the process ends.  On the host its name is only a
+// stand-in; the device address, different on every GPU, is looked up once
+// per device (chi0_create) and used instead.
+static __device__ __align__(256) char scratch[CHI0_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::vector<char*> g_scratch_ptr;  // per device; NULL until looked up
+
+// Looks up this device's copy of `scratch` (the device must be current).
+int scratch_lookup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device >= static_cast<int>(g_scratch_ptr.size())) g_scratch_ptr.resize(device + 1, nullptr);
+  if (g_scratch_ptr[device]) return CHI0_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    hipGetLastError();
+    return fail(CHI0_EDEVICE, "device address of the no-allocation scratch on device %d: %s", device,
+                hipGetErrorString(e));
+  }
+  g_scratch_ptr[device] = static_cast<char*>(p);
+  return CHI0_OK;
+}
+
+char* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device < static_cast<int>(g_scratch_ptr.size()) ? g_scratch_ptr[device] : nullptr;
+}
+
+// Argument checks shared by the two inverse entry points.
+int validate_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* vsqrt,
+                    const void* chi0, const void* eps, const void* eps_inv, const void* wc,
+                    uint32_t flags) {
+  if (npb < 1) return fail(CHI0_EINVAL, "npb = %d < 1", npb);
+  if (nomega < 1) return fail(CHI0_EINVAL, "nomega = %d < 1", nomega);
+  if (flags & ~static_cast<uint32_t>(CHI0_OUT_WC | CHI0_INV_METHOD_MASK))
+    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
+  const uint32_t method = flags & CHI0_INV_METHOD_MASK;
+  if (method != CHI0_INV_GJ && method != CHI0_INV_HPD && method != CHI0_INV_HPD_FALLBACK_GJ)
+    return fail(CHI0_EINVAL, "unknown inversion method %u", method);
+  if (!vsqrt || !chi0 || !eps_inv) return fail(CHI0_EINVAL, "vsqrt, chi0 and eps_inv must be non-NULL");
+  if ((flags & CHI0_OUT_WC) && !wc) return fail(CHI0_EINVAL, "CHI0_OUT_WC set but wc is NULL");
+  if (!aligned(chi0, 16) || !aligned(eps_inv, 16) || (eps && !aligned(eps, 16)) ||
+      ((flags & CHI0_OUT_WC) && !aligned(wc, 16)) || !aligned(vsqrt, 8))
+    return fail(CHI0_EINVAL, "buffers must be 16-byte aligned (vsqrt 8-byte)");
+  const size_t bytes = static_cast<size_t>(nomega) * npb * npb * 16;
+  auto overlap = [bytes](const void* a, const void* b) {
+    if (!a || !b) return false;
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+  };
+  if (overlap(eps_inv, chi0) || overlap(eps_inv, eps) || ((flags & CHI0_OUT_WC) && (overlap(wc, eps_inv) || overlap(wc, chi0))))
+    return fail(CHI0_EINVAL, "eps_inv / wc must not overlap chi0, eps or each other");
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  return CHI0_OK;
+}
+
+// Workspace of one inversion call: either the handle's growing buffers or
+// pieces of the fixed no-allocation array.
+struct InvWs {
+  double2* work = nullptr;               // [nomega][npb][npb] eps being inverted
+  double2 *hpd_p = nullptr, *hpd_c = nullptr, *hpd_dinv = nullptr;
+  double2* wrow = nullptr;               // Gauss-Jordan pivot rows
+  int32_t *piv = nullptr, *perm = nullptr;
+};
+
+// Layout of an inversion's workspace from byte 0 of one region (every piece
+// 256-byte aligned); returns the bytes used.
+size_t inv_layout(int32_t npb, int32_t nomega, char* base, InvWs* ws) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  const size_t n = static_cast<size_t>(npb), w = static_cast<size_t>(nomega);
+  const size_t hb = static_cast<size_t>(hpd_block_width()), gb = static_cast<size_t>(gj_panel_width());
+  InvWs t;
+  t.work = reinterpret_cast<double2*>(take(w * n * n * 16));
+  t.hpd_p = reinterpret_cast<double2*>(take(w * n * hb * 16));
+  t.hpd_c = reinterpret_cast<double2*>(take(w * n * hb * 16));
+  t.hpd_dinv = reinterpret_cast<double2*>(take(w * hb * hb * 16));
+  t.wrow = reinterpret_cast<double2*>(take(w * gb * n * 16));
+  t.piv = reinterpret_cast<int32_t*>(take(w * n * 4));
+  t.perm = reinterpret_cast<int32_t*>(take(w * n * 4));
+  if (ws) *ws = t;
+  return off;
+}
+
+// eps = 1 - v^1/2 chi0 v^1/2 and its inverse.  fixed: the workspace to use
+// (the no-allocation entry point); NULL: the handle's buffers, grown as
+// needed.
 int run_invert(chi0_ctx* h, int32_t npb, int32_t nomega, const double* vsqrt, const void* chi0,
-               void* eps, void* eps_inv, void* wc, uint32_t flags, hipStream_t s) {
+               void* eps, void* eps_inv, void* wc, uint32_t flags, hipStream_t s,
+               const InvWs* fixed = nullptr) {
   const size_t bytes = static_cast<size_t>(nomega) * npb * npb * 16;
   const uint32_t method = flags & CHI0_INV_METHOD_MASK;
   double2* wc_out = (flags & CHI0_OUT_WC) ? static_cast<double2*>(wc) : nullptr;
   int rc;
-  if ((rc = h->gj_work.reserve(bytes, &h->ws_gen))) return rc;
-  double2* work = static_cast<double2*>(h->gj_work.p);
+  if (!fixed && (rc = h->gj_work.reserve(bytes, &h->ws_gen))) return rc;
+  double2* work = fixed ? fixed->work : static_cast<double2*>(h->gj_work.p);
   hipError_t e = dielectric_build_launch(static_cast<const double2*>(chi0), vsqrt, work,
                                          static_cast<double2*>(eps), npb, nomega, s);
   if (e != hipSuccess) return fail(CHI0_EDEVICE, "eps build launch: %s", hipGetErrorString(e));
 
   if (method != CHI0_INV_GJ) {
     const int nb = hpd_block_width();
-    if ((rc = h->hpd_p.reserve(static_cast<size_t>(nomega) * npb * nb * 16, &h->ws_gen))) return rc;
-    if ((rc = h->hpd_c.reserve(static_cast<size_t>(nomega) * npb * nb * 16, &h->ws_gen))) return rc;
-    if ((rc = h->hpd_dinv.reserve(static_cast<size_t>(nomega) * nb * nb * 16, &h->ws_gen))) return rc;
-    double2* pb = static_cast<double2*>(h->hpd_p.p);
-    double2* cb = static_cast<double2*>(h->hpd_c.p);
-    double2* di = static_cast<double2*>(h->hpd_dinv.p);
+    if (!fixed) {
+      if ((rc = h->hpd_p.reserve(static_cast<size_t>(nomega) * npb * nb * 16, &h->ws_gen))) return rc;
+      if ((rc = h->hpd_c.reserve(static_cast<size_t>(nomega) * npb * nb * 16, &h->ws_gen))) return rc;
+      if ((rc = h->hpd_dinv.reserve(static_cast<size_t>(nomega) * nb * nb * 16, &h->ws_gen))) return rc;
+    }
+    double2* pb = fixed ? fixed->hpd_p : static_cast<double2*>(h->hpd_p.p);
+    double2* cb = fixed ? fixed->hpd_c : static_cast<double2*>(h->hpd_c.p);
+    double2* di = fixed ? fixed->hpd_dinv : static_cast<double2*>(h->hpd_dinv.p);
     const bool fallback = method == CHI0_INV_HPD_FALLBACK_GJ;
     e = hpd_status_clear_launch(h->d_status, s);
     for (int k0 = 0; k0 < npb && e == hipSuccess; k0 += nb)
@@ -1729,12 +1826,14 @@ int run_invert(chi0_ctx* h, int32_t npb, int32_t nomega, const double* vsqrt, co
   }
 
   const int nb = gj_panel_width();
-  if ((rc = h->gj_wrow.reserve(static_cast<size_t>(nomega) * nb * npb * 16, &h->ws_gen))) return rc;
-  if ((rc = h->gj_piv.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
-  if ((rc = h->gj_perm.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
-  double2* wrow = static_cast<double2*>(h->gj_wrow.p);
-  int32_t* piv = static_cast<int32_t*>(h->gj_piv.p);
-  int32_t* perm = static_cast<int32_t*>(h->gj_perm.p);
+  if (!fixed) {
+    if ((rc = h->gj_wrow.reserve(static_cast<size_t>(nomega) * nb * npb * 16, &h->ws_gen))) return rc;
+    if ((rc = h->gj_piv.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
+    if ((rc = h->gj_perm.reserve(static_cast<size_t>(nomega) * npb * 4, &h->ws_gen))) return rc;
+  }
+  double2* wrow = fixed ? fixed->wrow : static_cast<double2*>(h->gj_wrow.p);
+  int32_t* piv = fixed ? fixed->piv : static_cast<int32_t*>(h->gj_piv.p);
+  int32_t* perm = fixed ? fixed->perm : static_cast<int32_t*>(h->gj_perm.p);
   // Each panel of nb columns is eliminated as sub-panels: a sub-panel is
   // factored by one workgroup per frequency, then applied to the panel's
   // other columns by the interchange / pivot-row and update kernels
@@ -1799,6 +1898,8 @@ int chi0_create(chi0_handle* out, int device) {
   std::unique_ptr<chi0_ctx> h(new chi0_ctx());
   h->device = device;
   h->ncu = prop.multiProcessorCount;
+  int rc = scratch_lookup(device);
+  if (rc) return rc;
   HIP_TRY(hipMalloc(&h->d_status, 64));
   HIP_TRY(hipMemset(h->d_status, 0, 64));
   HIP_TRY(hipEventCreateWithFlags(&h->staging_done, hipEventDisableTiming));
@@ -1953,32 +2054,31 @@ int chi0_accumulate(chi0_handle h, const chi0_problem* probs, int32_t nprob, chi
 int dielectric_invert(chi0_handle h, int32_t npb, int32_t nomega, const double* vsqrt,
                       const void* chi0, void* eps, void* eps_inv, void* wc, uint32_t flags,
                       void* hip_stream) {
-  if (npb < 1) return fail(CHI0_EINVAL, "npb = %d < 1", npb);
-  if (nomega < 1) return fail(CHI0_EINVAL, "nomega = %d < 1", nomega);
-  if (flags & ~static_cast<uint32_t>(CHI0_OUT_WC | CHI0_INV_METHOD_MASK))
-    return fail(CHI0_EINVAL, "unknown flag bits 0x%x", flags);
-  const uint32_t method = flags & CHI0_INV_METHOD_MASK;
-  if (method != CHI0_INV_GJ && method != CHI0_INV_HPD && method != CHI0_INV_HPD_FALLBACK_GJ)
-    return fail(CHI0_EINVAL, "unknown inversion method %u", method);
-  if (!vsqrt || !chi0 || !eps_inv) return fail(CHI0_EINVAL, "vsqrt, chi0 and eps_inv must be non-NULL");
-  if ((flags & CHI0_OUT_WC) && !wc) return fail(CHI0_EINVAL, "CHI0_OUT_WC set but wc is NULL");
-  if (!aligned(chi0, 16) || !aligned(eps_inv, 16) || (eps && !aligned(eps, 16)) ||
-      ((flags & CHI0_OUT_WC) && !aligned(wc, 16)) || !aligned(vsqrt, 8))
-    return fail(CHI0_EINVAL, "buffers must be 16-byte aligned (vsqrt 8-byte)");
-  const size_t bytes = static_cast<size_t>(nomega) * npb * npb * 16;
-  auto overlap = [bytes](const void* a, const void* b) {
-    if (!a || !b) return false;
-    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-    return x < y + bytes && y < x + bytes;
-  };
-  if (overlap(eps_inv, chi0) || overlap(eps_inv, eps) || ((flags & CHI0_OUT_WC) && (overlap(wc, eps_inv) || overlap(wc, chi0))))
-    return fail(CHI0_EINVAL, "eps_inv / wc must not overlap chi0, eps or each other");
-  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  int rc = validate_invert(h, npb, nomega, vsqrt, chi0, eps, eps_inv, wc, flags);
+  if (rc) return rc;
   HIP_TRY(hipSetDevice(h->device));
   const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  int rc;
   if ((rc = call_begin(h, s))) return rc;
   return call_end(h, s, run_invert(h, npb, nomega, vsqrt, chi0, eps, eps_inv, wc, flags, s));
+}
+
+int dielectric_invert_noalloc(chi0_handle h, int32_t npb, int32_t nomega, const double* vsqrt,
+                              const void* chi0, void* eps, void* eps_inv, void* wc, uint32_t flags,
+                              void* hip_stream) {
+  int rc = validate_invert(h, npb, nomega, vsqrt, chi0, eps, eps_inv, wc, flags);
+  if (rc) return rc;
+  const size_t need = inv_layout(npb, nomega, nullptr, nullptr);
+  if (need > static_cast<size_t>(CHI0_NOALLOC_SCRATCH_BYTES))
+    return fail(CHI0_EINVAL, "npb = %d, nomega = %d needs %zu bytes of workspace; the no-allocation "
+                "inverse has %zu", npb, nomega, need, static_cast<size_t>(CHI0_NOALLOC_SCRATCH_BYTES));
+  char* base = scratch_of(h->device);
+  if (!base) return fail(CHI0_EDEVICE, "no-allocation scratch of device %d not looked up", h->device);
+  InvWs ws;
+  inv_layout(npb, nomega, base, &ws);
+  HIP_TRY(hipSetDevice(h->device));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((rc = call_begin(h, s))) return rc;
+  return call_end(h, s, run_invert(h, npb, nomega, vsqrt, chi0, eps, eps_inv, wc, flags, s, &ws));
 }
 
 int chi0_sync(chi0_handle h) {
