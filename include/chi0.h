@@ -37,6 +37,10 @@
  *     caller orders captured work.
  *   - Return values are chi0_status codes; chi0_last_error() gives a message
  *     for the calling thread's most recent failure.
+ *   - Debugging: with the environment variable CHI0_LOG set (to anything but
+ *     "0") when the library is first used, every rank-K launch (tile,
+ *     units, workgroups, workspace bytes) and every inversion (method,
+ *     workspace) is described on stderr, one line each.
  */
 #ifndef CHI0_H
 #define CHI0_H

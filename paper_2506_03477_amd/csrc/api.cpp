@@ -153,6 +153,27 @@ int kind_of(chi0_precision p) {
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// Debug log: with the environment variable CHI0_LOG set to a non-empty value
+// other than "0", every launch decision (plan, tile, workspace) is printed
+// to stderr, one line each.
+bool log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("CHI0_LOG");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+void debug_log(const char* fmt, ...) {
+  if (!log_on()) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[libchi0] %s\n", buf);
+}
+
 // Calls share the handle's workspace (partial tiles, weights, split planes,
 // plan tables, inverse buffers), so they are ordered across streams: a call
 // on another stream than the previous call's first waits for the event that
@@ -834,6 +855,11 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
   ra.accumulate = (flags & CHI0_ACCUMULATE) ? 1 : 0;
 
   const bool use_graph = (flags & CHI0_USE_GRAPH) && !h->profiling && !hk;
+  debug_log("rank-K launch: kind %d tile %d (%d x %d, %d threads), %d problem(s), %d units on %d "
+       "workgroups, %d tile jobs, partials %zu B, weights %zu B, pre-split %zu B%s%s",
+       kind, pl->tile_idx, TP, TQ, pl->tc.threads, nprob, pl->nunits, pl->nwg, pl->njobs,
+       static_cast<size_t>(pl->nunits) * TP * TQ * sizeof(double2), hk ? static_cast<size_t>(0) : wbytes,
+       zbytes, use_graph ? ", graph" : "", hk ? ", gathered rows" : "");
   if (use_graph) {
     // delta_min and the LO*LO flag are kernel arguments: the cached graph is
     // only reused with the same values, so they join the key
@@ -1789,6 +1815,8 @@ int run_invert(chi0_ctx* h, int32_t npb, int32_t nomega, const double* vsqrt, co
   const uint32_t method = flags & CHI0_INV_METHOD_MASK;
   double2* wc_out = (flags & CHI0_OUT_WC) ? static_cast<double2*>(wc) : nullptr;
   int rc;
+  debug_log("inverse: npb %d, %d frequencies, method %u%s, workspace %s", npb, nomega, method,
+       wc_out ? ", W^c" : "", fixed ? "fixed array" : "handle buffers");
   if (!fixed && (rc = h->gj_work.reserve(bytes, &h->ws_gen))) return rc;
   double2* work = fixed ? fixed->work : static_cast<double2*>(h->gj_work.p);
   hipError_t e = dielectric_build_launch(static_cast<const double2*>(chi0), vsqrt, work,

@@ -173,3 +173,41 @@ def test_partial_cap_splits_launches(ctx, path):
         ctx.set_partial_cap(0)
         ctx.set_tile(path, -1)
     ctx.sync()
+
+
+_LOG_SCRIPT = """
+import sys, torch
+sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+from gpu_common import device_problem
+from paper_2506_03477_amd import Context
+from synth import workload
+ctx = Context(0)
+wl = workload(0)
+prob, vsqrt, _ = device_problem(wl, ztype="c128")
+ctx.chi0_accumulate([prob], precision="fp64")
+inv = torch.empty_like(prob.chi0)
+ctx.dielectric_invert(vsqrt, prob.chi0, inv, method="hpd")
+ctx.sync()
+ctx.close()
+"""
+
+
+@pytest.mark.parametrize("value", ["1", "0"])
+def test_chi0_log_switch(value):
+    """CHI0_LOG describes each launch on stderr (a child process, since the
+    switch is read once per process); "0" keeps the library silent."""
+    import os
+    import subprocess
+    need_gpu()
+    tests = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(tests)
+    env = dict(os.environ, CHI0_LOG=value)
+    r = subprocess.run([sys.executable, "-c", _LOG_SCRIPT.format(root=root, tests=tests)],
+                       env=env, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[libchi0]")]
+    if value == "1":
+        assert any("rank-K launch: kind 0" in l for l in lines), r.stderr[-2000:]
+        assert any("inverse: npb 64, 4 frequencies, method 1" in l for l in lines), r.stderr[-2000:]
+    else:
+        assert lines == []
