@@ -313,7 +313,7 @@ int sigc_set_workspace_cap(chi0_handle h, int64_t bytes);
 
 /* Cap in bytes of the FP64 partial tiles of one rank-K launch of
  * chi0_accumulate, sigx_accumulate and chi0_hist_accumulate (0: the
- * default, 6e9).  Work above the cap is split into sequential launches on
+ * default, 12e9).  Work above the cap is split into sequential launches on
  * the call's stream; a cap below one frequency's tiles of a problem makes
  * the call return CHI0_ENOMEM.  CHI0_EINVAL for a negative value. */
 int chi0_set_partial_cap(chi0_handle h, int64_t bytes);
@@ -399,6 +399,10 @@ int chi0_set_tile(chi0_handle h, chi0_precision prec, int32_t tile);
 int chi0_get_tile(chi0_handle h, chi0_precision prec, int32_t* tile);
 int chi0_last_tile(chi0_handle h, chi0_precision prec, int32_t* tile);
 int chi0_tile_choice(chi0_precision prec, const chi0_problem* probs, int32_t nprob, int32_t* tile);
+/* Work lists per workgroup of a configuration: 1 when a workgroup takes
+ * each unit as a whole (tile_p x tile_q units), 4 when each of its four
+ * waves takes units of its own; CHI0_EINVAL for an unknown configuration. */
+int chi0_tile_lists(chi0_precision prec, int32_t tile);
 
 /* FP32 run length of the reduced-precision paths: the number of pairs summed
  * in FP32 before the partial sum is added into FP64.  By default it is
@@ -432,8 +436,10 @@ int chi0_profile_read(chi0_handle h, double* kernel_ms, int64_t* launches);
  * blocks' nocc / nunocc are read).  Returns the number of units and of tile
  * jobs; when units_out is not NULL (capacity units_cap units), writes 10
  * int32 per unit: problem, frequency, tile row, tile column, first block,
- * first pair, last block, end pair (exclusive), partial slot, workgroup.
- * load_max / load_mean give the planned per-workgroup cost (pairs). */
+ * first pair, last block, end pair (exclusive), partial slot, work list
+ * (the workgroup; for configurations with a list per wave,
+ * workgroup * chi0_tile_lists() + wave).  load_max / load_mean give the
+ * planned cost per work list (pairs). */
 int chi0_plan_inspect(const chi0_problem* probs, int32_t nprob, chi0_precision prec,
                       int32_t tile, int32_t nwg, int32_t* nunits, int32_t* njobs,
                       int32_t* units_out, int32_t units_cap, double* load_max,

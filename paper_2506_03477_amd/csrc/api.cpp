@@ -77,6 +77,7 @@ struct Plan {
   TileConfig tc{};
   int nwg = 0;
   int nunits = 0;
+  int64_t nslots = 0;
   int njobs = 0;
   int nblocks_total = 0;
   int nprob = 0;
@@ -116,7 +117,7 @@ struct chi0_ctx {
   int32_t hist_bins_used = 0;         // non-empty bins of the last histogram call
   int sigc_variant = 1;
   int64_t sigc_zw_cap = int64_t(4) << 30;
-  double partial_cap = 6.0e9;  // FP64 partial tiles per rank-K launch (bytes)
+  double partial_cap = 12.0e9;  // FP64 partial tiles per rank-K launch (bytes)
   uint64_t ws_gen = 1;
   int32_t* d_status = nullptr;
   void* staging = nullptr;  // pinned host staging for table uploads
@@ -358,7 +359,8 @@ int upload_sync(DevBuf& d, const std::vector<T>& v) {
 //    workgroups share an XCD (workgroups are dispatched round-robin over the
 //    8 XCDs), so units that read the same Z columns share an L2.
 struct HostPlan {
-  std::vector<Unit> units;
+  std::vector<Unit> units;      // work items (a unit may hold several frequencies)
+  int64_t nslots = 0;           // FP64 partial slots (one per frequency, tile and range)
   std::vector<TileJob> jobs;
   std::vector<int32_t> wg_off, wg_units;
   std::vector<double> cost;
@@ -367,7 +369,7 @@ struct HostPlan {
 };
 
 // Default upper bound on the FP64 partial tiles of one rank-K launch (bytes).
-constexpr double kMaxPartialBytes = 6.0e9;
+constexpr double kMaxPartialBytes = 12.0e9;
 
 // Lower-triangle tiles of a TP x TQ tiling of an npb x npb matrix: tile
 // (tp, tq) is needed iff it holds an entry on or below the diagonal.
@@ -380,9 +382,18 @@ void lower_tiles(int npb, int TP, int TQ, std::vector<std::pair<int, int>>& out)
   }
 }
 
-void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int nprob, HostPlan& hp,
-               double max_partial_bytes = kMaxPartialBytes) {
+void plan_host(const TileConfig& tc, int nwg_launch, const chi0_problem* probs, int nprob,
+               HostPlan& hp, double max_partial_bytes = kMaxPartialBytes) {
   const int TP = tc.tile, TQ = tc.tile_q;
+  // work lists: one per workgroup, or one per wave (W per workgroup); the
+  // dealing below is over lists, the placement keeps the W lists of a
+  // workgroup together
+  const int W = std::max(1, static_cast<int>(tc.wave_lists));
+  const int nwg = nwg_launch * W;
+  // frequencies per unit (frequency-group configurations); ngrp: units per
+  // (tile, range) of a problem with nomega frequencies
+  const int G = std::max(1, static_cast<int>(tc.omega_group));
+  auto ngrp = [G](int nomega) { return (nomega + G - 1) / G; };
   struct P {
     int npb, nomega, ntl, b0, nb;
     int64_t K;
@@ -406,7 +417,7 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
       q.cum[b + 1] = q.cum[b] + static_cast<int64_t>(probs[p].blocks[b].nocc) * probs[p].blocks[b].nunocc;
     q.K = q.cum[q.nb];
     bflat += q.nb;
-    work += static_cast<double>(q.nomega) * q.ntl * static_cast<double>(q.K);
+    work += static_cast<double>(ngrp(q.nomega)) * q.ntl * static_cast<double>(q.K);
   }
   hp.nblocks_total = bflat;
 
@@ -431,11 +442,12 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
   // rounds of the persistent grid (round-robin dealing is then exact)
   if (nprob == 1 && ps[0].K > 0) {
     const double jobs = static_cast<double>(ps[0].nomega) * ps[0].ntl;
+    const double units_per_range = static_cast<double>(ngrp(ps[0].nomega)) * ps[0].ntl;
     const int64_t s0 = std::max<int64_t>(1, std::llround(std::ceil(ps[0].K / per_unit)));
     for (int64_t sr = s0; sr <= s0 + 16 && sr <= ps[0].K; ++sr) {
-      const double nu = jobs * sr;
+      const double nu = units_per_range * sr;
       if (std::fmod(nu, static_cast<double>(nwg)) == 0.0 &&
-          nu * slot_bytes <= max_partial_bytes) {
+          jobs * sr * slot_bytes <= max_partial_bytes) {
         per_unit = static_cast<double>(ps[0].K) / sr * (1.0 + 1e-9);
         break;
       }
@@ -496,6 +508,8 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
           u.prob = p; u.iw = iw; u.tp = tp; u.tq = tq;
           u.b0 = rg.b0; u.p0 = rg.p0; u.b1 = rg.b1; u.p1 = rg.p1;
           u.slot = static_cast<int32_t>(hp.units.size());
+          u.nw = 1;
+          u.wstride = 0;
           hp.units.push_back(u);
           unit_range_idx.push_back(static_cast<int>(r));
           // cost: pairs rounded up to staging chunks per block touched, plus a
@@ -504,6 +518,35 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
           hp.cost.push_back(static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0);
         }
       }
+  }
+  hp.nslots = static_cast<int64_t>(hp.units.size());
+  // frequency groups: the units of up to G consecutive frequencies of one
+  // (problem, tile, range) become one unit (their slots are a fixed stride
+  // apart: the units above are in (problem, frequency, tile, range) order)
+  if (G > 1) {
+    std::vector<Unit> gu;
+    std::vector<double> gc;
+    std::vector<int> gr;
+    size_t base = 0;
+    for (int p = 0; p < nprob; ++p) {
+      const P& q = ps[p];
+      const size_t s_p = ranges[p].size(), ntl = q.tiles.size();
+      for (size_t t = 0; t < ntl; ++t)
+        for (size_t r = 0; r < s_p; ++r)
+          for (int iw0 = 0; iw0 < q.nomega; iw0 += G) {
+            const size_t idx = base + (static_cast<size_t>(iw0) * ntl + t) * s_p + r;
+            Unit u = hp.units[idx];
+            u.nw = std::min(G, q.nomega - iw0);
+            u.wstride = static_cast<int32_t>(ntl * s_p);
+            gu.push_back(u);
+            gc.push_back(hp.cost[idx]);
+            gr.push_back(static_cast<int>(r));
+          }
+      base += static_cast<size_t>(q.nomega) * ntl * s_p;
+    }
+    hp.units.swap(gu);
+    hp.cost.swap(gc);
+    unit_range_idx.swap(gr);
   }
   // locality order: (problem, range, tile, frequency)
   std::vector<int> order(hp.units.size());
@@ -553,12 +596,16 @@ void plan_host(const TileConfig& tc, int nwg, const chi0_problem* probs, int npr
       heap.push(sl);
     }
   }
-  // logical -> physical placement (XCD-major)
+  // logical -> physical placement (XCD-major over workgroups; a
+  // workgroup's W lists stay together)
   const int nxcd = 8;
   std::vector<int> phys_of(nwg);
-  if (nwg % nxcd == 0) {
-    const int per = nwg / nxcd;
-    for (int L = 0; L < nwg; ++L) phys_of[L] = (L % per) * nxcd + L / per;
+  if (nwg_launch % nxcd == 0) {
+    const int per = nwg_launch / nxcd;
+    for (int L = 0; L < nwg; ++L) {
+      const int lw = L / W;
+      phys_of[L] = ((lw % per) * nxcd + lw / per) * W + L % W;
+    }
   } else {
     for (int L = 0; L < nwg; ++L) phys_of[L] = L;
   }
@@ -592,6 +639,7 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
   plan_host(tc, nwg, probs, nprob, hp, h->partial_cap);
   pl.nblocks_total = hp.nblocks_total;
   pl.nunits = static_cast<int>(hp.units.size());
+  pl.nslots = hp.nslots;
   pl.njobs = static_cast<int>(hp.jobs.size());
   int rc;
   if ((rc = upload_sync(pl.d_units, hp.units))) return rc;
@@ -744,7 +792,7 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
   }
   if (pl->nunits == 0) return CHI0_OK;
   const int TP = pl->tc.tile, TQ = pl->tc.tile_q;
-  int rc = h->partials.reserve(static_cast<size_t>(pl->nunits) * TP * TQ * sizeof(double2), &h->ws_gen);
+  int rc = h->partials.reserve(static_cast<size_t>(pl->nslots) * TP * TQ * sizeof(double2), &h->ws_gen);
   if (rc) return rc;
   const int nblocks_total = pl->nblocks_total;
 
@@ -858,7 +906,7 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
   debug_log("rank-K launch: kind %d tile %d (%d x %d, %d threads), %d problem(s), %d units on %d "
        "workgroups, %d tile jobs, partials %zu B, weights %zu B, pre-split %zu B%s%s",
        kind, pl->tile_idx, TP, TQ, pl->tc.threads, nprob, pl->nunits, pl->nwg, pl->njobs,
-       static_cast<size_t>(pl->nunits) * TP * TQ * sizeof(double2), hk ? static_cast<size_t>(0) : wbytes,
+       static_cast<size_t>(pl->nslots) * TP * TQ * sizeof(double2), hk ? static_cast<size_t>(0) : wbytes,
        zbytes, use_graph ? ", graph" : "", hk ? ", gathered rows" : "");
   if (use_graph) {
     // delta_min and the LO*LO flag are kernel arguments: the cached graph is
@@ -2145,6 +2193,13 @@ int chi0_tile_info(chi0_precision prec, int32_t tile, int32_t* tile_p, int32_t* 
   return CHI0_OK;
 }
 
+int chi0_tile_lists(chi0_precision prec, int32_t tile) {
+  const int k = kind_of(prec);
+  if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
+  if (tile < 0 || tile >= herk_tile_count(k)) return fail(CHI0_EINVAL, "tile %d out of range", tile);
+  return std::max(1, static_cast<int>(herk_tile_config(k, tile).wave_lists));
+}
+
 int chi0_set_tile(chi0_handle h, chi0_precision prec, int32_t tile) {
   if (!h) return fail(CHI0_EINVAL, "handle is NULL");
   const int k = kind_of(prec);
@@ -2265,20 +2320,27 @@ int chi0_plan_inspect(const chi0_problem* probs, int32_t nprob, chi0_precision p
   }
   HostPlan hp;
   plan_host(herk_tile_config(k, tile), nwg, probs, nprob, hp);
-  if (nunits) *nunits = static_cast<int32_t>(hp.units.size());
+  // one row per frequency of every unit (a frequency-group unit gives one
+  // row for each of its frequencies, all owned by the unit's list)
+  if (nunits) *nunits = static_cast<int32_t>(hp.nslots);
   if (njobs) *njobs = static_cast<int32_t>(hp.jobs.size());
   if (units_out) {
-    if (units_cap < static_cast<int32_t>(hp.units.size()))
-      return fail(CHI0_EINVAL, "units_out holds %d units, %zu needed", units_cap, hp.units.size());
-    // per unit: prob, iw, tp, tq, b0, p0, b1, p1, slot, workgroup
+    if (units_cap < hp.nslots)
+      return fail(CHI0_EINVAL, "units_out holds %d units, %lld needed", units_cap,
+                  static_cast<long long>(hp.nslots));
+    // per row: prob, iw, tp, tq, b0, p0, b1, p1, slot, work list
     std::vector<int32_t> owner(hp.units.size(), -1);
-    for (int w = 0; w < nwg; ++w)
+    const int nlists = static_cast<int>(hp.wg_off.size()) - 1;
+    for (int w = 0; w < nlists; ++w)
       for (int i = hp.wg_off[w]; i < hp.wg_off[w + 1]; ++i) owner[hp.wg_units[i]] = w;
+    size_t row = 0;
     for (size_t u = 0; u < hp.units.size(); ++u) {
       const Unit& x = hp.units[u];
-      int32_t* o = units_out + 10 * u;
-      o[0] = x.prob; o[1] = x.iw; o[2] = x.tp; o[3] = x.tq; o[4] = x.b0;
-      o[5] = x.p0; o[6] = x.b1; o[7] = x.p1; o[8] = x.slot; o[9] = owner[u];
+      for (int w = 0; w < std::max(1, static_cast<int>(x.nw)); ++w, ++row) {
+        int32_t* o = units_out + 10 * row;
+        o[0] = x.prob; o[1] = x.iw + w; o[2] = x.tp; o[3] = x.tq; o[4] = x.b0;
+        o[5] = x.p0; o[6] = x.b1; o[7] = x.p1; o[8] = x.slot + w * x.wstride; o[9] = owner[u];
+      }
     }
   }
   double mx = 0.0, sum = 0.0;

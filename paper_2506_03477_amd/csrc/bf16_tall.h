@@ -138,13 +138,12 @@ __device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr,
 }
 
 // Add (or store, when first) a wave's (32 NBI) x 64 accumulators into the
-// FP64 partial tile (256 x 128, row-major); 16 old values are loaded as a
-// group.
-template <int NBI = 4>
+// FP64 partial tile (TQ columns, row-major: 256 x 128 for a workgroup's tile,
+// 128 x 64 for a wave's own); 16 old values are loaded as a group.
+template <int NBI = 4, int TQ = 128>
 __device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32x16 (&cr)[NBI][2],
                                            const f32x16 (&ci)[NBI][2], int wr, int wc, int lane,
                                            bool first) {
-  constexpr int TQ = 128;
   const int g = lane >> 5;
   const int cl = lane & 31;
   int base = (wr * (32 * NBI) + 4 * g) * TQ + wc * 64 + cl;

@@ -55,7 +55,12 @@ struct Unit {
   int32_t b1;     // last block (inclusive)
   int32_t p1;     // end pair (exclusive) of block b1
   int32_t slot;
-  int32_t pad[3];
+  // Frequency-group units (tile configurations with omega_group > 1): the
+  // unit covers frequencies iw .. iw + nw - 1, frequency iw + w writing
+  // partial slot slot + w * wstride.  Otherwise nw = 1.
+  int32_t nw;
+  int32_t wstride;
+  int32_t pad;
 };
 
 // Reduction job: the partial slots [slot0, slot0 + nslot) of one tile are
@@ -227,6 +232,11 @@ struct TileConfig {
   int32_t threads;   // workgroup size
   int32_t tile_q;    // tile columns (Q side); tile = tile_q or tile = 2 tile_q
   int32_t presplit;  // 1: the kernel reads the P side from BlockDesc::zs
+  int32_t wave_lists;  // work lists per workgroup: 0 or 1 (the workgroup takes
+                       // a unit as a whole), or one per wave (each wave takes
+                       // its own units, of tile x tile_q)
+  int32_t omega_group; // 0 or 1: a unit is one frequency; G > 1: a unit holds
+                       // up to G frequencies of one tile and pair range
 };
 
 // Groups of 4 pairs in a block's pre-split planes (whole 16-pair stages).

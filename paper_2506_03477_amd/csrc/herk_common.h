@@ -39,6 +39,40 @@ __device__ __forceinline__ X ld_const(const X* p, int i) {
   return ((const X __attribute__((address_space(4)))*)(p))[i];
 }
 
+// A unit and a problem descriptor read field by field through the scalar
+// cache (uniform values in scalar registers).
+__device__ __forceinline__ Unit ld_unit(const Unit* units, int idx) {
+  const Unit* p = units + idx;
+  Unit u;
+  u.prob = ld_const(&p->prob, 0);
+  u.iw = ld_const(&p->iw, 0);
+  u.tp = ld_const(&p->tp, 0);
+  u.tq = ld_const(&p->tq, 0);
+  u.b0 = ld_const(&p->b0, 0);
+  u.p0 = ld_const(&p->p0, 0);
+  u.b1 = ld_const(&p->b1, 0);
+  u.p1 = ld_const(&p->p1, 0);
+  u.slot = ld_const(&p->slot, 0);
+  u.nw = ld_const(&p->nw, 0);
+  u.wstride = ld_const(&p->wstride, 0);
+  u.pad = 0;
+  return u;
+}
+
+__device__ __forceinline__ ProbDesc ld_prob(const ProbDesc* probs, int idx) {
+  const ProbDesc* p = probs + idx;
+  ProbDesc d;
+  d.chi0 = ld_const(&p->chi0, 0);
+  d.omega = ld_const(&p->omega, 0);
+  d.wts = ld_const(&p->wts, 0);
+  d.ktot = ld_const(&p->ktot, 0);
+  d.npb = ld_const(&p->npb, 0);
+  d.nomega = ld_const(&p->nomega, 0);
+  d.flush = ld_const(&p->flush, 0);
+  d.pad = 0;
+  return d;
+}
+
 __device__ __forceinline__ int block_pairs(const BlockDesc* blocks, int b) {
   const BlockDesc* bp = blocks + b;
   const int* f = reinterpret_cast<const int*>(&bp->nocc);
@@ -102,9 +136,14 @@ int herk_bf16x3_tile_count();
 TileConfig herk_bf16x3_tile(int idx);
 hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s, bool gather);
 int herk_bf16x3_max_wg_per_cu(int idx);
-// Register-direct BF16x3 kernel (256 x 128 tall-tile units, P side pre-split).
-hipError_t herk_bf16x3_direct_launch(bool lolo, bool hint, const HerkArgs& a, int nwg,
-                                     hipStream_t s);
+// Register-direct BF16x3 kernel (P side pre-split): 256 x 128 workgroup
+// units, or 128 x 64 units on one work list per wave.
+hipError_t herk_bf16x3_direct_launch(bool lolo, bool hint, bool wave_units, const HerkArgs& a,
+                                     int nwg, hipStream_t s);
 int herk_bf16x3_direct_max_wg_per_cu();
+// BF16x3 kernel on frequency-group units (128 x 64 tiles, up to four
+// frequencies per workgroup, operands staged once in LDS).
+hipError_t herk_bf16x3_wgroup_launch(bool lolo, const HerkArgs& a, int nwg, hipStream_t s);
+int herk_bf16x3_wgroup_max_wg_per_cu();
 
 }  // namespace chi0

@@ -207,30 +207,39 @@ __device__ __forceinline__ void zero8(f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
     }
 }
 
-template <bool LOLO, bool HINT>
+// WAVE_UNITS = false: the workgroup takes 256 x 128 units, wave (wr, wc)
+// their 128 x 64 sub-tile.  WAVE_UNITS = true: every wave has its own work
+// list of 128 x 64 units (the planner deals a tile's frequencies to the
+// waves of one workgroup, so the four waves read the same rows of Z and the
+// L1 serves them once), and diagonal tiles cost no idle waves.
+template <bool LOLO, bool HINT, bool WAVE_UNITS>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_direct_kernel(HerkArgs a) {
-  constexpr int TP = 256, TQ = 128;
+  constexpr int TP = WAVE_UNITS ? 128 : 256, TQ = WAVE_UNITS ? 64 : 128;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = WAVE_UNITS ? 0 : wave >> 1, wc = WAVE_UNITS ? 0 : wave & 1;
   const int g8 = lane >> 5;
   const int l32 = lane & 31;
 
-  const int beg = a.wg_offsets[blockIdx.x];
-  const int end = a.wg_offsets[blockIdx.x + 1];
+  // work list, units and problem descriptors through the scalar cache (they
+  // are uniform: every branch on them stays a scalar branch)
+  const int list = WAVE_UNITS ? static_cast<int>(blockIdx.x) * (kNT / 64) + wave
+                              : static_cast<int>(blockIdx.x);
+  const int beg = ld_const(a.wg_offsets, list);
+  const int end = ld_const(a.wg_offsets, list + 1);
   for (int ui = beg; ui < end; ++ui) {
-    // The four waves start every unit together: a wave that skips its
-    // sub-tile must not run ahead into later units, or the workgroups of
-    // an XCD stop streaming the same rows of Z at the same time and its L2
-    // no longer serves them (measured: L2 hit rate 36% without this, HBM
-    // traffic ten times that of the LDS-staged kernel).
-    __syncthreads();
-    const Unit u = a.units[a.wg_units[ui]];
-    const ProbDesc pd = a.probs[u.prob];
+    // The four waves of a workgroup-wide unit start it together: a wave
+    // that skips its sub-tile must not run ahead into later units, or the
+    // workgroups of an XCD stop streaming the same rows of Z at the same
+    // time and its L2 no longer serves them (measured: L2 hit rate 36%
+    // without this, HBM traffic ten times that of the LDS-staged kernel).
+    if (!WAVE_UNITS) __syncthreads();
+    const Unit u = ld_unit(a.units, ld_const(a.wg_units, ui));
+    const ProbDesc pd = ld_prob(a.probs, u.prob);
     const int npb = pd.npb;
     const int r0 = u.tp * TP + wr * 128;
     const int c0 = u.tq * TQ + wc * 64;
-    if (r0 >= npb || c0 >= npb || r0 + 127 < c0) continue;   // nothing the reduction reads
+    if (!WAVE_UNITS && (r0 >= npb || c0 >= npb || r0 + 127 < c0)) continue;   // nothing read
     const uint32_t chunk = static_cast<uint32_t>(npb) * 16u;
     const uint32_t row = static_cast<uint32_t>(npb) * 8u;
     DirectLane lo;
@@ -323,35 +332,41 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_direct_kernel(HerkArgs a) 
         t0 += len;
         steps += len;
         if (steps >= frun) {
-          tall_flush(part, cr, ci, wr, wc, lane, first);
+          tall_flush<4, TQ>(part, cr, ci, wr, wc, lane, first);
           first = false;
           steps = 0;
           zero8(cr, ci);
         }
       }
     }
-    if (first || steps > 0) tall_flush(part, cr, ci, wr, wc, lane, first);
+    if (first || steps > 0) tall_flush<4, TQ>(part, cr, ci, wr, wc, lane, first);
   }
 }
 
 }  // namespace
 
-hipError_t herk_bf16x3_direct_launch(bool lolo, bool hint, const HerkArgs& a, int nwg,
-                                     hipStream_t s) {
+template <bool WU>
+static void direct_launch(bool lolo, bool hint, const HerkArgs& a, int nwg, hipStream_t s) {
   if (lolo) {
-    if (hint) hipLaunchKernelGGL((herk_bf16x3_direct_kernel<true, true>), dim3(nwg), dim3(kNT), 0, s, a);
-    else hipLaunchKernelGGL((herk_bf16x3_direct_kernel<true, false>), dim3(nwg), dim3(kNT), 0, s, a);
+    if (hint) hipLaunchKernelGGL((herk_bf16x3_direct_kernel<true, true, WU>), dim3(nwg), dim3(kNT), 0, s, a);
+    else hipLaunchKernelGGL((herk_bf16x3_direct_kernel<true, false, WU>), dim3(nwg), dim3(kNT), 0, s, a);
   } else {
-    if (hint) hipLaunchKernelGGL((herk_bf16x3_direct_kernel<false, true>), dim3(nwg), dim3(kNT), 0, s, a);
-    else hipLaunchKernelGGL((herk_bf16x3_direct_kernel<false, false>), dim3(nwg), dim3(kNT), 0, s, a);
+    if (hint) hipLaunchKernelGGL((herk_bf16x3_direct_kernel<false, true, WU>), dim3(nwg), dim3(kNT), 0, s, a);
+    else hipLaunchKernelGGL((herk_bf16x3_direct_kernel<false, false, WU>), dim3(nwg), dim3(kNT), 0, s, a);
   }
+}
+
+hipError_t herk_bf16x3_direct_launch(bool lolo, bool hint, bool wave_units, const HerkArgs& a,
+                                     int nwg, hipStream_t s) {
+  if (wave_units) direct_launch<true>(lolo, hint, a, nwg, s);
+  else direct_launch<false>(lolo, hint, a, nwg, s);
   return hipGetLastError();
 }
 
 int herk_bf16x3_direct_max_wg_per_cu() {
   int n = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_direct_kernel<false, false>, kNT, 0);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_direct_kernel<false, false, true>, kNT, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

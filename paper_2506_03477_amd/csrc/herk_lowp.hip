@@ -907,6 +907,10 @@ static const TileConfig kBf16Tiles[] = {
     {256, kKC, 4096, 512, 128, 1},   // 8: tall tiles, 8 waves (two per SIMD)
     {256, kKC, 4096, kNT, 128, 1},   // 9: tall tiles, operands straight to registers
     {256, kKC, 4096, kNT, 128, 1},   // 10: as 9, with issue-order hints
+    {128, kKC, 4096, kNT, 64, 1, 4},  // 11: as 9, one 128 x 64 work list per wave
+    {128, kKC, 4096, kNT, 64, 1, 4},  // 12: as 11, with issue-order hints
+    {128, kKC, 4096, kNT, 64, 1, 1, 4},  // 13: 128 x 64 tiles, four frequencies per
+                                         //     workgroup sharing LDS-staged operands
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -969,7 +973,11 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
       break;
     case 9:
     case 10:
-      return herk_bf16x3_direct_launch(lolo, idx == 10, a, nwg, s);
+    case 11:
+    case 12:
+      return herk_bf16x3_direct_launch(lolo, idx == 10 || idx == 12, idx >= 11, a, nwg, s);
+    case 13:
+      return herk_bf16x3_wgroup_launch(lolo, a, nwg, s);
     default:
       if (lolo)
         hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<true>, dim3(nwg), dim3(512), 0, s, a);
@@ -1003,7 +1011,11 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
       break;
     case 9:
     case 10:
+    case 11:
+    case 12:
       return herk_bf16x3_direct_max_wg_per_cu();
+    case 13:
+      return herk_bf16x3_wgroup_max_wg_per_cu();
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false>, 512, 0);
       break;

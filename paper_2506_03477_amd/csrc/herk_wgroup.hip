@@ -1,0 +1,344 @@
+// BF16x3 weighted Hermitian rank-K update on frequency-group units.
+//
+// Same contraction as the other rank-K kernels (S[P][Q] = sum_pairs
+// conj(Z[pair][P]) * (c * Z[pair][Q]) on one 128 x 64 lower tile, chi0 = -S,
+// Eq.(polfx) at i*omega), but a unit holds up to four frequencies of one tile
+// and pair range, and wave w of the workgroup accumulates frequency iw + w.
+// The frequencies share their operands -- Z and its pre-split planes are the
+// same, only the pair weight c differs -- so the workgroup stages each
+// 32-pair stage of the tile's operands once into LDS:
+//   P: the pre-split bf16 hi / lo words of the 128 tile rows (32 KB),
+//   Q: the raw complex64 Z of the 64 tile columns (16 KB),
+//   the pair weights of the four frequencies (512 B),
+// and every wave reads its MFMA fragments from there, scales its Q side by its
+// own frequency's weights, splits it into bf16 hi / lo words (plain and
+// rotated to (im, -re)) and issues the BF16x3 MFMAs.  Global traffic is a
+// quarter of what four waves loading their own operands would need, and the
+// barrier of every stage keeps the four waves, which do the same work, on
+// the same pairs.
+//
+// Pipeline of a stage (LDS double-buffered, one barrier per stage): the next
+// stage is loaded straight from global memory into the other LDS buffer
+// (buffer loads with an LDS destination: no staging registers) while the
+// current one is computed; the barrier that ends the stage waits for those
+// loads.  Within a stage, the fragments of a
+// k-step (8 pairs) are read from LDS while the previous k-step's MFMAs issue,
+// and each column block's conversion runs while the other column block's
+// MFMAs issue.  Loads past the run's pairs or the block's planes read zeros
+// (raw buffer bounds), so the tails need no masks.  The FP32 accumulators
+// are flushed to FP64 between runs of at most the problem's flush length.
+#include "bf16_tall.h"
+#include "common.h"
+#include "herk_common.h"
+
+namespace chi0 {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef const char __attribute__((address_space(1)))* gcptr;
+
+constexpr int kWgPairs = 32;                          // pairs per stage
+constexpr int kWgPBytes = 2 * (kWgPairs / 4) * 128 * 16;   // hi + lo planes, 128 rows
+constexpr int kWgQBytes = kWgPairs * 64 * 8;          // raw Z, 64 columns
+constexpr int kWgWBytes = 4 * 64 * 4;                 // weights, 64 pairs per frequency
+constexpr int kWgBuf = kWgPBytes + kWgQBytes + kWgWBytes;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wg_rsrc(gcptr base, int64_t bytes) {
+  const int32_t n = bytes <= 0 ? 0 : bytes >= INT32_MAX ? INT32_MAX : static_cast<int32_t>(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, n, 0x00020000);
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Bases of one run (pairs [q0, q0 + nv) of a block).
+struct WgRun {
+  gcptr hi, lo;       // pre-split planes at the run's first 4-pair group
+  int64_t pbytes;     // plane bytes from there to the block's padded end
+  gcptr z;            // Z row of the run's first pair
+  int64_t zbytes;     // Z bytes of the run's pairs
+  gcptr w;            // this wave's frequency's weight of the run's first pair
+  int64_t wbytes;     // weight bytes from there to the end of the problem's table
+  int32_t chunk;      // bytes per 4-pair group of a plane (npb * 16)
+  int32_t row;        // bytes per Z row (npb * 8)
+};
+
+// Per-lane byte offsets of the stage loads.  P: chunk m (16 bytes) of thread
+// t is group (t / 128) + 2 (m % 4) of plane m / 4, tile row t % 128.  Z:
+// dword m of thread t is pair (t + 256 m) / 128, tile column
+// ((t + 256 m) % 128) / 2, part (re / im) t % 2.
+struct WgLane {
+  uint32_t p[4];
+  uint32_t q[2];      // m even / odd (4 (m / 2) rows are added per load)
+};
+
+// Loads stage st of the run into LDS buffer buf: every wave writes 1 KB
+// (16-byte loads) or 256 bytes (dword loads) per instruction, lane i at
+// offset 16 i or 4 i of the wave's destination.
+__device__ __forceinline__ void wg_dma(const WgRun& r, int st, const WgLane& o, int wave, int lane,
+                                       char* buf) {
+  const int64_t po = static_cast<int64_t>(st) * (kWgPairs / 4) * r.chunk;
+  const __amdgpu_buffer_rsrc_t h = wg_rsrc(r.hi + po, r.pbytes - po);
+  const __amdgpu_buffer_rsrc_t l = wg_rsrc(r.lo + po, r.pbytes - po);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(h, (lds_ptr)(buf + (64 * wave + 256 * m) * 16), 16,
+                                             o.p[m], 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(l, (lds_ptr)(buf + (64 * wave + 256 * (m + 4)) * 16), 16,
+                                             o.p[m], 0, 0, 0);
+  }
+  const int64_t zo = static_cast<int64_t>(st) * kWgPairs * r.row;
+  const __amdgpu_buffer_rsrc_t z = wg_rsrc(r.z + zo, r.zbytes - zo);
+#pragma unroll
+  for (int m = 0; m < 16; ++m)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        z, (lds_ptr)(buf + kWgPBytes + (64 * wave + 256 * m) * 4), 4,
+        o.q[m & 1] + static_cast<uint32_t>(4 * (m >> 1)) * static_cast<uint32_t>(r.row), 0, 0, 0);
+  const int64_t wo = static_cast<int64_t>(st) * kWgPairs * 4;
+  const __amdgpu_buffer_rsrc_t w = wg_rsrc(r.w + wo, r.wbytes - wo);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(w, (lds_ptr)(buf + kWgPBytes + kWgQBytes + wave * 256), 4,
+                                           static_cast<uint32_t>(lane) * 4u, 0, 0, 0);
+}
+
+// One k-step's fragments of one wave, read from a stage in LDS.
+struct WgFrag {
+  u32x4 ph[4], pl[4];  // P hi / lo words of row blocks 0..3
+  u32x2 q[2][4];       // Z of column blocks 0..1, pairs 4 g + e
+  u32x4 w;             // the wave's weights of pairs 4 g .. 4 g + 3
+};
+
+__device__ __forceinline__ void wg_read(const char* buf, int ks, int g8, int l32, int wave,
+                                        WgFrag& f) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int off = ((2 * ks + g8) * 128 + 32 * i + l32) * 16;
+    f.ph[i] = *reinterpret_cast<const u32x4*>(buf + off);
+    f.pl[i] = *reinterpret_cast<const u32x4*>(buf + off + kWgPBytes / 2);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      f.q[j][e] = *reinterpret_cast<const u32x2*>(
+          buf + kWgPBytes + ((8 * ks + 4 * g8 + e) * 64 + 32 * j + l32) * 8);
+  f.w = *reinterpret_cast<const u32x4*>(buf + kWgPBytes + kWgQBytes + wave * 256 +
+                                          (8 * ks + 4 * g8) * 4);
+}
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited for).
+constexpr int kVmcnt0 = 0x3F70;
+
+__device__ __forceinline__ uint32_t wg_pack_rot(float re, float im) {
+  uint32_t r;
+  asm("v_cvt_pk_bf16_f32 %0, %1, -%2" : "=v"(r) : "v"(im), "v"(re));
+  return r;
+}
+
+struct WgWords {
+  u32x4 h[2], l[2], rh[2], rl[2];
+};
+
+// Column block j of a k-step into the wave's Q words (c Z split into bf16 hi
+// / lo, plain (re, im) and rotated (im, -re)).
+__device__ __forceinline__ void wg_convert(const WgFrag& f, int j, WgWords& o) {
+#pragma clang fp contract(off)
+  uint32_t h[4], l[4], rh[4], rl[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float c = __uint_as_float(f.w[e]);
+    const float x = __uint_as_float(f.q[j][e].x) * c;
+    const float y = __uint_as_float(f.q[j][e].y) * c;
+    h[e] = pack_bf16x2(x, y);
+    const float x1 = x - bf16_lo_to_f32(h[e]);
+    const float y1 = y - bf16_hi_to_f32(h[e]);
+    l[e] = pack_bf16x2(x1, y1);
+    rh[e] = wg_pack_rot(x, y);
+    rl[e] = wg_pack_rot(x1, y1);
+  }
+  o.h[j] = u32x4{h[0], h[1], h[2], h[3]};
+  o.l[j] = u32x4{l[0], l[1], l[2], l[3]};
+  o.rh[j] = u32x4{rh[0], rh[1], rh[2], rh[3]};
+  o.rl[j] = u32x4{rl[0], rl[1], rl[2], rl[3]};
+}
+
+__device__ __forceinline__ bf16x8 wfrag(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+template <bool LOLO>
+__device__ __forceinline__ void wg_mfma(const WgFrag& p, const WgWords& q, int j, f32x16 (&cr)[4][2],
+                                        f32x16 (&ci)[4][2]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.ph[i]), wfrag(q.h[j]), cr[i][j], 0, 0, 0);
+    ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.ph[i]), wfrag(q.rh[j]), ci[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.ph[i]), wfrag(q.l[j]), cr[i][j], 0, 0, 0);
+    ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.ph[i]), wfrag(q.rl[j]), ci[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.pl[i]), wfrag(q.h[j]), cr[i][j], 0, 0, 0);
+    ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.pl[i]), wfrag(q.rh[j]), ci[i][j], 0, 0, 0);
+  }
+  if (LOLO) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.pl[i]), wfrag(q.l[j]), cr[i][j], 0, 0, 0);
+      ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.pl[i]), wfrag(q.rl[j]), ci[i][j], 0, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void wg_zero(f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = f32x16{0};
+      ci[i][j] = f32x16{0};
+    }
+}
+
+// The four k-steps of the stage in `buf` for an active wave.
+template <bool LOLO>
+__device__ __forceinline__ void wg_compute(const char* buf, int g8, int l32, int wave,
+                                           f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
+  WgFrag F[2];
+  WgWords W;
+  wg_read(buf, 0, g8, l32, wave, F[0]);
+  wg_convert(F[0], 0, W);
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    if (ks < 3) wg_read(buf, ks + 1, g8, l32, wave, F[(ks + 1) & 1]);
+    wg_convert(F[ks & 1], 1, W);
+    wg_mfma<LOLO>(F[ks & 1], W, 0, cr, ci);
+    if (ks < 3) wg_convert(F[(ks + 1) & 1], 0, W);
+    wg_mfma<LOLO>(F[ks & 1], W, 1, cr, ci);
+    // keep each k-step's reads after the previous k-step's (the register
+    // sets above are all the scheduler may use)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <bool LOLO>
+__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
+  constexpr int TP = 128, TQ = 64;
+  __shared__ __attribute__((aligned(16))) char lds[2][kWgBuf];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g8 = lane >> 5;
+  const int l32 = lane & 31;
+
+  // work list, units and problem descriptors through the scalar cache (they
+  // are uniform: every branch on them stays a scalar branch)
+  const int beg = ld_const(a.wg_offsets, static_cast<int>(blockIdx.x));
+  const int end = ld_const(a.wg_offsets, static_cast<int>(blockIdx.x) + 1);
+  for (int ui = beg; ui < end; ++ui) {
+    const Unit u = ld_unit(a.units, ld_const(a.wg_units, ui));
+    const ProbDesc pd = ld_prob(a.probs, u.prob);
+    const int npb = pd.npb;
+    const bool active = wave < u.nw;
+    const int r0 = u.tp * TP, c0 = u.tq * TQ;
+    const int32_t chunk = npb * 16, row = npb * 8;
+    WgLane o;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int col = r0 + (tid & 127);
+      o.p[m] = static_cast<uint32_t>((tid >> 7) + 2 * m) * static_cast<uint32_t>(chunk) +
+               static_cast<uint32_t>(col < npb ? col : 0) * 16u;
+    }
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      // dword t + 256 m, m = 2 m2 + h2: pair 2 m2 + (t + 256 h2) / 128, column
+      // ((t + 256 h2) % 128) / 2, part t % 2
+      const int d = tid + 256 * h2;
+      const int col = c0 + ((d & 127) >> 1);
+      o.q[h2] = static_cast<uint32_t>(d >> 7) * static_cast<uint32_t>(row) +
+                static_cast<uint32_t>(col < npb ? col : 0) * 8u + static_cast<uint32_t>(d & 1) * 4u;
+    }
+    // FP32 runs of at most the problem's flush length (a multiple of 16
+    // pairs), made of granules of R pairs: whole 32-pair stages when the
+    // length allows, else 16 pairs (the stage's second half then reads zeros)
+    const int R = pd.flush >= kWgPairs ? kWgPairs : 16;
+    const int fr = max(1, pd.flush / R);
+    double2* part = a.partials + static_cast<size_t>(u.slot + wave * u.wstride) * TP * TQ;
+    // this wave's frequency (a wave past the group's frequencies reads the
+    // last one's weights and computes nothing)
+    const int wv = min(wave, u.nw - 1);
+    const float* wbase = static_cast<const float*>(pd.wts) + static_cast<size_t>(u.iw + wv) * pd.ktot;
+    const int64_t wend = (static_cast<int64_t>(pd.nomega) - u.iw - wv) * pd.ktot;  // floats from wbase
+
+    f32x16 cr[4][2], ci[4][2];
+    wg_zero(cr, ci);
+    bool first = true;
+    int acc = 0;   // granules in the FP32 accumulators
+    for (int b = u.b0; b <= u.b1; ++b) {
+      const BlockDesc* bp = a.blocks + b;
+      const int kb = block_pairs(a.blocks, b);
+      const int p0 = (b == u.b0) ? u.p0 : 0;
+      const int p1 = (b == u.b1) ? u.p1 : kb;
+      if (p0 >= p1) continue;
+      const gcptr zs = (gcptr)ld_const(&bp->zs, 0);
+      const int64_t plane = ld_const(&bp->zs_plane, 0);
+      const gcptr z = (gcptr)ld_const(&bp->z, 0);
+      const int64_t pbase = ld_const(&bp->pair_base, 0);
+      const int64_t groups = presplit_groups(kb);
+      const int ng = (p1 - p0 + R - 1) / R;   // granules of the segment (p0: a multiple of 16)
+      for (int g0 = 0; g0 < ng;) {
+        const int len = min(fr - acc, ng - g0);
+        const int q0 = p0 + R * g0;
+        const int nv = min(p1, q0 + R * len) - q0;
+        WgRun r;
+        r.chunk = chunk;
+        r.row = row;
+        r.hi = zs + static_cast<int64_t>(q0 >> 2) * chunk;
+        r.lo = r.hi + plane;
+        r.pbytes = (groups - (q0 >> 2)) * static_cast<int64_t>(chunk);
+        r.z = z + static_cast<int64_t>(q0) * row;
+        r.zbytes = static_cast<int64_t>(nv) * row;
+        r.w = (gcptr)(wbase + pbase + q0);
+        r.wbytes = (wend - pbase - q0) * 4;
+        const int nst = (nv + kWgPairs - 1) / kWgPairs;
+        wg_dma(r, 0, o, wave, lane, lds[0]);
+        __builtin_amdgcn_s_waitcnt(kVmcnt0);
+        __syncthreads();
+        for (int st = 0; st < nst; ++st) {
+          if (st + 1 < nst) wg_dma(r, st + 1, o, wave, lane, lds[(st + 1) & 1]);
+          if (active) wg_compute<LOLO>(lds[st & 1], g8, l32, wave, cr, ci);
+          __builtin_amdgcn_s_waitcnt(kVmcnt0);   // this wave's loads of stage st + 1
+          __syncthreads();
+        }
+        g0 += len;
+        acc += len;
+        if (acc >= fr) {
+          if (active) tall_flush<4, TQ>(part, cr, ci, 0, 0, lane, first);
+          first = false;
+          acc = 0;
+          wg_zero(cr, ci);
+        }
+      }
+    }
+    if (active && (first || acc > 0)) tall_flush<4, TQ>(part, cr, ci, 0, 0, lane, first);
+  }
+}
+
+}  // namespace
+
+hipError_t herk_bf16x3_wgroup_launch(bool lolo, const HerkArgs& a, int nwg, hipStream_t s) {
+  if (lolo)
+    hipLaunchKernelGGL(herk_bf16x3_wgroup_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL(herk_bf16x3_wgroup_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+int herk_bf16x3_wgroup_max_wg_per_cu() {
+  int n = 0;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false>, kNT, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
+}  // namespace chi0

@@ -149,3 +149,34 @@ def test_every_tile_configuration(ctx, path):
         outs.append(prob.chi0.clone())
     ctx.set_tile(path, -1)
     _say("  bitwise equal to tile 0: " + str([bool(torch.equal(outs[0], o)) for o in outs]))
+
+
+@pytest.mark.parametrize("npb,omega", [(131, (0.0, 0.1, 0.5, 2.0, 8.0)),     # odd npb, 5 frequencies
+                                       (256, (0.3, 3.0)),                     # group of two
+                                       (200, tuple(np.geomspace(0.01, 100.0, 9)))])
+def test_frequency_group_tile(ctx, npb, omega):
+    """The frequency-group kernel (four frequencies of a tile per workgroup,
+    operands staged once in LDS) on frequency counts that leave partial
+    groups, odd npb and several tiles: against the oracle and the split
+    model, and equal to the per-wave kernel's result up to FP32 rounding."""
+    wl = workload(3, nq=1, npb=npb, nk=16, omega=omega)
+    ref = oracle_chi0(wl)
+    mod = _model(wl, "bf16x3")
+    prob, _, _ = device_problem(wl)
+    grp = 13                                  # the frequency-group configuration
+    info = ctx.tile_info("bf16x3", grp)
+    assert (info["tile_p"], info["tile_q"], ctx.tile_lists("bf16x3", grp)) == (128, 64, 1)
+    got = {}
+    for tile in (grp, 11):
+        ctx.set_tile("bf16x3", tile)
+        ctx.chi0_accumulate([prob], precision="bf16x3")
+        ctx.sync()
+        got[tile] = prob.chi0.cpu().numpy()
+        assert_hermitian_exact(prob.chi0)
+    ctx.set_tile("bf16x3", -1)
+    e, em = rel_fro(got[grp], ref), rel_fro(got[grp], mod)
+    _say(f"frequency groups npb {npb}, {len(omega)} omega: vs oracle {e.max():.3e}, "
+         f"vs split model {em.max():.3e}, vs tile 11 {rel_fro(got[grp], got[11]).max():.3e}")
+    assert np.all(e <= TOL), e
+    assert np.all(em <= 3e-7), em
+    assert np.all(rel_fro(got[grp], got[11]) <= 3e-7)

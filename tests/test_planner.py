@@ -72,7 +72,8 @@ def _check(shapes, prec, tile, nwg):
     expected_jobs = sum(nomega * lower_tile_count(npb) for npb, nomega, _ in shapes)
     assert njobs == expected_jobs
     assert np.array_equal(np.sort(units[:, 8]), np.arange(len(units)))     # slots unique
-    assert np.all((units[:, 9] >= 0) & (units[:, 9] < nwg))                 # one owner each
+    nlists = nwg * lib.chi0_tile_lists(prec, tile)
+    assert np.all((units[:, 9] >= 0) & (units[:, 9] < nlists))              # one owner each
     jobs = {}
     for u in units:
         p, iw, tp, tq, b0, p0, b1, p1, slot, w = (int(x) for x in u)
