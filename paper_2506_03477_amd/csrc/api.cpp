@@ -705,25 +705,27 @@ struct GatherHook {
 };
 
 // Configuration for a call with no tile fixed or tuned.  Modeled time of a
-// candidate: rows x padded lower-triangle tile area x frequencies x a
+// candidate: rows x padded lower-triangle tile area x frequencies (for a
+// frequency-group kernel, the frequencies rounded up to whole groups) x a
 // per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
 // it.  Costs relative to the built-in default, fitted to MI355X timings at
-// npb 287, 384 and 2048: BF16x3 tall 256 x 128 (7) 1.0, 128^2 with two
-// workgroups per CU (4) 1.12, 64^2 (2) 1.70, the pre-split pass 144 per row
-// and column; FP64 128^2 with 8 waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42;
-// FP32 64^2 (1) 1.0, 128^2 (0) 0.914.  Another tile replaces the default
-// only when modeled at least 5% faster.
+// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (14) 1.0,
+// tall 256 x 128 (7) 1.20, 128^2 with two workgroups per CU (4) 1.34, 64^2
+// (2) 2.04, the pre-split pass 173 per row and column; FP64 128^2 with 8
+// waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42; FP32 64^2 (1) 1.0, 128^2 (0)
+// 0.914.  Another tile replaces the default only when modeled at least 5%
+// faster.
 int tile_for(int kind, const chi0_problem* probs, int nprob) {
   struct Cand {
     int idx;
     double cost;
   };
-  static const Cand bf16[] = {{7, 1.0}, {4, 1.12}, {2, 1.70}};
+  static const Cand bf16[] = {{14, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
   static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
   static const Cand fp32[] = {{1, 1.0}, {0, 0.914}};
   const int ndef = herk_default_tile(kind);
   const Cand* cands = kind == HERK_BF16X3 ? bf16 : kind == HERK_FP64 ? fp64 : fp32;
-  const int ncand = kind == HERK_FP32 ? 2 : 3;
+  const int ncand = kind == HERK_BF16X3 ? 4 : kind == HERK_FP64 ? 3 : 2;
   double def_time = -1.0, best_time = -1.0;
   int best = ndef;
   for (int ci = 0; ci < ncand; ++ci) {
@@ -741,8 +743,10 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
       double area = 0.0;
       for (int tp = 0; tp < ntp; ++tp)
         area += static_cast<double>(std::min(ntq, (tp * TP + TP - 1) / TQ + 1)) * TP * TQ;
-      t += rows * area * std::max(1, probs[p].nomega) * c.cost;
-      if (tc.presplit) t += rows * npb * 144.0;
+      const int G = std::max(1, static_cast<int>(tc.omega_group));
+      const int nw = (std::max(1, probs[p].nomega) + G - 1) / G * G;
+      t += rows * area * nw * c.cost;
+      if (tc.presplit) t += rows * npb * 173.0;
     }
     if (c.idx == ndef) def_time = t;
     if (best_time < 0.0 || t < best_time) {
@@ -1003,9 +1007,9 @@ int run_accumulate(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, chi0_p
   int tile_idx = tile_override >= 0 ? tile_override
                  : h->tile_sel[kind] >= 0 ? h->tile_sel[kind]
                  : h->tile_tuned[kind] >= 0 ? h->tile_tuned[kind]
-                 : !hk ? tile_for(kind, probs, nprob) : herk_default_tile(kind);
+                 : !hk ? tile_for(kind, probs, nprob) : herk_gather_tile(kind);
   if (tile_idx >= ntile) tile_idx = 0;
-  if (hk && !herk_tile_gathers(kind, tile_idx)) tile_idx = herk_default_tile(kind);
+  if (hk && !herk_tile_gathers(kind, tile_idx)) tile_idx = herk_gather_tile(kind);
   if (hk && !herk_tile_gathers(kind, tile_idx))
     return fail(CHI0_EUNSUPPORTED, "precision %d has no gathering kernel", prec);
   h->tile_last[kind] = tile_idx;

@@ -252,6 +252,7 @@ hipError_t pair_weights_launch(const BlockDesc* blocks, const ProbDesc* probs, i
                                hipStream_t s);
 int herk_tile_count(int kind);
 int herk_default_tile(int kind);
+int herk_gather_tile(int kind);
 TileConfig herk_tile_config(int kind, int idx);
 int herk_max_wg_per_cu(int kind, int idx);
 hipError_t herk_launch(int kind, int idx, const HerkArgs& a, int nwg,

@@ -911,6 +911,7 @@ static const TileConfig kBf16Tiles[] = {
     {128, kKC, 4096, kNT, 64, 1, 4},  // 12: as 11, with issue-order hints
     {128, kKC, 4096, kNT, 64, 1, 1, 4},  // 13: 128 x 64 tiles, four frequencies per
                                          //     workgroup sharing LDS-staged operands
+    {128, kKC, 4096, kNT, 64, 1, 1, 4},  // 14: as 13, with issue-order hints
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -977,7 +978,8 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
     case 12:
       return herk_bf16x3_direct_launch(lolo, idx == 10 || idx == 12, idx >= 11, a, nwg, s);
     case 13:
-      return herk_bf16x3_wgroup_launch(lolo, a, nwg, s);
+    case 14:
+      return herk_bf16x3_wgroup_launch(lolo, idx == 14, a, nwg, s);
     default:
       if (lolo)
         hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<true>, dim3(nwg), dim3(512), 0, s, a);
@@ -1015,6 +1017,7 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
     case 12:
       return herk_bf16x3_direct_max_wg_per_cu();
     case 13:
+    case 14:
       return herk_bf16x3_wgroup_max_wg_per_cu();
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false>, 512, 0);

@@ -44,9 +44,14 @@ constexpr int kWgQBytes = kWgPairs * 64 * 8;          // raw Z, 64 columns
 constexpr int kWgWBytes = 4 * 64 * 4;                 // weights, 64 pairs per frequency
 constexpr int kWgBuf = kWgPBytes + kWgQBytes + kWgWBytes;
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t wg_rsrc(gcptr base, int64_t bytes) {
-  const int32_t n = bytes <= 0 ? 0 : bytes >= INT32_MAX ? INT32_MAX : static_cast<int32_t>(bytes);
-  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, n, 0x00020000);
+// Raw buffer resource over [base, base + bytes): loads past the end read 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wg_rsrc(gcptr base, int32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, bytes > 0 ? bytes : 0, 0x00020000);
+}
+
+// Byte counts of a run capped at 2^31 - 1 (far beyond what a run reads).
+__device__ __forceinline__ int32_t wg_cap(int64_t bytes) {
+  return bytes >= INT32_MAX ? INT32_MAX : static_cast<int32_t>(bytes);
 }
 
 typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -54,11 +59,11 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 // Bases of one run (pairs [q0, q0 + nv) of a block).
 struct WgRun {
   gcptr hi, lo;       // pre-split planes at the run's first 4-pair group
-  int64_t pbytes;     // plane bytes from there to the block's padded end
   gcptr z;            // Z row of the run's first pair
-  int64_t zbytes;     // Z bytes of the run's pairs
   gcptr w;            // this wave's frequency's weight of the run's first pair
-  int64_t wbytes;     // weight bytes from there to the end of the problem's table
+  int32_t pbytes;     // plane bytes from there to the block's padded end (capped)
+  int32_t zbytes;     // Z bytes of the run's pairs
+  int32_t wbytes;     // weight bytes from there to the end of the problem's table (capped)
   int32_t chunk;      // bytes per 4-pair group of a plane (npb * 16)
   int32_t row;        // bytes per Z row (npb * 8)
 };
@@ -72,32 +77,46 @@ struct WgLane {
   uint32_t q[2];      // m even / odd (4 (m / 2) rows are added per load)
 };
 
-// Loads stage st of the run into LDS buffer buf: every wave writes 1 KB
-// (16-byte loads) or 256 bytes (dword loads) per instruction, lane i at
-// offset 16 i or 4 i of the wave's destination.
+// Part PART (0..3) of the loads of stage st of the run into LDS buffer buf
+// (0: P hi words, 1: P lo words, 2: Z dwords 0..7 and the weights, 3: Z
+// dwords 8..15): every wave writes 1 KB (16-byte loads) or 256 bytes (dword
+// loads) per instruction, lane i at offset 16 i or 4 i of the wave's
+// destination.
+template <int PART>
 __device__ __forceinline__ void wg_dma(const WgRun& r, int st, const WgLane& o, int wave, int lane,
                                        char* buf) {
-  const int64_t po = static_cast<int64_t>(st) * (kWgPairs / 4) * r.chunk;
-  const __amdgpu_buffer_rsrc_t h = wg_rsrc(r.hi + po, r.pbytes - po);
-  const __amdgpu_buffer_rsrc_t l = wg_rsrc(r.lo + po, r.pbytes - po);
+  if constexpr (PART < 2) {
+    const int32_t po = st * (kWgPairs / 4) * r.chunk;
+    const __amdgpu_buffer_rsrc_t h = wg_rsrc((PART == 0 ? r.hi : r.lo) + po, r.pbytes - po);
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(h, (lds_ptr)(buf + (64 * wave + 256 * m) * 16), 16,
-                                             o.p[m], 0, 0, 0);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(l, (lds_ptr)(buf + (64 * wave + 256 * (m + 4)) * 16), 16,
-                                             o.p[m], 0, 0, 0);
+    for (int m = 0; m < 4; ++m)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          h, (lds_ptr)(buf + (64 * wave + 256 * (m + 4 * PART)) * 16), 16, o.p[m], 0, 0, 0);
+  } else {
+    const int32_t zo = st * kWgPairs * r.row;
+    const __amdgpu_buffer_rsrc_t z = wg_rsrc(r.z + zo, r.zbytes - zo);
+#pragma unroll
+    for (int mm = 0; mm < 8; ++mm) {
+      const int m = mm + 8 * (PART - 2);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          z, (lds_ptr)(buf + kWgPBytes + (64 * wave + 256 * m) * 4), 4,
+          o.q[m & 1] + static_cast<uint32_t>(4 * (m >> 1)) * static_cast<uint32_t>(r.row), 0, 0, 0);
+    }
+    if constexpr (PART == 2) {
+      const int32_t wo = st * kWgPairs * 4;
+      const __amdgpu_buffer_rsrc_t w = wg_rsrc(r.w + wo, r.wbytes - wo);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(w, (lds_ptr)(buf + kWgPBytes + kWgQBytes + wave * 256),
+                                               4, static_cast<uint32_t>(lane) * 4u, 0, 0, 0);
+    }
   }
-  const int64_t zo = static_cast<int64_t>(st) * kWgPairs * r.row;
-  const __amdgpu_buffer_rsrc_t z = wg_rsrc(r.z + zo, r.zbytes - zo);
-#pragma unroll
-  for (int m = 0; m < 16; ++m)
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(
-        z, (lds_ptr)(buf + kWgPBytes + (64 * wave + 256 * m) * 4), 4,
-        o.q[m & 1] + static_cast<uint32_t>(4 * (m >> 1)) * static_cast<uint32_t>(r.row), 0, 0, 0);
-  const int64_t wo = static_cast<int64_t>(st) * kWgPairs * 4;
-  const __amdgpu_buffer_rsrc_t w = wg_rsrc(r.w + wo, r.wbytes - wo);
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(w, (lds_ptr)(buf + kWgPBytes + kWgQBytes + wave * 256), 4,
-                                           static_cast<uint32_t>(lane) * 4u, 0, 0, 0);
+}
+
+__device__ __forceinline__ void wg_dma_all(const WgRun& r, int st, const WgLane& o, int wave,
+                                           int lane, char* buf) {
+  wg_dma<0>(r, st, o, wave, lane, buf);
+  wg_dma<1>(r, st, o, wave, lane, buf);
+  wg_dma<2>(r, st, o, wave, lane, buf);
+  wg_dma<3>(r, st, o, wave, lane, buf);
 }
 
 // One k-step's fragments of one wave, read from a stage in LDS.
@@ -200,31 +219,45 @@ __device__ __forceinline__ void wg_zero(f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) 
     }
 }
 
-// The four k-steps of the stage in `buf` for an active wave.
-template <bool LOLO>
-__device__ __forceinline__ void wg_compute(const char* buf, int g8, int l32, int wave,
-                                           f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
-  WgFrag F[2];
-  WgWords W;
-  wg_read(buf, 0, g8, l32, wave, F[0]);
-  wg_convert(F[0], 0, W);
+// Issue order of a k-step with NDMA stage loads: the column-block-0 MFMAs
+// with the column-block-1 conversion (two VALU per MFMA), the next
+// k-step's fragment reads and the loads between them, then the
+// column-block-1 MFMAs with the next k-step's column-block-0 conversion.
+template <int NDMA>
+__device__ __forceinline__ void wg_order() {
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
-    if (ks < 3) wg_read(buf, ks + 1, g8, l32, wave, F[(ks + 1) & 1]);
-    wg_convert(F[ks & 1], 1, W);
-    wg_mfma<LOLO>(F[ks & 1], W, 0, cr, ci);
-    if (ks < 3) wg_convert(F[(ks + 1) & 1], 0, W);
-    wg_mfma<LOLO>(F[ks & 1], W, 1, cr, ci);
-    // keep each k-step's reads after the previous k-step's (the register
-    // sets above are all the scheduler may use)
-    __builtin_amdgcn_sched_barrier(0);
+  for (int m = 0; m < 24; ++m) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // VALU
+    if (m < 17) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);    // LDS read
+    if (m < NDMA) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // buffer load
+  }
+#pragma unroll
+  for (int m = 0; m < 24; ++m) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
   }
 }
 
+// K-step ks of the stage in `cur` (fragments in fc, its column-block-0 words
+// already in W), reading the next k-step's fragments (k-step ks + 1 of `cur`,
+// or k-step 0 of the next stage from `nxt`) into fn and converting their
+// column block 0.
 template <bool LOLO>
+__device__ __forceinline__ void wg_kstep(const char* src, int ksn, int g8, int l32, int wave,
+                                         const WgFrag& fc, WgFrag& fn, WgWords& W,
+                                         f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
+  wg_read(src, ksn, g8, l32, wave, fn);
+  wg_convert(fc, 1, W);
+  wg_mfma<LOLO>(fc, W, 0, cr, ci);
+  wg_convert(fn, 0, W);
+  wg_mfma<LOLO>(fc, W, 1, cr, ci);
+}
+
+template <bool LOLO, bool HINT>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
   constexpr int TP = 128, TQ = 64;
-  __shared__ __attribute__((aligned(16))) char lds[2][kWgBuf];
+  __shared__ __attribute__((aligned(16))) char lds[3][kWgBuf];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -264,8 +297,8 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
     const int R = pd.flush >= kWgPairs ? kWgPairs : 16;
     const int fr = max(1, pd.flush / R);
     double2* part = a.partials + static_cast<size_t>(u.slot + wave * u.wstride) * TP * TQ;
-    // this wave's frequency (a wave past the group's frequencies reads the
-    // last one's weights and computes nothing)
+    // this wave's frequency (a wave past the group's frequencies computes
+    // with the last one's weights and writes nothing)
     const int wv = min(wave, u.nw - 1);
     const float* wbase = static_cast<const float*>(pd.wts) + static_cast<size_t>(u.iw + wv) * pd.ktot;
     const int64_t wend = (static_cast<int64_t>(pd.nomega) - u.iw - wv) * pd.ktot;  // floats from wbase
@@ -295,21 +328,50 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
         r.row = row;
         r.hi = zs + static_cast<int64_t>(q0 >> 2) * chunk;
         r.lo = r.hi + plane;
-        r.pbytes = (groups - (q0 >> 2)) * static_cast<int64_t>(chunk);
+        r.pbytes = wg_cap((groups - (q0 >> 2)) * static_cast<int64_t>(chunk));
         r.z = z + static_cast<int64_t>(q0) * row;
-        r.zbytes = static_cast<int64_t>(nv) * row;
+        r.zbytes = wg_cap(static_cast<int64_t>(nv) * row);
         r.w = (gcptr)(wbase + pbase + q0);
-        r.wbytes = (wend - pbase - q0) * 4;
+        r.wbytes = wg_cap((wend - pbase - q0) * 4);
         const int nst = (nv + kWgPairs - 1) / kWgPairs;
-        wg_dma(r, 0, o, wave, lane, lds[0]);
+        // Three LDS buffers, stage s in buffer s % 3.  The barrier of stage
+        // s (after its k-step 2) follows the loads of stage s + 1, issued
+        // since the previous barrier, and every read of stage s - 1; the
+        // loads of stage s + 2 start after it, and so do the reads of stage
+        // s + 1 (k-step 3 prefetches its first fragments).
+        wg_dma_all(r, 0, o, wave, lane, lds[0]);
         __builtin_amdgcn_s_waitcnt(kVmcnt0);
         __syncthreads();
+        WgFrag F0, F1;
+        WgWords W;
+        wg_read(lds[0], 0, g8, l32, wave, F0);
+        wg_convert(F0, 0, W);
+        wg_dma<0>(r, 1, o, wave, lane, lds[1]);
+        int bc = 0;   // buffer of stage st
         for (int st = 0; st < nst; ++st) {
-          if (st + 1 < nst) wg_dma(r, st + 1, o, wave, lane, lds[(st + 1) & 1]);
-          if (active) wg_compute<LOLO>(lds[st & 1], g8, l32, wave, cr, ci);
+          const int bn = bc == 2 ? 0 : bc + 1, bnn = bn == 2 ? 0 : bn + 1;
+          const char* cur = lds[bc];
+          wg_kstep<LOLO>(cur, 1, g8, l32, wave, F0, F1, W, cr, ci);
+          wg_dma<1>(r, st + 1, o, wave, lane, lds[bn]);
+          if (HINT) wg_order<4>();
+          __builtin_amdgcn_sched_barrier(0);
+          wg_kstep<LOLO>(cur, 2, g8, l32, wave, F1, F0, W, cr, ci);
+          wg_dma<2>(r, st + 1, o, wave, lane, lds[bn]);
+          if (HINT) wg_order<9>();
+          __builtin_amdgcn_sched_barrier(0);
+          wg_kstep<LOLO>(cur, 3, g8, l32, wave, F0, F1, W, cr, ci);
+          wg_dma<3>(r, st + 1, o, wave, lane, lds[bn]);
+          if (HINT) wg_order<8>();
           __builtin_amdgcn_s_waitcnt(kVmcnt0);   // this wave's loads of stage st + 1
           __syncthreads();
+          wg_kstep<LOLO>(lds[bn], 0, g8, l32, wave, F1, F0, W, cr, ci);
+          wg_dma<0>(r, st + 2, o, wave, lane, lds[bnn]);
+          if (HINT) wg_order<4>();
+          __builtin_amdgcn_sched_barrier(0);
+          bc = bn;
         }
+        __builtin_amdgcn_s_waitcnt(kVmcnt0);     // loads past the run's stages
+        __syncthreads();
         g0 += len;
         acc += len;
         if (acc >= fr) {
@@ -326,18 +388,22 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
 
 }  // namespace
 
-hipError_t herk_bf16x3_wgroup_launch(bool lolo, const HerkArgs& a, int nwg, hipStream_t s) {
-  if (lolo)
-    hipLaunchKernelGGL(herk_bf16x3_wgroup_kernel<true>, dim3(nwg), dim3(kNT), 0, s, a);
-  else
-    hipLaunchKernelGGL(herk_bf16x3_wgroup_kernel<false>, dim3(nwg), dim3(kNT), 0, s, a);
+hipError_t herk_bf16x3_wgroup_launch(bool lolo, bool hint, const HerkArgs& a, int nwg,
+                                     hipStream_t s) {
+  if (lolo) {
+    if (hint) hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<true, true>), dim3(nwg), dim3(kNT), 0, s, a);
+    else hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<true, false>), dim3(nwg), dim3(kNT), 0, s, a);
+  } else {
+    if (hint) hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<false, true>), dim3(nwg), dim3(kNT), 0, s, a);
+    else hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<false, false>), dim3(nwg), dim3(kNT), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 int herk_bf16x3_wgroup_max_wg_per_cu() {
   int n = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false>, kNT, 0);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, false>, kNT, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

@@ -58,17 +58,26 @@ hipError_t reduce_launch(const ReduceArgs& a, int njobs, hipStream_t s) {
 }
 
 // Built-in default configuration per path (fastest measured on the
-// npb = 2048 and spin-polarised workloads: the 4-wave tall BF16x3 kernel
-// without scheduling hints, within run-to-run noise of the 8-wave one; the
-// 8-wave FP64 kernel; 64 x 64 FP32 tiles); the autotuner or chi0_set_tile
-// overrides it.
+// npb = 2048 and spin-polarised workloads: the BF16x3 frequency-group kernel
+// on 128 x 64 tiles with issue-order hints; the 8-wave FP64 kernel; 64 x 64
+// FP32 tiles); the autotuner or chi0_set_tile overrides it.
 int herk_default_tile(int kind) {
   switch (kind) {
     case HERK_FP64: return 3;
     case HERK_FP32: return 1;
-    case HERK_BF16X3: return 7;
+    case HERK_BF16X3: return 14;
   }
   return 0;
+}
+
+// Default configuration of calls that read gathered rows (the histogram
+// route): the fastest of the configurations that can.
+int herk_gather_tile(int kind) {
+  switch (kind) {
+    case HERK_FP64: return 3;
+    case HERK_BF16X3: return 7;
+  }
+  return herk_default_tile(kind);
 }
 
 int herk_tile_count(int kind) {
