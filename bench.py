@@ -27,8 +27,9 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 # sources of each rank-K kernel (the traffic counters are valid while these are unchanged)
-_LOWP = ("paper_2506_03477_amd/csrc/herk_lowp.hip", "paper_2506_03477_amd/csrc/bf16_tall.h",
-         "paper_2506_03477_amd/csrc/herk_common.h")
+_LOWP = ("paper_2506_03477_amd/csrc/herk_lowp.hip", "paper_2506_03477_amd/csrc/herk_wgroup.hip",
+         "paper_2506_03477_amd/csrc/herk_direct.hip", "paper_2506_03477_amd/csrc/bf16_tall.h",
+         "paper_2506_03477_amd/csrc/herk_common.h", "paper_2506_03477_amd/csrc/common.h")
 KERNEL_SOURCE = {"fp64": ("paper_2506_03477_amd/csrc/herk_fp64.hip", "paper_2506_03477_amd/csrc/herk_common.h"),
                  "fp32": _LOWP, "bf16x3": _LOWP}
 STEP_INVERSE = {"hpd_fallback_gj": "HPD sweeps, pivoted Gauss-Jordan if a pivot is not positive",
@@ -575,6 +576,9 @@ def main():
                     help="the step's FP64 inverse of eps")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile configuration index (default: the library's default)")
+    ap.add_argument("--flush", type=int, default=0,
+                    help="FP32 run length in pairs between flushes to the FP64 partials (0: the "
+                         "library's per-problem length, min(4096, 4 sqrt K))")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (byte-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -635,6 +639,8 @@ def main():
         raise SystemExit(f"precision {prec} has no kernel in this library")
     if args.tile >= 0:
         ctx.set_tile(prec, args.tile)
+    if args.flush:
+        ctx.set_flush(args.flush)
     ztype = "c128" if prec == "fp64" else "c64"
 
     if args.copy_calibration:
@@ -735,6 +741,8 @@ def main():
              "ms_per_q_chi0_plus_inverse": round(ms_per_step / wl.nq, 3),
              "nq_per_step": wl.nq, "tile": [tinfo["tile_p"], tinfo["tile_q"]],
              "tile_index": ctx.last_tile(prec), "npairs": npairs}
+    if args.flush:
+        extra["flush_pairs"] = args.flush
     if wl.paths and "fp64" in wl.paths and prec != "fp64" and not args.no_fp64_compare:
         # The FP64 path on the same values (the complex64 Z upcast exactly to
         # complex128): its time for the speed ratio (median of 3 after one
@@ -749,6 +757,7 @@ def main():
                                     for b in probs[q].blocks], probs[q].omega,
                                    torch.empty_like(chis[q])))
         ctx.profile_enable(False)
+        ctx.set_flush(0)
         ctx.chi0_accumulate(probs64, precision="fp64", delta_min=wl.delta_min)
         ctx.sync()
         fp64_runs = []

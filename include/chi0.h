@@ -68,14 +68,21 @@ typedef enum {
   CHI0_PREC_FP64 = 0,      /* complex128 Z, FP64 matrix cores                 */
   CHI0_PREC_FP32 = 1,      /* complex64 Z, FP32 matrix cores, FP32 runs of at
                               most the flush length, then FP64 accumulation   */
-  CHI0_PREC_BF16X3 = 2     /* complex64 Z; each operand split into bf16
+  CHI0_PREC_BF16X3 = 2,    /* complex64 Z; each operand split into bf16
                               hi + lo, products hi*hi + hi*lo + lo*hi on BF16
                               matrix cores with FP32 accumulation, FP64 flush */
+  /* not precisions: these two make every int a value of the type, so an
+     unknown value passed from C is rejected (CHI0_EINVAL) rather than
+     undefined in the C++ library */
+  CHI0_PREC_RANGE_MIN_ = -2147483647 - 1,
+  CHI0_PREC_RANGE_MAX_ = 2147483647
 } chi0_precision;
 
 typedef enum {
   CHI0_Z_C128 = 0,         /* Z is complex128 (required by CHI0_PREC_FP64)    */
-  CHI0_Z_C64 = 1           /* Z is complex64 (required by FP32 and BF16X3)    */
+  CHI0_Z_C64 = 1,          /* Z is complex64 (required by FP32 and BF16X3)    */
+  CHI0_Z_RANGE_MIN_ = -2147483647 - 1,   /* not types: as for chi0_precision */
+  CHI0_Z_RANGE_MAX_ = 2147483647
 } chi0_ztype;
 
 /* chi0_accumulate flags (bitwise or) */

@@ -15,7 +15,9 @@ from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libchi0.so")
+# CHI0_LIB names another build of the same library (the host-sanitized build
+# of build.build_host_sanitized()); by default the in-tree libchi0.so
+LIB_PATH = os.environ.get("CHI0_LIB") or os.path.join(_HERE, "libchi0.so")
 
 CHI0_OK = 0
 CHI0_EINVAL = -1

@@ -17,11 +17,12 @@
 // barrier of every stage keeps the four waves, which do the same work, on
 // the same pairs.
 //
-// Pipeline of a stage (LDS double-buffered, one barrier per stage): the next
-// stage is loaded straight from global memory into the other LDS buffer
+// Pipeline of a stage (three LDS buffers, one barrier per stage): the next
+// stage is loaded straight from global memory into another LDS buffer
 // (buffer loads with an LDS destination: no staging registers) while the
-// current one is computed; the barrier that ends the stage waits for those
-// loads.  Within a stage, the fragments of a
+// current one is computed; the barrier before the stage's last k-step waits
+// for those loads, and the third buffer lets the loads of the stage after
+// next start right after that barrier.  Within a stage, the fragments of a
 // k-step (8 pairs) are read from LDS while the previous k-step's MFMAs issue,
 // and each column block's conversion runs while the other column block's
 // MFMAs issue.  Loads past the run's pairs or the block's planes read zeros
