@@ -444,6 +444,33 @@ def bench_sigc(args):
                 "launches_per_step": launches_per_step,
                 "executed_mfma_tflops": round(exe, 3),
                 "executed_mfma_frac": round(exe / PEAK_TFLOPS[prec], 4)}
+    extra = {}
+    if prec != "fp64" and not args.no_fp64_compare:
+        # The FP64 path on the same inputs (it is checked against the oracle
+        # by the GPU tests): its time (median of 3 after one untimed call)
+        # and the relative Frobenius error of the timed output against it.
+        ctx.profile_enable(False)
+        out64 = torch.empty_like(out)
+        prob64 = SigcProblem(prob.blocks, eps_qp, wl.omega_array(), out64)
+        ctx.sigc_accumulate([prob64], precision="fp64")
+        ctx.sync()
+        runs = []
+        for r in range(3):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.sigc_accumulate([prob64], precision="fp64")
+            b.record(stream)
+            b.synchronize()
+            runs.append(a.elapsed_time(b))
+        fp64_ms = sorted(runs)[1]
+        err = float((torch.linalg.norm(out - out64) / torch.linalg.norm(out64)).item())
+        extra = {"fp64_ms_per_q": round(fp64_ms, 3), "fp64_ms_runs": [round(x, 3) for x in runs],
+                 "split_speedup_vs_fp64": round(fp64_ms / ms, 3),
+                 "max_rel_err": {"sigma_c": float(f"{err:.3e}"),
+                                 "vs": "FP64 path on the same inputs (relative Frobenius "
+                                       "error, whole matrix)"}}
+        log(f"rel err vs FP64: {err:.3e}; FP64 {fp64_ms:.1f} ms")
     cpu = None if args.no_cpu_baseline else sigc_cpu_baseline(wl)
     print(json.dumps({
         "metric": "I^c TFLOP/s per q-point (imaginary-axis correlation self-energy, Eq. sigci)",
@@ -455,7 +482,7 @@ def bench_sigc(args):
                    "nmu": wl.nunocc, "nomega": wl.nomega, "path": prec,
                    "variant": args.tile if args.tile >= 0 else 1},
         "flops_first": first, "flops_second": second,
-        "roofline": roof, "cpu_baseline": cpu}), flush=True)
+        "roofline": roof, "cpu_baseline": cpu, **extra}), flush=True)
     ctx.close()
 
 

@@ -148,8 +148,8 @@ int kind_of(chi0_precision p) {
     case CHI0_PREC_FP64: return HERK_FP64;
     case CHI0_PREC_FP32: return HERK_FP32;
     case CHI0_PREC_BF16X3: return HERK_BF16X3;
+    default: return -1;
   }
-  return -1;
 }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -709,7 +709,7 @@ struct GatherHook {
 // frequency-group kernel, the frequencies rounded up to whole groups) x a
 // per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
 // it.  Costs relative to the built-in default, fitted to MI355X timings at
-// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (14) 1.0,
+// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (15) 1.0,
 // tall 256 x 128 (7) 1.20, 128^2 with two workgroups per CU (4) 1.34, 64^2
 // (2) 2.04, the pre-split pass 173 per row and column; FP64 128^2 with 8
 // waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42; FP32 64^2 (1) 1.0, 128^2 (0)
@@ -720,7 +720,7 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
     int idx;
     double cost;
   };
-  static const Cand bf16[] = {{14, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
+  static const Cand bf16[] = {{15, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
   static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
   static const Cand fp32[] = {{1, 1.0}, {0, 0.914}};
   const int ndef = herk_default_tile(kind);

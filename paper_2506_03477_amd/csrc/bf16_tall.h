@@ -139,8 +139,12 @@ __device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr,
 
 // Add (or store, when first) a wave's (32 NBI) x 64 accumulators into the
 // FP64 partial tile (TQ columns, row-major: 256 x 128 for a workgroup's tile,
-// 128 x 64 for a wave's own); 16 old values are loaded as a group.
-template <int NBI = 4, int TQ = 128>
+// 128 x 64 for a wave's own); 16 old values are loaded as a group.  With
+// ATOM the additions are FP64 atomic adds without return, done in L2: the
+// wave issues them all and waits for none (a slot belongs to one wave, whose
+// accesses to one address stay in order, so the sums are those of the
+// load-add-store form, in the same order).
+template <int NBI = 4, int TQ = 128, bool ATOM = false>
 __device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32x16 (&cr)[NBI][2],
                                            const f32x16 (&ci)[NBI][2], int wr, int wc, int lane,
                                            bool first) {
@@ -153,6 +157,16 @@ __device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       double2* blk = part + base + i * 32 * TQ + j * 32;
+      if (ATOM && !first) {
+        typedef double __attribute__((address_space(1)))* gdp;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          double* d = reinterpret_cast<double*>(blk + (8 * (r >> 2) + (r & 3)) * TQ);
+          __builtin_amdgcn_global_atomic_fadd_f64((gdp)d, static_cast<double>(cr[i][j][r]));
+          __builtin_amdgcn_global_atomic_fadd_f64((gdp)(d + 1), static_cast<double>(ci[i][j][r]));
+        }
+        continue;
+      }
       double2 o[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) o[r] = double2{0.0, 0.0};

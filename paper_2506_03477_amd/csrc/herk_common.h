@@ -143,7 +143,7 @@ hipError_t herk_bf16x3_direct_launch(bool lolo, bool hint, bool wave_units, cons
 int herk_bf16x3_direct_max_wg_per_cu();
 // BF16x3 kernel on frequency-group units (128 x 64 tiles, up to four
 // frequencies per workgroup, operands staged once in LDS).
-hipError_t herk_bf16x3_wgroup_launch(bool lolo, bool hint, const HerkArgs& a, int nwg,
+hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, int nwg,
                                      hipStream_t s);
 int herk_bf16x3_wgroup_max_wg_per_cu();
 

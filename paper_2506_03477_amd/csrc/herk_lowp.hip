@@ -912,6 +912,7 @@ static const TileConfig kBf16Tiles[] = {
     {128, kKC, 4096, kNT, 64, 1, 1, 4},  // 13: 128 x 64 tiles, four frequencies per
                                          //     workgroup sharing LDS-staged operands
     {128, kKC, 4096, kNT, 64, 1, 1, 4},  // 14: as 13, with issue-order hints
+    {128, kKC, 4096, kNT, 64, 1, 1, 4},  // 15: as 14, flushes by FP64 atomic adds
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -979,7 +980,8 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
       return herk_bf16x3_direct_launch(lolo, idx == 10 || idx == 12, idx >= 11, a, nwg, s);
     case 13:
     case 14:
-      return herk_bf16x3_wgroup_launch(lolo, idx == 14, a, nwg, s);
+    case 15:
+      return herk_bf16x3_wgroup_launch(lolo, idx - 13, a, nwg, s);
     default:
       if (lolo)
         hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<true>, dim3(nwg), dim3(512), 0, s, a);
@@ -1018,6 +1020,7 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
       return herk_bf16x3_direct_max_wg_per_cu();
     case 13:
     case 14:
+    case 15:
       return herk_bf16x3_wgroup_max_wg_per_cu();
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false>, 512, 0);

@@ -255,7 +255,7 @@ __device__ __forceinline__ void wg_kstep(const char* src, int ksn, int g8, int l
   wg_mfma<LOLO>(fc, W, 1, cr, ci);
 }
 
-template <bool LOLO, bool HINT>
+template <bool LOLO, bool HINT, bool ATOM>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
   constexpr int TP = 128, TQ = 64;
   __shared__ __attribute__((aligned(16))) char lds[3][kWgBuf];
@@ -376,35 +376,42 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
         g0 += len;
         acc += len;
         if (acc >= fr) {
-          if (active) tall_flush<4, TQ>(part, cr, ci, 0, 0, lane, first);
+          if (active) tall_flush<4, TQ, ATOM>(part, cr, ci, 0, 0, lane, first);
           first = false;
           acc = 0;
           wg_zero(cr, ci);
         }
       }
     }
-    if (active && (first || acc > 0)) tall_flush<4, TQ>(part, cr, ci, 0, 0, lane, first);
+    if (active && (first || acc > 0)) tall_flush<4, TQ, ATOM>(part, cr, ci, 0, 0, lane, first);
   }
 }
 
 }  // namespace
 
-hipError_t herk_bf16x3_wgroup_launch(bool lolo, bool hint, const HerkArgs& a, int nwg,
+hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, int nwg,
                                      hipStream_t s) {
+  // variant 0: compiler scheduling; 1: issue-order hints; 2: hints and
+  // atomic flushes
+#define CHI0_WG_LAUNCH(L, H, A) \
+  hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<L, H, A>), dim3(nwg), dim3(kNT), 0, s, a)
   if (lolo) {
-    if (hint) hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<true, true>), dim3(nwg), dim3(kNT), 0, s, a);
-    else hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<true, false>), dim3(nwg), dim3(kNT), 0, s, a);
+    if (variant == 0) CHI0_WG_LAUNCH(true, false, false);
+    else if (variant == 1) CHI0_WG_LAUNCH(true, true, false);
+    else CHI0_WG_LAUNCH(true, true, true);
   } else {
-    if (hint) hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<false, true>), dim3(nwg), dim3(kNT), 0, s, a);
-    else hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<false, false>), dim3(nwg), dim3(kNT), 0, s, a);
+    if (variant == 0) CHI0_WG_LAUNCH(false, false, false);
+    else if (variant == 1) CHI0_WG_LAUNCH(false, true, false);
+    else CHI0_WG_LAUNCH(false, true, true);
   }
+#undef CHI0_WG_LAUNCH
   return hipGetLastError();
 }
 
 int herk_bf16x3_wgroup_max_wg_per_cu() {
   int n = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, false>, kNT, 0);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, true, false>, kNT, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
