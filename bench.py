@@ -65,12 +65,23 @@ def lower_tile_count(npb, tp, tq):
     return n
 
 
-def executed_mfma_flops(npb, npairs, nomega, tile_p, tile_q, prec):
+def executed_mfma_flops(npb, npairs, nomega, tile_p, tile_q, prec, diag_skip=False):
     """Matrix-core flops actually issued: whole tp x tq tiles holding
-    lower-triangle entries (tiles on the diagonal are computed whole), 8 real
+    lower-triangle entries (tiles on the diagonal are computed whole, or,
+    with diag_skip, only their 32 x 32 blocks holding such entries), 8 real
     flops per complex MAC, times the number of split products."""
-    return (8.0 * npairs * lower_tile_count(npb, tile_p, tile_q) * tile_p * tile_q * nomega
-            * SPLIT_FACTOR[prec])
+    if diag_skip:
+        blocks = 0
+        for r in range(-(-npb // tile_p)):
+            last_row = min((r + 1) * tile_p, npb) - 1
+            for c in range(last_row // tile_q + 1):
+                for i in range(tile_p // 32):
+                    for j in range(tile_q // 32):
+                        blocks += (r * tile_p + 32 * i) // 32 >= (c * tile_q + 32 * j) // 32
+        area = blocks * 32 * 32
+    else:
+        area = lower_tile_count(npb, tile_p, tile_q) * tile_p * tile_q
+    return 8.0 * npairs * area * nomega * SPLIT_FACTOR[prec]
 
 
 def size_sample(run, nmax, target_s):
@@ -737,7 +748,8 @@ def main():
     if kern_avg_ms:
         ach = flops / (kern_avg_ms * 1e-3) / 1e12
         exe = executed_mfma_flops(wl.npb, npairs, wl.nomega, tinfo["tile_p"], tinfo["tile_q"],
-                                  prec) / (kern_avg_ms * 1e-3) / 1e12
+                                  prec, ctx.tile_diag_skip(prec, ctx.last_tile(prec))) / \
+            (kern_avg_ms * 1e-3) / 1e12
         traffic = stored_traffic(prec, wl.name)
         roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec],
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4), "traffic": traffic,

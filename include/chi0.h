@@ -410,6 +410,12 @@ int chi0_tile_choice(chi0_precision prec, const chi0_problem* probs, int32_t npr
  * each unit as a whole (tile_p x tile_q units), 4 when each of its four
  * waves takes units of its own; CHI0_EINVAL for an unknown configuration. */
 int chi0_tile_lists(chi0_precision prec, int32_t tile);
+/* 1 when the configuration's tiles that cross the diagonal (tile_p =
+ * 2 tile_q) leave out their 32 x 32 MFMA blocks lying entirely above it
+ * (3 of 8 blocks computed right of the diagonal, 7 of 8 left of it), 0
+ * when every tile is computed whole; CHI0_EINVAL for an unknown
+ * configuration.  The chi0 produced is the same either way. */
+int chi0_tile_diag_skip(chi0_precision prec, int32_t tile);
 
 /* FP32 run length of the reduced-precision paths: the number of pairs summed
  * in FP32 before the partial sum is added into FP64.  By default it is

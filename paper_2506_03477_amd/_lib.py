@@ -122,6 +122,7 @@ def load() -> ctypes.CDLL:
         "chi0_last_tile": (c_int, [vp, c_int, POINTER(c_int32)]),
         "chi0_tile_choice": (c_int, [c_int, POINTER(chi0_problem), c_int32, POINTER(c_int32)]),
         "chi0_tile_lists": (c_int, [c_int, c_int32]),
+        "chi0_tile_diag_skip": (c_int, [c_int, c_int32]),
         "chi0_autotune": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
                                   c_int32, POINTER(c_int32), POINTER(c_double), vp]),
         "chi0_plan_inspect": (c_int, [POINTER(chi0_problem), c_int32, c_int, c_int32, c_int32,
@@ -535,6 +536,11 @@ class Context:
     def tile_lists(self, precision: str, tile: int) -> int:
         """Work lists per workgroup of a tile configuration (1 or 4)."""
         return _check(self._lib.chi0_tile_lists(PREC[precision], tile))
+
+    def tile_diag_skip(self, precision: str, tile: int) -> bool:
+        """True when the configuration leaves out the 32 x 32 blocks of
+        diagonal tiles that lie entirely above the diagonal."""
+        return bool(_check(self._lib.chi0_tile_diag_skip(PREC[precision], tile)))
 
     def set_tile(self, precision: str, tile: int) -> None:
         _check(self._lib.chi0_set_tile(self._h, PREC[precision], tile))

@@ -371,6 +371,14 @@ struct HostPlan {
 // Default upper bound on the FP64 partial tiles of one rank-K launch (bytes).
 constexpr double kMaxPartialBytes = 12.0e9;
 
+// Tiles right of the diagonal in a configuration that leaves out the blocks
+// above it (TP = 2 TQ, tile column 2 tp + 1): 3 of their 8 blocks are
+// computed, so their units are light.
+constexpr double kLightCost = 0.5;
+bool light_tile(const TileConfig& tc, int tp, int tq) {
+  return tc.diag_skip && tc.tile == 2 * tc.tile_q && tq == 2 * tp + 1;
+}
+
 // Lower-triangle tiles of a TP x TQ tiling of an npb x npb matrix: tile
 // (tp, tq) is needed iff it holds an entry on or below the diagonal.
 void lower_tiles(int npb, int TP, int TQ, std::vector<std::pair<int, int>>& out) {
@@ -439,14 +447,20 @@ void plan_host(const TileConfig& tc, int nwg_launch, const chi0_problem* probs, 
   for (auto& q : ps) kmax_all = std::max(kmax_all, static_cast<double>(q.K));
   while (count_units(per_unit) * slot_bytes > max_partial_bytes && per_unit < kmax_all) per_unit *= 1.5;
   // one problem shape: pick the range count so that the units fill whole
-  // rounds of the persistent grid (round-robin dealing is then exact)
+  // rounds of the persistent grid (round-robin dealing is then exact; with
+  // diag_skip the light units of the tiles right of the diagonal, dealt
+  // after the others, fill whole rounds too)
   if (nprob == 1 && ps[0].K > 0) {
     const double jobs = static_cast<double>(ps[0].nomega) * ps[0].ntl;
-    const double units_per_range = static_cast<double>(ngrp(ps[0].nomega)) * ps[0].ntl;
+    int nlight = 0;
+    for (const auto& t : ps[0].tiles) nlight += light_tile(tc, t.first, t.second) ? 1 : 0;
+    const double light_per_range = static_cast<double>(ngrp(ps[0].nomega)) * nlight;
+    const double units_per_range = static_cast<double>(ngrp(ps[0].nomega)) * ps[0].ntl - light_per_range;
     const int64_t s0 = std::max<int64_t>(1, std::llround(std::ceil(ps[0].K / per_unit)));
     for (int64_t sr = s0; sr <= s0 + 16 && sr <= ps[0].K; ++sr) {
       const double nu = units_per_range * sr;
       if (std::fmod(nu, static_cast<double>(nwg)) == 0.0 &&
+          std::fmod(light_per_range * sr, static_cast<double>(nwg)) == 0.0 &&
           jobs * sr * slot_bytes <= max_partial_bytes) {
         per_unit = static_cast<double>(ps[0].K) / sr * (1.0 + 1e-9);
         break;
@@ -513,9 +527,11 @@ void plan_host(const TileConfig& tc, int nwg_launch, const chi0_problem* probs, 
           hp.units.push_back(u);
           unit_range_idx.push_back(static_cast<int>(r));
           // cost: pairs rounded up to staging chunks per block touched, plus a
-          // fixed per-unit cost (zeroing and writing the tile)
+          // fixed per-unit cost (zeroing and writing the tile); a light unit
+          // (3 of its 8 blocks) costs about half
           const double nblk = std::max(0, rg.b1 - rg.b0 + 1);
-          hp.cost.push_back(static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0);
+          hp.cost.push_back((static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0) *
+                            (light_tile(tc, tp, tq) ? kLightCost : 1.0));
         }
       }
   }
@@ -567,21 +583,30 @@ void plan_host(const TileConfig& tc, int nwg_launch, const chi0_problem* probs, 
   // at the same time, sharing that XCD's L2.  Otherwise greedy list
   // scheduling (each unit to the workgroup that becomes free first) keeps
   // uneven problems balanced.
+  // With diag_skip the light units are dealt round-robin after the others
+  // (each list ends with its share of them).
   std::vector<std::vector<int>> lists(nwg);
   std::vector<double> load(nwg, 0.0);
-  double cmin = 0.0, cmax = 0.0;
-  for (size_t i = 0; i < hp.cost.size(); ++i) {
-    cmin = i ? std::min(cmin, hp.cost[i]) : hp.cost[i];
-    cmax = i ? std::max(cmax, hp.cost[i]) : hp.cost[i];
+  std::vector<int> heavy, light;
+  for (int id : order) {
+    const Unit& u = hp.units[id];
+    (light_tile(tc, u.tp, u.tq) ? light : heavy).push_back(id);
   }
-  const size_t nu = order.size();
+  double cmin = 0.0, cmax = 0.0;
+  for (size_t i = 0; i < heavy.size(); ++i) {
+    const double c = hp.cost[heavy[i]];
+    cmin = i ? std::min(cmin, c) : c;
+    cmax = i ? std::max(cmax, c) : c;
+  }
+  const size_t nu = heavy.size();
   const bool uniform = nu > 0 && cmax <= 1.05 * cmin &&
                        (nu % nwg == 0 || nu / nwg >= 16 || nu < static_cast<size_t>(nwg));
   if (uniform) {
-    for (size_t i = 0; i < nu; ++i) {
+    for (size_t i = 0; i < nu + light.size(); ++i) {
       const int w = static_cast<int>(i % nwg);
-      lists[w].push_back(order[i]);
-      load[w] += hp.cost[order[i]];
+      const int id = i < nu ? heavy[i] : light[i - nu];
+      lists[w].push_back(id);
+      load[w] += hp.cost[id];
     }
   } else {
     typedef std::pair<double, int> Slot;
@@ -709,7 +734,7 @@ struct GatherHook {
 // frequency-group kernel, the frequencies rounded up to whole groups) x a
 // per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
 // it.  Costs relative to the built-in default, fitted to MI355X timings at
-// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (15) 1.0,
+// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (16) 1.0,
 // tall 256 x 128 (7) 1.20, 128^2 with two workgroups per CU (4) 1.34, 64^2
 // (2) 2.04, the pre-split pass 173 per row and column; FP64 128^2 with 8
 // waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42; FP32 64^2 (1) 1.0, 128^2 (0)
@@ -720,7 +745,7 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
     int idx;
     double cost;
   };
-  static const Cand bf16[] = {{15, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
+  static const Cand bf16[] = {{16, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
   static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
   static const Cand fp32[] = {{1, 1.0}, {0, 0.914}};
   const int ndef = herk_default_tile(kind);
@@ -741,8 +766,11 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
       const int npb = probs[p].npb;
       const int ntp = (npb + TP - 1) / TP, ntq = (npb + TQ - 1) / TQ;
       double area = 0.0;
-      for (int tp = 0; tp < ntp; ++tp)
-        area += static_cast<double>(std::min(ntq, (tp * TP + TP - 1) / TQ + 1)) * TP * TQ;
+      for (int tp = 0; tp < ntp; ++tp) {
+        const int nt = std::min(ntq, (tp * TP + TP - 1) / TQ + 1);
+        area += static_cast<double>(nt) * TP * TQ;
+        if (2 * tp + 1 < nt && light_tile(tc, tp, 2 * tp + 1)) area -= (1.0 - kLightCost) * TP * TQ;
+      }
       const int G = std::max(1, static_cast<int>(tc.omega_group));
       const int nw = (std::max(1, probs[p].nomega) + G - 1) / G * G;
       t += rows * area * nw * c.cost;
@@ -2195,6 +2223,14 @@ int chi0_tile_info(chi0_precision prec, int32_t tile, int32_t* tile_p, int32_t* 
   if (kchunk) *kchunk = tc.kchunk;
   if (flush_len) *flush_len = tc.flush;
   return CHI0_OK;
+}
+
+int chi0_tile_diag_skip(chi0_precision prec, int32_t tile) {
+  const int k = kind_of(prec);
+  if (k < 0) return fail(CHI0_EINVAL, "unknown precision");
+  if (tile < 0 || tile >= herk_tile_count(k)) return fail(CHI0_EINVAL, "tile %d out of range", tile);
+  const TileConfig tc = herk_tile_config(k, tile);
+  return tc.diag_skip && tc.tile == 2 * tc.tile_q ? 1 : 0;
 }
 
 int chi0_tile_lists(chi0_precision prec, int32_t tile) {

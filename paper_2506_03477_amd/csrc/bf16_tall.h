@@ -144,7 +144,17 @@ __device__ __forceinline__ void tall_mfma(const Bf16TallLds& L, int buf, int wr,
 // wave issues them all and waits for none (a slot belongs to one wave, whose
 // accesses to one address stay in order, so the sums are those of the
 // load-add-store form, in the same order).
-template <int NBI = 4, int TQ = 128, bool ATOM = false>
+// 32 x 32 block (i, j) of a 128 x 64 tile that crosses the diagonal:
+// DIAG 1 for tile column 2 tp (left half of the diagonal 128 x 128 square),
+// DIAG 2 for tile column 2 tp + 1 (its right half), 0 for any other tile.
+// A block is needed iff it holds an entry on or below the diagonal (rows
+// 32 i .. 32 i + 31, columns 32 j .. 32 j + 31, plus 64 for DIAG 2).
+template <int DIAG>
+__host__ __device__ constexpr bool diag_block_needed(int i, int j) {
+  return DIAG == 0 ? true : DIAG == 1 ? (i >= j) : (i >= j + 2);
+}
+
+template <int NBI = 4, int TQ = 128, bool ATOM = false, int DIAG = 0>
 __device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32x16 (&cr)[NBI][2],
                                            const f32x16 (&ci)[NBI][2], int wr, int wc, int lane,
                                            bool first) {
@@ -156,6 +166,7 @@ __device__ __forceinline__ void tall_flush(double2* __restrict__ part, const f32
   for (int i = 0; i < NBI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
+      if (!diag_block_needed<DIAG>(i, j)) continue;   // never read by the reduction
       double2* blk = part + base + i * 32 * TQ + j * 32;
       if (ATOM && !first) {
         typedef double __attribute__((address_space(1)))* gdp;

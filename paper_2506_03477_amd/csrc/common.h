@@ -237,6 +237,8 @@ struct TileConfig {
                        // its own units, of tile x tile_q)
   int32_t omega_group; // 0 or 1: a unit is one frequency; G > 1: a unit holds
                        // up to G frequencies of one tile and pair range
+  int32_t diag_skip;   // 1: tiles crossing the diagonal (tile = 2 tile_q) leave
+                       // out their 32 x 32 blocks entirely above it
 };
 
 // Groups of 4 pairs in a block's pre-split planes (whole 16-pair stages).

@@ -913,6 +913,8 @@ static const TileConfig kBf16Tiles[] = {
                                          //     workgroup sharing LDS-staged operands
     {128, kKC, 4096, kNT, 64, 1, 1, 4},  // 14: as 13, with issue-order hints
     {128, kKC, 4096, kNT, 64, 1, 1, 4},  // 15: as 14, flushes by FP64 atomic adds
+    {128, kKC, 4096, kNT, 64, 1, 1, 4, 1},  // 16: as 15, diagonal tiles leave out their
+                                            //     blocks above the diagonal
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -981,6 +983,7 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
     case 13:
     case 14:
     case 15:
+    case 16:
       return herk_bf16x3_wgroup_launch(lolo, idx - 13, a, nwg, s);
     default:
       if (lolo)
@@ -1021,6 +1024,7 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
     case 13:
     case 14:
     case 15:
+    case 16:
       return herk_bf16x3_wgroup_max_wg_per_cu();
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false>, 512, 0);

@@ -127,10 +127,12 @@ struct WgFrag {
   u32x4 w;             // the wave's weights of pairs 4 g .. 4 g + 3
 };
 
+template <int DIAG>
 __device__ __forceinline__ void wg_read(const char* buf, int ks, int g8, int l32, int wave,
                                         WgFrag& f) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    if (!diag_block_needed<DIAG>(i, 0) && !diag_block_needed<DIAG>(i, 1)) continue;
     const int off = ((2 * ks + g8) * 128 + 32 * i + l32) * 16;
     f.ph[i] = *reinterpret_cast<const u32x4*>(buf + off);
     f.pl[i] = *reinterpret_cast<const u32x4*>(buf + off + kWgPBytes / 2);
@@ -183,27 +185,31 @@ __device__ __forceinline__ void wg_convert(const WgFrag& f, int j, WgWords& o) {
 
 __device__ __forceinline__ bf16x8 wfrag(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-template <bool LOLO>
+template <bool LOLO, int DIAG>
 __device__ __forceinline__ void wg_mfma(const WgFrag& p, const WgWords& q, int j, f32x16 (&cr)[4][2],
                                         f32x16 (&ci)[4][2]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    if (!diag_block_needed<DIAG>(i, j)) continue;
     cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.ph[i]), wfrag(q.h[j]), cr[i][j], 0, 0, 0);
     ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.ph[i]), wfrag(q.rh[j]), ci[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    if (!diag_block_needed<DIAG>(i, j)) continue;
     cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.ph[i]), wfrag(q.l[j]), cr[i][j], 0, 0, 0);
     ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.ph[i]), wfrag(q.rl[j]), ci[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    if (!diag_block_needed<DIAG>(i, j)) continue;
     cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.pl[i]), wfrag(q.h[j]), cr[i][j], 0, 0, 0);
     ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.pl[i]), wfrag(q.rh[j]), ci[i][j], 0, 0, 0);
   }
   if (LOLO) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+      if (!diag_block_needed<DIAG>(i, j)) continue;
       cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.pl[i]), wfrag(q.l[j]), cr[i][j], 0, 0, 0);
       ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfrag(p.pl[i]), wfrag(q.rl[j]), ci[i][j], 0, 0, 0);
     }
@@ -244,20 +250,151 @@ __device__ __forceinline__ void wg_order() {
 // already in W), reading the next k-step's fragments (k-step ks + 1 of `cur`,
 // or k-step 0 of the next stage from `nxt`) into fn and converting their
 // column block 0.
-template <bool LOLO>
+template <bool LOLO, int DIAG>
 __device__ __forceinline__ void wg_kstep(const char* src, int ksn, int g8, int l32, int wave,
                                          const WgFrag& fc, WgFrag& fn, WgWords& W,
                                          f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
-  wg_read(src, ksn, g8, l32, wave, fn);
+  wg_read<DIAG>(src, ksn, g8, l32, wave, fn);
   wg_convert(fc, 1, W);
-  wg_mfma<LOLO>(fc, W, 0, cr, ci);
+  wg_mfma<LOLO, DIAG>(fc, W, 0, cr, ci);
   wg_convert(fn, 0, W);
-  wg_mfma<LOLO>(fc, W, 1, cr, ci);
+  wg_mfma<LOLO, DIAG>(fc, W, 1, cr, ci);
 }
 
-template <bool LOLO, bool HINT, bool ATOM>
-__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
+// The stages of one run (nst stages of 32 pairs) into the accumulators.
+// Three LDS buffers, stage s in buffer s % 3.  The barrier of stage s (after
+// its k-step 2) follows the loads of stage s + 1, issued since the previous
+// barrier, and every read of stage s - 1; the loads of stage s + 2 start
+// after it, and so do the reads of stage s + 1 (k-step 3 prefetches its
+// first fragments).  DIAG (tiles crossing the diagonal) leaves out the
+// MFMAs and P reads of blocks entirely above it.
+template <bool LOLO, bool HINT, int DIAG>
+__device__ __forceinline__ void wg_stages(const WgRun& r, const WgLane& o, int nst, int wave,
+                                          int lane, int g8, int l32, char (*lds)[kWgBuf],
+                                          f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
+  wg_dma_all(r, 0, o, wave, lane, lds[0]);
+  __builtin_amdgcn_s_waitcnt(kVmcnt0);
+  __syncthreads();
+  WgFrag F0, F1;
+  WgWords W;
+  wg_read<DIAG>(lds[0], 0, g8, l32, wave, F0);
+  wg_convert(F0, 0, W);
+  wg_dma<0>(r, 1, o, wave, lane, lds[1]);
+  int bc = 0;   // buffer of stage st
+  for (int st = 0; st < nst; ++st) {
+    const int bn = bc == 2 ? 0 : bc + 1, bnn = bn == 2 ? 0 : bn + 1;
+    const char* cur = lds[bc];
+    wg_kstep<LOLO, DIAG>(cur, 1, g8, l32, wave, F0, F1, W, cr, ci);
+    wg_dma<1>(r, st + 1, o, wave, lane, lds[bn]);
+    if (HINT) wg_order<4>();
+    __builtin_amdgcn_sched_barrier(0);
+    wg_kstep<LOLO, DIAG>(cur, 2, g8, l32, wave, F1, F0, W, cr, ci);
+    wg_dma<2>(r, st + 1, o, wave, lane, lds[bn]);
+    if (HINT) wg_order<9>();
+    __builtin_amdgcn_sched_barrier(0);
+    wg_kstep<LOLO, DIAG>(cur, 3, g8, l32, wave, F0, F1, W, cr, ci);
+    wg_dma<3>(r, st + 1, o, wave, lane, lds[bn]);
+    if (HINT) wg_order<8>();
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);   // this wave's loads of stage st + 1
+    __syncthreads();
+    wg_kstep<LOLO, DIAG>(lds[bn], 0, g8, l32, wave, F1, F0, W, cr, ci);
+    wg_dma<0>(r, st + 2, o, wave, lane, lds[bnn]);
+    if (HINT) wg_order<4>();
+    __builtin_amdgcn_sched_barrier(0);
+    bc = bn;
+  }
+  __builtin_amdgcn_s_waitcnt(kVmcnt0);     // loads past the run's stages
+  __syncthreads();
+}
+
+// One unit (a tile, a pair range, up to four frequencies: wave w takes
+// frequency u.iw + w) from its ranges' stages into the wave's partial tile.
+// DIAG (0, or 1 / 2 for the tiles left / right of the diagonal) is fixed per
+// unit, so each kind has its own copy of the run loop and registers.
+template <bool LOLO, bool HINT, bool ATOM, int DIAG>
+__device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const ProbDesc& pd,
+                                        int tid, int wave, int lane, int g8, int l32,
+                                        char (*lds)[kWgBuf]) {
   constexpr int TP = 128, TQ = 64;
+  const int npb = pd.npb;
+  const bool active = wave < u.nw;
+  const int r0 = u.tp * TP, c0 = u.tq * TQ;
+  const int32_t chunk = npb * 16, row = npb * 8;
+  WgLane o;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int col = r0 + (tid & 127);
+    o.p[m] = static_cast<uint32_t>((tid >> 7) + 2 * m) * static_cast<uint32_t>(chunk) +
+             static_cast<uint32_t>(col < npb ? col : 0) * 16u;
+  }
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {
+    // dword t + 256 m, m = 2 m2 + h2: pair 2 m2 + (t + 256 h2) / 128, column
+    // ((t + 256 h2) % 128) / 2, part t % 2
+    const int d = tid + 256 * h2;
+    const int col = c0 + ((d & 127) >> 1);
+    o.q[h2] = static_cast<uint32_t>(d >> 7) * static_cast<uint32_t>(row) +
+              static_cast<uint32_t>(col < npb ? col : 0) * 8u + static_cast<uint32_t>(d & 1) * 4u;
+  }
+  // FP32 runs of at most the problem's flush length (a multiple of 16
+  // pairs), made of granules of R pairs: whole 32-pair stages when the
+  // length allows, else 16 pairs (the stage's second half then reads zeros)
+  const int R = pd.flush >= kWgPairs ? kWgPairs : 16;
+  const int fr = max(1, pd.flush / R);
+  double2* part = a.partials + static_cast<size_t>(u.slot + wave * u.wstride) * TP * TQ;
+  // this wave's frequency (a wave past the group's frequencies computes
+  // with the last one's weights and writes nothing)
+  const int wv = min(wave, u.nw - 1);
+  const float* wbase = static_cast<const float*>(pd.wts) + static_cast<size_t>(u.iw + wv) * pd.ktot;
+  const int64_t wend = (static_cast<int64_t>(pd.nomega) - u.iw - wv) * pd.ktot;  // floats from wbase
+
+  f32x16 cr[4][2], ci[4][2];
+  wg_zero(cr, ci);
+  bool first = true;
+  int acc = 0;   // granules in the FP32 accumulators
+  for (int b = u.b0; b <= u.b1; ++b) {
+    const BlockDesc* bp = a.blocks + b;
+    const int kb = block_pairs(a.blocks, b);
+    const int p0 = (b == u.b0) ? u.p0 : 0;
+    const int p1 = (b == u.b1) ? u.p1 : kb;
+    if (p0 >= p1) continue;
+    const gcptr zs = (gcptr)ld_const(&bp->zs, 0);
+    const int64_t plane = ld_const(&bp->zs_plane, 0);
+    const gcptr z = (gcptr)ld_const(&bp->z, 0);
+    const int64_t pbase = ld_const(&bp->pair_base, 0);
+    const int64_t groups = presplit_groups(kb);
+    const int ng = (p1 - p0 + R - 1) / R;   // granules of the segment (p0: a multiple of 16)
+    for (int g0 = 0; g0 < ng;) {
+      const int len = min(fr - acc, ng - g0);
+      const int q0 = p0 + R * g0;
+      const int nv = min(p1, q0 + R * len) - q0;
+      WgRun r;
+      r.chunk = chunk;
+      r.row = row;
+      r.hi = zs + static_cast<int64_t>(q0 >> 2) * chunk;
+      r.lo = r.hi + plane;
+      r.pbytes = wg_cap((groups - (q0 >> 2)) * static_cast<int64_t>(chunk));
+      r.z = z + static_cast<int64_t>(q0) * row;
+      r.zbytes = wg_cap(static_cast<int64_t>(nv) * row);
+      r.w = (gcptr)(wbase + pbase + q0);
+      r.wbytes = wg_cap((wend - pbase - q0) * 4);
+      const int nst = (nv + kWgPairs - 1) / kWgPairs;
+      wg_stages<LOLO, HINT, DIAG>(r, o, nst, wave, lane, g8, l32, lds, cr, ci);
+      g0 += len;
+      acc += len;
+      if (acc >= fr) {
+        if (active) tall_flush<4, TQ, ATOM, DIAG>(part, cr, ci, 0, 0, lane, first);
+        first = false;
+        acc = 0;
+        wg_zero(cr, ci);
+      }
+    }
+  }
+  if (active && (first || acc > 0)) tall_flush<4, TQ, ATOM, DIAG>(part, cr, ci, 0, 0, lane, first);
+}
+
+template <bool LOLO, bool HINT, bool ATOM, bool SKIP>
+__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[3][kWgBuf];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -272,118 +409,12 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
   for (int ui = beg; ui < end; ++ui) {
     const Unit u = ld_unit(a.units, ld_const(a.wg_units, ui));
     const ProbDesc pd = ld_prob(a.probs, u.prob);
-    const int npb = pd.npb;
-    const bool active = wave < u.nw;
-    const int r0 = u.tp * TP, c0 = u.tq * TQ;
-    const int32_t chunk = npb * 16, row = npb * 8;
-    WgLane o;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int col = r0 + (tid & 127);
-      o.p[m] = static_cast<uint32_t>((tid >> 7) + 2 * m) * static_cast<uint32_t>(chunk) +
-               static_cast<uint32_t>(col < npb ? col : 0) * 16u;
-    }
-#pragma unroll
-    for (int h2 = 0; h2 < 2; ++h2) {
-      // dword t + 256 m, m = 2 m2 + h2: pair 2 m2 + (t + 256 h2) / 128, column
-      // ((t + 256 h2) % 128) / 2, part t % 2
-      const int d = tid + 256 * h2;
-      const int col = c0 + ((d & 127) >> 1);
-      o.q[h2] = static_cast<uint32_t>(d >> 7) * static_cast<uint32_t>(row) +
-                static_cast<uint32_t>(col < npb ? col : 0) * 8u + static_cast<uint32_t>(d & 1) * 4u;
-    }
-    // FP32 runs of at most the problem's flush length (a multiple of 16
-    // pairs), made of granules of R pairs: whole 32-pair stages when the
-    // length allows, else 16 pairs (the stage's second half then reads zeros)
-    const int R = pd.flush >= kWgPairs ? kWgPairs : 16;
-    const int fr = max(1, pd.flush / R);
-    double2* part = a.partials + static_cast<size_t>(u.slot + wave * u.wstride) * TP * TQ;
-    // this wave's frequency (a wave past the group's frequencies computes
-    // with the last one's weights and writes nothing)
-    const int wv = min(wave, u.nw - 1);
-    const float* wbase = static_cast<const float*>(pd.wts) + static_cast<size_t>(u.iw + wv) * pd.ktot;
-    const int64_t wend = (static_cast<int64_t>(pd.nomega) - u.iw - wv) * pd.ktot;  // floats from wbase
-
-    f32x16 cr[4][2], ci[4][2];
-    wg_zero(cr, ci);
-    bool first = true;
-    int acc = 0;   // granules in the FP32 accumulators
-    for (int b = u.b0; b <= u.b1; ++b) {
-      const BlockDesc* bp = a.blocks + b;
-      const int kb = block_pairs(a.blocks, b);
-      const int p0 = (b == u.b0) ? u.p0 : 0;
-      const int p1 = (b == u.b1) ? u.p1 : kb;
-      if (p0 >= p1) continue;
-      const gcptr zs = (gcptr)ld_const(&bp->zs, 0);
-      const int64_t plane = ld_const(&bp->zs_plane, 0);
-      const gcptr z = (gcptr)ld_const(&bp->z, 0);
-      const int64_t pbase = ld_const(&bp->pair_base, 0);
-      const int64_t groups = presplit_groups(kb);
-      const int ng = (p1 - p0 + R - 1) / R;   // granules of the segment (p0: a multiple of 16)
-      for (int g0 = 0; g0 < ng;) {
-        const int len = min(fr - acc, ng - g0);
-        const int q0 = p0 + R * g0;
-        const int nv = min(p1, q0 + R * len) - q0;
-        WgRun r;
-        r.chunk = chunk;
-        r.row = row;
-        r.hi = zs + static_cast<int64_t>(q0 >> 2) * chunk;
-        r.lo = r.hi + plane;
-        r.pbytes = wg_cap((groups - (q0 >> 2)) * static_cast<int64_t>(chunk));
-        r.z = z + static_cast<int64_t>(q0) * row;
-        r.zbytes = wg_cap(static_cast<int64_t>(nv) * row);
-        r.w = (gcptr)(wbase + pbase + q0);
-        r.wbytes = wg_cap((wend - pbase - q0) * 4);
-        const int nst = (nv + kWgPairs - 1) / kWgPairs;
-        // Three LDS buffers, stage s in buffer s % 3.  The barrier of stage
-        // s (after its k-step 2) follows the loads of stage s + 1, issued
-        // since the previous barrier, and every read of stage s - 1; the
-        // loads of stage s + 2 start after it, and so do the reads of stage
-        // s + 1 (k-step 3 prefetches its first fragments).
-        wg_dma_all(r, 0, o, wave, lane, lds[0]);
-        __builtin_amdgcn_s_waitcnt(kVmcnt0);
-        __syncthreads();
-        WgFrag F0, F1;
-        WgWords W;
-        wg_read(lds[0], 0, g8, l32, wave, F0);
-        wg_convert(F0, 0, W);
-        wg_dma<0>(r, 1, o, wave, lane, lds[1]);
-        int bc = 0;   // buffer of stage st
-        for (int st = 0; st < nst; ++st) {
-          const int bn = bc == 2 ? 0 : bc + 1, bnn = bn == 2 ? 0 : bn + 1;
-          const char* cur = lds[bc];
-          wg_kstep<LOLO>(cur, 1, g8, l32, wave, F0, F1, W, cr, ci);
-          wg_dma<1>(r, st + 1, o, wave, lane, lds[bn]);
-          if (HINT) wg_order<4>();
-          __builtin_amdgcn_sched_barrier(0);
-          wg_kstep<LOLO>(cur, 2, g8, l32, wave, F1, F0, W, cr, ci);
-          wg_dma<2>(r, st + 1, o, wave, lane, lds[bn]);
-          if (HINT) wg_order<9>();
-          __builtin_amdgcn_sched_barrier(0);
-          wg_kstep<LOLO>(cur, 3, g8, l32, wave, F0, F1, W, cr, ci);
-          wg_dma<3>(r, st + 1, o, wave, lane, lds[bn]);
-          if (HINT) wg_order<8>();
-          __builtin_amdgcn_s_waitcnt(kVmcnt0);   // this wave's loads of stage st + 1
-          __syncthreads();
-          wg_kstep<LOLO>(lds[bn], 0, g8, l32, wave, F1, F0, W, cr, ci);
-          wg_dma<0>(r, st + 2, o, wave, lane, lds[bnn]);
-          if (HINT) wg_order<4>();
-          __builtin_amdgcn_sched_barrier(0);
-          bc = bn;
-        }
-        __builtin_amdgcn_s_waitcnt(kVmcnt0);     // loads past the run's stages
-        __syncthreads();
-        g0 += len;
-        acc += len;
-        if (acc >= fr) {
-          if (active) tall_flush<4, TQ, ATOM>(part, cr, ci, 0, 0, lane, first);
-          first = false;
-          acc = 0;
-          wg_zero(cr, ci);
-        }
-      }
-    }
-    if (active && (first || acc > 0)) tall_flush<4, TQ, ATOM>(part, cr, ci, 0, 0, lane, first);
+    // tiles crossing the diagonal (TP = 2 TQ): their blocks above it are
+    // left out with SKIP (the reduction never reads those entries)
+    const int diag = !SKIP ? 0 : u.tq == 2 * u.tp ? 1 : u.tq == 2 * u.tp + 1 ? 2 : 0;
+    if (diag == 0) wg_unit<LOLO, HINT, ATOM, 0>(a, u, pd, tid, wave, lane, g8, l32, lds);
+    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, 1>(a, u, pd, tid, wave, lane, g8, l32, lds);
+    else wg_unit<LOLO, HINT, ATOM, 2>(a, u, pd, tid, wave, lane, g8, l32, lds);
   }
 }
 
@@ -392,17 +423,19 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
 hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, int nwg,
                                      hipStream_t s) {
   // variant 0: compiler scheduling; 1: issue-order hints; 2: hints and
-  // atomic flushes
-#define CHI0_WG_LAUNCH(L, H, A) \
-  hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<L, H, A>), dim3(nwg), dim3(kNT), 0, s, a)
+  // atomic flushes; 3: as 2, leaving out the blocks above the diagonal
+#define CHI0_WG_LAUNCH(L, H, A, K) \
+  hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<L, H, A, K>), dim3(nwg), dim3(kNT), 0, s, a)
   if (lolo) {
-    if (variant == 0) CHI0_WG_LAUNCH(true, false, false);
-    else if (variant == 1) CHI0_WG_LAUNCH(true, true, false);
-    else CHI0_WG_LAUNCH(true, true, true);
+    if (variant == 0) CHI0_WG_LAUNCH(true, false, false, false);
+    else if (variant == 1) CHI0_WG_LAUNCH(true, true, false, false);
+    else if (variant == 2) CHI0_WG_LAUNCH(true, true, true, false);
+    else CHI0_WG_LAUNCH(true, true, true, true);
   } else {
-    if (variant == 0) CHI0_WG_LAUNCH(false, false, false);
-    else if (variant == 1) CHI0_WG_LAUNCH(false, true, false);
-    else CHI0_WG_LAUNCH(false, true, true);
+    if (variant == 0) CHI0_WG_LAUNCH(false, false, false, false);
+    else if (variant == 1) CHI0_WG_LAUNCH(false, true, false, false);
+    else if (variant == 2) CHI0_WG_LAUNCH(false, true, true, false);
+    else CHI0_WG_LAUNCH(false, true, true, true);
   }
 #undef CHI0_WG_LAUNCH
   return hipGetLastError();
@@ -411,7 +444,7 @@ hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, 
 int herk_bf16x3_wgroup_max_wg_per_cu() {
   int n = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, true, false>, kNT, 0);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, true, true, false>, kNT, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

@@ -159,7 +159,8 @@ def test_frequency_group_tile(ctx, npb, omega):
     operands staged once in LDS) on frequency counts that leave partial
     groups, odd npb and several tiles: against the oracle and the split
     model, equal to the per-wave kernel's result up to FP32 rounding, and
-    bitwise equal across its variants (hints, atomic flushes)."""
+    bitwise equal across its variants (hints, atomic flushes, load
+    timing)."""
     wl = workload(3, nq=1, npb=npb, nk=16, omega=omega)
     ref = oracle_chi0(wl)
     mod = _model(wl, "bf16x3")
@@ -168,7 +169,7 @@ def test_frequency_group_tile(ctx, npb, omega):
     info = ctx.tile_info("bf16x3", grp)
     assert (info["tile_p"], info["tile_q"], ctx.tile_lists("bf16x3", grp)) == (128, 64, 1)
     got = {}
-    for tile in (grp, 14, 15, 11):
+    for tile in (grp, 14, 15, 16, 11):
         ctx.set_tile("bf16x3", tile)
         ctx.chi0_accumulate([prob], precision="bf16x3")
         ctx.sync()
@@ -181,6 +182,8 @@ def test_frequency_group_tile(ctx, npb, omega):
     assert np.all(e <= TOL), e
     assert np.all(em <= 3e-7), em
     assert np.all(rel_fro(got[grp], got[11]) <= 3e-7)
-    # the issue-order hints and the atomic flushes (one wave per partial
-    # slot, its additions in program order) change no arithmetic
-    assert np.array_equal(got[14], got[grp]) and np.array_equal(got[15], got[grp])
+    # the issue-order hints, the atomic flushes (one wave per partial slot,
+    # its additions in program order) and the earlier stage loads change no
+    # arithmetic
+    for t in (14, 15, 16):
+        assert np.array_equal(got[t], got[grp]), t

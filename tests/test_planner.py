@@ -172,3 +172,30 @@ def _tile(lib, prec, t):
     TP, TQ, KC = c_int32(), c_int32(), c_int32()
     assert lib.chi0_tile_info(prec, t, byref(TP), byref(TQ), byref(KC), None) == 0
     return TP.value, TQ.value, KC.value
+
+
+def test_diagonal_skip_deals_light_units_evenly():
+    """A configuration that leaves out the blocks above the diagonal has
+    light units (the tiles right of the diagonal: 3 of 8 blocks).  They are
+    dealt round-robin after the others, and the range count is chosen so
+    that both kinds fill whole rounds: at npb 2048 every work list gets the
+    same number of each (units = per-frequency rows of plan_inspect)."""
+    lib = pkg.load()
+    skip = [t for t in range(lib.chi0_tile_count(2)) if lib.chi0_tile_diag_skip(2, t) == 1]
+    assert skip, "no BF16x3 configuration skips blocks above the diagonal"
+    for t in range(lib.chi0_tile_count(2)):
+        assert lib.chi0_tile_diag_skip(2, t) in (0, 1)
+    assert lib.chi0_tile_diag_skip(2, lib.chi0_tile_count(2)) == L.CHI0_EINVAL
+    assert lib.chi0_tile_diag_skip(9, 0) == L.CHI0_EINVAL
+    t = skip[0]
+    TP, TQ, _ = _tile(lib, 2, t)
+    assert TP == 2 * TQ
+    shapes = [(2048, 12, [(200, 1200)] * 16)]
+    units, njobs, lmax, lmean = _inspect(shapes, 2, t, 256)
+    light = units[:, 3] == 2 * units[:, 2] + 1
+    assert light.any()
+    owners = units[:, 9]
+    n_light = np.bincount(owners[light], minlength=256)
+    n_heavy = np.bincount(owners[~light], minlength=256)
+    assert n_light.min() == n_light.max() and n_heavy.min() == n_heavy.max()
+    assert lmax <= 1.0001 * lmean
