@@ -79,6 +79,7 @@ struct Plan {
   int nunits = 0;
   int64_t nslots = 0;
   int njobs = 0;
+  bool round_robin = false;    // units dealt round-robin (equal costs)
   int nblocks_total = 0;
   int nprob = 0;
   DevBuf d_units, d_wg_off, d_wg_units, d_jobs, d_blocks, d_probs;
@@ -105,6 +106,7 @@ struct chi0_ctx {
   DevBuf partials;
   DevBuf wts;           // pair weights of the current call
   DevBuf zsplit;        // pre-split P-side planes of the current call
+  DevBuf sync_prog;     // per-workgroup progress words of the XCD lockstep
   DevBuf gj_work, gj_wrow, gj_piv, gj_perm;
   DevBuf hpd_p, hpd_c, hpd_dinv;  // HPD inverse: kept panel, new panel, D^{-1}
   DevBuf sigc_tab, sigc_wt, sigc_zw, sigc_part, sigc_acc, sigc_split;  // correlation self-energy
@@ -366,6 +368,7 @@ struct HostPlan {
   std::vector<double> cost;
   std::vector<double> wg_load;
   int nblocks_total = 0;
+  bool round_robin = false;
 };
 
 // Default upper bound on the FP64 partial tiles of one rank-K launch (bytes).
@@ -377,6 +380,11 @@ constexpr double kMaxPartialBytes = 12.0e9;
 constexpr double kLightCost = 0.5;
 bool light_tile(const TileConfig& tc, int tp, int tq) {
   return tc.diag_skip && tc.tile == 2 * tc.tile_q && tq == 2 * tp + 1;
+}
+// diag_skip 1: light units are costed as such and dealt after the others;
+// 2: they keep their place in the locality order and a full unit's cost
+bool deal_light_apart(const TileConfig& tc, int tp, int tq) {
+  return tc.diag_skip == 1 && light_tile(tc, tp, tq);
 }
 
 // Lower-triangle tiles of a TP x TQ tiling of an npb x npb matrix: tile
@@ -453,7 +461,7 @@ void plan_host(const TileConfig& tc, int nwg_launch, const chi0_problem* probs, 
   if (nprob == 1 && ps[0].K > 0) {
     const double jobs = static_cast<double>(ps[0].nomega) * ps[0].ntl;
     int nlight = 0;
-    for (const auto& t : ps[0].tiles) nlight += light_tile(tc, t.first, t.second) ? 1 : 0;
+    for (const auto& t : ps[0].tiles) nlight += deal_light_apart(tc, t.first, t.second) ? 1 : 0;
     const double light_per_range = static_cast<double>(ngrp(ps[0].nomega)) * nlight;
     const double units_per_range = static_cast<double>(ngrp(ps[0].nomega)) * ps[0].ntl - light_per_range;
     const int64_t s0 = std::max<int64_t>(1, std::llround(std::ceil(ps[0].K / per_unit)));
@@ -531,7 +539,7 @@ void plan_host(const TileConfig& tc, int nwg_launch, const chi0_problem* probs, 
           // (3 of its 8 blocks) costs about half
           const double nblk = std::max(0, rg.b1 - rg.b0 + 1);
           hp.cost.push_back((static_cast<double>(rg.n) + nblk * tc.kchunk + 64.0) *
-                            (light_tile(tc, tp, tq) ? kLightCost : 1.0));
+                            (deal_light_apart(tc, tp, tq) ? kLightCost : 1.0));
         }
       }
   }
@@ -590,7 +598,7 @@ void plan_host(const TileConfig& tc, int nwg_launch, const chi0_problem* probs, 
   std::vector<int> heavy, light;
   for (int id : order) {
     const Unit& u = hp.units[id];
-    (light_tile(tc, u.tp, u.tq) ? light : heavy).push_back(id);
+    (deal_light_apart(tc, u.tp, u.tq) ? light : heavy).push_back(id);
   }
   double cmin = 0.0, cmax = 0.0;
   for (size_t i = 0; i < heavy.size(); ++i) {
@@ -601,6 +609,7 @@ void plan_host(const TileConfig& tc, int nwg_launch, const chi0_problem* probs, 
   const size_t nu = heavy.size();
   const bool uniform = nu > 0 && cmax <= 1.05 * cmin &&
                        (nu % nwg == 0 || nu / nwg >= 16 || nu < static_cast<size_t>(nwg));
+  hp.round_robin = uniform;
   if (uniform) {
     for (size_t i = 0; i < nu + light.size(); ++i) {
       const int w = static_cast<int>(i % nwg);
@@ -666,6 +675,7 @@ int build_plan(chi0_ctx* h, Plan& pl, int kind, int tile_idx, const chi0_problem
   pl.nunits = static_cast<int>(hp.units.size());
   pl.nslots = hp.nslots;
   pl.njobs = static_cast<int>(hp.jobs.size());
+  pl.round_robin = hp.round_robin;
   int rc;
   if ((rc = upload_sync(pl.d_units, hp.units))) return rc;
   if ((rc = upload_sync(pl.d_wg_off, hp.wg_off))) return rc;
@@ -734,7 +744,7 @@ struct GatherHook {
 // frequency-group kernel, the frequencies rounded up to whole groups) x a
 // per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
 // it.  Costs relative to the built-in default, fitted to MI355X timings at
-// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (16) 1.0,
+// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (18) 1.0,
 // tall 256 x 128 (7) 1.20, 128^2 with two workgroups per CU (4) 1.34, 64^2
 // (2) 2.04, the pre-split pass 173 per row and column; FP64 128^2 with 8
 // waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42; FP32 64^2 (1) 1.0, 128^2 (0)
@@ -745,7 +755,7 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
     int idx;
     double cost;
   };
-  static const Cand bf16[] = {{16, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
+  static const Cand bf16[] = {{18, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
   static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
   static const Cand fp32[] = {{1, 1.0}, {0, 0.914}};
   const int ndef = herk_default_tile(kind);
@@ -924,7 +934,19 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
   ha.partials = static_cast<double2*>(h->partials.p);
   ha.delta_min = delta_min;
   ha.flags = static_cast<int32_t>(flags);
-  ha.pad = 0;
+  ha.sync_prog = nullptr;
+  ha.sync_slack = 0;
+  if (pl->tc.xcd_sync > 0 && pl->round_robin) {
+    // one progress word per workgroup; a fresh buffer starts at 0 (the
+    // kernel leaves INT_MAX in each word when its workgroup finishes)
+    const size_t bytes = static_cast<size_t>(pl->nwg) * sizeof(int32_t);
+    if (h->sync_prog.n < bytes) {
+      if ((rc = h->sync_prog.reserve(bytes, &h->ws_gen))) return rc;
+      HIP_TRY(hipMemset(h->sync_prog.p, 0, h->sync_prog.n));
+    }
+    ha.sync_prog = static_cast<int32_t*>(h->sync_prog.p);
+    ha.sync_slack = pl->tc.xcd_sync;
+  }
   ReduceArgs ra;
   ra.jobs = static_cast<const TileJob*>(pl->d_jobs.p);
   ra.probs = ha.probs;
@@ -2024,6 +2046,7 @@ int chi0_destroy(chi0_handle h) {
   h->partials.release();
   h->wts.release();
   h->zsplit.release();
+  h->sync_prog.release();
   h->gj_work.release();
   h->gj_wrow.release();
   h->gj_piv.release();

@@ -82,9 +82,11 @@ struct HerkArgs {
   const BlockDesc* blocks;
   const ProbDesc* probs;
   double2* partials;          // [nslots][T][T] complex128
+  int32_t* sync_prog;         // [nwg] stages done per workgroup (sync_slack > 0)
   double delta_min;
   int32_t flags;
-  int32_t pad;
+  int32_t sync_slack;         // > 0: a workgroup more than this many stages ahead
+                              // of the slowest one on its XCD waits (bounded)
 };
 
 struct ReduceArgs {
@@ -237,8 +239,12 @@ struct TileConfig {
                        // its own units, of tile x tile_q)
   int32_t omega_group; // 0 or 1: a unit is one frequency; G > 1: a unit holds
                        // up to G frequencies of one tile and pair range
-  int32_t diag_skip;   // 1: tiles crossing the diagonal (tile = 2 tile_q) leave
-                       // out their 32 x 32 blocks entirely above it
+  int32_t diag_skip;   // 1, 2: tiles crossing the diagonal (tile = 2 tile_q)
+                       // leave out their 32 x 32 blocks entirely above it; the
+                       // light units right of it are dealt after the others
+                       // (1) or in locality order like the rest (2)
+  int32_t xcd_sync;    // > 0: with round-robin dealing, the workgroups of an
+                       // XCD keep within this many stages of one another
 };
 
 // Groups of 4 pairs in a block's pre-split planes (whole 16-pair stages).

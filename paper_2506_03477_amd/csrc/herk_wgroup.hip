@@ -307,6 +307,33 @@ __device__ __forceinline__ void wg_stages(const WgRun& r, const WgLane& o, int n
   __syncthreads();
 }
 
+// Lockstep of the workgroups of one XCD (workgroup b runs on XCD b % 8):
+// before a run, wave 0 publishes the stages its workgroup has done and, while
+// that is more than sync_slack stages ahead of the slowest peer on the XCD,
+// sleeps and polls again, at most kSyncPolls times (the wait always ends;
+// it only keeps the peers, which stream the same pair ranges in the same
+// rounds, close enough to share the XCD's L2).  A finished workgroup
+// publishes INT_MAX, so it never holds the others, in this launch or the
+// next.  The other waves meet wave 0 at the run's first barrier.
+constexpr int kSyncPolls = 2048;
+
+__device__ __forceinline__ void wg_sync(const HerkArgs& a, int done, int wave, int lane) {
+  if (wave != 0) return;
+  int32_t* prog = a.sync_prog;
+  if (lane == 0) __hip_atomic_store(prog + blockIdx.x, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int peer = static_cast<int>(blockIdx.x & 7u) + 8 * lane;
+  const bool mine = peer < static_cast<int>(gridDim.x);
+  for (int it = 0; it < kSyncPolls; ++it) {
+    int v = mine ? __hip_atomic_load(prog + peer, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                 : INT32_MAX;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    v = __builtin_amdgcn_readfirstlane(v);
+    if (done - v <= a.sync_slack) break;
+    __builtin_amdgcn_s_sleep(8);
+  }
+}
+
 // One unit (a tile, a pair range, up to four frequencies: wave w takes
 // frequency u.iw + w) from its ranges' stages into the wave's partial tile.
 // DIAG (0, or 1 / 2 for the tiles left / right of the diagonal) is fixed per
@@ -314,7 +341,7 @@ __device__ __forceinline__ void wg_stages(const WgRun& r, const WgLane& o, int n
 template <bool LOLO, bool HINT, bool ATOM, int DIAG>
 __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const ProbDesc& pd,
                                         int tid, int wave, int lane, int g8, int l32,
-                                        char (*lds)[kWgBuf]) {
+                                        char (*lds)[kWgBuf], int& done) {
   constexpr int TP = 128, TQ = 64;
   const int npb = pd.npb;
   const bool active = wave < u.nw;
@@ -379,7 +406,9 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
       r.w = (gcptr)(wbase + pbase + q0);
       r.wbytes = wg_cap((wend - pbase - q0) * 4);
       const int nst = (nv + kWgPairs - 1) / kWgPairs;
+      if (a.sync_slack > 0) wg_sync(a, done, wave, lane);
       wg_stages<LOLO, HINT, DIAG>(r, o, nst, wave, lane, g8, l32, lds, cr, ci);
+      done += nst;
       g0 += len;
       acc += len;
       if (acc >= fr) {
@@ -406,16 +435,19 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
   // are uniform: every branch on them stays a scalar branch)
   const int beg = ld_const(a.wg_offsets, static_cast<int>(blockIdx.x));
   const int end = ld_const(a.wg_offsets, static_cast<int>(blockIdx.x) + 1);
+  int done = 0;   // stages of this workgroup's runs so far (XCD lockstep)
   for (int ui = beg; ui < end; ++ui) {
     const Unit u = ld_unit(a.units, ld_const(a.wg_units, ui));
     const ProbDesc pd = ld_prob(a.probs, u.prob);
     // tiles crossing the diagonal (TP = 2 TQ): their blocks above it are
     // left out with SKIP (the reduction never reads those entries)
     const int diag = !SKIP ? 0 : u.tq == 2 * u.tp ? 1 : u.tq == 2 * u.tp + 1 ? 2 : 0;
-    if (diag == 0) wg_unit<LOLO, HINT, ATOM, 0>(a, u, pd, tid, wave, lane, g8, l32, lds);
-    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, 1>(a, u, pd, tid, wave, lane, g8, l32, lds);
-    else wg_unit<LOLO, HINT, ATOM, 2>(a, u, pd, tid, wave, lane, g8, l32, lds);
+    if (diag == 0) wg_unit<LOLO, HINT, ATOM, 0>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
+    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, 1>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
+    else wg_unit<LOLO, HINT, ATOM, 2>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
   }
+  if (a.sync_slack > 0 && tid == 0)
+    __hip_atomic_store(a.sync_prog + blockIdx.x, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace

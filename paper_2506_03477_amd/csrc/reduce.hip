@@ -65,7 +65,7 @@ int herk_default_tile(int kind) {
   switch (kind) {
     case HERK_FP64: return 3;
     case HERK_FP32: return 1;
-    case HERK_BF16X3: return 16;
+    case HERK_BF16X3: return 18;
   }
   return 0;
 }
