@@ -744,7 +744,7 @@ struct GatherHook {
 // frequency-group kernel, the frequencies rounded up to whole groups) x a
 // per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
 // it.  Costs relative to the built-in default, fitted to MI355X timings at
-// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (18) 1.0,
+// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (19) 1.0,
 // tall 256 x 128 (7) 1.20, 128^2 with two workgroups per CU (4) 1.34, 64^2
 // (2) 2.04, the pre-split pass 173 per row and column; FP64 128^2 with 8
 // waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42; FP32 64^2 (1) 1.0, 128^2 (0)
@@ -755,7 +755,7 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
     int idx;
     double cost;
   };
-  static const Cand bf16[] = {{18, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
+  static const Cand bf16[] = {{19, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
   static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
   static const Cand fp32[] = {{1, 1.0}, {0, 0.914}};
   const int ndef = herk_default_tile(kind);
@@ -953,7 +953,7 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
   ra.partials = ha.partials;
   ra.tile_p = TP;
   ra.tile_q = TQ;
-  ra.pad = 0;
+  ra.planar = pl->tc.planar ? 1 : 0;
   ra.accumulate = (flags & CHI0_ACCUMULATE) ? 1 : 0;
 
   const bool use_graph = (flags & CHI0_USE_GRAPH) && !h->profiling && !hk;

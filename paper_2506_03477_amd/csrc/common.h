@@ -96,7 +96,8 @@ struct ReduceArgs {
   int32_t tile_p;             // tile rows
   int32_t tile_q;             // tile columns
   int32_t accumulate;
-  int32_t pad;
+  int32_t planar;             // 1: each partial tile is a plane of real parts,
+                              // then one of imaginary parts (FP64 each)
 };
 
 // Imaginary-axis correlation self-energy (Eq.(sigci)): one k-point block of
@@ -245,6 +246,8 @@ struct TileConfig {
                        // (1) or in locality order like the rest (2)
   int32_t xcd_sync;    // > 0: with round-robin dealing, the workgroups of an
                        // XCD keep within this many stages of one another
+  int32_t planar;      // 1: the kernel writes partial tiles as separate real
+                       // and imaginary FP64 planes
 };
 
 // Groups of 4 pairs in a block's pre-split planes (whole 16-pair stages).

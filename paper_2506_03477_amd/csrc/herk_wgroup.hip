@@ -334,11 +334,65 @@ __device__ __forceinline__ void wg_sync(const HerkArgs& a, int done, int wave, i
   }
 }
 
+// The wave's 128 x 64 accumulators into its partial tile stored as two
+// planes (128 x 64 real parts, then 128 x 64 imaginary parts): the real and
+// the imaginary atomic adds of a flush then each cover whole cache lines
+// (32 lanes, 256 contiguous bytes) instead of every other 8 bytes of the
+// same lines.  Blocks above the diagonal of a diagonal tile are skipped as
+// in tall_flush.
+template <bool ATOM, int DIAG>
+__device__ __forceinline__ void wg_flush_planar(double2* slot, const f32x16 (&cr)[4][2],
+                                                const f32x16 (&ci)[4][2], int lane, bool first) {
+  constexpr int TQ = 64, NE = 128 * 64;
+  typedef double __attribute__((address_space(1)))* gdp;
+  double* pre = reinterpret_cast<double*>(slot);
+  double* pim = pre + NE;
+  int base = 4 * (lane >> 5) * TQ + (lane & 31);
+  asm volatile("" : "+v"(base));
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!diag_block_needed<DIAG>(i, j)) continue;
+      const int b0 = base + i * 32 * TQ + j * 32;
+      if (ATOM && !first) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int e = b0 + (8 * (r >> 2) + (r & 3)) * TQ;
+          __builtin_amdgcn_global_atomic_fadd_f64((gdp)(pre + e), static_cast<double>(cr[i][j][r]));
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int e = b0 + (8 * (r >> 2) + (r & 3)) * TQ;
+          __builtin_amdgcn_global_atomic_fadd_f64((gdp)(pim + e), static_cast<double>(ci[i][j][r]));
+        }
+        continue;
+      }
+      double o[16], q[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[r] = q[r] = 0.0;
+      if (!first) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int e = b0 + (8 * (r >> 2) + (r & 3)) * TQ;
+          o[r] = pre[e];
+          q[r] = pim[e];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int e = b0 + (8 * (r >> 2) + (r & 3)) * TQ;
+        pre[e] = static_cast<double>(cr[i][j][r]) + o[r];
+        pim[e] = static_cast<double>(ci[i][j][r]) + q[r];
+      }
+    }
+}
+
 // One unit (a tile, a pair range, up to four frequencies: wave w takes
 // frequency u.iw + w) from its ranges' stages into the wave's partial tile.
 // DIAG (0, or 1 / 2 for the tiles left / right of the diagonal) is fixed per
 // unit, so each kind has its own copy of the run loop and registers.
-template <bool LOLO, bool HINT, bool ATOM, int DIAG>
+template <bool LOLO, bool HINT, bool ATOM, bool PLANAR, int DIAG>
 __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const ProbDesc& pd,
                                         int tid, int wave, int lane, int g8, int l32,
                                         char (*lds)[kWgBuf], int& done) {
@@ -412,17 +466,23 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
       g0 += len;
       acc += len;
       if (acc >= fr) {
-        if (active) tall_flush<4, TQ, ATOM, DIAG>(part, cr, ci, 0, 0, lane, first);
+        if (active) {
+          if (PLANAR) wg_flush_planar<ATOM, DIAG>(part, cr, ci, lane, first);
+          else tall_flush<4, TQ, ATOM, DIAG>(part, cr, ci, 0, 0, lane, first);
+        }
         first = false;
         acc = 0;
         wg_zero(cr, ci);
       }
     }
   }
-  if (active && (first || acc > 0)) tall_flush<4, TQ, ATOM, DIAG>(part, cr, ci, 0, 0, lane, first);
+  if (active && (first || acc > 0)) {
+    if (PLANAR) wg_flush_planar<ATOM, DIAG>(part, cr, ci, lane, first);
+    else tall_flush<4, TQ, ATOM, DIAG>(part, cr, ci, 0, 0, lane, first);
+  }
 }
 
-template <bool LOLO, bool HINT, bool ATOM, bool SKIP>
+template <bool LOLO, bool HINT, bool ATOM, bool SKIP, bool PLANAR>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[3][kWgBuf];
   const int tid = threadIdx.x;
@@ -442,9 +502,9 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
     // tiles crossing the diagonal (TP = 2 TQ): their blocks above it are
     // left out with SKIP (the reduction never reads those entries)
     const int diag = !SKIP ? 0 : u.tq == 2 * u.tp ? 1 : u.tq == 2 * u.tp + 1 ? 2 : 0;
-    if (diag == 0) wg_unit<LOLO, HINT, ATOM, 0>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
-    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, 1>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
-    else wg_unit<LOLO, HINT, ATOM, 2>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
+    if (diag == 0) wg_unit<LOLO, HINT, ATOM, PLANAR, 0>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
+    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, PLANAR, 1>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
+    else wg_unit<LOLO, HINT, ATOM, PLANAR, 2>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
   }
   if (a.sync_slack > 0 && tid == 0)
     __hip_atomic_store(a.sync_prog + blockIdx.x, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -455,19 +515,22 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
 hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, int nwg,
                                      hipStream_t s) {
   // variant 0: compiler scheduling; 1: issue-order hints; 2: hints and
-  // atomic flushes; 3: as 2, leaving out the blocks above the diagonal
-#define CHI0_WG_LAUNCH(L, H, A, K) \
-  hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<L, H, A, K>), dim3(nwg), dim3(kNT), 0, s, a)
+  // atomic flushes; 3: as 2, leaving out the blocks above the diagonal; 4:
+  // as 3, partial tiles as real and imaginary planes
+#define CHI0_WG_LAUNCH(L, H, A, K, P) \
+  hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<L, H, A, K, P>), dim3(nwg), dim3(kNT), 0, s, a)
   if (lolo) {
-    if (variant == 0) CHI0_WG_LAUNCH(true, false, false, false);
-    else if (variant == 1) CHI0_WG_LAUNCH(true, true, false, false);
-    else if (variant == 2) CHI0_WG_LAUNCH(true, true, true, false);
-    else CHI0_WG_LAUNCH(true, true, true, true);
+    if (variant == 0) CHI0_WG_LAUNCH(true, false, false, false, false);
+    else if (variant == 1) CHI0_WG_LAUNCH(true, true, false, false, false);
+    else if (variant == 2) CHI0_WG_LAUNCH(true, true, true, false, false);
+    else if (variant == 3) CHI0_WG_LAUNCH(true, true, true, true, false);
+    else CHI0_WG_LAUNCH(true, true, true, true, true);
   } else {
-    if (variant == 0) CHI0_WG_LAUNCH(false, false, false, false);
-    else if (variant == 1) CHI0_WG_LAUNCH(false, true, false, false);
-    else if (variant == 2) CHI0_WG_LAUNCH(false, true, true, false);
-    else CHI0_WG_LAUNCH(false, true, true, true);
+    if (variant == 0) CHI0_WG_LAUNCH(false, false, false, false, false);
+    else if (variant == 1) CHI0_WG_LAUNCH(false, true, false, false, false);
+    else if (variant == 2) CHI0_WG_LAUNCH(false, true, true, false, false);
+    else if (variant == 3) CHI0_WG_LAUNCH(false, true, true, true, false);
+    else CHI0_WG_LAUNCH(false, true, true, true, true);
   }
 #undef CHI0_WG_LAUNCH
   return hipGetLastError();
@@ -476,7 +539,7 @@ hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, 
 int herk_bf16x3_wgroup_max_wg_per_cu() {
   int n = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, true, true, false>, kNT, 0);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, true, true, false, false>, kNT, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

@@ -1,11 +1,13 @@
 // Cross-block FP64 reduction of the partial tiles and Hermitian write of chi0.
 //
 // Every lower-triangle tile (tp >= tq) of every frequency owns a contiguous
-// run of FP64 partial slots (one per block range).  They are summed in slot
-// order, so the result does not depend on which workgroup produced which
-// slot.  chi0 = -S (Eq.(polfx) at i*omega carries the minus sign); the lower
-// triangle is written and mirrored with conjugation, and the imaginary part
-// of the diagonal is set to zero, so chi0 is exactly Hermitian.
+// run of FP64 partial slots (one per block range), complex interleaved or,
+// for kernels that write them so, as a real plane and an imaginary plane.
+// They are summed in slot order, so the result does not depend on which
+// workgroup produced which slot.  chi0 = -S (Eq.(polfx) at i*omega carries
+// the minus sign); the lower triangle is written and mirrored with
+// conjugation, and the imaginary part of the diagonal is set to zero, so
+// chi0 is exactly Hermitian.
 #include "common.h"
 #include "herk_common.h"
 
@@ -27,11 +29,20 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   if (J > I) return;  // upper triangle: mirrored from the lower half
   double re = 0.0, im = 0.0;
   const size_t slot = static_cast<size_t>(TP) * TQ;
-  const double2* src = a.partials + static_cast<size_t>(j.slot0) * slot + e;
-  for (int s = 0; s < j.nslot; ++s) {
-    const double2 v = src[static_cast<size_t>(s) * slot];
-    re += v.x;
-    im += v.y;
+  if (a.planar) {
+    // slot s: TP x TQ real parts, then TP x TQ imaginary parts
+    const double* src = reinterpret_cast<const double*>(a.partials + static_cast<size_t>(j.slot0) * slot) + e;
+    for (int s = 0; s < j.nslot; ++s) {
+      re += src[2 * static_cast<size_t>(s) * slot];
+      im += src[2 * static_cast<size_t>(s) * slot + slot];
+    }
+  } else {
+    const double2* src = a.partials + static_cast<size_t>(j.slot0) * slot + e;
+    for (int s = 0; s < j.nslot; ++s) {
+      const double2 v = src[static_cast<size_t>(s) * slot];
+      re += v.x;
+      im += v.y;
+    }
   }
   re = -re;
   im = -im;
@@ -65,7 +76,7 @@ int herk_default_tile(int kind) {
   switch (kind) {
     case HERK_FP64: return 3;
     case HERK_FP32: return 1;
-    case HERK_BF16X3: return 18;
+    case HERK_BF16X3: return 19;
   }
   return 0;
 }
