@@ -426,6 +426,18 @@ int chi0_tile_diag_skip(chi0_precision prec, int32_t tile);
  * restores it. */
 int chi0_set_flush(chi0_handle h, int32_t pairs);
 
+/* XCD lockstep of the BF16X3 frequency-group configurations that use it
+ * (the default among them): with units dealt round-robin, the workgroups on
+ * one XCD, which stream the same pair ranges, wait before each FP32 run
+ * while they are more than `stages` 32-pair stages ahead of the slowest of
+ * them, so their shared rows stay in the XCD's L2.  The wait is bounded
+ * (and a workgroup whose wait reaches the bound stops waiting for the rest
+ * of the launch); results do not depend on it.  stages: -1 the
+ * configuration's value (16), 0 off, > 0 the slack (at most 2^20); -2 makes
+ * every wait unmeetable, so each workgroup waits the full bound once and
+ * then runs without the lockstep (for tests of the bound). */
+int chi0_set_xcd_slack(chi0_handle h, int32_t stages);
+
 /* Autotuner: time every tile configuration of `prec` on the given problems
  * (their chi0 outputs are overwritten), keep the fastest as the handle's
  * default for `prec`, and return its index in *best (may be NULL).  Timings

@@ -123,6 +123,7 @@ def load() -> ctypes.CDLL:
         "chi0_tile_choice": (c_int, [c_int, POINTER(chi0_problem), c_int32, POINTER(c_int32)]),
         "chi0_tile_lists": (c_int, [c_int, c_int32]),
         "chi0_tile_diag_skip": (c_int, [c_int, c_int32]),
+        "chi0_set_xcd_slack": (c_int, [vp, c_int32]),
         "chi0_autotune": (c_int, [vp, POINTER(chi0_problem), c_int32, c_int, c_int, c_double,
                                   c_int32, POINTER(c_int32), POINTER(c_double), vp]),
         "chi0_plan_inspect": (c_int, [POINTER(chi0_problem), c_int32, c_int, c_int32, c_int32,
@@ -544,6 +545,10 @@ class Context:
 
     def set_tile(self, precision: str, tile: int) -> None:
         _check(self._lib.chi0_set_tile(self._h, PREC[precision], tile))
+
+    def set_xcd_slack(self, stages: int) -> None:
+        """XCD lockstep slack in stages (-1 default, 0 off, -2 unmeetable)."""
+        _check(self._lib.chi0_set_xcd_slack(self._h, int(stages)))
 
     def set_flush(self, pairs: int) -> None:
         _check(self._lib.chi0_set_flush(self._h, int(pairs)))

@@ -131,6 +131,7 @@ struct chi0_ctx {
   int tile_tuned[3] = {-1, -1, -1};
   int tile_last[3] = {-1, -1, -1};   // configuration of the last rank-K launch
   int flush_override = 0;
+  int xcd_slack = -1;   // -1: the configuration's; 0: off; > 0: stages; -2: unmeetable (tests)
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
   std::vector<hipEvent_t> event_pool;
@@ -936,7 +937,8 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
   ha.flags = static_cast<int32_t>(flags);
   ha.sync_prog = nullptr;
   ha.sync_slack = 0;
-  if (pl->tc.xcd_sync > 0 && pl->round_robin) {
+  const int slack = h->xcd_slack == -1 ? pl->tc.xcd_sync : h->xcd_slack;
+  if (pl->tc.xcd_sync > 0 && slack != 0 && pl->round_robin) {
     // one progress word per workgroup; a fresh buffer starts at 0 (the
     // kernel leaves INT_MAX in each word when its workgroup finishes)
     const size_t bytes = static_cast<size_t>(pl->nwg) * sizeof(int32_t);
@@ -945,7 +947,7 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
       HIP_TRY(hipMemset(h->sync_prog.p, 0, h->sync_prog.n));
     }
     ha.sync_prog = static_cast<int32_t*>(h->sync_prog.p);
-    ha.sync_slack = pl->tc.xcd_sync;
+    ha.sync_slack = slack == -2 ? INT32_MIN / 2 : slack;
   }
   ReduceArgs ra;
   ra.jobs = static_cast<const TileJob*>(pl->d_jobs.p);
@@ -958,10 +960,11 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
 
   const bool use_graph = (flags & CHI0_USE_GRAPH) && !h->profiling && !hk;
   debug_log("rank-K launch: kind %d tile %d (%d x %d, %d threads), %d problem(s), %d units on %d "
-       "workgroups, %d tile jobs, partials %zu B, weights %zu B, pre-split %zu B%s%s",
+       "workgroups, %d tile jobs, partials %zu B, weights %zu B, pre-split %zu B%s%s%s",
        kind, pl->tile_idx, TP, TQ, pl->tc.threads, nprob, pl->nunits, pl->nwg, pl->njobs,
        static_cast<size_t>(pl->nslots) * TP * TQ * sizeof(double2), hk ? static_cast<size_t>(0) : wbytes,
-       zbytes, use_graph ? ", graph" : "", hk ? ", gathered rows" : "");
+       zbytes, use_graph ? ", graph" : "", hk ? ", gathered rows" : "",
+       ha.sync_prog ? ", XCD lockstep" : "");
   if (use_graph) {
     // delta_min and the LO*LO flag are kernel arguments: the cached graph is
     // only reused with the same values, so they join the key
@@ -2311,6 +2314,14 @@ int chi0_set_flush(chi0_handle h, int32_t pairs) {
   if (pairs != 0 && (pairs < 16 || pairs > 65536 || pairs % 16 != 0))
     return fail(CHI0_EINVAL, "flush length %d must be 0 or a multiple of 16 in [16, 65536]", pairs);
   h->flush_override = pairs;
+  return CHI0_OK;
+}
+
+int chi0_set_xcd_slack(chi0_handle h, int32_t stages) {
+  if (!h) return fail(CHI0_EINVAL, "handle is NULL");
+  if (stages < -2 || stages > 1 << 20)
+    return fail(CHI0_EINVAL, "XCD lockstep slack %d must be -2, -1 or in [0, 2^20]", stages);
+  h->xcd_slack = stages;
   return CHI0_OK;
 }
 

@@ -82,11 +82,12 @@ struct HerkArgs {
   const BlockDesc* blocks;
   const ProbDesc* probs;
   double2* partials;          // [nslots][T][T] complex128
-  int32_t* sync_prog;         // [nwg] stages done per workgroup (sync_slack > 0)
+  int32_t* sync_prog;         // [nwg] stages done per workgroup (null: no lockstep)
   double delta_min;
   int32_t flags;
-  int32_t sync_slack;         // > 0: a workgroup more than this many stages ahead
-                              // of the slowest one on its XCD waits (bounded)
+  int32_t sync_slack;         // with sync_prog: a workgroup more than this many
+                              // stages ahead of the slowest one on its XCD waits
+                              // (bounded)
 };
 
 struct ReduceArgs {

@@ -312,13 +312,16 @@ __device__ __forceinline__ void wg_stages(const WgRun& r, const WgLane& o, int n
 // that is more than sync_slack stages ahead of the slowest peer on the XCD,
 // sleeps and polls again, at most kSyncPolls times (the wait always ends;
 // it only keeps the peers, which stream the same pair ranges in the same
-// rounds, close enough to share the XCD's L2).  A finished workgroup
-// publishes INT_MAX, so it never holds the others, in this launch or the
-// next.  The other waves meet wave 0 at the run's first barrier.
+// rounds, close enough to share the XCD's L2).  A wait that reaches the
+// limit turns the lockstep off for the rest of the launch in this workgroup
+// (returns false), so a peer that never catches up costs one bounded wait.
+// A finished workgroup publishes INT_MAX, so it never holds the others, in
+// this launch or the next.  The other waves meet wave 0 at the run's first
+// barrier.
 constexpr int kSyncPolls = 2048;
 
-__device__ __forceinline__ void wg_sync(const HerkArgs& a, int done, int wave, int lane) {
-  if (wave != 0) return;
+__device__ __forceinline__ bool wg_sync(const HerkArgs& a, int done, int wave, int lane) {
+  if (wave != 0) return true;
   int32_t* prog = a.sync_prog;
   if (lane == 0) __hip_atomic_store(prog + blockIdx.x, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int peer = static_cast<int>(blockIdx.x & 7u) + 8 * lane;
@@ -329,9 +332,10 @@ __device__ __forceinline__ void wg_sync(const HerkArgs& a, int done, int wave, i
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
     v = __builtin_amdgcn_readfirstlane(v);
-    if (done - v <= a.sync_slack) break;
+    if (done - v <= a.sync_slack) return true;
     __builtin_amdgcn_s_sleep(8);
   }
+  return false;
 }
 
 // The wave's 128 x 64 accumulators into its partial tile stored as two
@@ -395,7 +399,7 @@ __device__ __forceinline__ void wg_flush_planar(double2* slot, const f32x16 (&cr
 template <bool LOLO, bool HINT, bool ATOM, bool PLANAR, int DIAG>
 __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const ProbDesc& pd,
                                         int tid, int wave, int lane, int g8, int l32,
-                                        char (*lds)[kWgBuf], int& done) {
+                                        char (*lds)[kWgBuf], int& done, bool& sync_on) {
   constexpr int TP = 128, TQ = 64;
   const int npb = pd.npb;
   const bool active = wave < u.nw;
@@ -460,7 +464,7 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
       r.w = (gcptr)(wbase + pbase + q0);
       r.wbytes = wg_cap((wend - pbase - q0) * 4);
       const int nst = (nv + kWgPairs - 1) / kWgPairs;
-      if (a.sync_slack > 0) wg_sync(a, done, wave, lane);
+      if (a.sync_prog != nullptr && sync_on) sync_on = wg_sync(a, done, wave, lane);
       wg_stages<LOLO, HINT, DIAG>(r, o, nst, wave, lane, g8, l32, lds, cr, ci);
       done += nst;
       g0 += len;
@@ -495,18 +499,19 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
   // are uniform: every branch on them stays a scalar branch)
   const int beg = ld_const(a.wg_offsets, static_cast<int>(blockIdx.x));
   const int end = ld_const(a.wg_offsets, static_cast<int>(blockIdx.x) + 1);
-  int done = 0;   // stages of this workgroup's runs so far (XCD lockstep)
+  int done = 0;          // stages of this workgroup's runs so far (XCD lockstep)
+  bool sync_on = true;    // lockstep still on for this workgroup
   for (int ui = beg; ui < end; ++ui) {
     const Unit u = ld_unit(a.units, ld_const(a.wg_units, ui));
     const ProbDesc pd = ld_prob(a.probs, u.prob);
     // tiles crossing the diagonal (TP = 2 TQ): their blocks above it are
     // left out with SKIP (the reduction never reads those entries)
     const int diag = !SKIP ? 0 : u.tq == 2 * u.tp ? 1 : u.tq == 2 * u.tp + 1 ? 2 : 0;
-    if (diag == 0) wg_unit<LOLO, HINT, ATOM, PLANAR, 0>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
-    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, PLANAR, 1>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
-    else wg_unit<LOLO, HINT, ATOM, PLANAR, 2>(a, u, pd, tid, wave, lane, g8, l32, lds, done);
+    if (diag == 0) wg_unit<LOLO, HINT, ATOM, PLANAR, 0>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
+    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, PLANAR, 1>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
+    else wg_unit<LOLO, HINT, ATOM, PLANAR, 2>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
   }
-  if (a.sync_slack > 0 && tid == 0)
+  if (a.sync_prog != nullptr && tid == 0)
     __hip_atomic_store(a.sync_prog + blockIdx.x, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

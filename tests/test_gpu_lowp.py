@@ -3,6 +3,7 @@ FP32 runs flushed into FP64) against the FP64 oracle at 1e-6 relative
 Frobenius error per frequency, and against a numpy model of the split
 arithmetic (which isolates kernel mistakes from the split's own error)."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -149,6 +150,32 @@ def test_every_tile_configuration(ctx, path):
         outs.append(prob.chi0.clone())
     ctx.set_tile(path, -1)
     _say("  bitwise equal to tile 0: " + str([bool(torch.equal(outs[0], o)) for o in outs]))
+
+
+def test_xcd_lockstep_bounded_and_neutral(ctx):
+    """The XCD lockstep of the default BF16x3 kernel changes timing only:
+    its output is bitwise the same with the lockstep off, at its default
+    slack, at a slack of one stage, and with every wait made unmeetable
+    (each workgroup then waits the full bound once and runs on without the
+    lockstep, so the launch still ends within a bounded time)."""
+    wl = workload(2, npb=256, nk=4)          # one problem of equal blocks: round-robin units
+    prob, _, _ = device_problem(wl)
+    ctx.set_tile("bf16x3", ctx.get_tile("bf16x3"))
+    outs, secs = {}, {}
+    for slack in (-1, 0, 1, -2, -1):
+        ctx.set_xcd_slack(slack)
+        t0 = time.perf_counter()
+        ctx.chi0_accumulate([prob], precision="bf16x3", delta_min=wl.delta_min)
+        ctx.sync()
+        secs[slack] = time.perf_counter() - t0
+        outs.setdefault(slack, prob.chi0.clone())
+        assert torch.equal(prob.chi0, outs[-1]), slack
+    ctx.set_xcd_slack(-1)
+    ctx.set_tile("bf16x3", -1)
+    _say("lockstep slack -> seconds: " + ", ".join(f"{k}: {v:.3f}" for k, v in secs.items()))
+    assert secs[-2] < 30.0
+    with pytest.raises(Exception):
+        ctx.set_xcd_slack(-3)
 
 
 @pytest.mark.parametrize("npb,omega", [(131, (0.0, 0.1, 0.5, 2.0, 8.0)),     # odd npb, 5 frequencies
