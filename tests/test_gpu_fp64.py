@@ -49,7 +49,7 @@ def _run(ctx, wl, prec="fp64", ztype=None, **kw):
 
 
 @pytest.mark.parametrize("cfg,over", [
-    (0, {}),                                                     # configs[0], full size
+    (0, {}),                                                     # npb 64 workload, full size
     (1, dict(npb=200, nk=3, nocc=7, nunocc=45)),                 # ragged npb, several tiles
     (3, dict(nq=1, npb=130, nk=5, ztype="c128")),                # uneven blocks
     (4, dict(npb=96, nk=3, ztype="c128")),                       # spins, intraband cut

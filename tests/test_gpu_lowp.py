@@ -47,9 +47,9 @@ def _model(wl, path, lolo=False):
 # (K / npb = 1500 for npb = 2048).  FP32 has no such floor.
 CASES = {
     "bf16x3": [
-        (0, dict(ztype="c64", nk=64)),                            # configs[0] shape, 64 k-points
+        (0, dict(ztype="c64", nk=64)),                            # npb 64 shape, 64 k-points
         (1, dict(npb=200, nk=4, ztype="c64")),                    # ragged npb, several tiles
-        (2, dict(npb=160, nk=2, nocc=40, nunocc=500)),            # configs[2] generator
+        (2, dict(npb=160, nk=2, nocc=40, nunocc=500)),            # npb 2048 workload generator
         (3, dict(nq=1, npb=130, nk=16)),                          # uneven blocks
         (4, dict(npb=96, nk=4)),                                  # spins, intraband cut
     ],
