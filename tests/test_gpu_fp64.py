@@ -260,7 +260,7 @@ def test_dielectric_gj_sizes_pivoting(ctx, n):
         assert res <= 64 * n * kappa * u
 
 
-@pytest.mark.parametrize("n", [1, 31, 32, 33, 100, 130])
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 63, 64, 65, 100, 129, 130, 200])
 def test_dielectric_hpd_sizes(ctx, n):
     """Hermitian positive definite inverse (symmetric sweeps) at block-
     ragged sizes, against the oracle's Cholesky inverse."""
