@@ -393,9 +393,10 @@ const char* chi0_last_error(void);
  * built-in default configuration.  With none fixed or tuned, calls that do
  * not gather rows choose per call by a cost model of the padded tile area
  * (rows x padded lower-triangle area x frequencies x a per-configuration
- * cost; BF16X3 and FP64 take their large default tiles for large npb and
- * smaller square tiles when npb is a few hundred, FP32 128^2 tiles for large
- * npb and 64^2 otherwise); chi0_tile_choice() returns that model's choice for
+ * cost; BF16X3 and FP32 take their frequency-group default for several
+ * frequencies and small square tiles for one frequency at small npb, FP64
+ * its large default tiles for large npb and smaller square ones when npb is
+ * a few hundred); chi0_tile_choice() returns that model's choice for
  * a set of problems (host data only: nocc, nunocc, npb, nomega; no handle,
  * no device), and chi0_last_tile() reports the configuration of the handle's
  * last rank-K launch for a precision (-1 before the first). */

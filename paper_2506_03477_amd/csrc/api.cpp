@@ -748,9 +748,9 @@ struct GatherHook {
 // npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (19) 1.0,
 // tall 256 x 128 (7) 1.20, 128^2 with two workgroups per CU (4) 1.34, 64^2
 // (2) 2.04, the pre-split pass 173 per row and column; FP64 128^2 with 8
-// waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42; FP32 64^2 (1) 1.0, 128^2 (0)
-// 0.914.  Another tile replaces the default only when modeled at least 5%
-// faster.
+// waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42; FP32 frequency groups on
+// 128 x 64 tiles (2) 1.0, 64^2 (1) 1.27, 128^2 (0) 1.16.  Another tile
+// replaces the default only when modeled at least 5% faster.
 int tile_for(int kind, const chi0_problem* probs, int nprob) {
   struct Cand {
     int idx;
@@ -758,10 +758,10 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
   };
   static const Cand bf16[] = {{19, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
   static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
-  static const Cand fp32[] = {{1, 1.0}, {0, 0.914}};
+  static const Cand fp32[] = {{2, 1.0}, {1, 1.27}, {0, 1.16}};
   const int ndef = herk_default_tile(kind);
   const Cand* cands = kind == HERK_BF16X3 ? bf16 : kind == HERK_FP64 ? fp64 : fp32;
-  const int ncand = kind == HERK_BF16X3 ? 4 : kind == HERK_FP64 ? 3 : 2;
+  const int ncand = kind == HERK_BF16X3 ? 4 : 3;
   double def_time = -1.0, best_time = -1.0;
   int best = ndef;
   for (int ci = 0; ci < ncand; ++ci) {

@@ -146,5 +146,8 @@ int herk_bf16x3_direct_max_wg_per_cu();
 hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, int nwg,
                                      hipStream_t s);
 int herk_bf16x3_wgroup_max_wg_per_cu();
+// FP32 contraction on the same frequency-group units.
+hipError_t herk_fp32_wgroup_launch(const HerkArgs& a, int nwg, hipStream_t s);
+int herk_fp32_wgroup_max_wg_per_cu();
 
 }  // namespace chi0

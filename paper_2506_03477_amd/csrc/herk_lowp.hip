@@ -922,6 +922,7 @@ static const TileConfig kBf16Tiles[] = {
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
     {64, kKC, 4096, kNT, 64},
+    {128, kKC, 4096, kNT, 64, 0, 1, 4, 1, 16, 1},   // 2: frequency groups on 128 x 64 tiles
 };
 
 int herk_bf16x3_tile_count() { return sizeof(kBf16Tiles) / sizeof(kBf16Tiles[0]); }
@@ -1046,6 +1047,7 @@ int herk_fp32_tile_count() { return sizeof(kFp32Tiles) / sizeof(kFp32Tiles[0]); 
 TileConfig herk_fp32_tile(int idx) { return kFp32Tiles[idx]; }
 hipError_t herk_fp32_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) {
   if (idx < 0 || idx >= herk_fp32_tile_count()) return hipErrorInvalidValue;
+  if (idx == 2) return herk_fp32_wgroup_launch(a, nwg, s);
   if (kFp32Tiles[idx].tile == 128)
     hipLaunchKernelGGL(herk_fp32_kernel<128>, dim3(nwg), dim3(kNT), 0, s, a);
   else
@@ -1053,6 +1055,7 @@ hipError_t herk_fp32_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s) 
   return hipGetLastError();
 }
 int herk_fp32_max_wg_per_cu(int idx) {
+  if (idx == 2) return herk_fp32_wgroup_max_wg_per_cu();
   int n = 0;
   hipError_t e = kFp32Tiles[idx].tile == 128
       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp32_kernel<128>, kNT, 0)

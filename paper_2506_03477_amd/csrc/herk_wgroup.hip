@@ -76,6 +76,7 @@ struct WgRun {
 struct WgLane {
   uint32_t p[4];
   uint32_t q[2];      // m even / odd (4 (m / 2) rows are added per load)
+  uint32_t pf;        // FP32 path: dword t of a pair's 128 raw P values (row t / 2, part t % 2)
 };
 
 // Part PART (0..3) of the loads of stage st of the run into LDS buffer buf
@@ -307,6 +308,94 @@ __device__ __forceinline__ void wg_stages(const WgRun& r, const WgLane& o, int n
   __syncthreads();
 }
 
+// FP32 path.  A 32-pair stage in LDS holds the raw complex64 Z of the tile's
+// 128 P rows as [pair][row] (32 KB, where the BF16x3 stage holds the
+// pre-split words), the 64 Q columns as [pair][column] and the weights, as
+// the BF16x3 stage does; stage s + 1 is loaded while stage s is computed
+// (two buffers: a buffer is refilled only after the barrier that ends the
+// stage that read it).  Per pair and wave: the A operand of row block i is
+// lane l -> (row 32 i + l % 32, re if l < 32 else im), the B operand of
+// column block j is c (re, im) of column 32 j + l % 32 and the rotated one
+// c (im, -re), so one v_mfma_f32_32x32x2f32 gives Re and one Im of
+// conj(Z_P) c Z_Q (the contraction index runs over re and im).
+__device__ __forceinline__ void f32_dma(const WgRun& r, int st, const WgLane& o, int wave, int lane,
+                                        char* buf) {
+  const int32_t zo = st * kWgPairs * r.row;
+  const __amdgpu_buffer_rsrc_t z = wg_rsrc(r.z + zo, r.zbytes - zo);
+  // Running offsets, opaque to the compiler, so that the 48 offsets are not
+  // all kept in registers across the stage (their reloads would wait for
+  // the loads in flight).  P: pair m, dword t of its 128 rows.  Q: dword
+  // t + 256 m is pair t / 128 + 2 m, column (t % 128) / 2, part t % 2.
+  uint32_t off = o.pf;
+#pragma unroll
+  for (int m = 0; m < kWgPairs; ++m) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(z, (lds_ptr)(buf + (256 * m + 64 * wave) * 4), 4, off,
+                                             0, 0, 0);
+    off += static_cast<uint32_t>(r.row);
+    asm volatile("" : "+v"(off));
+  }
+  off = o.q[0];
+#pragma unroll
+  for (int m = 0; m < kWgPairs / 2; ++m) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        z, (lds_ptr)(buf + kWgPBytes + (64 * wave + 256 * m) * 4), 4, off, 0, 0, 0);
+    off += 2u * static_cast<uint32_t>(r.row);
+    asm volatile("" : "+v"(off));
+  }
+  const int32_t wo = st * kWgPairs * 4;
+  const __amdgpu_buffer_rsrc_t w = wg_rsrc(r.w + wo, r.wbytes - wo);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(w, (lds_ptr)(buf + kWgPBytes + kWgQBytes + wave * 256),
+                                           4, static_cast<uint32_t>(lane) * 4u, 0, 0, 0);
+}
+
+template <int DIAG>
+__device__ __forceinline__ void f32_pairs(const char* buf, int wave, int lane, f32x16 (&cr)[4][2],
+                                          f32x16 (&ci)[4][2]) {
+  const int l32 = lane & 31, h = lane >> 5;
+  const float sgn = h ? -1.0f : 1.0f;
+  const float* P = reinterpret_cast<const float*>(buf);
+  const float* Q = reinterpret_cast<const float*>(buf + kWgPBytes);
+  const float* W = reinterpret_cast<const float*>(buf + kWgPBytes + kWgQBytes + wave * 256);
+#pragma unroll 4
+  for (int p = 0; p < kWgPairs; ++p) {
+    const float c = W[p];
+    float av[4], b[2], bp[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      av[i] = (diag_block_needed<DIAG>(i, 0) || diag_block_needed<DIAG>(i, 1))
+                  ? P[(p * 128 + 32 * i + l32) * 2 + h] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      b[j] = Q[(p * 64 + 32 * j + l32) * 2 + h] * c;
+      bp[j] = Q[(p * 64 + 32 * j + l32) * 2 + (1 - h)] * (c * sgn);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (!diag_block_needed<DIAG>(i, j)) continue;
+        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], b[j], cr[i][j], 0, 0, 0);
+        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bp[j], ci[i][j], 0, 0, 0);
+      }
+  }
+}
+
+template <int DIAG>
+__device__ __forceinline__ void f32_stages(const WgRun& r, const WgLane& o, int nst, int wave,
+                                           int lane, char (*lds)[kWgBuf], f32x16 (&cr)[4][2],
+                                           f32x16 (&ci)[4][2]) {
+  f32_dma(r, 0, o, wave, lane, lds[0]);
+  __builtin_amdgcn_s_waitcnt(kVmcnt0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int b = st & 1;
+    if (st + 1 < nst) f32_dma(r, st + 1, o, wave, lane, lds[b ^ 1]);
+    f32_pairs<DIAG>(lds[b], wave, lane, cr, ci);
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);   // this wave's loads of stage st + 1
+    __syncthreads();
+  }
+}
+
 // Lockstep of the workgroups of one XCD (workgroup b runs on XCD b % 8):
 // before a run, wave 0 publishes the stages its workgroup has done and, while
 // that is more than sync_slack stages ahead of the slowest peer on the XCD,
@@ -396,7 +485,7 @@ __device__ __forceinline__ void wg_flush_planar(double2* slot, const f32x16 (&cr
 // frequency u.iw + w) from its ranges' stages into the wave's partial tile.
 // DIAG (0, or 1 / 2 for the tiles left / right of the diagonal) is fixed per
 // unit, so each kind has its own copy of the run loop and registers.
-template <bool LOLO, bool HINT, bool ATOM, bool PLANAR, int DIAG>
+template <bool LOLO, bool HINT, bool ATOM, bool PLANAR, int DIAG, bool F32 = false>
 __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const ProbDesc& pd,
                                         int tid, int wave, int lane, int g8, int l32,
                                         char (*lds)[kWgBuf], int& done, bool& sync_on) {
@@ -420,6 +509,10 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
     const int col = c0 + ((d & 127) >> 1);
     o.q[h2] = static_cast<uint32_t>(d >> 7) * static_cast<uint32_t>(row) +
               static_cast<uint32_t>(col < npb ? col : 0) * 8u + static_cast<uint32_t>(d & 1) * 4u;
+  }
+  {
+    const int prow = r0 + (tid >> 1);
+    o.pf = static_cast<uint32_t>(prow < npb ? prow : 0) * 8u + static_cast<uint32_t>(tid & 1) * 4u;
   }
   // FP32 runs of at most the problem's flush length (a multiple of 16
   // pairs), made of granules of R pairs: whole 32-pair stages when the
@@ -465,7 +558,8 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
       r.wbytes = wg_cap((wend - pbase - q0) * 4);
       const int nst = (nv + kWgPairs - 1) / kWgPairs;
       if (a.sync_prog != nullptr && sync_on) sync_on = wg_sync(a, done, wave, lane);
-      wg_stages<LOLO, HINT, DIAG>(r, o, nst, wave, lane, g8, l32, lds, cr, ci);
+      if constexpr (F32) f32_stages<DIAG>(r, o, nst, wave, lane, lds, cr, ci);
+      else wg_stages<LOLO, HINT, DIAG>(r, o, nst, wave, lane, g8, l32, lds, cr, ci);
       done += nst;
       g0 += len;
       acc += len;
@@ -486,9 +580,8 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
   }
 }
 
-template <bool LOLO, bool HINT, bool ATOM, bool SKIP, bool PLANAR>
-__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
-  __shared__ __attribute__((aligned(16))) char lds[3][kWgBuf];
+template <bool LOLO, bool HINT, bool ATOM, bool SKIP, bool PLANAR, bool F32>
+__device__ __forceinline__ void wg_body(const HerkArgs& a, char (*lds)[kWgBuf]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -507,12 +600,25 @@ __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) 
     // tiles crossing the diagonal (TP = 2 TQ): their blocks above it are
     // left out with SKIP (the reduction never reads those entries)
     const int diag = !SKIP ? 0 : u.tq == 2 * u.tp ? 1 : u.tq == 2 * u.tp + 1 ? 2 : 0;
-    if (diag == 0) wg_unit<LOLO, HINT, ATOM, PLANAR, 0>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
-    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, PLANAR, 1>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
-    else wg_unit<LOLO, HINT, ATOM, PLANAR, 2>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
+    if (diag == 0) wg_unit<LOLO, HINT, ATOM, PLANAR, 0, F32>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
+    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, PLANAR, 1, F32>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
+    else wg_unit<LOLO, HINT, ATOM, PLANAR, 2, F32>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
   }
   if (a.sync_prog != nullptr && tid == 0)
     __hip_atomic_store(a.sync_prog + blockIdx.x, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LOLO, bool HINT, bool ATOM, bool SKIP, bool PLANAR>
+__global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
+  __shared__ __attribute__((aligned(16))) char lds[3][kWgBuf];
+  wg_body<LOLO, HINT, ATOM, SKIP, PLANAR, false>(a, lds);
+}
+
+// FP32 contraction on the same units (frequency groups, diagonal blocks
+// left out, XCD lockstep, planar partial tiles, atomic flushes).
+__global__ __launch_bounds__(kNT, 1) void herk_fp32_wgroup_kernel(HerkArgs a) {
+  __shared__ __attribute__((aligned(16))) char lds[2][kWgBuf];
+  wg_body<false, false, true, true, true, true>(a, lds);
 }
 
 }  // namespace
@@ -539,6 +645,17 @@ hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, 
   }
 #undef CHI0_WG_LAUNCH
   return hipGetLastError();
+}
+
+hipError_t herk_fp32_wgroup_launch(const HerkArgs& a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(herk_fp32_wgroup_kernel, dim3(nwg), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+int herk_fp32_wgroup_max_wg_per_cu() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_fp32_wgroup_kernel, kNT, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
 }
 
 int herk_bf16x3_wgroup_max_wg_per_cu() {

@@ -75,7 +75,7 @@ hipError_t reduce_launch(const ReduceArgs& a, int njobs, hipStream_t s) {
 int herk_default_tile(int kind) {
   switch (kind) {
     case HERK_FP64: return 3;
-    case HERK_FP32: return 1;
+    case HERK_FP32: return 2;
     case HERK_BF16X3: return 19;
   }
   return 0;
