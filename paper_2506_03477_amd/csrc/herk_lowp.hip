@@ -28,6 +28,12 @@
 // Each workgroup adds its FP32 accumulators into its FP64 partial tile in
 // global memory every `flush` pairs (per problem) and at the end of the unit,
 // so no FP32 sum runs over more than `flush` pairs.
+//
+// The default BF16x3 and FP32 configurations are the frequency-group
+// kernels of herk_wgroup.hip (128 x 64 tiles, four frequencies per
+// workgroup); the register-direct BF16x3 kernels are in herk_direct.hip.
+// This file holds the tile tables of both paths and dispatches every
+// configuration.
 #include "bf16_tall.h"
 #include "common.h"
 #include "herk_common.h"

@@ -1,4 +1,6 @@
-// BF16x3 weighted Hermitian rank-K update on frequency-group units.
+// BF16x3 (and FP32) weighted Hermitian rank-K update on frequency-group
+// units.  The FP32 form, further down, shares the units, runs, lockstep and
+// flushes and replaces the split stage (see "FP32 path").
 //
 // Same contraction as the other rank-K kernels (S[P][Q] = sum_pairs
 // conj(Z[pair][P]) * (c * Z[pair][Q]) on one 128 x 64 lower tile, chi0 = -S,
