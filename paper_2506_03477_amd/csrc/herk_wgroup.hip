@@ -350,6 +350,48 @@ __device__ __forceinline__ void f32_dma(const WgRun& r, int st, const WgLane& o,
                                            4, static_cast<uint32_t>(lane) * 4u, 0, 0, 0);
 }
 
+// One pair's operands as read from LDS (weight applied later).
+struct F32Frag {
+  float a[4];    // A operands of the row blocks
+  float q[2];    // (re or im) of column block j, the B operand before scaling
+  float qr[2];   // the other part, for the rotated B operand
+};
+
+template <int DIAG>
+__device__ __forceinline__ void f32_read(const float* P, const float* Q, int p, int l32, int h,
+                                         F32Frag& f) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    f.a[i] = (diag_block_needed<DIAG>(i, 0) || diag_block_needed<DIAG>(i, 1))
+                 ? P[(p * 128 + 32 * i + l32) * 2 + h] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    f.q[j] = Q[(p * 64 + 32 * j + l32) * 2 + h];
+    f.qr[j] = Q[(p * 64 + 32 * j + l32) * 2 + (1 - h)];
+  }
+}
+
+template <int DIAG>
+__device__ __forceinline__ void f32_mfma(const F32Frag& f, float c, float cs, f32x16 (&cr)[4][2],
+                                         f32x16 (&ci)[4][2]) {
+  float b[2], bp[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    b[j] = f.q[j] * c;
+    bp[j] = f.qr[j] * cs;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!diag_block_needed<DIAG>(i, j)) continue;
+      cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[i], b[j], cr[i][j], 0, 0, 0);
+      ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[i], bp[j], ci[i][j], 0, 0, 0);
+    }
+}
+
+// The 32 pairs of a stage, software-pipelined: the operands of pair p + 1
+// are read from LDS while the MFMAs of pair p issue.
 template <int DIAG>
 __device__ __forceinline__ void f32_pairs(const char* buf, int wave, int lane, f32x16 (&cr)[4][2],
                                           f32x16 (&ci)[4][2]) {
@@ -358,27 +400,15 @@ __device__ __forceinline__ void f32_pairs(const char* buf, int wave, int lane, f
   const float* P = reinterpret_cast<const float*>(buf);
   const float* Q = reinterpret_cast<const float*>(buf + kWgPBytes);
   const float* W = reinterpret_cast<const float*>(buf + kWgPBytes + kWgQBytes + wave * 256);
-#pragma unroll 4
-  for (int p = 0; p < kWgPairs; ++p) {
-    const float c = W[p];
-    float av[4], b[2], bp[2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      av[i] = (diag_block_needed<DIAG>(i, 0) || diag_block_needed<DIAG>(i, 1))
-                  ? P[(p * 128 + 32 * i + l32) * 2 + h] : 0.0f;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      b[j] = Q[(p * 64 + 32 * j + l32) * 2 + h] * c;
-      bp[j] = Q[(p * 64 + 32 * j + l32) * 2 + (1 - h)] * (c * sgn);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (!diag_block_needed<DIAG>(i, j)) continue;
-        cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], b[j], cr[i][j], 0, 0, 0);
-        ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bp[j], ci[i][j], 0, 0, 0);
-      }
+  F32Frag f0, f1;
+  f32_read<DIAG>(P, Q, 0, l32, h, f0);
+#pragma unroll 2
+  for (int p = 0; p < kWgPairs; p += 2) {
+    const float c0 = W[p], c1 = W[p + 1];
+    f32_read<DIAG>(P, Q, p + 1, l32, h, f1);
+    f32_mfma<DIAG>(f0, c0, c0 * sgn, cr, ci);
+    if (p + 2 < kWgPairs) f32_read<DIAG>(P, Q, p + 2, l32, h, f0);
+    f32_mfma<DIAG>(f1, c1, c1 * sgn, cr, ci);
   }
 }
 
