@@ -215,3 +215,33 @@ def test_frequency_group_tile(ctx, npb, omega):
     # arithmetic
     for t in (14, 15, 16, 17, 18, 19):
         assert np.array_equal(got[t], got[grp]), t
+
+
+@pytest.mark.parametrize("npb,omega", [(131, (0.0, 0.1, 0.5, 2.0, 8.0)),     # odd npb, 5 frequencies
+                                       (256, (0.3, 3.0)),                     # group of two
+                                       (200, tuple(np.geomspace(0.01, 100.0, 9)))])
+def test_fp32_frequency_group_tile(ctx, npb, omega):
+    """The FP32 frequency-group kernel on partial frequency groups, odd npb
+    and several tiles: against the oracle and the exact-product model, and
+    close to the 64^2 FP32 kernel (the FP32 sums differ in order only)."""
+    wl = workload(3, nq=1, npb=npb, nk=16, omega=omega)
+    ref = oracle_chi0(wl)
+    mod = _model(wl, "fp32")
+    prob, _, _ = device_problem(wl)
+    grp = 2                                   # the FP32 frequency-group configuration
+    info = ctx.tile_info("fp32", grp)
+    assert (info["tile_p"], info["tile_q"]) == (128, 64) and ctx.tile_diag_skip("fp32", grp)
+    got = {}
+    for tile in (grp, 1):
+        ctx.set_tile("fp32", tile)
+        ctx.chi0_accumulate([prob], precision="fp32")
+        ctx.sync()
+        got[tile] = prob.chi0.cpu().numpy()
+        assert_hermitian_exact(prob.chi0)
+    ctx.set_tile("fp32", -1)
+    e, em = rel_fro(got[grp], ref), rel_fro(got[grp], mod)
+    _say(f"fp32 frequency groups npb {npb}, {len(omega)} omega: vs oracle {e.max():.3e}, "
+         f"vs exact-product model {em.max():.3e}, vs tile 1 {rel_fro(got[grp], got[1]).max():.3e}")
+    assert np.all(e <= TOL), e
+    assert np.all(em <= 3e-7), em
+    assert np.all(rel_fro(got[grp], got[1]) <= 3e-7)
