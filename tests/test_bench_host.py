@@ -94,11 +94,16 @@ def test_committed_traffic_files_well_formed():
     (100.0, 0.0, 1000, False, 0.0),    # one state already exceeds the target
     (0.04, 0.0, 200, True, 2.5),       # a fixed cost per call dominates small samples
     (0.7, 0.0, 1000, False, 6.0),
+    (0.2, -1.0, 200, True, 0.0),       # the probe itself slowed (to 3 s) by noise
 ])
 def test_size_sample(per_state, warm, nmax, tuple_out, fixed):
     calls = []
 
     def run(n):
+        if warm < 0:                   # noise on the first two calls
+            t = (3.0 if len(calls) < 2 else 0.0) + fixed + per_state * n
+            calls.append(n)
+            return (t, 7 * n) if tuple_out else t
         t = (warm if not calls else 0.0) + fixed + per_state * n
         calls.append(n)
         return (t, 7 * n) if tuple_out else t
