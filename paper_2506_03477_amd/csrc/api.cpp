@@ -745,7 +745,7 @@ struct GatherHook {
 // frequency-group kernel, the frequencies rounded up to whole groups) x a
 // per-kernel cost, plus the pre-split pass (rows x npb) of kernels that read
 // it.  Costs relative to the built-in default, fitted to MI355X timings at
-// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (19) 1.0,
+// npb 287, 384 and 2048: BF16x3 frequency groups on 128 x 64 tiles (20) 1.0,
 // tall 256 x 128 (7) 1.20, 128^2 with two workgroups per CU (4) 1.34, 64^2
 // (2) 2.04, the pre-split pass 173 per row and column; FP64 128^2 with 8
 // waves (3) 1.0, 64^2 (1) 1.36, 32^2 (2) 1.42; FP32 frequency groups on
@@ -756,7 +756,7 @@ int tile_for(int kind, const chi0_problem* probs, int nprob) {
     int idx;
     double cost;
   };
-  static const Cand bf16[] = {{19, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
+  static const Cand bf16[] = {{20, 1.0}, {7, 1.20}, {4, 1.34}, {2, 2.04}};
   static const Cand fp64[] = {{3, 1.0}, {1, 1.36}, {2, 1.42}};
   static const Cand fp32[] = {{2, 1.0}, {1, 1.27}, {0, 1.16}};
   const int ndef = herk_default_tile(kind);
@@ -877,6 +877,7 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
   bt.reserve(pl->nblocks_total);
   std::vector<ProbDesc> ptab(nprob);
   size_t woff = 0, zoff = 0;
+  bool z16 = true;
   for (int p = 0; p < nprob; ++p) {
     ptab[p].chi0 = static_cast<double2*>(probs[p].chi0);
     ptab[p].omega = probs[p].omega;
@@ -891,6 +892,7 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
       const chi0_block& bl = probs[p].blocks[b];
       BlockDesc d;
       d.z = bl.z;
+      if (probs[p].npb & 1) z16 = false;   // (every Z is 16-byte aligned: validated)
       d.eps_occ = bl.eps_occ;
       d.eps_unocc = bl.eps_unocc;
       d.wk = bl.wk;
@@ -937,6 +939,8 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
   ha.flags = static_cast<int32_t>(flags);
   ha.sync_prog = nullptr;
   ha.sync_slack = 0;
+  ha.z16 = z16 ? 1 : 0;
+  ha.pad = 0;
   const int slack = h->xcd_slack == -1 ? pl->tc.xcd_sync : h->xcd_slack;
   if (pl->tc.xcd_sync > 0 && slack != 0 && pl->round_robin) {
     // one progress word per workgroup; a fresh buffer starts at 0 (the
@@ -970,7 +974,7 @@ int run_accumulate_group(chi0_ctx* h, const chi0_problem* probs, int32_t nprob, 
     // only reused with the same values, so they join the key
     const int gi = ra.accumulate;
     char kb[96];
-    snprintf(kb, sizeof(kb), "#g%d/%a/%u/m%d", gi, delta_min, flags, mode);
+    snprintf(kb, sizeof(kb), "#g%d/%a/%u/m%d/z%d", gi, delta_min, flags, mode, ha.z16);
     const std::string gkey = key + kb;
     auto git = h->plans.find(gkey);
     Plan* gp = nullptr;

@@ -88,6 +88,9 @@ struct HerkArgs {
   int32_t sync_slack;         // with sync_prog: a workgroup more than this many
                               // stages ahead of the slowest one on its XCD waits
                               // (bounded)
+  int32_t z16;                // 1: every npb even, so Z rows (16-byte aligned
+                              // blocks) may be read in 16-byte chunks
+  int32_t pad;
 };
 
 struct ReduceArgs {

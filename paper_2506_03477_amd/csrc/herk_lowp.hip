@@ -924,6 +924,7 @@ static const TileConfig kBf16Tiles[] = {
     {128, kKC, 4096, kNT, 64, 1, 1, 4, 2},  // 17: as 16, light units dealt in locality order
     {128, kKC, 4096, kNT, 64, 1, 1, 4, 1, 16},  // 18: as 16, workgroups of an XCD in lockstep
     {128, kKC, 4096, kNT, 64, 1, 1, 4, 1, 16, 1},  // 19: as 18, planar partial tiles
+    {128, kKC, 4096, kNT, 64, 1, 1, 4, 1, 16, 1},  // 20: as 19, Z loaded in 16-byte chunks
 };
 static const TileConfig kFp32Tiles[] = {
     {128, kKC, 4096, kNT, 128},
@@ -997,7 +998,8 @@ hipError_t herk_bf16x3_launch(int idx, const HerkArgs& a, int nwg, hipStream_t s
     case 17:
     case 18:
     case 19:
-      return herk_bf16x3_wgroup_launch(lolo, idx == 19 ? 4 : idx >= 16 ? 3 : idx - 13, a, nwg, s);
+    case 20:
+      return herk_bf16x3_wgroup_launch(lolo, idx >= 19 ? idx - 15 : idx >= 16 ? 3 : idx - 13, a, nwg, s);
     default:
       if (lolo)
         hipLaunchKernelGGL(herk_bf16x3_tall8_kernel<true>, dim3(nwg), dim3(512), 0, s, a);
@@ -1041,6 +1043,7 @@ int herk_bf16x3_max_wg_per_cu(int idx) {
     case 17:
     case 18:
     case 19:
+    case 20:
       return herk_bf16x3_wgroup_max_wg_per_cu();
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_tall8_kernel<false>, 512, 0);

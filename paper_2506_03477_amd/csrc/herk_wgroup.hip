@@ -74,19 +74,25 @@ struct WgRun {
 // Per-lane byte offsets of the stage loads.  P: chunk m (16 bytes) of thread
 // t is group (t / 128) + 2 (m % 4) of plane m / 4, tile row t % 128.  Z:
 // dword m of thread t is pair (t + 256 m) / 128, tile column
-// ((t + 256 m) % 128) / 2, part (re / im) t % 2.
+// ((t + 256 m) % 128) / 2, part (re / im) t % 2; or, with 16-byte loads
+// (launched only when npb is even: Z rows then stay 16-byte aligned), chunk m of
+// lane l of wave w is pair 2 w + l / 32 + 8 m, tile columns 2 (l % 32) and
+// 2 (l % 32) + 1 (an even column: below npb, or clamped to 0, together with
+// the next one).
 struct WgLane {
   uint32_t p[4];
   uint32_t q[2];      // m even / odd (4 (m / 2) rows are added per load)
+  uint32_t q16;       // 16-byte Z loads: chunk 0 (8 m rows are added per load)
   uint32_t pf;        // FP32 path: dword t of a pair's 128 raw P values (row t / 2, part t % 2)
 };
 
 // Part PART (0..3) of the loads of stage st of the run into LDS buffer buf
-// (0: P hi words, 1: P lo words, 2: Z dwords 0..7 and the weights, 3: Z
-// dwords 8..15): every wave writes 1 KB (16-byte loads) or 256 bytes (dword
-// loads) per instruction, lane i at offset 16 i or 4 i of the wave's
-// destination.
-template <int PART>
+// (0: P hi words, 1: P lo words, 2: Z dwords 0..7 (Q16: chunks 0, 1) and
+// the weights, 3: Z dwords 8..15 (Q16: chunks 2, 3)): every wave writes
+// 1 KB (16-byte loads) or 256 bytes (dword loads) per instruction, lane i
+// at offset 16 i or 4 i of the wave's destination.  Both Z forms give the
+// same LDS layout ([pair][column], complex64).
+template <int PART, bool Q16>
 __device__ __forceinline__ void wg_dma(const WgRun& r, int st, const WgLane& o, int wave, int lane,
                                        char* buf) {
   if constexpr (PART < 2) {
@@ -99,12 +105,22 @@ __device__ __forceinline__ void wg_dma(const WgRun& r, int st, const WgLane& o, 
   } else {
     const int32_t zo = st * kWgPairs * r.row;
     const __amdgpu_buffer_rsrc_t z = wg_rsrc(r.z + zo, r.zbytes - zo);
+    if constexpr (Q16) {
 #pragma unroll
-    for (int mm = 0; mm < 8; ++mm) {
-      const int m = mm + 8 * (PART - 2);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          z, (lds_ptr)(buf + kWgPBytes + (64 * wave + 256 * m) * 4), 4,
-          o.q[m & 1] + static_cast<uint32_t>(4 * (m >> 1)) * static_cast<uint32_t>(r.row), 0, 0, 0);
+      for (int mm = 0; mm < 2; ++mm) {
+        const int m = mm + 2 * (PART - 2);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            z, (lds_ptr)(buf + kWgPBytes + (64 * wave + 256 * m) * 16), 16,
+            o.q16 + static_cast<uint32_t>(8 * m) * static_cast<uint32_t>(r.row), 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int mm = 0; mm < 8; ++mm) {
+        const int m = mm + 8 * (PART - 2);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            z, (lds_ptr)(buf + kWgPBytes + (64 * wave + 256 * m) * 4), 4,
+            o.q[m & 1] + static_cast<uint32_t>(4 * (m >> 1)) * static_cast<uint32_t>(r.row), 0, 0, 0);
+      }
     }
     if constexpr (PART == 2) {
       const int32_t wo = st * kWgPairs * 4;
@@ -115,12 +131,13 @@ __device__ __forceinline__ void wg_dma(const WgRun& r, int st, const WgLane& o, 
   }
 }
 
+template <bool Q16>
 __device__ __forceinline__ void wg_dma_all(const WgRun& r, int st, const WgLane& o, int wave,
                                            int lane, char* buf) {
-  wg_dma<0>(r, st, o, wave, lane, buf);
-  wg_dma<1>(r, st, o, wave, lane, buf);
-  wg_dma<2>(r, st, o, wave, lane, buf);
-  wg_dma<3>(r, st, o, wave, lane, buf);
+  wg_dma<0, Q16>(r, st, o, wave, lane, buf);
+  wg_dma<1, Q16>(r, st, o, wave, lane, buf);
+  wg_dma<2, Q16>(r, st, o, wave, lane, buf);
+  wg_dma<3, Q16>(r, st, o, wave, lane, buf);
 }
 
 // One k-step's fragments of one wave, read from a stage in LDS.
@@ -271,37 +288,37 @@ __device__ __forceinline__ void wg_kstep(const char* src, int ksn, int g8, int l
 // after it, and so do the reads of stage s + 1 (k-step 3 prefetches its
 // first fragments).  DIAG (tiles crossing the diagonal) leaves out the
 // MFMAs and P reads of blocks entirely above it.
-template <bool LOLO, bool HINT, int DIAG>
+template <bool LOLO, bool HINT, int DIAG, bool Q16>
 __device__ __forceinline__ void wg_stages(const WgRun& r, const WgLane& o, int nst, int wave,
                                           int lane, int g8, int l32, char (*lds)[kWgBuf],
                                           f32x16 (&cr)[4][2], f32x16 (&ci)[4][2]) {
-  wg_dma_all(r, 0, o, wave, lane, lds[0]);
+  wg_dma_all<Q16>(r, 0, o, wave, lane, lds[0]);
   __builtin_amdgcn_s_waitcnt(kVmcnt0);
   __syncthreads();
   WgFrag F0, F1;
   WgWords W;
   wg_read<DIAG>(lds[0], 0, g8, l32, wave, F0);
   wg_convert(F0, 0, W);
-  wg_dma<0>(r, 1, o, wave, lane, lds[1]);
+  wg_dma<0, Q16>(r, 1, o, wave, lane, lds[1]);
   int bc = 0;   // buffer of stage st
   for (int st = 0; st < nst; ++st) {
     const int bn = bc == 2 ? 0 : bc + 1, bnn = bn == 2 ? 0 : bn + 1;
     const char* cur = lds[bc];
     wg_kstep<LOLO, DIAG>(cur, 1, g8, l32, wave, F0, F1, W, cr, ci);
-    wg_dma<1>(r, st + 1, o, wave, lane, lds[bn]);
+    wg_dma<1, Q16>(r, st + 1, o, wave, lane, lds[bn]);
     if (HINT) wg_order<4>();
     __builtin_amdgcn_sched_barrier(0);
     wg_kstep<LOLO, DIAG>(cur, 2, g8, l32, wave, F1, F0, W, cr, ci);
-    wg_dma<2>(r, st + 1, o, wave, lane, lds[bn]);
-    if (HINT) wg_order<9>();
+    wg_dma<2, Q16>(r, st + 1, o, wave, lane, lds[bn]);
+    if (HINT) wg_order<Q16 ? 3 : 9>();
     __builtin_amdgcn_sched_barrier(0);
     wg_kstep<LOLO, DIAG>(cur, 3, g8, l32, wave, F0, F1, W, cr, ci);
-    wg_dma<3>(r, st + 1, o, wave, lane, lds[bn]);
-    if (HINT) wg_order<8>();
+    wg_dma<3, Q16>(r, st + 1, o, wave, lane, lds[bn]);
+    if (HINT) wg_order<Q16 ? 2 : 8>();
     __builtin_amdgcn_s_waitcnt(kVmcnt0);   // this wave's loads of stage st + 1
     __syncthreads();
     wg_kstep<LOLO, DIAG>(lds[bn], 0, g8, l32, wave, F1, F0, W, cr, ci);
-    wg_dma<0>(r, st + 2, o, wave, lane, lds[bnn]);
+    wg_dma<0, Q16>(r, st + 2, o, wave, lane, lds[bnn]);
     if (HINT) wg_order<4>();
     __builtin_amdgcn_sched_barrier(0);
     bc = bn;
@@ -517,7 +534,7 @@ __device__ __forceinline__ void wg_flush_planar(double2* slot, const f32x16 (&cr
 // frequency u.iw + w) from its ranges' stages into the wave's partial tile.
 // DIAG (0, or 1 / 2 for the tiles left / right of the diagonal) is fixed per
 // unit, so each kind has its own copy of the run loop and registers.
-template <bool LOLO, bool HINT, bool ATOM, bool PLANAR, int DIAG, bool F32 = false>
+template <bool LOLO, bool HINT, bool ATOM, bool PLANAR, int DIAG, bool F32, bool Q16>
 __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const ProbDesc& pd,
                                         int tid, int wave, int lane, int g8, int l32,
                                         char (*lds)[kWgBuf], int& done, bool& sync_on) {
@@ -541,6 +558,11 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
     const int col = c0 + ((d & 127) >> 1);
     o.q[h2] = static_cast<uint32_t>(d >> 7) * static_cast<uint32_t>(row) +
               static_cast<uint32_t>(col < npb ? col : 0) * 8u + static_cast<uint32_t>(d & 1) * 4u;
+  }
+  {
+    const int col = c0 + 2 * (lane & 31);
+    o.q16 = static_cast<uint32_t>(2 * wave + (lane >> 5)) * static_cast<uint32_t>(row) +
+            static_cast<uint32_t>(col < npb ? col : 0) * 8u;
   }
   {
     const int prow = r0 + (tid >> 1);
@@ -591,7 +613,7 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
       const int nst = (nv + kWgPairs - 1) / kWgPairs;
       if (a.sync_prog != nullptr && sync_on) sync_on = wg_sync(a, done, wave, lane);
       if constexpr (F32) f32_stages<DIAG>(r, o, nst, wave, lane, lds, cr, ci);
-      else wg_stages<LOLO, HINT, DIAG>(r, o, nst, wave, lane, g8, l32, lds, cr, ci);
+      else wg_stages<LOLO, HINT, DIAG, Q16>(r, o, nst, wave, lane, g8, l32, lds, cr, ci);
       done += nst;
       g0 += len;
       acc += len;
@@ -612,7 +634,7 @@ __device__ __forceinline__ void wg_unit(const HerkArgs& a, const Unit& u, const 
   }
 }
 
-template <bool LOLO, bool HINT, bool ATOM, bool SKIP, bool PLANAR, bool F32>
+template <bool LOLO, bool HINT, bool ATOM, bool SKIP, bool PLANAR, bool F32, bool Q16>
 __device__ __forceinline__ void wg_body(const HerkArgs& a, char (*lds)[kWgBuf]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -632,25 +654,25 @@ __device__ __forceinline__ void wg_body(const HerkArgs& a, char (*lds)[kWgBuf]) 
     // tiles crossing the diagonal (TP = 2 TQ): their blocks above it are
     // left out with SKIP (the reduction never reads those entries)
     const int diag = !SKIP ? 0 : u.tq == 2 * u.tp ? 1 : u.tq == 2 * u.tp + 1 ? 2 : 0;
-    if (diag == 0) wg_unit<LOLO, HINT, ATOM, PLANAR, 0, F32>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
-    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, PLANAR, 1, F32>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
-    else wg_unit<LOLO, HINT, ATOM, PLANAR, 2, F32>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
+    if (diag == 0) wg_unit<LOLO, HINT, ATOM, PLANAR, 0, F32, Q16>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
+    else if (diag == 1) wg_unit<LOLO, HINT, ATOM, PLANAR, 1, F32, Q16>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
+    else wg_unit<LOLO, HINT, ATOM, PLANAR, 2, F32, Q16>(a, u, pd, tid, wave, lane, g8, l32, lds, done, sync_on);
   }
   if (a.sync_prog != nullptr && tid == 0)
     __hip_atomic_store(a.sync_prog + blockIdx.x, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool LOLO, bool HINT, bool ATOM, bool SKIP, bool PLANAR>
+template <bool LOLO, bool HINT, bool ATOM, bool SKIP, bool PLANAR, bool Q16>
 __global__ __launch_bounds__(kNT, 1) void herk_bf16x3_wgroup_kernel(HerkArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[3][kWgBuf];
-  wg_body<LOLO, HINT, ATOM, SKIP, PLANAR, false>(a, lds);
+  wg_body<LOLO, HINT, ATOM, SKIP, PLANAR, false, Q16>(a, lds);
 }
 
 // FP32 contraction on the same units (frequency groups, diagonal blocks
 // left out, XCD lockstep, planar partial tiles, atomic flushes).
 __global__ __launch_bounds__(kNT, 1) void herk_fp32_wgroup_kernel(HerkArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[2][kWgBuf];
-  wg_body<false, false, true, true, true, true>(a, lds);
+  wg_body<false, false, true, true, true, true, false>(a, lds);
 }
 
 }  // namespace
@@ -659,21 +681,26 @@ hipError_t herk_bf16x3_wgroup_launch(bool lolo, int variant, const HerkArgs& a, 
                                      hipStream_t s) {
   // variant 0: compiler scheduling; 1: issue-order hints; 2: hints and
   // atomic flushes; 3: as 2, leaving out the blocks above the diagonal; 4:
-  // as 3, partial tiles as real and imaginary planes
-#define CHI0_WG_LAUNCH(L, H, A, K, P) \
-  hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<L, H, A, K, P>), dim3(nwg), dim3(kNT), 0, s, a)
+  // as 3, partial tiles as real and imaginary planes; 5: as 4, Z loaded in
+  // 16-byte chunks (only when every npb is even, so that Z rows are 16-byte
+  // aligned; else 4)
+  if (variant == 5 && !a.z16) variant = 4;
+#define CHI0_WG_LAUNCH(L, H, A, K, P, Q) \
+  hipLaunchKernelGGL((herk_bf16x3_wgroup_kernel<L, H, A, K, P, Q>), dim3(nwg), dim3(kNT), 0, s, a)
   if (lolo) {
-    if (variant == 0) CHI0_WG_LAUNCH(true, false, false, false, false);
-    else if (variant == 1) CHI0_WG_LAUNCH(true, true, false, false, false);
-    else if (variant == 2) CHI0_WG_LAUNCH(true, true, true, false, false);
-    else if (variant == 3) CHI0_WG_LAUNCH(true, true, true, true, false);
-    else CHI0_WG_LAUNCH(true, true, true, true, true);
+    if (variant == 0) CHI0_WG_LAUNCH(true, false, false, false, false, false);
+    else if (variant == 1) CHI0_WG_LAUNCH(true, true, false, false, false, false);
+    else if (variant == 2) CHI0_WG_LAUNCH(true, true, true, false, false, false);
+    else if (variant == 3) CHI0_WG_LAUNCH(true, true, true, true, false, false);
+    else if (variant == 4) CHI0_WG_LAUNCH(true, true, true, true, true, false);
+    else CHI0_WG_LAUNCH(true, true, true, true, true, true);
   } else {
-    if (variant == 0) CHI0_WG_LAUNCH(false, false, false, false, false);
-    else if (variant == 1) CHI0_WG_LAUNCH(false, true, false, false, false);
-    else if (variant == 2) CHI0_WG_LAUNCH(false, true, true, false, false);
-    else if (variant == 3) CHI0_WG_LAUNCH(false, true, true, true, false);
-    else CHI0_WG_LAUNCH(false, true, true, true, true);
+    if (variant == 0) CHI0_WG_LAUNCH(false, false, false, false, false, false);
+    else if (variant == 1) CHI0_WG_LAUNCH(false, true, false, false, false, false);
+    else if (variant == 2) CHI0_WG_LAUNCH(false, true, true, false, false, false);
+    else if (variant == 3) CHI0_WG_LAUNCH(false, true, true, true, false, false);
+    else if (variant == 4) CHI0_WG_LAUNCH(false, true, true, true, true, false);
+    else CHI0_WG_LAUNCH(false, true, true, true, true, true);
   }
 #undef CHI0_WG_LAUNCH
   return hipGetLastError();
@@ -693,7 +720,7 @@ int herk_fp32_wgroup_max_wg_per_cu() {
 int herk_bf16x3_wgroup_max_wg_per_cu() {
   int n = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, true, true, false, false>, kNT, 0);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, herk_bf16x3_wgroup_kernel<false, true, true, false, false, false>, kNT, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

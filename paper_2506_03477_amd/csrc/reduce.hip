@@ -69,14 +69,14 @@ hipError_t reduce_launch(const ReduceArgs& a, int njobs, hipStream_t s) {
 }
 
 // Built-in default configuration per path (fastest measured on the
-// npb = 2048 and spin-polarised workloads: the BF16x3 frequency-group kernel
-// on 128 x 64 tiles with issue-order hints; the 8-wave FP64 kernel; 64 x 64
-// FP32 tiles); the autotuner or chi0_set_tile overrides it.
+// npb = 2048 and spin-polarised workloads: the BF16x3 and FP32
+// frequency-group kernels on 128 x 64 tiles; the 8-wave FP64 kernel); the
+// autotuner or chi0_set_tile overrides it.
 int herk_default_tile(int kind) {
   switch (kind) {
     case HERK_FP64: return 3;
     case HERK_FP32: return 2;
-    case HERK_BF16X3: return 19;
+    case HERK_BF16X3: return 20;
   }
   return 0;
 }

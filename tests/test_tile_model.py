@@ -14,8 +14,8 @@ BATCH = [(384, 12, [(32, 250)] * 2)] * 32             # 32 q-points at npb 384
 SIGX = [(287, 1, [(92, 2097)] * 16)]                  # exchange self-energy, nqp 287
 
 CASES = [
-    (HEADLINE, {"bf16x3": 19, "fp32": 2, "fp64": 3}),
-    (BATCH, {"bf16x3": 19, "fp32": 2, "fp64": 3}),
+    (HEADLINE, {"bf16x3": 20, "fp32": 2, "fp64": 3}),
+    (BATCH, {"bf16x3": 20, "fp32": 2, "fp64": 3}),
     (SIGX, {"bf16x3": 2, "fp32": 1, "fp64": 2}),
 ]
 
