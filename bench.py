@@ -569,6 +569,8 @@ def bench_hist(args):
     out = torch.empty((wl.nomega, wl.npb, wl.npb), dtype=torch.complex128, device="cuda")
     prob = Problem([Block(z, eo, eu, wk) for z, eo, eu, wk, _ in blks], omega, out)
     spec = HistSpec(edges, HIST_SIGMA)
+    if args.tile >= 0:
+        ctx.set_tile(prec, args.tile)
     for _ in range(args.warmup):
         ctx.chi0_hist_accumulate([prob], [spec], precision=prec, delta_min=wl.delta_min)
     ctx.sync()
