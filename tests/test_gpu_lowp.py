@@ -12,7 +12,7 @@ import torch
 import oracle
 from gpu_common import (assert_hermitian_exact, device_problem, need_gpu, oracle_chi0,
                         rel_fro)
-from paper_2506_03477_amd import Context, Problem
+from paper_2506_03477_amd import Block, Context, Problem
 from splitmodel import chi0_model
 from synth import workload
 
@@ -202,6 +202,21 @@ def test_frequency_group_tile(ctx, npb, omega):
         ctx.sync()
         got[tile] = prob.chi0.cpu().numpy()
         assert_hermitian_exact(prob.chi0)
+    # tile 20 reads Z in 16-byte chunks (even npb): the same values two
+    # complex64 elements into a larger allocation (16-byte aligned, not
+    # cache-line aligned) give the same bits
+    shifted = []
+    for b in prob.blocks:
+        buf = torch.empty(b.z.numel() + 2, dtype=b.z.dtype, device=b.z.device)
+        zz = buf[2:].view(b.z.shape)
+        zz.copy_(b.z)
+        assert zz.data_ptr() % 128 == 16
+        shifted.append(Block(zz, b.eps_occ, b.eps_unocc, b.wk))
+    prob16 = Problem(shifted, prob.omega, torch.empty_like(prob.chi0))
+    ctx.set_tile("bf16x3", 20)
+    ctx.chi0_accumulate([prob16], precision="bf16x3")
+    ctx.sync()
+    got["20/16"] = prob16.chi0.cpu().numpy()
     ctx.set_tile("bf16x3", -1)
     e, em = rel_fro(got[grp], ref), rel_fro(got[grp], mod)
     _say(f"frequency groups npb {npb}, {len(omega)} omega: vs oracle {e.max():.3e}, "
@@ -213,7 +228,7 @@ def test_frequency_group_tile(ctx, npb, omega):
     # its additions in program order), the blocks left out above the
     # diagonal, the XCD lockstep, the planar partial tiles and the 16-byte
     # Z loads (odd npb: dword loads) change no arithmetic
-    for t in (14, 15, 16, 17, 18, 19, 20):
+    for t in (14, 15, 16, 17, 18, 19, 20, "20/16"):
         assert np.array_equal(got[t], got[grp]), t
 
 
