@@ -427,8 +427,8 @@ int chi0_tile_diag_skip(chi0_precision prec, int32_t tile);
  * restores it. */
 int chi0_set_flush(chi0_handle h, int32_t pairs);
 
-/* XCD lockstep of the BF16X3 frequency-group configurations that use it
- * (the default among them): with units dealt round-robin, the workgroups on
+/* XCD lockstep of the BF16X3 and FP32 frequency-group configurations that
+ * use it (their defaults among them): with units dealt round-robin, the workgroups on
  * one XCD, which stream the same pair ranges, wait before each FP32 run
  * while they are more than `stages` 32-pair stages ahead of the slowest of
  * them, so their shared rows stay in the XCD's L2.  The wait is bounded
