@@ -46,6 +46,9 @@ __device__ __forceinline__ void split2(float re, float im, uint32_t& hi, uint32_
   // side, the rounded product), and x - hi is exact in FP32
 #pragma clang fp contract(off)
   hi = pack_bf16x2(re, im);
+  // the packed word itself is unpacked: left visible, the compiler re-packs
+  // re alone for its low half (one more conversion per value)
+  asm("" : "+v"(hi));
   lo = pack_bf16x2(re - bf16_lo_to_f32(hi), im - bf16_hi_to_f32(hi));
 }
 

@@ -191,6 +191,9 @@ __device__ __forceinline__ void wg_convert(const WgFrag& f, int j, WgWords& o) {
     const float x = __uint_as_float(f.q[j][e].x) * c;
     const float y = __uint_as_float(f.q[j][e].y) * c;
     h[e] = pack_bf16x2(x, y);
+    // the packed word itself is unpacked: left visible, the compiler
+    // re-packs x alone for its low half (one more conversion per value)
+    asm("" : "+v"(h[e]));
     const float x1 = x - bf16_lo_to_f32(h[e]);
     const float y1 = y - bf16_hi_to_f32(h[e]);
     l[e] = pack_bf16x2(x1, y1);
